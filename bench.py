@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X DZS gravity step.
+
+Workload (the 128^3 configuration): 128^3 particles, periodic box L = 256 Mpc/h, PM mesh 256^3,
+split scale r_s = 1.25 mesh cells, cutoff 4.5 r_s, Zel'dovich start at z = 49 from a seeded
+Gaussian random field with a LCDM-shaped (BBKS, Omega_m = 0.3, sigma_8 = 0.8) spectrum,
+observer at the box corner, 50 log-spaced KDK steps to z = 0, all in the FP64 plain form.
+Each step is one kdk_step call: kick, drift + lightcone crossing output, DZS coarsening
+(2x2x2, theta = 0.1, b = 5 lambda; the host check skips the merge kernels at boundaries where
+no node can qualify), Morton sort, tree build, PM force, tree force (opening angle 0.5), kick.
+
+value = particle force updates per second = N * K / wall time of the K timed steps (inputs
+resident in HBM; the timed region is bracketed by torch.cuda.synchronize()).  The same K steps
+are then run as the full-resolution twin (no DZS) for the DZS/full-resolution wall-time ratio.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "particle force updates/sec on 1 GPU; DZS vs full-res wall time at equal accuracy"
+UNIT = "particle force updates/s"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+FLOP_PER_INTERACTION = 24
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(n_side=128, L=256.0, ng=256):
+    import dzs_ics
+    lam = L / n_side
+    return dict(n_side=n_side, N=n_side ** 3, L=L, ng=ng, r_s=1.25 * L / ng,
+                r_cut=4.5 * 1.25 * L / ng, eps0=lam / 40, m0=dzs_ics.particle_mass(L, n_side ** 3),
+                lam=lam, a_init=1.0 / 50.0, n_steps=50, theta_tree=0.5, theta_dzs=0.1,
+                b=5 * lam, lmax_over_lambda=2, seed=20050529)
+
+
+def k_min_for(n_side, j):
+    k = 0
+    while n_side > j * (1 << k):
+        k += 1
+    return k
+
+
+def make_params(dz, W, do_coarsen):
+    a = np.exp(np.linspace(math.log(W["a_init"]), 0.0, W["n_steps"] + 1))
+    out = []
+    for s in range(W["n_steps"]):
+        sp = dz.step_factors(float(a[s]), float(a[s + 1]), 0.3)
+        sp.do_lightcone = 1
+        sp.do_coarsen = 1 if do_coarsen else 0
+        sp.coarsen.R_lc = math.sqrt(sp.lc.chi2_1)
+        sp.coarsen.b = W["b"]
+        sp.coarsen.theta = W["theta_dzs"]
+        sp.coarsen.k_min = k_min_for(W["n_side"], W["lmax_over_lambda"])
+        sp.pm = dz.PMParams(W["ng"], dz.DZS_FP64, W["r_s"], 0, 0)
+        sp.tree = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], 8, 64, dz.DZS_FP64, 0)
+        out.append(sp)
+    return out
+
+
+def copy_state(dst, src):
+    for k in src.F64 + ("mult", "id", "type"):
+        getattr(dst, k).copy_(getattr(src, k))
+    dst.n = src.n
+
+
+# algorithmic bytes moved per launch, by kernel class (per particle N, per mesh cell C)
+def algorithmic_bytes(cls, N, C):
+    return {
+        "kick": 72 * N, "drift_lightcone": 72 * N, "morton_keys": 36 * N,
+        "pm_deposit": 28 * N + 8 * C, "pm_fft_x": 24 * C, "pm_fft_y": 32 * C,
+        "pm_fft_z_green": 32 * C, "pm_interp": 48 * N + 8 * C,
+    }.get(cls)
+
+
+def cpu_baseline(W, ics, box_o):
+    """The oracle timed on the host: one full force evaluation (PM on the full mesh plus the
+    direct-sum short range for a bounded sample of targets, extrapolated to N)."""
+    import oracle
+    oracle.build(force=False)
+    n_sample = 100000
+    rng = np.random.default_rng(1)
+    targets = np.sort(rng.choice(W["N"], n_sample, replace=False))
+    t0 = time.perf_counter()
+    oracle.pm_force(ics.x, ics.y, ics.z, ics.mult, box_o, W["ng"], W["r_s"])
+    t_pm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.short_range(ics.x, ics.y, ics.z, ics.mult, box_o, W["r_s"], W["r_cut"], targets)
+    t_sr = time.perf_counter() - t0
+    t_total = t_pm + t_sr * W["N"] / n_sample
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": W["N"] / t_total, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": (f"one force evaluation of the z=49 initial state: full PM {W['ng']}^3 "
+                       f"({t_pm:.2f} s) + direct-sum short range on {n_sample} of {W['N']} "
+                       f"targets ({t_sr:.2f} s), extrapolated to all targets; FP64")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-side", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-twin", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, ROOT)
+    import dzs_ics
+    import paper_2005_05328_amd as dz
+
+    W = workload(n_side=args.n_side, L=256.0 * args.n_side / 128, ng=2 * args.n_side)
+    K = max(1, min(args.steps, W["n_steps"]))
+    log(f"workload N={W['N']} L={W['L']} ng={W['ng']} steps={K} warmup={args.warmup}")
+    ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
+    box = dz.make_box(W["L"], W["m0"], W["eps0"])
+    ctx = dz.Context(W["N"], W["ng"])
+    st0 = dz.State.from_host(ics)
+    ctx.pm_force(box, st0, dz.PMParams(W["ng"], dz.DZS_FP64, W["r_s"], 0, 0))
+    ctx.tree_force(box, st0, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], 8, 64,
+                                           dz.DZS_FP64, 1))
+    torch.cuda.synchronize()
+    params_dzs = make_params(dz, W, True)
+    params_std = make_params(dz, W, False)
+    st = dz.State(W["N"])
+    ring = dz.LCRing(W["N"])
+
+    def run(params, steps, timed):
+        copy_state(st, st0)
+        ring.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        merged = 0
+        for s in range(steps):
+            rep = ctx.kdk_step(box, st, params[s], ring)
+            merged += int(rep.n_groups)
+            if timed and (s + 1) % 10 == 0:
+                log(f"  step {s + 1}/{steps}")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, merged
+
+    log("warmup")
+    run(params_dzs, args.warmup, False)
+    log("timed DZS run")
+    ctx.timing(enable=True, reset=True)
+    ctx.pair_interactions(reset=True)
+    t_dzs, merged = run(params_dzs, K, True)
+    kern = ctx.timing(enable=False, reset=True)
+    pairs = ctx.pair_interactions(reset=True)
+    n_records = int(ring.count.item())
+    final_dzs = {k: getattr(st, k)[: st.n].clone() for k in ("x", "y", "z", "px", "py", "pz")}
+    n_final = st.n
+    twin = None
+    if not args.no_twin:
+        log("timed full-resolution twin")
+        t_std, _ = run(params_std, K, True)
+        same = n_final == st.n and all(torch.equal(final_dzs[k], getattr(st, k)[: st.n])
+                                       for k in final_dzs)
+        twin = {"std_s": t_std, "dzs_s": t_dzs, "dzs_over_std": t_dzs / t_std,
+                "twins_bitwise_identical": bool(same), "merged_nodes": merged}
+
+    N, C = W["N"], W["ng"] ** 3
+    totals = {c: ms * calls for c, (ms, calls) in kern.items() if calls}
+    dom = max(totals, key=totals.get)
+    avg_ms, calls = kern[dom]
+    if dom == "tree_walk":
+        flops = FLOP_PER_INTERACTION * pairs / calls
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                    "kernel": dom, "avg_ms": avg_ms,
+                    "work_per_launch": f"{pairs / calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP"}
+    else:
+        b = algorithmic_bytes(dom, N, C)
+        achieved = (b / (avg_ms * 1e-3) / 1e9) if b else None
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                    "kernel": dom, "avg_ms": avg_ms}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        import oracle
+        box_o = oracle.Box(L=W["L"], m0=W["m0"], eps0=W["eps0"])
+        cpu = cpu_baseline(W, ics, box_o)
+
+    ms_per_step = 1e3 * t_dzs / K
+    out = {
+        "metric": METRIC, "value": N * K / t_dzs, "unit": UNIT, "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"{W['n_side']}^3 particles, L={W['L']:g} Mpc/h, mesh "
+                                f"{W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, "
+                                f"{K} of 50 log KDK steps to z=0, DZS 2x2x2 + lightcone, "
+                                f"tree theta {W['theta_tree']}, FP64 plain form"),
+                   "particles": N, "mesh": W["ng"], "box": W["L"], "parallelism": "1 GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "dzs_twin": twin,
+        "pair_interactions_per_step": pairs / K, "lightcone_records": n_records,
+        "particles_final": n_final,
+        "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
+                                                                    key=lambda kv: -kv[1])},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

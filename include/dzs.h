@@ -1,0 +1,248 @@
+/*
+ * dzs.h — C ABI of the MI355X (gfx950) DZS gravity-step library, libdzs.so.
+ *
+ * The library implements one gravity step of a periodic dark-matter N-body run on a
+ * mixed-mass particle set whose resolution is lowered outside the observer's past lightcone
+ * (Dynamic Zoom Simulations, Garaldi, Nori & Baldi 2020, arXiv:2005.05328):
+ *
+ *   dzs_coarsen    — DZS node merging, Sec. 2.2 and 2.2.1 (eqs. 1 and 3, l_max cap,
+ *                    softening rescale by (M/M_init)^(1/3), type change of merged particles)
+ *   pm_force       — long-range TreePM part, Sec. 2.1: density on a uniform grid, Poisson
+ *                    equation in Fourier space, Gaussian split kernel
+ *   tree_force     — short-range TreePM part, Sec. 2.1: monopole oct-tree with a geometric
+ *                    opening criterion (eq. 1)
+ *   lightcone_emit — on-the-fly lightcone output, Sec. 1 (R_lc) and Sec. 3.1.3 (particles
+ *                    saved as they reach the shrinking lightcone sphere)
+ *   kdk_step       — the whole step: kick, drift + lightcone, DZS, force, kick
+ *
+ * Conventions (all calls)
+ *   Units: lengths Mpc/h, velocities km/s, masses 1e10 Msun/h; G in those units.
+ *   State: structure of arrays in caller-owned DEVICE memory (dzs_particles).  Positions are
+ *   comoving, in [0, L).  Momenta p = a^2 dx/dt.  mass_i = mult_i * m0.  Softening
+ *   eps_i = eps0 * mult_i^(1/3) (spline support 2.8 eps_i).
+ *   Streams: every call is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *   returns without waiting for the GPU, except where a call is documented to synchronise.
+ *   Errors: every call returns a dzs_status; DZS_OK is 0, failures are negative.  Nothing
+ *   aborts or throws across the ABI.  dzs_last_error() gives a text for the context's last
+ *   failure.  Argument errors (DZS_EINVAL, DZS_ECAPACITY on sizes) are detected on the host
+ *   before anything is enqueued.
+ *   Threading: a context is used by one host thread and one stream at a time.
+ *   Determinism: given identical inputs every call produces bit-identical outputs (the
+ *   lightcone record order excepted; records are identified by id).
+ */
+#ifndef DZS_H
+#define DZS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dzs_status;
+#define DZS_OK 0
+#define DZS_EINVAL (-1)     /* bad argument, size or pointer */
+#define DZS_ENOMEM (-2)     /* device allocation failed at context creation */
+#define DZS_ECAPACITY (-3)  /* a size exceeds the context's capacity, or a device-side
+                               overflow (lightcone ring, tree walk stack) was detected */
+#define DZS_EHIP (-4)       /* a HIP runtime call failed */
+
+#define DZS_CHEB_MAX 24     /* maximum Chebyshev coefficients per function */
+
+typedef struct dzs_ctx dzs_ctx;
+
+/* Capacities fixed at context creation; the context allocates all its scratch then. */
+typedef struct {
+    uint64_t max_particles;  /* largest particle count any call will see */
+    uint32_t max_mesh_side;  /* largest PM mesh side N_g (N_g = 2^a 3^b, 8 <= N_g <= 1024) */
+    uint32_t reserved;
+} dzs_capacity;
+
+/* Periodic box. */
+typedef struct {
+    double L;     /* box side */
+    double m0;    /* mass of a multiplicity-1 particle */
+    double eps0;  /* Plummer-equivalent softening of a multiplicity-1 particle */
+    double G;     /* gravitational constant */
+} dzs_box;
+
+/* Particle state, caller-owned device arrays of at least `capacity` elements each. */
+typedef struct {
+    double *x, *y, *z;     /* positions in [0, L) */
+    double *px, *py, *pz;  /* momenta */
+    double *gx, *gy, *gz;  /* accelerations (written by the force calls) */
+    uint32_t *mult;        /* multiplicity (number of original particles represented) */
+    uint32_t *id;          /* identifier; a merged particle takes its smallest member id */
+    uint8_t *type;         /* 0 = original resolution, 1 = de-refined (merged) */
+    uint64_t n;            /* current count (host value; dzs_coarsen and kdk_step update it) */
+    uint64_t capacity;
+} dzs_particles;
+
+/* DZS de-refinement parameters (Sec. 2.2.1).  Geometric criterion: a node of side l_k
+ * (level k, l_k = L / 2^k) merges when l_k < theta * D_n with
+ * D_n = max(|x_com - x_obs|_min-image - R_lc - b, 0) (eq. 3), when k >= k_min (l_k <= l_max)
+ * and when it holds at least two particles.  Each particle joins its shallowest merging
+ * node (top-down walk).  The node centre of mass is the Neumaier-compensated FP64 sum over
+ * its members in ascending (Morton key, id) order divided by their total multiplicity. */
+typedef struct {
+    double x_obs[3];  /* observer position */
+    double R_lc;      /* lightcone radius at the coarsening epoch */
+    double b;         /* buffer width */
+    double theta;     /* geometric de-refinement angle (> 0) */
+    int32_t k_min;    /* shallowest level allowed to merge, 1..21 */
+    int32_t reserved;
+} dzs_coarsen_params;
+
+typedef struct {
+    uint64_t n_before, n_after, n_groups;  /* n_groups = merged nodes created */
+} dzs_coarsen_report;
+
+#define DZS_FP64 0        /* plain form: every step in FP64 */
+#define DZS_FP32 1        /* precision form: pair and mesh arithmetic in FP32 */
+
+/* PM (long-range) parameters: mesh points at j*Delta, Delta = L/ng; cloud-in-cell
+ * assignment; Green's function -4 pi G exp(-k^2 r_s^2) / (k^2 W(k)^2) with the CIC window
+ * W deconvolved twice; 4-point finite-difference gradient; CIC interpolation. */
+typedef struct {
+    int32_t ng;          /* mesh side */
+    int32_t precision;   /* DZS_FP64 (the only form implemented for the mesh so far) */
+    double r_s;          /* split scale */
+    int32_t accumulate;  /* 0: g = g_long, 1: g += g_long */
+    int32_t reserved;
+} dzs_pm_params;
+
+/* Tree (short-range) parameters: g_i = -G sum m_j r_ij g_soft(r_ij, h_ij) S(r_ij/r_s) over
+ * sources closer than r_cut, S(u) = erfc(u/2) + u/sqrt(pi) exp(-u^2/4); nodes whose side l
+ * satisfies l < theta * d (d = distance from the target group's bounding box to the node
+ * centre of mass) act as monopoles.  theta = 0 opens every node (exact direct sum). */
+typedef struct {
+    double r_s, r_cut;   /* split scale and cutoff (r_cut < L/2) */
+    double theta;        /* opening angle, >= 0 */
+    int32_t leaf_size;   /* particles per tree leaf, 1..64 (0 = default 8) */
+    int32_t group_size;  /* targets per wavefront group, 1..64 (0 = default 64) */
+    int32_t precision;   /* DZS_FP64 (plain form) */
+    int32_t accumulate;  /* 0: g = g_short, 1: g += g_short */
+} dzs_tree_params;
+
+/* Lightcone crossing over one drift a0 -> a1 (positions at a0, momenta constant).
+ * d0 = min-image(x - x_obs); d1 = d0 + p D.  A particle is emitted iff
+ * |d0|^2 - chi2_0 < 0 <= |d1|^2 - chi2_1 (the sphere of radius chi(a) shrinks with a).
+ * The crossing time solves |d0 + p D(a0,a)| = chi(a) on [a0, a1] using the Chebyshev
+ * series of chi(a) and D(a0,a) on [a0, a1] (dzs_step_factors fills all of this). */
+typedef struct {
+    double x_obs[3];
+    double a0, a1;
+    double D;               /* D(a0, a1) = int da / (a^3 H) */
+    double chi2_0, chi2_1;  /* chi(a0)^2, chi(a1)^2 */
+    int32_t n_cheb;         /* coefficients used, 1..DZS_CHEB_MAX */
+    int32_t reserved;
+    double cheb_chi[DZS_CHEB_MAX];    /* chi(a),    a = a0 + (t+1)(a1-a0)/2, t in [-1,1] */
+    double cheb_drift[DZS_CHEB_MAX];  /* D(a0, a),  same variable */
+} dzs_lc_params;
+
+/* One lightcone record (64 bytes). */
+typedef struct {
+    uint32_t id, mult;
+    double a_cross;   /* scale factor at the crossing */
+    double d[3];      /* offset from the observer at the crossing */
+    double p[3];      /* momentum during the drift */
+} dzs_lc_record;
+
+/* Caller-owned device ring of records.  *count (device) is advanced atomically; records
+ * beyond `capacity` are dropped and *overflow (device) is set to 1.  The caller resets
+ * both between uses. */
+typedef struct {
+    dzs_lc_record *records;
+    uint64_t capacity;
+    unsigned long long *count;
+    uint32_t *overflow;
+} dzs_lc_ring;
+
+typedef struct {
+    double K1, K2;            /* kick factors K(a0, a_h), K(a_h, a1), a_h = sqrt(a0 a1) */
+    dzs_lc_params lc;         /* drift and lightcone */
+    int32_t do_lightcone;     /* 0: skip the crossing test */
+    int32_t do_coarsen;       /* 0: skip DZS */
+    dzs_coarsen_params coarsen;
+    dzs_pm_params pm;
+    dzs_tree_params tree;
+} dzs_step_params;
+
+/* ---- context ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` and allocate all its scratch for `cap`.
+ * Returns DZS_ENOMEM if the device memory does not suffice. */
+dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap);
+dzs_status dzs_ctx_destroy(dzs_ctx *ctx);
+/* Text of the context's last failure ("" if none); valid until the next call. */
+const char *dzs_last_error(const dzs_ctx *ctx);
+
+/* Host helper: flat LCDM (Omega_m = omega_m, no radiation) kick, drift and lightcone
+ * factors for the step a0 -> a1: K1, K2, lc.D, lc.chi2_0, lc.chi2_1, lc.a0, lc.a1 and the
+ * Chebyshev series, by Gauss-Legendre quadrature.  Leaves every other field untouched. */
+dzs_status dzs_step_factors(double a0, double a1, double omega_m, dzs_step_params *out);
+
+/* ---- the gravity step ---------------------------------------------------------------- */
+
+/* DZS coarsening (Sec. 2.2).  Reorders the state in place to ascending (Morton key, id),
+ * replaces each merging node's members by one particle (mult = sum, x = centre of mass,
+ * p = mult-weighted mean momentum, id = smallest member id, type = 1) and updates inout->n.
+ * g is not preserved.  group_of (optional, device, >= n entries) receives for each
+ * particle's index on entry the index of the particle representing it on exit.
+ * Synchronises the stream (the new count is read back). */
+dzs_status dzs_coarsen(dzs_ctx *ctx, const dzs_box *box, dzs_particles *inout,
+                       const dzs_coarsen_params *prm, uint32_t *group_of,
+                       dzs_coarsen_report *report, void *stream);
+
+/* PM long-range acceleration into g (or added to g).  Particle order is left unchanged. */
+dzs_status pm_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                    const dzs_pm_params *prm, void *stream);
+
+/* Tree short-range acceleration into g (or added to g).  Particle order is left unchanged
+ * (the tree is built on a sorted copy).  Synchronises the stream during the tree build. */
+dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                      const dzs_tree_params *prm, void *stream);
+
+/* Lightcone crossing test and solve for the drift described by prm (does not move the
+ * particles). */
+dzs_status lightcone_emit(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                          const dzs_lc_params *prm, dzs_lc_ring *ring, void *stream);
+
+/* One kick-drift-kick step a0 -> a1:
+ *   p += g K1; lightcone over the drift (optional); x = wrap(x + p D);
+ *   DZS coarsening at a1 (optional; skipped when R_lc + b >= sqrt(3)/2 L, where no node can
+ *   qualify); reorder the state by Morton key; g = PM + tree; p += g K2.
+ * The state is left sorted by Morton key.  report (optional) receives the coarsening
+ * counts.  Synchronises the stream (tree build; coarsening). */
+dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *state,
+                    const dzs_step_params *prm, dzs_lc_ring *ring, dzs_coarsen_report *report,
+                    void *stream);
+
+/* ---- parts of the path, exposed for testing and measurement --------------------------- */
+
+/* Morton keys (21 bits per dimension, x in the highest bit of each triple) of the
+ * particles in their current order into keys (device, n entries). */
+dzs_status dzs_morton_keys(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                           uint64_t *keys, void *stream);
+
+/* Reorder the state in place by ascending Morton key (stable), optionally breaking ties by
+ * ascending id; perm (optional, device) receives the entry index of each sorted slot. */
+dzs_status dzs_sort_state(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p,
+                          int32_t ties_by_id, uint32_t *perm, void *stream);
+
+/* Number of source-target interactions inside the cutoff evaluated by the tree walk since
+ * the context was created or last reset (the algorithmic pair work).  Synchronises the
+ * device. */
+dzs_status dzs_counters(dzs_ctx *ctx, int32_t reset, uint64_t *pair_interactions);
+
+/* Average duration in milliseconds of each internal kernel class over the calls made since
+ * the last reset, measured with HIP events on the call's stream when timing is enabled.
+ * names/values: caller arrays of `cap` entries; returns the number of classes written. */
+int32_t dzs_timing(dzs_ctx *ctx, int32_t enable, int32_t reset, const char **names,
+                   double *ms_avg, uint64_t *calls, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DZS_H */

@@ -1,0 +1,113 @@
+"""ctypes mirror of include/dzs.h and argument marshalling for libdzs.so.
+
+Nothing here computes any part of the gravity step: every call goes through the C ABI into
+the HIP kernels.  PyTorch supplies device memory (tensors) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdzs.so")
+
+DZS_OK, DZS_EINVAL, DZS_ENOMEM, DZS_ECAPACITY, DZS_EHIP = 0, -1, -2, -3, -4
+DZS_CHEB_MAX = 24
+DZS_FP64, DZS_FP32 = 0, 1
+
+# every entry point include/dzs.h declares
+EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_factors",
+           "dzs_coarsen", "pm_force", "tree_force", "lightcone_emit", "kdk_step",
+           "dzs_morton_keys", "dzs_sort_state", "dzs_counters", "dzs_timing")
+
+
+class Capacity(C.Structure):
+    _fields_ = [("max_particles", C.c_uint64), ("max_mesh_side", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class Box(C.Structure):
+    _fields_ = [("L", C.c_double), ("m0", C.c_double), ("eps0", C.c_double), ("G", C.c_double)]
+
+
+class Particles(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "px", "py", "pz", "gx", "gy", "gz",
+                                          "mult", "id", "type")] + \
+               [("n", C.c_uint64), ("capacity", C.c_uint64)]
+
+
+class CoarsenParams(C.Structure):
+    _fields_ = [("x_obs", C.c_double * 3), ("R_lc", C.c_double), ("b", C.c_double),
+                ("theta", C.c_double), ("k_min", C.c_int32), ("reserved", C.c_int32)]
+
+
+class CoarsenReport(C.Structure):
+    _fields_ = [("n_before", C.c_uint64), ("n_after", C.c_uint64), ("n_groups", C.c_uint64)]
+
+
+class PMParams(C.Structure):
+    _fields_ = [("ng", C.c_int32), ("precision", C.c_int32), ("r_s", C.c_double),
+                ("accumulate", C.c_int32), ("reserved", C.c_int32)]
+
+
+class TreeParams(C.Structure):
+    _fields_ = [("r_s", C.c_double), ("r_cut", C.c_double), ("theta", C.c_double),
+                ("leaf_size", C.c_int32), ("group_size", C.c_int32), ("precision", C.c_int32),
+                ("accumulate", C.c_int32)]
+
+
+class LCParams(C.Structure):
+    _fields_ = [("x_obs", C.c_double * 3), ("a0", C.c_double), ("a1", C.c_double),
+                ("D", C.c_double), ("chi2_0", C.c_double), ("chi2_1", C.c_double),
+                ("n_cheb", C.c_int32), ("reserved", C.c_int32),
+                ("cheb_chi", C.c_double * DZS_CHEB_MAX), ("cheb_drift", C.c_double * DZS_CHEB_MAX)]
+
+
+class LCRecord(C.Structure):
+    _fields_ = [("id", C.c_uint32), ("mult", C.c_uint32), ("a_cross", C.c_double),
+                ("d", C.c_double * 3), ("p", C.c_double * 3)]
+
+
+class LCRing(C.Structure):
+    _fields_ = [("records", C.c_void_p), ("capacity", C.c_uint64), ("count", C.c_void_p),
+                ("overflow", C.c_void_p)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("K1", C.c_double), ("K2", C.c_double), ("lc", LCParams),
+                ("do_lightcone", C.c_int32), ("do_coarsen", C.c_int32),
+                ("coarsen", CoarsenParams), ("pm", PMParams), ("tree", TreeParams)]
+
+
+assert C.sizeof(LCRecord) == 64
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdzs.so not found at {LIB_PATH}: build it with "
+                          "`python -m paper_2005_05328_amd.build` (the GPU path has no fallback)")
+    L = C.CDLL(LIB_PATH)
+    P, i32, st = C.c_void_p, C.c_int32, C.c_int32
+    L.dzs_ctx_create.argtypes = [C.POINTER(P), i32, C.POINTER(Capacity)]
+    L.dzs_ctx_destroy.argtypes = [P]
+    L.dzs_last_error.argtypes = [P]
+    L.dzs_last_error.restype = C.c_char_p
+    L.dzs_step_factors.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(StepParams)]
+    L.dzs_coarsen.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(CoarsenParams),
+                              P, C.POINTER(CoarsenReport), P]
+    L.pm_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(PMParams), P]
+    L.tree_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(TreeParams), P]
+    L.lightcone_emit.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(LCParams),
+                                 C.POINTER(LCRing), P]
+    L.kdk_step.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(StepParams),
+                           C.POINTER(LCRing), C.POINTER(CoarsenReport), P]
+    L.dzs_morton_keys.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), P, P]
+    L.dzs_sort_state.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), i32, P, P]
+    L.dzs_counters.argtypes = [P, i32, C.POINTER(C.c_uint64)]
+    L.dzs_timing.argtypes = [P, i32, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                             C.POINTER(C.c_uint64), i32]
+    for name in ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_step_factors", "dzs_coarsen",
+                 "pm_force", "tree_force", "lightcone_emit", "kdk_step", "dzs_morton_keys",
+                 "dzs_sort_state", "dzs_counters", "dzs_timing"):
+        getattr(L, name).restype = st
+    return L

@@ -1,0 +1,498 @@
+// The C ABI of libdzs: context lifetime, argument checks, orchestration of the step, and
+// HIP-event timing of the kernel classes.
+#include <math.h>
+#include <stdarg.h>
+#include <stdlib.h>
+
+#include "internal.h"
+
+const char *const dzs_kclass_names[KC_COUNT] = {
+    "kick",        "drift_lightcone", "morton_keys", "radix_sort",  "permute",
+    "tree_build",  "tree_moments",    "tree_groups", "tree_walk",   "pm_deposit",
+    "pm_fft_x",    "pm_fft_y",        "pm_fft_z_green", "pm_interp", "dzs_levels",
+    "dzs_compact", "misc"};
+
+dzs_status dzs_fail(dzs_ctx *ctx, dzs_status code, const char *fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+dzs_status dzs_check_launch(dzs_ctx *ctx, const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return dzs_fail(ctx, DZS_EHIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return DZS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------------------
+static void drain_timers(dzs_ctx *ctx) {
+    dzs_timer_pool *P = ctx->timers;
+    if (!P)
+        return;
+    for (int i = 0; i < P->used; ++i) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(P->stop[i]) == hipSuccess &&
+            hipEventElapsedTime(&ms, P->start[i], P->stop[i]) == hipSuccess) {
+            ctx->t_ms[P->cls[i]] += ms;
+            ctx->t_calls[P->cls[i]] += 1;
+        }
+    }
+    P->used = 0;
+}
+
+void dzs_time_begin(dzs_ctx *ctx, int cls, hipStream_t s, int *slot) {
+    *slot = -1;
+    if (!ctx->timing || !ctx->timers)
+        return;
+    dzs_timer_pool *P = ctx->timers;
+    if (P->used >= dzs_timer_pool::CAP)
+        drain_timers(ctx);
+    const int k = P->used++;
+    P->cls[k] = cls;
+    if (hipEventRecord(P->start[k], s) == hipSuccess)
+        *slot = k;
+    else
+        P->used--;
+}
+
+void dzs_time_end(dzs_ctx *ctx, hipStream_t s, int slot) {
+    if (slot < 0)
+        return;
+    (void)hipEventRecord(ctx->timers->stop[slot], s);
+}
+
+extern "C" dzs_status dzs_counters(dzs_ctx *ctx, int32_t reset, uint64_t *pair_interactions) {
+    if (!ctx || !pair_interactions)
+        return DZS_EINVAL;
+    uint64_t v = 0;
+    DZS_HIP(ctx, hipDeviceSynchronize());
+    DZS_HIP(ctx, hipMemcpy(&v, ctx->walk_counter + 8, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    *pair_interactions = v;
+    if (reset)
+        DZS_HIP(ctx, hipMemset(ctx->walk_counter + 8, 0, sizeof(uint64_t)));
+    return DZS_OK;
+}
+
+extern "C" int32_t dzs_timing(dzs_ctx *ctx, int32_t enable, int32_t reset, const char **names,
+                              double *ms_avg, uint64_t *calls, int32_t cap) {
+    if (!ctx)
+        return 0;
+    if (enable && !ctx->timers) {
+        ctx->timers = new dzs_timer_pool();
+        for (int i = 0; i < dzs_timer_pool::CAP; ++i) {
+            (void)hipEventCreate(&ctx->timers->start[i]);
+            (void)hipEventCreate(&ctx->timers->stop[i]);
+        }
+        ctx->timers->created = true;
+    }
+    drain_timers(ctx);
+    int32_t w = 0;
+    for (int c = 0; c < KC_COUNT && w < cap; ++c) {
+        if (names)
+            names[w] = dzs_kclass_names[c];
+        if (ms_avg)
+            ms_avg[w] = ctx->t_calls[c] ? ctx->t_ms[c] / (double)ctx->t_calls[c] : 0.0;
+        if (calls)
+            calls[w] = ctx->t_calls[c];
+        ++w;
+    }
+    if (reset) {
+        for (int c = 0; c < KC_COUNT; ++c) {
+            ctx->t_ms[c] = 0.0;
+            ctx->t_calls[c] = 0;
+        }
+    }
+    ctx->timing = enable != 0;
+    return w;
+}
+
+// ---------------------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------------------
+template <typename T>
+static dzs_status alloc(dzs_ctx *ctx, T **p, uint64_t count) {
+    void *v = nullptr;
+    uint64_t bytes = sizeof(T) * (count > 0 ? count : 1);
+    hipError_t e = hipMalloc(&v, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return dzs_fail(ctx, DZS_ENOMEM, "hipMalloc of %llu bytes failed: %s",
+                        (unsigned long long)bytes, hipGetErrorString(e));
+    }
+    *p = (T *)v;
+    return DZS_OK;
+}
+
+static void release(dzs_ctx *ctx) {
+    void *ptrs[] = {ctx->key, ctx->key_alt, ctx->idx, ctx->idx_alt, ctx->hist, ctx->hist_scan,
+                    ctx->scan_tmp, ctx->gather_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult,
+                    ctx->sgx, ctx->sgy, ctx->sgz, ctx->nd_first, ctx->nd_count, ctx->nd_child,
+                    ctx->nd_nchild, ctx->nd_level, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
+                    ctx->nd_bmax, ctx->nd_hmax, ctx->frontier, ctx->frontier_next,
+                    ctx->fr_nchild, ctx->fr_ninternal, ctx->fr_child_off, ctx->fr_int_off,
+                    ctx->child_bounds, ctx->grp_flag, ctx->grp_scan, ctx->grp_first,
+                    ctx->walk_stack, ctx->walk_counter, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                    ctx->pm_tables, ctx->dz_head, ctx->dz_flag, ctx->dz_scan, ctx->dz_new,
+                    ctx->dz_newmult, ctx->dz_newid, ctx->dz_perm, ctx->d_small};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    if (ctx->h_small)
+        (void)hipHostFree(ctx->h_small);
+    if (ctx->timers) {
+        for (int i = 0; i < dzs_timer_pool::CAP; ++i) {
+            (void)hipEventDestroy(ctx->timers->start[i]);
+            (void)hipEventDestroy(ctx->timers->stop[i]);
+        }
+        delete ctx->timers;
+    }
+}
+
+static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
+    const uint64_t n = cap->max_particles + 64;
+    const uint64_t ng = cap->max_mesh_side;
+    const uint64_t ng3 = ng * ng * ng;
+    c->cap_n = n;
+    c->cap_ng = (uint32_t)ng;
+    DZS_TRY(alloc(c, &c->key, n));
+    DZS_TRY(alloc(c, &c->key_alt, n));
+    DZS_TRY(alloc(c, &c->idx, n));
+    DZS_TRY(alloc(c, &c->idx_alt, n));
+    c->hist_cap = dzs_sort_hist_words(n);
+    DZS_TRY(alloc(c, &c->hist, c->hist_cap));
+    DZS_TRY(alloc(c, &c->hist_scan, c->hist_cap));
+    uint64_t scan_n = n > c->hist_cap ? n : c->hist_cap;
+    c->scan_tmp_cap = dzs_scan_tmp_words(scan_n);
+    DZS_TRY(alloc(c, &c->scan_tmp, c->scan_tmp_cap));
+    double *gt = nullptr;
+    DZS_TRY(alloc(c, &gt, n));
+    c->gather_tmp = gt;
+    DZS_TRY(alloc(c, &c->sx, n));
+    DZS_TRY(alloc(c, &c->sy, n));
+    DZS_TRY(alloc(c, &c->sz, n));
+    DZS_TRY(alloc(c, &c->smult, n));
+    DZS_TRY(alloc(c, &c->sgx, n));
+    DZS_TRY(alloc(c, &c->sgy, n));
+    DZS_TRY(alloc(c, &c->sgz, n));
+    const uint64_t nn = n + 4096;
+    c->cap_nodes = nn;
+    DZS_TRY(alloc(c, &c->nd_first, nn));
+    DZS_TRY(alloc(c, &c->nd_count, nn));
+    DZS_TRY(alloc(c, &c->nd_child, nn));
+    DZS_TRY(alloc(c, &c->nd_nchild, nn));
+    DZS_TRY(alloc(c, &c->nd_level, nn));
+    DZS_TRY(alloc(c, &c->nd_mass, nn));
+    DZS_TRY(alloc(c, &c->nd_com, 3 * nn));
+    DZS_TRY(alloc(c, &c->nd_bmin, 3 * nn));
+    DZS_TRY(alloc(c, &c->nd_bmax, 3 * nn));
+    DZS_TRY(alloc(c, &c->nd_hmax, nn));
+    DZS_TRY(alloc(c, &c->frontier, n));
+    DZS_TRY(alloc(c, &c->frontier_next, n));
+    DZS_TRY(alloc(c, &c->fr_nchild, n));
+    DZS_TRY(alloc(c, &c->fr_ninternal, n));
+    DZS_TRY(alloc(c, &c->fr_child_off, n));
+    DZS_TRY(alloc(c, &c->fr_int_off, n));
+    DZS_TRY(alloc(c, &c->child_bounds, 9 * n));
+    DZS_TRY(alloc(c, &c->grp_flag, n));
+    DZS_TRY(alloc(c, &c->grp_scan, n));
+    DZS_TRY(alloc(c, &c->grp_first, n + 1));
+    c->walk_stack_slots = 4096;
+    c->walk_stack_depth = 8192;
+    DZS_TRY(alloc(c, &c->walk_stack, c->walk_stack_slots * c->walk_stack_depth));
+    DZS_TRY(alloc(c, &c->walk_counter, 64));
+    DZS_HIP(c, hipMemset(c->walk_counter, 0, 64 * sizeof(uint32_t)));
+    if (ng > 0) {
+        DZS_TRY(alloc(c, &c->mesh_q, ng3));
+        DZS_TRY(alloc(c, &c->mesh_c, ng3));
+        DZS_TRY(alloc(c, &c->mesh_phi, ng3));
+        DZS_TRY(alloc(c, &c->pm_tables, 4 * ng));
+    }
+    DZS_TRY(alloc(c, &c->dz_head, n));
+    DZS_TRY(alloc(c, &c->dz_flag, n));
+    DZS_TRY(alloc(c, &c->dz_scan, n));
+    DZS_TRY(alloc(c, &c->dz_new, 6 * n));
+    DZS_TRY(alloc(c, &c->dz_newmult, n));
+    DZS_TRY(alloc(c, &c->dz_newid, n));
+    DZS_TRY(alloc(c, &c->dz_perm, n));
+    DZS_TRY(alloc(c, &c->d_small, 64));
+    void *h = nullptr;
+    DZS_HIP(c, hipHostMalloc(&h, 64 * sizeof(uint32_t), hipHostMallocDefault));
+    c->h_small = (uint32_t *)h;
+    memset(c->h_small, 0, 64 * sizeof(uint32_t));
+    return DZS_OK;
+}
+
+extern "C" dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap) {
+    if (!out || !cap || cap->max_particles == 0 || cap->max_particles > 0xfffff000ull)
+        return DZS_EINVAL;
+    if (cap->max_mesh_side != 0 && !dzs_pm_mesh_ok((int)cap->max_mesh_side))
+        return DZS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return DZS_EHIP;
+    if (hipSetDevice(device) != hipSuccess)
+        return DZS_EHIP;
+    dzs_ctx *c = new dzs_ctx();
+    c->device = device;
+    dzs_status st = create(c, cap);
+    if (st != DZS_OK) {
+        release(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return DZS_OK;
+}
+
+extern "C" dzs_status dzs_ctx_destroy(dzs_ctx *ctx) {
+    if (!ctx)
+        return DZS_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    release(ctx);
+    delete ctx;
+    return DZS_OK;
+}
+
+extern "C" const char *dzs_last_error(const dzs_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+// ---------------------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------------------
+static dzs_status check_common(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p) {
+    if (!ctx)
+        return DZS_EINVAL;
+    ctx->err[0] = 0;
+    if (!box || !p)
+        return dzs_fail(ctx, DZS_EINVAL, "null box or particle view");
+    if (!(box->L > 0.0) || !(box->m0 > 0.0) || !(box->eps0 > 0.0) || !(box->G > 0.0))
+        return dzs_fail(ctx, DZS_EINVAL, "box L, m0, eps0 and G must be positive");
+    if (p->n > p->capacity)
+        return dzs_fail(ctx, DZS_EINVAL, "n (%llu) exceeds the view's capacity (%llu)",
+                        (unsigned long long)p->n, (unsigned long long)p->capacity);
+    if (p->n + 64 > ctx->cap_n)
+        return dzs_fail(ctx, DZS_ECAPACITY, "n (%llu) exceeds the context capacity (%llu)",
+                        (unsigned long long)p->n, (unsigned long long)(ctx->cap_n - 64));
+    if (p->n > 0 && (!p->x || !p->y || !p->z || !p->mult))
+        return dzs_fail(ctx, DZS_EINVAL, "null position or multiplicity array");
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device)
+        DZS_HIP(ctx, hipSetDevice(ctx->device));
+    return DZS_OK;
+}
+
+static dzs_status check_tree(dzs_ctx *ctx, const dzs_box *box, const dzs_tree_params *t,
+                             dzs_tree_params *out) {
+    if (!t)
+        return dzs_fail(ctx, DZS_EINVAL, "null tree parameters");
+    *out = *t;
+    if (out->leaf_size == 0)
+        out->leaf_size = 8;
+    if (out->group_size == 0)
+        out->group_size = 64;
+    if (!(t->r_s > 0.0) || !(t->r_cut > 0.0) || !(t->r_cut < 0.5 * box->L) || !(t->theta >= 0.0))
+        return dzs_fail(ctx, DZS_EINVAL, "tree: need r_s > 0, 0 < r_cut < L/2, theta >= 0");
+    if (out->leaf_size < 1 || out->leaf_size > 64 || out->group_size < 1 || out->group_size > 64)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: leaf_size and group_size must be in 1..64");
+    if (t->precision != DZS_FP64)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: only the FP64 form is available");
+    return DZS_OK;
+}
+
+static dzs_status check_pm(dzs_ctx *ctx, const dzs_pm_params *m) {
+    if (!m)
+        return dzs_fail(ctx, DZS_EINVAL, "null PM parameters");
+    if (!dzs_pm_mesh_ok(m->ng))
+        return dzs_fail(ctx, DZS_EINVAL, "pm: mesh side %d must be 2^a 3^b in [8, 1024]", m->ng);
+    if ((uint32_t)m->ng > ctx->cap_ng)
+        return dzs_fail(ctx, DZS_ECAPACITY, "pm: mesh side %d exceeds the context's %u", m->ng,
+                        ctx->cap_ng);
+    if (!(m->r_s > 0.0))
+        return dzs_fail(ctx, DZS_EINVAL, "pm: r_s must be positive");
+    if (m->precision != DZS_FP64)
+        return dzs_fail(ctx, DZS_EINVAL, "pm: only the FP64 form is available");
+    return DZS_OK;
+}
+
+static dzs_status check_coarsen(dzs_ctx *ctx, const dzs_coarsen_params *c) {
+    if (!c)
+        return dzs_fail(ctx, DZS_EINVAL, "null coarsening parameters");
+    if (!(c->theta > 0.0) || c->k_min < 1 || c->k_min > DZS_KEY_BITS || !(c->R_lc >= 0.0) ||
+        !(c->b >= 0.0))
+        return dzs_fail(ctx, DZS_EINVAL, "coarsen: need theta > 0, 1 <= k_min <= 21, R_lc, b >= 0");
+    return DZS_OK;
+}
+
+static dzs_status check_lc(dzs_ctx *ctx, const dzs_lc_params *lc, const dzs_lc_ring *ring) {
+    if (!lc || !ring || !ring->records || !ring->count || !ring->overflow)
+        return dzs_fail(ctx, DZS_EINVAL, "lightcone: null parameters or ring");
+    if (lc->n_cheb < 1 || lc->n_cheb > DZS_CHEB_MAX || !(lc->a1 > lc->a0))
+        return dzs_fail(ctx, DZS_EINVAL, "lightcone: need 1 <= n_cheb <= %d and a1 > a0",
+                        DZS_CHEB_MAX);
+    return DZS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// sorting the state
+// ---------------------------------------------------------------------------------------
+static dzs_status sort_state(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p, int ties_by_id,
+                             int with_g, hipStream_t s) {
+    DZS_TRY(dzs_launch_keys(ctx, p->x, p->y, p->z, p->n, box->L, ctx->key, ctx->idx, s));
+    DZS_TRY(dzs_radix_sort(ctx, p->n, s));
+    if (ties_by_id)
+        DZS_TRY(dzs_fix_ties(ctx, p->n, p->id, s));
+    return dzs_permute_state(ctx, p, ctx->idx, with_g, s);
+}
+
+extern "C" dzs_status dzs_morton_keys(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                                      uint64_t *keys, void *stream) {
+    DZS_TRY(check_common(ctx, box, p));
+    if (!keys && p->n)
+        return dzs_fail(ctx, DZS_EINVAL, "null keys");
+    return dzs_launch_keys(ctx, p->x, p->y, p->z, p->n, box->L, keys, nullptr,
+                           (hipStream_t)stream);
+}
+
+extern "C" dzs_status dzs_sort_state(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p,
+                                     int32_t ties_by_id, uint32_t *perm, void *stream) {
+    DZS_TRY(check_common(ctx, box, p));
+    if (p->n > 0 && (!p->px || !p->py || !p->pz || !p->id || !p->type || !p->gx || !p->gy ||
+                     !p->gz))
+        return dzs_fail(ctx, DZS_EINVAL, "null state array");
+    hipStream_t s = (hipStream_t)stream;
+    DZS_TRY(sort_state(ctx, box, p, ties_by_id, 1, s));
+    if (perm && p->n)
+        DZS_HIP(ctx, hipMemcpyAsync(perm, ctx->idx, sizeof(uint32_t) * p->n,
+                                    hipMemcpyDeviceToDevice, s));
+    return DZS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// the five calls
+// ---------------------------------------------------------------------------------------
+extern "C" dzs_status dzs_coarsen(dzs_ctx *ctx, const dzs_box *box, dzs_particles *inout,
+                                  const dzs_coarsen_params *prm, uint32_t *group_of,
+                                  dzs_coarsen_report *report, void *stream) {
+    DZS_TRY(check_common(ctx, box, inout));
+    DZS_TRY(check_coarsen(ctx, prm));
+    if (inout->n > 0 && (!inout->px || !inout->py || !inout->pz || !inout->id || !inout->type))
+        return dzs_fail(ctx, DZS_EINVAL, "null state array");
+    hipStream_t s = (hipStream_t)stream;
+    if (inout->n == 0) {
+        if (report)
+            *report = dzs_coarsen_report{0, 0, 0};
+        return DZS_OK;
+    }
+    DZS_TRY(sort_state(ctx, box, inout, 1, 0, s));
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->dz_perm, ctx->idx, sizeof(uint32_t) * inout->n,
+                                hipMemcpyDeviceToDevice, s));
+    return dzs_coarsen_sorted(ctx, box, inout, prm, group_of, report, s);
+}
+
+extern "C" dzs_status pm_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                               const dzs_pm_params *prm, void *stream) {
+    DZS_TRY(check_common(ctx, box, p));
+    DZS_TRY(check_pm(ctx, prm));
+    if (p->n > 0 && (!p->gx || !p->gy || !p->gz))
+        return dzs_fail(ctx, DZS_EINVAL, "null acceleration array");
+    return dzs_pm_run(ctx, box, p, prm, (hipStream_t)stream);
+}
+
+extern "C" dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                                 const dzs_tree_params *prm, void *stream) {
+    DZS_TRY(check_common(ctx, box, p));
+    dzs_tree_params t;
+    DZS_TRY(check_tree(ctx, box, prm, &t));
+    if (p->n > 0 && (!p->gx || !p->gy || !p->gz))
+        return dzs_fail(ctx, DZS_EINVAL, "null acceleration array");
+    const uint64_t n = p->n;
+    if (n == 0)
+        return DZS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    DZS_TRY(dzs_launch_keys(ctx, p->x, p->y, p->z, n, box->L, ctx->key, ctx->idx, s));
+    DZS_TRY(dzs_radix_sort(ctx, n, s));
+    {
+        dzs_timed tm(ctx, KC_PERMUTE, s);
+        DZS_TRY(dzs_gather_f64(ctx, p->x, ctx->idx, ctx->sx, n, s));
+        DZS_TRY(dzs_gather_f64(ctx, p->y, ctx->idx, ctx->sy, n, s));
+        DZS_TRY(dzs_gather_f64(ctx, p->z, ctx->idx, ctx->sz, n, s));
+        DZS_TRY(dzs_gather_u32(ctx, p->mult, ctx->idx, ctx->smult, n, s));
+    }
+    DZS_TRY(dzs_tree_build(ctx, box, n, ctx->sx, ctx->sy, ctx->sz, ctx->smult, t.leaf_size,
+                           t.group_size, s));
+    dzs_tree_params tw = t;
+    tw.accumulate = 0;
+    DZS_TRY(dzs_tree_walk(ctx, box, n, ctx->sx, ctx->sy, ctx->sz, ctx->smult, ctx->sgx, ctx->sgy,
+                          ctx->sgz, &tw, s));
+    {
+        dzs_timed tm(ctx, KC_PERMUTE, s);
+        DZS_TRY(dzs_scatter_add_f64(ctx, ctx->sgx, ctx->idx, p->gx, n, t.accumulate, s));
+        DZS_TRY(dzs_scatter_add_f64(ctx, ctx->sgy, ctx->idx, p->gy, n, t.accumulate, s));
+        DZS_TRY(dzs_scatter_add_f64(ctx, ctx->sgz, ctx->idx, p->gz, n, t.accumulate, s));
+    }
+    return DZS_OK;
+}
+
+extern "C" dzs_status lightcone_emit(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                                     const dzs_lc_params *prm, dzs_lc_ring *ring, void *stream) {
+    DZS_TRY(check_common(ctx, box, p));
+    DZS_TRY(check_lc(ctx, prm, ring));
+    if (p->n > 0 && (!p->px || !p->py || !p->pz || !p->id))
+        return dzs_fail(ctx, DZS_EINVAL, "null state array");
+    return dzs_launch_drift_lc(ctx, box, p, prm, ring, 1, 0, (hipStream_t)stream);
+}
+
+extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st,
+                               const dzs_step_params *prm, dzs_lc_ring *ring,
+                               dzs_coarsen_report *report, void *stream) {
+    DZS_TRY(check_common(ctx, box, st));
+    if (!prm)
+        return dzs_fail(ctx, DZS_EINVAL, "null step parameters");
+    if (st->n > 0 && (!st->px || !st->py || !st->pz || !st->gx || !st->gy || !st->gz || !st->id ||
+                      !st->type))
+        return dzs_fail(ctx, DZS_EINVAL, "null state array");
+    dzs_tree_params t;
+    DZS_TRY(check_tree(ctx, box, &prm->tree, &t));
+    DZS_TRY(check_pm(ctx, &prm->pm));
+    if (prm->do_lightcone)
+        DZS_TRY(check_lc(ctx, &prm->lc, ring));
+    else if (!(prm->lc.D == prm->lc.D))
+        return dzs_fail(ctx, DZS_EINVAL, "step: drift factor is NaN");
+    if (prm->do_coarsen)
+        DZS_TRY(check_coarsen(ctx, &prm->coarsen));
+    hipStream_t s = (hipStream_t)stream;
+    if (report)
+        *report = dzs_coarsen_report{st->n, st->n, 0};
+
+    DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s));
+    DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &prm->lc, ring, prm->do_lightcone, 1, s));
+    const bool can_merge = prm->do_coarsen &&
+                           prm->coarsen.R_lc + prm->coarsen.b < 0.5 * sqrt(3.0) * box->L;
+    if (can_merge && st->n > 0) {
+        DZS_TRY(sort_state(ctx, box, st, 1, 0, s));
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->dz_perm, ctx->idx, sizeof(uint32_t) * st->n,
+                                    hipMemcpyDeviceToDevice, s));
+        DZS_TRY(dzs_coarsen_sorted(ctx, box, st, &prm->coarsen, nullptr, report, s));
+    }
+    if (st->n > 0) {
+        DZS_TRY(sort_state(ctx, box, st, 0, 0, s));
+        DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
+                               t.group_size, s));
+        dzs_pm_params pm = prm->pm;
+        pm.accumulate = 0;
+        DZS_TRY(dzs_pm_run(ctx, box, st, &pm, s));
+        t.accumulate = 1;
+        DZS_TRY(dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx, st->gy,
+                              st->gz, &t, s));
+        DZS_TRY(dzs_launch_kick(ctx, st, prm->K2, s));
+    }
+    return DZS_OK;
+}

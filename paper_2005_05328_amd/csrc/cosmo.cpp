@@ -1,0 +1,144 @@
+// Host-side cosmology for the step: kick and drift factors, comoving distance and the
+// Chebyshev series the lightcone crossing solve evaluates on the GPU.  Flat LCDM without
+// radiation, H(a) = H0 sqrt(Om a^-3 + 1 - Om), H0 = 100 km/s/(Mpc/h).
+//
+//   K(a0,a1) = int da / (a^2 H)   (p = a^2 dx/dt, dp/dt = g/a)
+//   D(a0,a1) = int da / (a^3 H)   (dx/dt = p/a^2)
+//   chi(a)   = c int_a^1 da / (a^2 H)
+//
+// Integrals: composite 16-point Gauss-Legendre on panels [a, a(1+1/4)] (capped at width
+// 0.05), whose Bernstein-ellipse margin to the a = 0 singularity makes each panel exact to
+// well below double rounding.
+#include <math.h>
+#include <string.h>
+
+#include "../../include/dzs.h"
+
+namespace {
+
+const double kH0 = 100.0;
+const double kC = 299792.458;
+
+struct GaussLegendre16 {
+    double x[16], w[16];
+    GaussLegendre16() {
+        const int n = 16;
+        for (int i = 0; i < n; ++i) {
+            long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+            for (int it = 0; it < 100; ++it) {
+                long double p0 = 1.0L, p1 = z;
+                for (int k = 2; k <= n; ++k) {
+                    long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                long double dp = n * (z * p1 - p0) / (z * z - 1.0L);
+                long double dz = p1 / dp;
+                z -= dz;
+                if (fabsl(dz) < 1e-19L)
+                    break;
+            }
+            long double p0 = 1.0L, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            long double dp = n * (z * p1 - p0) / (z * z - 1.0L);
+            x[i] = (double)z;
+            w[i] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
+        }
+    }
+};
+
+const GaussLegendre16 &gl16() {
+    static GaussLegendre16 g;
+    return g;
+}
+
+inline long double E(long double a, double om) {
+    return sqrtl((long double)om / (a * a * a) + (1.0L - om));
+}
+
+// int_{lo}^{hi} a^-pow / E(a) da
+long double integrate(double lo, double hi, int pw, double om) {
+    if (hi <= lo)
+        return 0.0L;
+    const GaussLegendre16 &g = gl16();
+    long double sum = 0.0L;
+    double a = lo;
+    while (a < hi) {
+        double w = 0.25 * a;
+        if (w > 0.05)
+            w = 0.05;
+        double b = a + w;
+        if (b > hi || hi - b < 1e-3 * w)
+            b = hi;
+        long double c = 0.5L * ((long double)a + b), h = 0.5L * ((long double)b - a);
+        long double s = 0.0L;
+        for (int i = 0; i < 16; ++i) {
+            long double t = c + h * g.x[i];
+            long double ap = powl(t, (long double)pw);
+            s += g.w[i] / (ap * E(t, om));
+        }
+        sum += s * h;
+        a = b;
+    }
+    return sum;
+}
+
+double kick(double a0, double a1, double om) { return (double)(integrate(a0, a1, 2, om) / kH0); }
+double drift(double a0, double a1, double om) { return (double)(integrate(a0, a1, 3, om) / kH0); }
+double chi(double a, double om) { return (double)(kC * integrate(a, 1.0, 2, om) / kH0); }
+
+// Chebyshev coefficients of f on [a0, a1] from n samples at the Chebyshev nodes.
+template <typename F>
+void cheb_fit(F f, double a0, double a1, int n, double *c) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    long double fv[DZS_CHEB_MAX];
+    for (int j = 0; j < n; ++j) {
+        long double th = pi * (j + 0.5L) / n;
+        long double t = cosl(th);
+        double a = (double)(0.5L * (a0 + a1) + 0.5L * (a1 - a0) * t);
+        fv[j] = f(a);
+    }
+    for (int k = 0; k < n; ++k) {
+        long double s = 0.0L;
+        for (int j = 0; j < n; ++j)
+            s += fv[j] * cosl(pi * k * (j + 0.5L) / n);
+        c[k] = (double)(s * (k == 0 ? 1.0L : 2.0L) / n);
+    }
+}
+
+}  // namespace
+
+void dzs_merge_thresholds(double L, double R_lc, double b, double theta, double *T2) {
+    for (int k = 0; k <= 21; ++k) {
+        double lk = ldexp(L, -k);
+        double T = (R_lc + b) + lk / theta;
+        T2[k] = T * T;
+    }
+}
+
+extern "C" dzs_status dzs_step_factors(double a0, double a1, double omega_m,
+                                       dzs_step_params *out) {
+    if (!out || !(a0 > 0.0) || !(a1 > a0) || !(a1 <= 1.0) || !(omega_m > 0.0) ||
+        !(omega_m <= 1.0))
+        return DZS_EINVAL;
+    const double ah = sqrt(a0 * a1);
+    out->K1 = kick(a0, ah, omega_m);
+    out->K2 = kick(ah, a1, omega_m);
+    out->lc.a0 = a0;
+    out->lc.a1 = a1;
+    out->lc.D = drift(a0, a1, omega_m);
+    const double c0 = chi(a0, omega_m), c1 = a1 < 1.0 ? chi(a1, omega_m) : 0.0;
+    out->lc.chi2_0 = c0 * c0;
+    out->lc.chi2_1 = c1 * c1;
+    const int n = 20;
+    out->lc.n_cheb = n;
+    memset(out->lc.cheb_chi, 0, sizeof(out->lc.cheb_chi));
+    memset(out->lc.cheb_drift, 0, sizeof(out->lc.cheb_drift));
+    cheb_fit([&](double a) { return a < 1.0 ? chi(a, omega_m) : 0.0; }, a0, a1, n, out->lc.cheb_chi);
+    cheb_fit([&](double a) { return drift(a0, a, omega_m); }, a0, a1, n, out->lc.cheb_drift);
+    return DZS_OK;
+}

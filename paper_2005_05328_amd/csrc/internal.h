@@ -1,0 +1,254 @@
+// Internal declarations of libdzs: the context, error handling, launch timing and the
+// launchers each translation unit provides.  Device code for gfx950 (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/dzs.h"
+
+#define DZS_KEY_BITS 21
+#define DZS_KEY_SIDE 2097152.0
+
+// ---------------------------------------------------------------------------------------
+// kernel classes timed by dzs_timing
+// ---------------------------------------------------------------------------------------
+enum dzs_kclass {
+    KC_KICK = 0,
+    KC_DRIFT_LC,
+    KC_KEYS,
+    KC_SORT,
+    KC_PERMUTE,
+    KC_TREE_BUILD,
+    KC_TREE_MOMENTS,
+    KC_TREE_GROUPS,
+    KC_TREE_WALK,
+    KC_PM_DEPOSIT,
+    KC_PM_FFT_X,
+    KC_PM_FFT_Y,
+    KC_PM_FFT_Z_GREEN,
+    KC_PM_INTERP,
+    KC_DZS_LEVELS,
+    KC_DZS_COMPACT,
+    KC_MISC,
+    KC_COUNT
+};
+
+extern const char *const dzs_kclass_names[KC_COUNT];
+
+struct dzs_timer_pool {
+    static const int CAP = 8192;
+    hipEvent_t start[CAP], stop[CAP];
+    int cls[CAP];
+    int used = 0;
+    bool created = false;
+};
+
+struct dzs_ctx {
+    int device = 0;
+    uint64_t cap_n = 0;
+    uint32_t cap_ng = 0;
+    char err[512] = {0};
+
+    // ---- sort / permutation scratch
+    uint64_t *key = nullptr, *key_alt = nullptr;
+    uint32_t *idx = nullptr, *idx_alt = nullptr;
+    uint32_t *hist = nullptr, *hist_scan = nullptr;  // radix histograms (256 * tiles)
+    uint64_t hist_cap = 0;
+    uint32_t *scan_tmp = nullptr;  // partial sums for the multi-level scan
+    uint64_t scan_tmp_cap = 0;
+    void *gather_tmp = nullptr;  // one array of max_particles doubles for in-place permutes
+
+    // ---- sorted copies used by tree_force on an unsorted input
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    uint32_t *smult = nullptr;
+    double *sgx = nullptr, *sgy = nullptr, *sgz = nullptr;
+
+    // ---- octree (structure of arrays)
+    uint64_t cap_nodes = 0;
+    uint32_t *nd_first = nullptr, *nd_count = nullptr, *nd_child = nullptr;
+    uint8_t *nd_nchild = nullptr, *nd_level = nullptr;
+    double *nd_mass = nullptr, *nd_com = nullptr /*3*cap*/, *nd_bmin = nullptr /*3*cap*/,
+           *nd_bmax = nullptr /*3*cap*/, *nd_hmax = nullptr;
+    uint32_t *frontier = nullptr, *frontier_next = nullptr;
+    uint32_t *fr_nchild = nullptr, *fr_ninternal = nullptr, *fr_child_off = nullptr,
+             *fr_int_off = nullptr;
+    uint32_t *child_bounds = nullptr;  // 9 per frontier node
+    uint32_t *grp_flag = nullptr, *grp_scan = nullptr, *grp_first = nullptr;
+    uint32_t *walk_stack = nullptr;
+    uint64_t walk_stack_slots = 0, walk_stack_depth = 0;
+    uint32_t *walk_counter = nullptr;  // [0] work counter, [1] overflow flag
+    uint32_t level_start[DZS_KEY_BITS + 3] = {0};
+    int n_levels = 0;
+    uint32_t n_nodes = 0, n_groups = 0;
+
+    // ---- PM mesh
+    long long *mesh_q = nullptr;  // fixed-point density accumulator, ng^3
+    double2 *mesh_c = nullptr;    // complex work mesh, ng^3
+    double *mesh_phi = nullptr;   // real potential, ng^3
+    double *pm_tables = nullptr;  // per-axis tables (twiddles, Green factors)
+    int pm_tab_ng = 0;
+    double pm_tab_L = 0.0, pm_tab_rs = 0.0;
+
+    // ---- DZS
+    uint32_t *dz_head = nullptr;     // group head (sorted index) or 0xffffffff
+    uint32_t *dz_flag = nullptr, *dz_scan = nullptr;
+    double *dz_new = nullptr;        // 6 * cap: merged x,y,z,px,py,pz at the head slot
+    uint32_t *dz_newmult = nullptr, *dz_newid = nullptr;
+    uint32_t *dz_perm = nullptr;     // entry index of each sorted slot
+
+    // ---- small device / host scalars
+    uint32_t *d_small = nullptr;  // 64 words of device scratch
+    uint32_t *h_small = nullptr;  // 64 words of pinned host memory
+
+    // ---- timing
+    bool timing = false;
+    dzs_timer_pool *timers = nullptr;
+    double t_ms[KC_COUNT] = {0};
+    uint64_t t_calls[KC_COUNT] = {0};
+};
+
+// ---------------------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------------------
+dzs_status dzs_fail(dzs_ctx *ctx, dzs_status code, const char *fmt, ...);
+
+#define DZS_HIP(ctx, call)                                                                 \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return dzs_fail((ctx), DZS_EHIP, "%s failed: %s (%s:%d)", #call,               \
+                            hipGetErrorString(e_), __FILE__, __LINE__);                    \
+    } while (0)
+
+#define DZS_TRY(expr)                                                                      \
+    do {                                                                                   \
+        dzs_status s_ = (expr);                                                            \
+        if (s_ != DZS_OK)                                                                  \
+            return s_;                                                                     \
+    } while (0)
+
+// launch timing: record an event pair around the launches between begin and end
+void dzs_time_begin(dzs_ctx *ctx, int cls, hipStream_t s, int *slot);
+void dzs_time_end(dzs_ctx *ctx, hipStream_t s, int slot);
+dzs_status dzs_check_launch(dzs_ctx *ctx, const char *what);
+
+struct dzs_timed {
+    dzs_ctx *ctx;
+    hipStream_t s;
+    int slot;
+    dzs_timed(dzs_ctx *c, int cls, hipStream_t st) : ctx(c), s(st), slot(-1) {
+        dzs_time_begin(c, cls, st, &slot);
+    }
+    ~dzs_timed() { dzs_time_end(ctx, s, slot); }
+};
+
+// ---------------------------------------------------------------------------------------
+// device helpers shared by the kernels of this library
+// ---------------------------------------------------------------------------------------
+
+// minimum image of one separation component: into [-L/2, L/2)
+__device__ __forceinline__ double dzs_min_image(double d, double L) {
+    if (d >= 0.5 * L)
+        d -= L;
+    else if (d < -0.5 * L)
+        d += L;
+    return d;
+}
+
+// x - L floor(x/L); a result equal to L becomes 0
+__device__ __forceinline__ double dzs_wrap(double x, double L) {
+    double q = floor(x / L);
+    double w = x - L * q;
+    if (w >= L)
+        w = 0.0;
+    return w;
+}
+
+// spread the low 21 bits of v to every third bit
+__device__ __forceinline__ uint64_t dzs_spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ __forceinline__ uint64_t dzs_cell(double v, double s) {
+    double t = floor(v * s);
+    t = t < 0.0 ? 0.0 : t;
+    t = t > DZS_KEY_SIDE - 1.0 ? DZS_KEY_SIDE - 1.0 : t;
+    return (uint64_t)t;
+}
+
+__device__ __forceinline__ uint64_t dzs_morton(double x, double y, double z, double s) {
+    return (dzs_spread3(dzs_cell(x, s)) << 2) | (dzs_spread3(dzs_cell(y, s)) << 1) |
+           dzs_spread3(dzs_cell(z, s));
+}
+
+// wave64 helpers
+__device__ __forceinline__ uint32_t dzs_lane() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t dzs_wave_incl_scan(uint32_t v) {
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d)
+            v += t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------------------
+
+// scan.hip / sort.hip
+uint64_t dzs_scan_tmp_words(uint64_t n);
+dzs_status dzs_scan_u32(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n,
+                        uint32_t *total_dev, hipStream_t s);
+uint64_t dzs_sort_hist_words(uint64_t n);
+dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s);  // ctx->key/idx in+out
+dzs_status dzs_fix_ties(dzs_ctx *ctx, uint64_t n, const uint32_t *id, hipStream_t s);
+
+// particles.hip
+dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipStream_t s);
+dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                               const dzs_lc_params *lc, dzs_lc_ring *ring, int do_lc,
+                               int do_drift, hipStream_t s);
+dzs_status dzs_launch_keys(dzs_ctx *ctx, const double *x, const double *y, const double *z,
+                           uint64_t n, double L, uint64_t *key, uint32_t *idx, hipStream_t s);
+dzs_status dzs_permute_state(dzs_ctx *ctx, dzs_particles *p, const uint32_t *perm,
+                             int with_g, hipStream_t s);
+dzs_status dzs_gather_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm, double *dst,
+                          uint64_t n, hipStream_t s);
+dzs_status dzs_gather_u32(dzs_ctx *ctx, const uint32_t *src, const uint32_t *perm,
+                          uint32_t *dst, uint64_t n, hipStream_t s);
+dzs_status dzs_scatter_add_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm,
+                               double *dst, uint64_t n, int accumulate, hipStream_t s);
+
+// tree.hip
+dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                          const double *y, const double *z, const uint32_t *mult,
+                          int leaf_size, int group_size, hipStream_t s);
+dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                         const double *y, const double *z, const uint32_t *mult, double *gx,
+                         double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s);
+
+// pm.hip
+bool dzs_pm_mesh_ok(int ng);
+dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                      const dzs_pm_params *prm, hipStream_t s);
+
+// coarsen.hip
+dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p,
+                              const dzs_coarsen_params *prm, uint32_t *group_of,
+                              dzs_coarsen_report *report, hipStream_t s);
+
+// cosmo.cpp (host)
+void dzs_merge_thresholds(double L, double R_lc, double b, double theta, double *T2);

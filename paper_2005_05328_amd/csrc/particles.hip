@@ -1,0 +1,281 @@
+// Per-particle streaming kernels: kick, drift with the lightcone crossing test, Morton keys,
+// and the gathers that apply a sort permutation to the structure-of-arrays state.
+// All are HBM-bound: one thread per particle, coalesced loads and stores of each array.
+#include "internal.h"
+
+#define PT_THREADS 256
+
+static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------------------
+// kick: p <- p + g K (one rounded product, one rounded sum: no contraction)
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(PT_THREADS) void k_kick(uint64_t n, double *__restrict__ px,
+                                                     double *__restrict__ py,
+                                                     double *__restrict__ pz,
+                                                     const double *__restrict__ gx,
+                                                     const double *__restrict__ gy,
+                                                     const double *__restrict__ gz, double K) {
+    uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n)
+        return;
+    px[i] = px[i] + gx[i] * K;
+    py[i] = py[i] + gy[i] * K;
+    pz[i] = pz[i] + gz[i] * K;
+}
+
+dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipStream_t s) {
+    if (p->n == 0)
+        return DZS_OK;
+    dzs_timed t(ctx, KC_KICK, s);
+    hipLaunchKernelGGL(k_kick, dim3(blocks_for(p->n, PT_THREADS)), dim3(PT_THREADS), 0, s, p->n,
+                       p->px, p->py, p->pz, (const double *)p->gx, (const double *)p->gy,
+                       (const double *)p->gz, K);
+    return dzs_check_launch(ctx, "kick");
+}
+
+// ---------------------------------------------------------------------------------------
+// drift + lightcone
+// ---------------------------------------------------------------------------------------
+struct lc_args {
+    double xo[3];
+    double chi2_0, chi2_1, D, a0, a1;
+    int n_cheb;
+    double cchi[DZS_CHEB_MAX];
+    double cdrift[DZS_CHEB_MAX];
+};
+
+__device__ __forceinline__ double cheb_eval(const double *c, int n, double t) {
+    // Clenshaw recurrence for sum_k c_k T_k(t)
+    double b1 = 0.0, b2 = 0.0;
+    const double t2 = 2.0 * t;
+    for (int k = n - 1; k >= 1; --k) {
+        double b0 = fma(t2, b1, c[k] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(t, b1, c[0] - b2);
+}
+
+// Crossing of the shrinking lightcone sphere: the root of
+// F(t) = |d0 + p D(a0, a(t))|^2 - chi(a(t))^2 on t in [-1, 1], F(-1) < 0 <= F(1), by bisection
+// to the last bit of t.  Returns t; *dc receives d0 + p D(a0, a(t)).
+__device__ double lc_solve(const lc_args &A, double d0x, double d0y, double d0z, double px,
+                           double py, double pz, double *dcx, double *dcy, double *dcz) {
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 62; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi)
+            break;
+        double Dm = cheb_eval(A.cdrift, A.n_cheb, mid);
+        double cm = cheb_eval(A.cchi, A.n_cheb, mid);
+        double x = d0x + px * Dm, y = d0y + py * Dm, z = d0z + pz * Dm;
+        double F = (x * x + y * y + z * z) - cm * cm;
+        if (F < 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    double t = 0.5 * (lo + hi);
+    double Dt = cheb_eval(A.cdrift, A.n_cheb, t);
+    *dcx = d0x + px * Dt;
+    *dcy = d0y + py * Dt;
+    *dcz = d0z + pz * Dt;
+    return t;
+}
+
+__global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
+    uint64_t n, double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+    const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
+    const uint32_t *__restrict__ id, const uint32_t *__restrict__ mult, double L, lc_args A,
+    int do_lc, int do_drift, dzs_lc_record *__restrict__ rec, uint64_t rec_cap,
+    unsigned long long *__restrict__ rec_count, uint32_t *__restrict__ overflow) {
+    uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n)
+        return;
+    const double xi = x[i], yi = y[i], zi = z[i];
+    const double pxi = px[i], pyi = py[i], pzi = pz[i];
+    const double sx = pxi * A.D, sy = pyi * A.D, sz = pzi * A.D;
+    if (do_lc) {
+        const double dx = dzs_min_image(xi - A.xo[0], L);
+        const double dy = dzs_min_image(yi - A.xo[1], L);
+        const double dz = dzs_min_image(zi - A.xo[2], L);
+        const double f0 = (dx * dx + dy * dy + dz * dz) - A.chi2_0;
+        const double ex = dx + sx, ey = dy + sy, ez = dz + sz;
+        const double f1 = (ex * ex + ey * ey + ez * ez) - A.chi2_1;
+        if (f0 < 0.0 && f1 >= 0.0) {
+            double cx, cy, cz;
+            double t = lc_solve(A, dx, dy, dz, pxi, pyi, pzi, &cx, &cy, &cz);
+            unsigned long long slot = atomicAdd(rec_count, 1ull);
+            if (slot < rec_cap) {
+                dzs_lc_record r;
+                r.id = id[i];
+                r.mult = mult[i];
+                r.a_cross = A.a0 + 0.5 * (t + 1.0) * (A.a1 - A.a0);
+                r.d[0] = cx;
+                r.d[1] = cy;
+                r.d[2] = cz;
+                r.p[0] = pxi;
+                r.p[1] = pyi;
+                r.p[2] = pzi;
+                rec[slot] = r;
+            } else {
+                *overflow = 1u;
+            }
+        }
+    }
+    if (do_drift) {
+        x[i] = dzs_wrap(xi + sx, L);
+        y[i] = dzs_wrap(yi + sy, L);
+        z[i] = dzs_wrap(zi + sz, L);
+    }
+}
+
+dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                               const dzs_lc_params *lc, dzs_lc_ring *ring, int do_lc,
+                               int do_drift, hipStream_t s) {
+    if (p->n == 0)
+        return DZS_OK;
+    lc_args A;
+    memset(&A, 0, sizeof(A));
+    for (int d = 0; d < 3; ++d)
+        A.xo[d] = lc->x_obs[d];
+    A.chi2_0 = lc->chi2_0;
+    A.chi2_1 = lc->chi2_1;
+    A.D = lc->D;
+    A.a0 = lc->a0;
+    A.a1 = lc->a1;
+    A.n_cheb = lc->n_cheb;
+    for (int k = 0; k < DZS_CHEB_MAX; ++k) {
+        A.cchi[k] = lc->cheb_chi[k];
+        A.cdrift[k] = lc->cheb_drift[k];
+    }
+    dzs_lc_record *rec = nullptr;
+    uint64_t cap = 0;
+    unsigned long long *cnt = nullptr;
+    uint32_t *ovf = nullptr;
+    if (do_lc) {
+        rec = ring->records;
+        cap = ring->capacity;
+        cnt = ring->count;
+        ovf = ring->overflow;
+    }
+    dzs_timed t(ctx, KC_DRIFT_LC, s);
+    hipLaunchKernelGGL(k_drift_lc, dim3(blocks_for(p->n, PT_THREADS)), dim3(PT_THREADS), 0, s,
+                       p->n, p->x, p->y, p->z, (const double *)p->px, (const double *)p->py,
+                       (const double *)p->pz, (const uint32_t *)p->id,
+                       (const uint32_t *)p->mult, box->L, A, do_lc, do_drift, rec, cap, cnt,
+                       ovf);
+    return dzs_check_launch(ctx, "drift_lc");
+}
+
+// ---------------------------------------------------------------------------------------
+// Morton keys + identity index
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(PT_THREADS) void k_keys(uint64_t n, const double *__restrict__ x,
+                                                     const double *__restrict__ y,
+                                                     const double *__restrict__ z, double s,
+                                                     uint64_t *__restrict__ key,
+                                                     uint32_t *__restrict__ idx) {
+    uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n)
+        return;
+    key[i] = dzs_morton(x[i], y[i], z[i], s);
+    if (idx)
+        idx[i] = (uint32_t)i;
+}
+
+dzs_status dzs_launch_keys(dzs_ctx *ctx, const double *x, const double *y, const double *z,
+                           uint64_t n, double L, uint64_t *key, uint32_t *idx, hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    const double scale = DZS_KEY_SIDE / L;
+    dzs_timed t(ctx, KC_KEYS, s);
+    hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n, x, y,
+                       z, scale, key, idx);
+    return dzs_check_launch(ctx, "keys");
+}
+
+// ---------------------------------------------------------------------------------------
+// gathers / scatters through a permutation
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(PT_THREADS) void k_gather(uint64_t n, const T *__restrict__ src,
+                                                       const uint32_t *__restrict__ perm,
+                                                       T *__restrict__ dst) {
+    uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i < n)
+        dst[i] = src[perm[i]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT_THREADS) void k_copy(uint64_t n, const T *__restrict__ src,
+                                                     T *__restrict__ dst) {
+    uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(PT_THREADS) void k_scatter(uint64_t n, const double *__restrict__ src,
+                                                        const uint32_t *__restrict__ perm,
+                                                        double *__restrict__ dst, int accumulate) {
+    uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n)
+        return;
+    uint32_t j = perm[i];
+    dst[j] = accumulate ? dst[j] + src[i] : src[i];
+}
+
+template <typename T>
+static dzs_status permute_one(dzs_ctx *ctx, T *arr, const uint32_t *perm, uint64_t n,
+                              hipStream_t s) {
+    T *tmp = (T *)ctx->gather_tmp;
+    uint32_t b = blocks_for(n, PT_THREADS);
+    hipLaunchKernelGGL(k_gather<T>, dim3(b), dim3(PT_THREADS), 0, s, n, (const T *)arr, perm, tmp);
+    DZS_TRY(dzs_check_launch(ctx, "gather"));
+    hipLaunchKernelGGL(k_copy<T>, dim3(b), dim3(PT_THREADS), 0, s, n, (const T *)tmp, arr);
+    return dzs_check_launch(ctx, "copy");
+}
+
+dzs_status dzs_permute_state(dzs_ctx *ctx, dzs_particles *p, const uint32_t *perm, int with_g,
+                             hipStream_t s) {
+    const uint64_t n = p->n;
+    if (n == 0)
+        return DZS_OK;
+    dzs_timed t(ctx, KC_PERMUTE, s);
+    double *f64[9] = {p->x, p->y, p->z, p->px, p->py, p->pz, p->gx, p->gy, p->gz};
+    const int nf = with_g ? 9 : 6;
+    for (int k = 0; k < nf; ++k)
+        DZS_TRY(permute_one<double>(ctx, f64[k], perm, n, s));
+    DZS_TRY(permute_one<uint32_t>(ctx, p->mult, perm, n, s));
+    DZS_TRY(permute_one<uint32_t>(ctx, p->id, perm, n, s));
+    DZS_TRY(permute_one<uint8_t>(ctx, p->type, perm, n, s));
+    return DZS_OK;
+}
+
+dzs_status dzs_gather_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm, double *dst,
+                          uint64_t n, hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_gather<double>, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s,
+                       n, src, perm, dst);
+    return dzs_check_launch(ctx, "gather_f64");
+}
+
+dzs_status dzs_gather_u32(dzs_ctx *ctx, const uint32_t *src, const uint32_t *perm,
+                          uint32_t *dst, uint64_t n, hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_gather<uint32_t>, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0,
+                       s, n, src, perm, dst);
+    return dzs_check_launch(ctx, "gather_u32");
+}
+
+dzs_status dzs_scatter_add_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm,
+                               double *dst, uint64_t n, int accumulate, hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n, src,
+                       perm, dst, accumulate);
+    return dzs_check_launch(ctx, "scatter_f64");
+}

@@ -1,0 +1,464 @@
+// Particle-mesh long-range force (paper Sec. 2.1: density on a uniform grid, Poisson
+// equation in Fourier space, Gaussian split kernel).
+//
+//   deposit     cloud-in-cell, deterministic: each contribution mult * w_x w_y w_z is rounded
+//               to 32.32 fixed point and added with 64-bit integer atomics, so the mesh does
+//               not depend on the order the GPU adds in
+//   FFT         3-D complex transform as three passes of 1-D line transforms, each line held
+//               in LDS (mixed radix 4/2/3 Stockham, autosorting, twiddles from a host table);
+//               the x pass reads the fixed-point mesh directly, the z pass multiplies by the
+//               Green's function and transforms back in the same kernel, the last inverse x
+//               pass writes the real potential
+//   Green       -4 pi G exp(-k^2 r_s^2) / (k^2 W(k)^2) / N_g^3, separable per-axis tables
+//   gradient +  the 4-point difference of the potential at the 8 cloud-in-cell corners of each
+//   interp      particle, weighted with the same cloud-in-cell weights (one kernel)
+//
+// Mesh layout: index (ix * N_g + iy) * N_g + iz.  Mesh points at j * Delta, Delta = L / N_g.
+#include <math.h>
+#include <vector>
+
+#include "internal.h"
+
+#define PM_THREADS 256
+#define FFT_THREADS 256
+#define FFT_ELEMS 2048       // complex elements per workgroup tile (32 KB in FP64)
+#define FFT_MAX_STAGES 12
+#define FFT_MAX_SLOTS 4
+#define DEP_FRAC 4294967296.0  // 2^32: fixed-point scale of the deposit
+
+static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+struct fft_plan {
+    int n;                       // line length
+    int n_stages;
+    int radix[FFT_MAX_STAGES];
+};
+
+// ---------------------------------------------------------------------------------------
+// LDS line FFT
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_small(double2 *v) {
+    if (R == 2) {
+        double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if (R == 4) {
+        double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        double2 c = cadd(v[1], v[3]), t = csub(v[1], v[3]);
+        // forward: t * (-i) = (t.y, -t.x); inverse: t * (+i) = (-t.y, t.x)
+        double2 d = INV ? make_double2(-t.y, t.x) : make_double2(t.y, -t.x);
+        v[0] = cadd(a, c);
+        v[1] = cadd(b, d);
+        v[2] = csub(a, c);
+        v[3] = csub(b, d);
+    } else {  // R == 3
+        const double s3 = 0.86602540378443865;  // sqrt(3)/2
+        double2 t = cadd(v[1], v[2]), s = csub(v[1], v[2]);
+        double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+        // forward: X1 = m - i s3 s, X2 = m + i s3 s ; inverse swaps the sign of i
+        double2 is = INV ? make_double2(-s3 * s.y, s3 * s.x) : make_double2(s3 * s.y, -s3 * s.x);
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, is);
+        v[2] = csub(m, is);
+    }
+}
+
+// One Stockham stage over TL lines held in LDS.  Element e of line l lives at
+// buf[e * se + l * sl].  All loads of the stage complete before any store (barrier), so the
+// stage runs in place.
+template <int R, bool INV>
+__device__ void fft_stage(double2 *buf, const double2 *tw, int n, int TL, int se, int sl,
+                          int Ns) {
+    const int nb = n / R;
+    const int total = TL * nb;
+    const int step = n / (Ns * R);
+    double2 v[FFT_MAX_SLOTS][R];
+#pragma unroll
+    for (int q = 0; q < FFT_MAX_SLOTS; ++q) {
+        const int b = threadIdx.x + q * FFT_THREADS;
+        if (b < total) {
+            int l, j;
+            if (sl == 1) {
+                l = b % TL;
+                j = b / TL;
+            } else {
+                j = b % nb;
+                l = b / nb;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[q][r] = buf[(j + r * nb) * se + l * sl];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < FFT_MAX_SLOTS; ++q) {
+        const int b = threadIdx.x + q * FFT_THREADS;
+        if (b < total) {
+            int l, j;
+            if (sl == 1) {
+                l = b % TL;
+                j = b / TL;
+            } else {
+                j = b % nb;
+                l = b / nb;
+            }
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                double2 w = tw[r * k * step];
+                if (INV)
+                    w.y = -w.y;
+                v[q][r] = cmul(v[q][r], w);
+            }
+            dft_small<R, INV>(v[q]);
+            const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                buf[(idxD + r * Ns) * se + l * sl] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool INV>
+__device__ void fft_lines(double2 *buf, const double2 *tw, const fft_plan &P, int TL, int se,
+                          int sl) {
+    int Ns = 1;
+    for (int s = 0; s < P.n_stages; ++s) {
+        const int R = P.radix[s];
+        if (R == 4)
+            fft_stage<4, INV>(buf, tw, P.n, TL, se, sl, Ns);
+        else if (R == 2)
+            fft_stage<2, INV>(buf, tw, P.n, TL, se, sl, Ns);
+        else
+            fft_stage<3, INV>(buf, tw, P.n, TL, se, sl, Ns);
+        Ns *= R;
+    }
+}
+
+__device__ __forceinline__ void load_twiddles(double2 *s_tw, const double2 *tw, int n) {
+    for (int i = threadIdx.x; i < n; i += FFT_THREADS)
+        s_tw[i] = tw[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// deposit
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void cic_axis(double x, double delta, int ng, int &i0, int &i1,
+                                         double &w0, double &w1) {
+    const double u = x / delta;
+    const double f = floor(u);
+    int i = (int)f;
+    w1 = u - f;
+    w0 = 1.0 - w1;
+    i %= ng;
+    if (i < 0)
+        i += ng;
+    i0 = i;
+    i1 = i + 1 == ng ? 0 : i + 1;
+}
+
+__global__ __launch_bounds__(PM_THREADS) void k_pm_deposit(uint64_t n, const double *__restrict__ x,
+                                                           const double *__restrict__ y,
+                                                           const double *__restrict__ z,
+                                                           const uint32_t *__restrict__ mult,
+                                                           double delta, int ng,
+                                                           unsigned long long *__restrict__ q) {
+    uint64_t p = (uint64_t)blockIdx.x * PM_THREADS + threadIdx.x;
+    if (p >= n)
+        return;
+    int ix[2], iy[2], iz[2];
+    double wx[2], wy[2], wz[2];
+    cic_axis(x[p], delta, ng, ix[0], ix[1], wx[0], wx[1]);
+    cic_axis(y[p], delta, ng, iy[0], iy[1], wy[0], wy[1]);
+    cic_axis(z[p], delta, ng, iz[0], iz[1], wz[0], wz[1]);
+    const double m = (double)mult[p] * DEP_FRAC;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double v = m * wx[a] * wy[b] * wz[c];
+                const unsigned long long iv = (unsigned long long)llrint(v);
+                if (iv)
+                    atomicAdd(&q[((uint64_t)ix[a] * ng + iy[b]) * ng + iz[c]], iv);
+            }
+}
+
+// ---------------------------------------------------------------------------------------
+// strided passes (x or y): a tile is TZ consecutive iz values x all n positions along the
+// axis, for a fixed other index.  stride_axis = N_g^2 (x) or N_g (y).
+// ---------------------------------------------------------------------------------------
+template <int MODE>  // 0: x forward from fixed point, 1: y forward, 2: y inverse, 3: x inverse to phi
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
+    const unsigned long long *__restrict__ q, double2 *__restrict__ c, double *__restrict__ phi,
+    const double2 *__restrict__ tw, fft_plan P, int TZ, double q_scale) {
+    __shared__ double2 s_buf[FFT_ELEMS];
+    __shared__ double2 s_tw[1024];
+    const int n = P.n;
+    const int tiles_z = n / TZ;
+    const int other = blockIdx.x / tiles_z;  // iy for the x pass, ix for the y pass
+    const int iz0 = (blockIdx.x % tiles_z) * TZ;
+    const bool xpass = (MODE == 0 || MODE == 3);
+    const uint64_t stride_axis = xpass ? (uint64_t)n * n : (uint64_t)n;
+    const uint64_t base = xpass ? (uint64_t)other * n + iz0 : (uint64_t)other * n * n + iz0;
+    load_twiddles(s_tw, tw, n);
+    const int total = n * TZ;
+    for (int e = threadIdx.x; e < total; e += FFT_THREADS) {
+        const int t = e % TZ, a = e / TZ;
+        const uint64_t gi = base + (uint64_t)a * stride_axis + t;
+        double2 v;
+        if (MODE == 0)
+            v = make_double2((double)(long long)q[gi] * q_scale, 0.0);
+        else
+            v = c[gi];
+        s_buf[a * TZ + t] = v;
+    }
+    __syncthreads();
+    if (MODE == 0 || MODE == 1)
+        fft_lines<false>(s_buf, s_tw, P, TZ, TZ, 1);
+    else
+        fft_lines<true>(s_buf, s_tw, P, TZ, TZ, 1);
+    for (int e = threadIdx.x; e < total; e += FFT_THREADS) {
+        const int t = e % TZ, a = e / TZ;
+        const uint64_t gi = base + (uint64_t)a * stride_axis + t;
+        if (MODE == 3)
+            phi[gi] = s_buf[a * TZ + t].x;
+        else
+            c[gi] = s_buf[a * TZ + t];
+    }
+}
+
+// z pass: TL whole contiguous lines (fixed ix, consecutive iy): forward FFT, Green's
+// function, inverse FFT.
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(double2 *__restrict__ c,
+                                                              const double2 *__restrict__ tw,
+                                                              const double *__restrict__ gt,
+                                                              const double *__restrict__ k2t,
+                                                              fft_plan P, int TL, double gconst) {
+    __shared__ double2 s_buf[FFT_ELEMS];
+    __shared__ double2 s_tw[1024];
+    const int n = P.n;
+    const int tiles_y = n / TL;
+    const int ix = blockIdx.x / tiles_y;
+    const int iy0 = (blockIdx.x % tiles_y) * TL;
+    const uint64_t base = ((uint64_t)ix * n + iy0) * n;
+    load_twiddles(s_tw, tw, n);
+    const int total = n * TL;
+    for (int e = threadIdx.x; e < total; e += FFT_THREADS)
+        s_buf[e] = c[base + e];
+    __syncthreads();
+    fft_lines<false>(s_buf, s_tw, P, TL, 1, n);
+    for (int e = threadIdx.x; e < total; e += FFT_THREADS) {
+        const int iz = e % n, l = e / n;
+        const int iy = iy0 + l;
+        const double k2 = k2t[ix] + k2t[iy] + k2t[iz];
+        double gk = 0.0;
+        if (k2 > 0.0)
+            gk = gconst * gt[ix] * gt[iy] * gt[iz] / k2;
+        double2 v = s_buf[e];
+        s_buf[e] = make_double2(v.x * gk, v.y * gk);
+    }
+    __syncthreads();
+    fft_lines<true>(s_buf, s_tw, P, TL, 1, n);
+    for (int e = threadIdx.x; e < total; e += FFT_THREADS)
+        c[base + e] = s_buf[e];
+}
+
+// ---------------------------------------------------------------------------------------
+// gradient + interpolation
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(PM_THREADS) void k_pm_interp(
+    uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ phi, double delta, int ng,
+    double *__restrict__ gx, double *__restrict__ gy, double *__restrict__ gz, int accumulate) {
+    uint64_t p = (uint64_t)blockIdx.x * PM_THREADS + threadIdx.x;
+    if (p >= n)
+        return;
+    int ix[2], iy[2], iz[2];
+    double wx[2], wy[2], wz[2];
+    cic_axis(x[p], delta, ng, ix[0], ix[1], wx[0], wx[1]);
+    cic_axis(y[p], delta, ng, iy[0], iy[1], wy[0], wy[1]);
+    cic_axis(z[p], delta, ng, iz[0], iz[1], wz[0], wz[1]);
+    const uint64_t N = (uint64_t)ng;
+    auto at = [&](int a, int b, int c) -> double {
+        a = (a % ng + ng) % ng;
+        b = (b % ng + ng) % ng;
+        c = (c % ng + ng) % ng;
+        return phi[((uint64_t)a * N + b) * N + c];
+    };
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const double w = wx[a] * wy[b] * wz[c];
+                const int i = ix[a], j = iy[b], k = iz[c];
+                const double dxp = 2.0 / 3.0 * (at(i + 1, j, k) - at(i - 1, j, k)) -
+                                   1.0 / 12.0 * (at(i + 2, j, k) - at(i - 2, j, k));
+                const double dyp = 2.0 / 3.0 * (at(i, j + 1, k) - at(i, j - 1, k)) -
+                                   1.0 / 12.0 * (at(i, j + 2, k) - at(i, j - 2, k));
+                const double dzp = 2.0 / 3.0 * (at(i, j, k + 1) - at(i, j, k - 1)) -
+                                   1.0 / 12.0 * (at(i, j, k + 2) - at(i, j, k - 2));
+                sx += w * dxp;
+                sy += w * dyp;
+                sz += w * dzp;
+            }
+    const double s = -1.0 / delta;
+    if (accumulate) {
+        gx[p] += s * sx;
+        gy[p] += s * sy;
+        gz[p] += s * sz;
+    } else {
+        gx[p] = s * sx;
+        gy[p] = s * sy;
+        gz[p] = s * sz;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
+static bool make_plan(int n, fft_plan *P) {
+    P->n = n;
+    P->n_stages = 0;
+    int m = n;
+    while (m % 4 == 0 && P->n_stages < FFT_MAX_STAGES) {
+        P->radix[P->n_stages++] = 4;
+        m /= 4;
+    }
+    while (m % 2 == 0 && P->n_stages < FFT_MAX_STAGES) {
+        P->radix[P->n_stages++] = 2;
+        m /= 2;
+    }
+    while (m % 3 == 0 && P->n_stages < FFT_MAX_STAGES) {
+        P->radix[P->n_stages++] = 3;
+        m /= 3;
+    }
+    return m == 1;
+}
+
+// largest power of two t <= cap with t * ng <= FFT_ELEMS and t dividing ng
+static int tile_lines(int ng, int cap) {
+    int t = 1;
+    while (2 * t <= cap && 2 * t * ng <= FFT_ELEMS && ng % (2 * t) == 0)
+        t *= 2;
+    return t;
+}
+
+bool dzs_pm_mesh_ok(int ng) {
+    fft_plan P;
+    return ng >= 8 && ng <= 1024 && make_plan(ng, &P);
+}
+
+// tables at ctx->pm_tables: [0, 2n) twiddles (double2), [2n, 3n) gt, [3n, 4n) k^2
+static dzs_status upload_tables(dzs_ctx *ctx, int ng, double L, double r_s, hipStream_t s) {
+    std::vector<double> h(4 * (size_t)ng);
+    const long double pi = 3.14159265358979323846264338327950288L;
+    for (int m = 0; m < ng; ++m) {
+        long double ang = -2.0L * pi * m / ng;
+        h[2 * m] = (double)cosl(ang);
+        h[2 * m + 1] = (double)sinl(ang);
+    }
+    const double delta = L / ng;
+    for (int m = 0; m < ng; ++m) {
+        const int nn = m < ng / 2 ? m : m - ng;  // frequency index in [-ng/2, ng/2)
+        const long double k = 2.0L * pi * nn / L;
+        long double hh = 0.5L * k * delta;
+        long double sinc = hh == 0.0L ? 1.0L : sinl(hh) / hh;
+        long double w2 = sinc * sinc * sinc * sinc;  // W^2 per axis: sinc^4
+        h[2 * ng + m] = (double)(expl(-k * k * (long double)r_s * r_s) / w2);
+        h[3 * ng + m] = (double)(k * k);
+    }
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->pm_tables, h.data(), sizeof(double) * h.size(),
+                                hipMemcpyHostToDevice, s));
+    DZS_HIP(ctx, hipStreamSynchronize(s));
+    return DZS_OK;
+}
+
+dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                      const dzs_pm_params *prm, hipStream_t s) {
+    const int ng = prm->ng;
+    fft_plan P;
+    if (!make_plan(ng, &P))
+        return dzs_fail(ctx, DZS_EINVAL, "pm_force: mesh side %d is not 2^a 3^b", ng);
+    const uint64_t ng3 = (uint64_t)ng * ng * ng;
+    const double delta = box->L / ng;
+    if (ctx->pm_tab_ng != ng || ctx->pm_tab_L != box->L || ctx->pm_tab_rs != prm->r_s) {
+        DZS_TRY(upload_tables(ctx, ng, box->L, prm->r_s, s));
+        ctx->pm_tab_ng = ng;
+        ctx->pm_tab_L = box->L;
+        ctx->pm_tab_rs = prm->r_s;
+    }
+    const double2 *tw = (const double2 *)ctx->pm_tables;
+    const double *gt = ctx->pm_tables + 2 * ng;
+    const double *k2t = ctx->pm_tables + 3 * ng;
+    {
+        dzs_timed t(ctx, KC_PM_DEPOSIT, s);
+        DZS_HIP(ctx, hipMemsetAsync(ctx->mesh_q, 0, sizeof(long long) * ng3, s));
+        if (p->n > 0) {
+            hipLaunchKernelGGL(k_pm_deposit, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS),
+                               0, s, p->n, (const double *)p->x, (const double *)p->y,
+                               (const double *)p->z, (const uint32_t *)p->mult, delta, ng,
+                               (unsigned long long *)ctx->mesh_q);
+            DZS_TRY(dzs_check_launch(ctx, "pm_deposit"));
+        }
+    }
+    const int TZ = tile_lines(ng, 16);
+    const int TL = tile_lines(ng, FFT_ELEMS);
+    const uint32_t strided_blocks = (uint32_t)((uint64_t)ng * (ng / TZ));
+    const uint32_t z_blocks = (uint32_t)((uint64_t)ng * (ng / TL));
+    const double q_scale = box->m0 / (DEP_FRAC * delta * delta * delta);
+    const double gconst = -4.0 * 3.14159265358979323846 * box->G / (double)ng3;
+    {
+        dzs_timed t(ctx, KC_PM_FFT_X, s);
+        hipLaunchKernelGGL(k_fft_strided<0>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
+                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                           tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_x_fwd"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_Y, s);
+        hipLaunchKernelGGL(k_fft_strided<1>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
+                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                           tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_y_fwd"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_Z_GREEN, s);
+        hipLaunchKernelGGL(k_fft_z_green, dim3(z_blocks), dim3(FFT_THREADS), 0, s, ctx->mesh_c, tw,
+                           gt, k2t, P, TL, gconst);
+        DZS_TRY(dzs_check_launch(ctx, "fft_z_green"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_Y, s);
+        hipLaunchKernelGGL(k_fft_strided<2>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
+                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                           tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_y_inv"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_X, s);
+        hipLaunchKernelGGL(k_fft_strided<3>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
+                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                           tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_x_inv"));
+    }
+    if (p->n > 0) {
+        dzs_timed t(ctx, KC_PM_INTERP, s);
+        hipLaunchKernelGGL(k_pm_interp, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0, s,
+                           p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,
+                           (const double *)ctx->mesh_phi, delta, ng, p->gx, p->gy, p->gz,
+                           prm->accumulate);
+        DZS_TRY(dzs_check_launch(ctx, "pm_interp"));
+    }
+    return DZS_OK;
+}

@@ -1,0 +1,283 @@
+// Exclusive prefix scan (u32) and stable LSD radix sort of (u64 Morton key, u32 index)
+// pairs for gfx950.
+//
+// Sort: 8 passes of 8-bit digits.  Per pass: (1) each 256-thread block counts the digits of
+// its 4096-key tile in LDS; (2) one exclusive scan over the digit-major table gives every
+// (digit, tile) its global start; (3) each block ranks its tile stably — wave-level digit
+// matching through eight ballots, per-wave counts combined in LDS — stages the tile in LDS in
+// local digit order, and writes it out so that consecutive lanes write consecutive addresses
+// of the same digit run.
+#include "internal.h"
+
+#define SCAN_THREADS 256
+#define SCAN_ITEMS 16
+#define SCAN_TILE (SCAN_THREADS * SCAN_ITEMS)
+
+#define SORT_THREADS 256
+#define SORT_ITEMS 16
+#define SORT_TILE (SORT_THREADS * SORT_ITEMS)
+
+// ---------------------------------------------------------------------------------------
+// block-wide exclusive scan of one value per thread (256 threads = 4 wave64)
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_wave,
+                                                       uint32_t *total) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t incl = dzs_wave_incl_scan(v);
+    if (lane == 63)
+        s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t w = 0; w < wave; ++w)
+        off += s_wave[w];
+    uint32_t tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
+    if (total)
+        *total = tot;
+    return off + incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *__restrict__ in,
+                                                              uint64_t n,
+                                                              uint32_t *__restrict__ part) {
+    __shared__ uint32_t s_wave[4];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t sum = 0;
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t e = base + (uint64_t)r * SCAN_THREADS + threadIdx.x;
+        if (e < n)
+            sum += in[e];
+    }
+    uint32_t tot;
+    block_excl_scan_256(sum, s_wave, &tot);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = tot;
+}
+
+// scan one tile (blocked: thread t owns items t*16 .. t*16+15), adding the tile offset
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile(const uint32_t *__restrict__ in,
+                                                            uint32_t *__restrict__ out,
+                                                            uint64_t n,
+                                                            const uint32_t *__restrict__ offs,
+                                                            uint32_t *__restrict__ total) {
+    __shared__ uint32_t s_wave[4];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t e = base + r;
+        v[r] = e < n ? in[e] : 0u;
+        sum += v[r];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan_256(sum, s_wave, &tot);
+    if (offs)
+        run += offs[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t e = base + r;
+        if (e < n)
+            out[e] = run;
+        run += v[r];
+    }
+    if (total && threadIdx.x == SCAN_THREADS - 1 && blockIdx.x == gridDim.x - 1)
+        *total = run;
+}
+
+uint64_t dzs_scan_tmp_words(uint64_t n) {
+    uint64_t words = 0;
+    while (n > SCAN_TILE) {
+        uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+        words += 2 * nb;
+        n = nb;
+    }
+    return words + 64;
+}
+
+static dzs_status scan_rec(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n,
+                           uint32_t *total_dev, uint32_t *tmp, hipStream_t s) {
+    uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb <= 1) {
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SCAN_THREADS), 0, s, in, out, n,
+                           (const uint32_t *)nullptr, total_dev);
+        return dzs_check_launch(ctx, "scan_tile");
+    }
+    uint32_t *part = tmp, *part_scan = tmp + nb;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, n, part);
+    DZS_TRY(dzs_check_launch(ctx, "scan_reduce"));
+    DZS_TRY(scan_rec(ctx, part, part_scan, nb, nullptr, tmp + 2 * nb, s));
+    hipLaunchKernelGGL(k_scan_tile, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, out, n,
+                       (const uint32_t *)part_scan, total_dev);
+    return dzs_check_launch(ctx, "scan_tile");
+}
+
+dzs_status dzs_scan_u32(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n,
+                        uint32_t *total_dev, hipStream_t s) {
+    if (n == 0) {
+        if (total_dev)
+            DZS_HIP(ctx, hipMemsetAsync(total_dev, 0, sizeof(uint32_t), s));
+        return DZS_OK;
+    }
+    if (dzs_scan_tmp_words(n) > ctx->scan_tmp_cap)
+        return dzs_fail(ctx, DZS_ECAPACITY, "scan of %llu elements exceeds scratch",
+                        (unsigned long long)n);
+    return scan_rec(ctx, in, out, n, total_dev, ctx->scan_tmp, s);
+}
+
+// ---------------------------------------------------------------------------------------
+// radix sort
+// ---------------------------------------------------------------------------------------
+uint64_t dzs_sort_hist_words(uint64_t n) {
+    uint64_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+    if (tiles == 0)
+        tiles = 1;
+    return 256 * tiles;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__restrict__ key,
+                                                             uint64_t n, int shift,
+                                                             uint32_t *__restrict__ hist,
+                                                             uint32_t tiles) {
+    __shared__ uint32_t s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        uint64_t e = base + (uint64_t)r * SORT_THREADS + threadIdx.x;
+        if (e < n)
+            atomicAdd(&s_h[(uint32_t)(key[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * tiles + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+    const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
+    uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out, uint64_t n, int shift,
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hist_scan, uint32_t tiles) {
+    __shared__ uint64_t s_key[SORT_TILE];
+    __shared__ uint32_t s_idx[SORT_TILE];
+    __shared__ uint32_t s_lstart[256], s_run[256], s_gstart[256];
+    __shared__ uint32_t s_wcnt[4][256];
+    __shared__ uint32_t s_wave[4];
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
+    const uint32_t cnt = (uint32_t)((n - base) < SORT_TILE ? (n - base) : SORT_TILE);
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+
+    uint32_t c = hist[(uint64_t)tid * tiles + blockIdx.x];
+    s_gstart[tid] = hist_scan[(uint64_t)tid * tiles + blockIdx.x];
+    uint32_t ls = block_excl_scan_256(c, s_wave, nullptr);
+    s_lstart[tid] = ls;
+    s_run[tid] = 0;
+    for (int w = 0; w < 4; ++w)
+        s_wcnt[w][tid] = 0;
+    __syncthreads();
+
+    for (uint32_t r = 0; r < SORT_ITEMS; ++r) {
+        const uint32_t local = r * SORT_THREADS + tid;
+        const bool valid = local < cnt;
+        uint64_t k = valid ? key_in[base + local] : 0ull;
+        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t bal = __ballot(((d >> bit) & 1u) != 0u);
+            m &= ((d >> bit) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & lt_mask);
+        const uint32_t wcount = (uint32_t)__popcll(m);
+        const uint32_t tag = r + 1;
+        if (valid && rank == 0)
+            s_wcnt[wave][d] = (tag << 16) | wcount;
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = 0;
+            for (uint32_t w = 0; w < wave; ++w) {
+                uint32_t v = s_wcnt[w][d];
+                pre += ((v >> 16) == tag) ? (v & 0xffffu) : 0u;
+            }
+            uint32_t lp = s_lstart[d] + s_run[d] + pre + rank;
+            s_key[lp] = k;
+            s_idx[lp] = idx_in[base + local];
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            uint32_t v = s_wcnt[w][tid];
+            tot += ((v >> 16) == tag) ? (v & 0xffffu) : 0u;
+        }
+        s_run[tid] += tot;
+        __syncthreads();
+    }
+    for (uint32_t i = tid; i < cnt; i += SORT_THREADS) {
+        uint64_t k = s_key[i];
+        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t gp = (uint64_t)s_gstart[d] + (i - s_lstart[d]);
+        key_out[gp] = k;
+        idx_out[gp] = s_idx[i];
+    }
+}
+
+dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s) {
+    if (n <= 1)
+        return DZS_OK;
+    if (n > 0xffffffffull)
+        return dzs_fail(ctx, DZS_EINVAL, "radix sort: n exceeds 2^32-1");
+    const uint32_t tiles = (uint32_t)((n + SORT_TILE - 1) / SORT_TILE);
+    const uint64_t words = 256ull * tiles;
+    if (words > ctx->hist_cap)
+        return dzs_fail(ctx, DZS_ECAPACITY, "radix sort histogram exceeds scratch");
+    dzs_timed t(ctx, KC_SORT, s);
+    uint64_t *kin = ctx->key, *kout = ctx->key_alt;
+    uint32_t *iin = ctx->idx, *iout = ctx->idx_alt;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, kin, n, shift,
+                           ctx->hist, tiles);
+        DZS_TRY(dzs_check_launch(ctx, "radix_hist"));
+        DZS_TRY(dzs_scan_u32(ctx, ctx->hist, ctx->hist_scan, words, nullptr, s));
+        hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(SORT_THREADS), 0, s, kin, iin,
+                           kout, iout, n, shift, ctx->hist, ctx->hist_scan, tiles);
+        DZS_TRY(dzs_check_launch(ctx, "radix_scatter"));
+        uint64_t *tk = kin; kin = kout; kout = tk;
+        uint32_t *ti = iin; iin = iout; iout = ti;
+    }
+    // eight passes: the result is back in ctx->key / ctx->idx
+    return DZS_OK;
+}
+
+// Equal keys keep their input order (the sort is stable); where a canonical order is
+// needed, runs of equal keys are re-ordered by ascending particle id (runs are short).
+__global__ void k_fix_ties(const uint64_t *__restrict__ key, uint32_t *__restrict__ idx,
+                           const uint32_t *__restrict__ id, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i + 1 >= n)
+        return;
+    if (key[i] != key[i + 1] || (i > 0 && key[i - 1] == key[i]))
+        return;
+    uint64_t e = i + 1;
+    while (e < n && key[e] == key[i])
+        ++e;
+    for (uint64_t a = i + 1; a < e; ++a) {
+        uint32_t v = idx[a];
+        uint32_t vid = id[v];
+        uint64_t b = a;
+        while (b > i && id[idx[b - 1]] > vid) {
+            idx[b] = idx[b - 1];
+            --b;
+        }
+        idx[b] = v;
+    }
+}
+
+dzs_status dzs_fix_ties(dzs_ctx *ctx, uint64_t n, const uint32_t *id, hipStream_t s) {
+    if (n <= 1)
+        return DZS_OK;
+    dzs_timed t(ctx, KC_SORT, s);
+    uint32_t blocks = (uint32_t)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fix_ties, dim3(blocks), dim3(256), 0, s, ctx->key, ctx->idx, id, n);
+    return dzs_check_launch(ctx, "fix_ties");
+}

@@ -1,0 +1,606 @@
+// Oct-tree on Morton-sorted particles and the wavefront-cooperative short-range walk.
+//
+// Build (paper Sec. 2.1: root = box, each node split into its 8 octants while it holds more
+// than one particle; here a node stops splitting at `leaf_size` particles): level by level
+// from the root.  A node's particles are a contiguous range of the sorted order and its
+// children are the sub-ranges with equal next 3 key bits, found by binary search.  Nodes are
+// stored level-major, children of a node contiguous and in Morton order.  Moments (mass,
+// centre of mass, particle bounding box, largest softening) are accumulated bottom-up.
+//
+// Walk: one wave64 per target group (<= 64 Morton-contiguous particles inside one node,
+// one target per lane).  The wave pops up to 64 nodes from its stack at a time; each lane
+// classifies one node against the group's bounding box: skip (farther than r_cut),
+// monopole (side < theta * distance of the node's centre of mass from the box), leaf, or
+// open.  Opened nodes push their children; monopoles and leaf particles are appended,
+// shifted to the periodic image nearest the group, to an interaction list staged in LDS.
+// When the list fills, every lane sums its target's interactions with the whole list
+// (LDS broadcast reads).
+#include "internal.h"
+
+#define TB_THREADS 256
+#define WALK_LIST 256
+#define WALK_DEPTH 8192u
+#define WALK_SLOTS_MAX 4096u
+
+static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------------------
+// build
+// ---------------------------------------------------------------------------------------
+__global__ void k_tree_root(uint32_t n, uint32_t *nd_first, uint32_t *nd_count,
+                            uint32_t *nd_child, uint8_t *nd_nchild, uint8_t *nd_level,
+                            uint32_t *frontier) {
+    nd_first[0] = 0;
+    nd_count[0] = n;
+    nd_child[0] = 0;
+    nd_nchild[0] = 0;
+    nd_level[0] = 0;
+    frontier[0] = 0;
+}
+
+// For each frontier node at level k: the 9 bounds of its 8 octant sub-ranges.
+__global__ __launch_bounds__(TB_THREADS) void k_tree_split(
+    const uint32_t *__restrict__ frontier, uint32_t nf, int k, const uint64_t *__restrict__ key,
+    const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
+    uint32_t *__restrict__ bounds, uint32_t *__restrict__ nchild, uint32_t *__restrict__ ninternal,
+    uint32_t leaf) {
+    uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (f >= nf)
+        return;
+    const uint32_t node = frontier[f];
+    const uint32_t s = nd_first[node], e = s + nd_count[node];
+    const int shift = 3 * (DZS_KEY_BITS - (k + 1));
+    uint32_t b[9];
+    b[0] = s;
+    b[8] = e;
+    for (uint32_t d = 1; d < 8; ++d) {
+        // first index in [b[d-1], e) whose digit is >= d
+        uint32_t lo = b[d - 1], hi = e;
+        while (lo < hi) {
+            uint32_t mid = lo + ((hi - lo) >> 1);
+            uint32_t dig = (uint32_t)(key[mid] >> shift) & 7u;
+            if (dig < d)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        b[d] = lo;
+    }
+    uint32_t nc = 0, ni = 0;
+    for (int d = 0; d < 8; ++d) {
+        uint32_t c = b[d + 1] - b[d];
+        bounds[(uint64_t)f * 9 + d] = b[d];
+        nc += c > 0;
+        ni += (c > leaf && k + 1 < DZS_KEY_BITS);
+    }
+    bounds[(uint64_t)f * 9 + 8] = e;
+    nchild[f] = nc;
+    ninternal[f] = ni;
+}
+
+__global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
+    const uint32_t *__restrict__ frontier, uint32_t nf, int k, const uint32_t *__restrict__ bounds,
+    const uint32_t *__restrict__ child_off, const uint32_t *__restrict__ int_off, uint32_t base,
+    uint32_t *__restrict__ nd_first, uint32_t *__restrict__ nd_count, uint32_t *__restrict__ nd_child,
+    uint8_t *__restrict__ nd_nchild, uint8_t *__restrict__ nd_level,
+    uint32_t *__restrict__ frontier_next, uint32_t leaf) {
+    uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (f >= nf)
+        return;
+    const uint32_t node = frontier[f];
+    uint32_t c = base + child_off[f];
+    uint32_t q = int_off[f];
+    nd_child[node] = c;
+    uint32_t nc = 0;
+    for (int d = 0; d < 8; ++d) {
+        uint32_t s = bounds[(uint64_t)f * 9 + d], e = bounds[(uint64_t)f * 9 + d + 1];
+        if (e == s)
+            continue;
+        nd_first[c] = s;
+        nd_count[c] = e - s;
+        nd_child[c] = 0;
+        nd_nchild[c] = 0;
+        nd_level[c] = (uint8_t)(k + 1);
+        if (e - s > leaf && k + 1 < DZS_KEY_BITS)
+            frontier_next[q++] = c;
+        ++c;
+        ++nc;
+    }
+    nd_nchild[node] = (uint8_t)nc;
+}
+
+// Bottom-up moments of the nodes [lo, hi) (one level).
+__global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
+    uint32_t lo, uint32_t hi, uint64_t cap, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const uint32_t *__restrict__ mult,
+    double m0, double h0, const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
+    const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild,
+    double *__restrict__ nd_mass, double *__restrict__ nd_com, double *__restrict__ nd_bmin,
+    double *__restrict__ nd_bmax, double *__restrict__ nd_hmax) {
+    uint32_t v = lo + blockIdx.x * TB_THREADS + threadIdx.x;
+    if (v >= hi)
+        return;
+    double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, hmax = 0.0;
+    double mnx = 1e300, mny = 1e300, mnz = 1e300, mxx = -1e300, mxy = -1e300, mxz = -1e300;
+    const uint32_t nc = nd_nchild[v];
+    if (nc == 0) {
+        const uint32_t s = nd_first[v], e = s + nd_count[v];
+        for (uint32_t j = s; j < e; ++j) {
+            const double mj = m0 * (double)mult[j];
+            const double hj = h0 * cbrt((double)mult[j]);
+            const double xj = x[j], yj = y[j], zj = z[j];
+            m += mj;
+            sx += mj * xj;
+            sy += mj * yj;
+            sz += mj * zj;
+            mnx = fmin(mnx, xj); mny = fmin(mny, yj); mnz = fmin(mnz, zj);
+            mxx = fmax(mxx, xj); mxy = fmax(mxy, yj); mxz = fmax(mxz, zj);
+            hmax = fmax(hmax, hj);
+        }
+    } else {
+        const uint32_t c0 = nd_child[v];
+        for (uint32_t c = c0; c < c0 + nc; ++c) {
+            const double mc = nd_mass[c];
+            m += mc;
+            sx += mc * nd_com[c];
+            sy += mc * nd_com[cap + c];
+            sz += mc * nd_com[2 * cap + c];
+            mnx = fmin(mnx, nd_bmin[c]); mny = fmin(mny, nd_bmin[cap + c]);
+            mnz = fmin(mnz, nd_bmin[2 * cap + c]);
+            mxx = fmax(mxx, nd_bmax[c]); mxy = fmax(mxy, nd_bmax[cap + c]);
+            mxz = fmax(mxz, nd_bmax[2 * cap + c]);
+            hmax = fmax(hmax, nd_hmax[c]);
+        }
+    }
+    nd_mass[v] = m;
+    nd_com[v] = sx / m;
+    nd_com[cap + v] = sy / m;
+    nd_com[2 * cap + v] = sz / m;
+    nd_bmin[v] = mnx; nd_bmin[cap + v] = mny; nd_bmin[2 * cap + v] = mnz;
+    nd_bmax[v] = mxx; nd_bmax[cap + v] = mxy; nd_bmax[2 * cap + v] = mxz;
+    nd_hmax[v] = hmax;
+}
+
+// Target groups: each node with more than G particles packs its consecutive children that
+// hold at most G particles into bins of at most G (greedy, Morton order); a bin starts a
+// group.  Leaves with more than G particles (coincident particles at the finest level) are
+// cut into chunks of G.
+__global__ __launch_bounds__(TB_THREADS) void k_tree_groups(
+    uint32_t n_nodes, const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
+    const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild, uint32_t G,
+    uint32_t *__restrict__ flag) {
+    uint32_t v = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (v >= n_nodes)
+        return;
+    const uint32_t cnt = nd_count[v];
+    if (v == 0 && cnt <= G) {
+        flag[0] = 1u;
+        return;
+    }
+    if (cnt <= G)
+        return;
+    const uint32_t nc = nd_nchild[v];
+    if (nc == 0) {
+        for (uint32_t j = nd_first[v]; j < nd_first[v] + cnt; j += G)
+            flag[j] = 1u;
+        return;
+    }
+    uint32_t bin = 0;
+    const uint32_t c0 = nd_child[v];
+    for (uint32_t c = c0; c < c0 + nc; ++c) {
+        const uint32_t cc = nd_count[c];
+        if (cc > G) {
+            bin = 0;
+        } else if (bin > 0 && bin + cc <= G) {
+            bin += cc;
+        } else {
+            flag[nd_first[c]] = 1u;
+            bin = cc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(TB_THREADS) void k_group_compact(uint32_t n,
+                                                              const uint32_t *__restrict__ flag,
+                                                              const uint32_t *__restrict__ scan,
+                                                              uint32_t *__restrict__ grp_first) {
+    uint32_t i = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (i < n && flag[i])
+        grp_first[scan[i]] = i;
+    if (i == 0)
+        grp_first[scan[n - 1] + flag[n - 1]] = n;
+}
+
+dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const double *x,
+                          const double *y, const double *z, const uint32_t *mult, int leaf_size,
+                          int group_size, hipStream_t s) {
+    const uint32_t n = (uint32_t)n64;
+    ctx->n_nodes = 0;
+    ctx->n_groups = 0;
+    if (n == 0)
+        return DZS_OK;
+    const uint32_t leaf = (uint32_t)leaf_size;
+    const uint64_t cap = ctx->cap_nodes;
+    {
+        dzs_timed t(ctx, KC_TREE_BUILD, s);
+        hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, n, ctx->nd_first, ctx->nd_count,
+                           ctx->nd_child, ctx->nd_nchild, ctx->nd_level, ctx->frontier);
+        DZS_TRY(dzs_check_launch(ctx, "tree_root"));
+    }
+    uint32_t n_nodes = 1;
+    ctx->level_start[0] = 0;
+    ctx->level_start[1] = 1;
+    int n_levels = 1;
+    uint32_t nf = n > leaf ? 1u : 0u;
+    uint32_t *fr = ctx->frontier, *fr_next = ctx->frontier_next;
+    for (int k = 0; nf > 0 && k < DZS_KEY_BITS; ++k) {
+        {
+            dzs_timed t(ctx, KC_TREE_BUILD, s);
+            hipLaunchKernelGGL(k_tree_split, dim3(blocks_for(nf, TB_THREADS)), dim3(TB_THREADS), 0,
+                               s, fr, nf, k, ctx->key, ctx->nd_first, ctx->nd_count,
+                               ctx->child_bounds, ctx->fr_nchild, ctx->fr_ninternal, leaf);
+            DZS_TRY(dzs_check_launch(ctx, "tree_split"));
+            DZS_TRY(dzs_scan_u32(ctx, ctx->fr_nchild, ctx->fr_child_off, nf, ctx->d_small, s));
+            DZS_TRY(dzs_scan_u32(ctx, ctx->fr_ninternal, ctx->fr_int_off, nf, ctx->d_small + 1, s));
+            DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small, ctx->d_small, 2 * sizeof(uint32_t),
+                                        hipMemcpyDeviceToHost, s));
+        }
+        DZS_HIP(ctx, hipStreamSynchronize(s));
+        const uint32_t n_children = ctx->h_small[0], n_internal = ctx->h_small[1];
+        if ((uint64_t)n_nodes + n_children > cap)
+            return dzs_fail(ctx, DZS_ECAPACITY, "tree needs more than %llu nodes",
+                            (unsigned long long)cap);
+        {
+            dzs_timed t(ctx, KC_TREE_BUILD, s);
+            hipLaunchKernelGGL(k_tree_emit, dim3(blocks_for(nf, TB_THREADS)), dim3(TB_THREADS), 0,
+                               s, fr, nf, k, ctx->child_bounds, ctx->fr_child_off,
+                               ctx->fr_int_off, n_nodes, ctx->nd_first, ctx->nd_count,
+                               ctx->nd_child, ctx->nd_nchild, ctx->nd_level, fr_next, leaf);
+            DZS_TRY(dzs_check_launch(ctx, "tree_emit"));
+        }
+        n_nodes += n_children;
+        ctx->level_start[k + 2] = n_nodes;
+        n_levels = k + 2;
+        uint32_t *tmp = fr;
+        fr = fr_next;
+        fr_next = tmp;
+        nf = n_internal;
+    }
+    ctx->n_nodes = n_nodes;
+    ctx->n_levels = n_levels;
+    {
+        dzs_timed t(ctx, KC_TREE_MOMENTS, s);
+        for (int k = n_levels - 1; k >= 0; --k) {
+            const uint32_t lo = ctx->level_start[k], hi = ctx->level_start[k + 1];
+            if (hi <= lo)
+                continue;
+            hipLaunchKernelGGL(k_tree_moments, dim3(blocks_for(hi - lo, TB_THREADS)),
+                               dim3(TB_THREADS), 0, s, lo, hi, cap, x, y, z, mult, box->m0,
+                               2.8 * box->eps0, ctx->nd_first, ctx->nd_count, ctx->nd_child,
+                               ctx->nd_nchild, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
+                               ctx->nd_bmax, ctx->nd_hmax);
+            DZS_TRY(dzs_check_launch(ctx, "tree_moments"));
+        }
+    }
+    {
+        dzs_timed t(ctx, KC_TREE_GROUPS, s);
+        DZS_HIP(ctx, hipMemsetAsync(ctx->grp_flag, 0, sizeof(uint32_t) * n, s));
+        hipLaunchKernelGGL(k_tree_groups, dim3(blocks_for(n_nodes, TB_THREADS)), dim3(TB_THREADS),
+                           0, s, n_nodes, ctx->nd_first, ctx->nd_count, ctx->nd_child,
+                           ctx->nd_nchild, (uint32_t)group_size, ctx->grp_flag);
+        DZS_TRY(dzs_check_launch(ctx, "tree_groups"));
+        DZS_TRY(dzs_scan_u32(ctx, ctx->grp_flag, ctx->grp_scan, n, ctx->d_small + 2, s));
+        hipLaunchKernelGGL(k_group_compact, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s,
+                           n, ctx->grp_flag, ctx->grp_scan, ctx->grp_first);
+        DZS_TRY(dzs_check_launch(ctx, "group_compact"));
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 2, ctx->d_small + 2, sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, s));
+    }
+    DZS_HIP(ctx, hipStreamSynchronize(s));
+    ctx->n_groups = ctx->h_small[2];
+    return DZS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// walk + pair evaluation (FP64)
+// ---------------------------------------------------------------------------------------
+struct walk_args {
+    const uint32_t *grp_first;
+    uint32_t n_groups;
+    const double *x, *y, *z;
+    const uint32_t *mult;
+    const uint32_t *nd_first, *nd_count, *nd_child;
+    const uint8_t *nd_nchild, *nd_level;
+    const double *nd_mass, *nd_com, *nd_bmin, *nd_bmax, *nd_hmax;
+    uint64_t cap;
+    double L, halfL, rcut2, theta2, rs_inv, G, m0, h0;
+    double *gx, *gy, *gz;
+    int accumulate;
+    uint32_t *stack;
+    uint32_t depth;
+    uint32_t *counter;  // [0] next group, [1] overflow flag
+    unsigned long long *pair_count;
+};
+
+// Cubic-spline softened 1/r^3 (enclosed-mass force / r), r < h.
+__device__ __forceinline__ double gsoft_inner(double r, double h) {
+    const double hinv = 1.0 / h;
+    const double u = r * hinv;
+    const double h3 = hinv * hinv * hinv;
+    if (u < 0.5)
+        return h3 * (10.666666666666666 + u * u * (32.0 * u - 38.4));
+    return h3 * (21.333333333333332 - 48.0 * u + 38.4 * u * u - 10.666666666666666 * u * u * u -
+                 0.066666666666666666 / (u * u * u));
+}
+
+__global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
+    __shared__ double sx[WALK_LIST], sy[WALK_LIST], sz[WALK_LIST], sm[WALK_LIST], sh[WALK_LIST];
+    __shared__ uint32_t q_node[64];
+    __shared__ uint32_t q_pref[65];
+    __shared__ double q_shift[3][64];
+    __shared__ uint32_t s_g;
+
+    const uint32_t lane = threadIdx.x;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t *stk = A.stack + (uint64_t)blockIdx.x * A.depth;
+    const double inv_sqrt_pi = 0.56418958354775628;
+
+    for (;;) {
+        if (lane == 0)
+            s_g = atomicAdd(&A.counter[0], 1u);
+        __syncthreads();
+        const uint32_t g = s_g;
+        __syncthreads();
+        if (g >= A.n_groups)
+            break;
+        const uint32_t first = A.grp_first[g];
+        const uint32_t cnt = A.grp_first[g + 1] - first;
+        const bool valid = lane < cnt;
+        const uint32_t i = valid ? first + lane : first;
+        const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+        const double hi = A.h0 * cbrt((double)A.mult[i]);
+        // group bounding box
+        double mnx = xi, mny = yi, mnz = zi, mxx = xi, mxy = yi, mxz = zi;
+        for (int o = 32; o >= 1; o >>= 1) {
+            mnx = fmin(mnx, __shfl_xor(mnx, o, 64));
+            mny = fmin(mny, __shfl_xor(mny, o, 64));
+            mnz = fmin(mnz, __shfl_xor(mnz, o, 64));
+            mxx = fmax(mxx, __shfl_xor(mxx, o, 64));
+            mxy = fmax(mxy, __shfl_xor(mxy, o, 64));
+            mxz = fmax(mxz, __shfl_xor(mxz, o, 64));
+        }
+        const double gcx = 0.5 * (mnx + mxx), gcy = 0.5 * (mny + mxy), gcz = 0.5 * (mnz + mxz);
+        const double ghx = 0.5 * (mxx - mnx), ghy = 0.5 * (mxy - mny), ghz = 0.5 * (mxz - mnz);
+
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        uint32_t nlist = 0;
+        uint32_t n_pairs = 0;  // interactions inside the cutoff (algorithmic work)
+
+        auto flush = [&]() {
+            __syncthreads();
+            for (uint32_t j = 0; j < nlist; ++j) {
+                // sources were shifted to the image nearest the group's centre; for groups
+                // or leaves wide compared with L/2 - r_cut that is not every pair's nearest
+                // image, so the separation is reduced to the minimum image here as well
+                const double dx = dzs_min_image(sx[j] - xi, A.L);
+                const double dy = dzs_min_image(sy[j] - yi, A.L);
+                const double dz = dzs_min_image(sz[j] - zi, A.L);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < A.rcut2 && r2 > 0.0) {
+                    ++n_pairs;
+                    const double r = sqrt(r2);
+                    const double u = r * A.rs_inv;
+                    const double S = erfc(0.5 * u) + u * inv_sqrt_pi * exp(-0.25 * u * u);
+                    const double h = fmax(sh[j], hi);
+                    const double f = r >= h ? 1.0 / (r2 * r) : gsoft_inner(r, h);
+                    const double w = sm[j] * f * S;
+                    ax += w * dx;
+                    ay += w * dy;
+                    az += w * dz;
+                }
+            }
+            nlist = 0;
+            __syncthreads();
+        };
+
+        uint32_t sp = 1;
+        if (lane == 0)
+            stk[0] = 0;
+        __threadfence_block();
+        bool overflow = false;
+        while (sp > 0) {
+            const uint32_t take = sp < 64 ? sp : 64;
+            sp -= take;
+            const bool has = lane < take;
+            const uint32_t node = has ? stk[sp + lane] : 0u;
+            // classify: 0 skip, 1 leaf, 2 monopole, 3 open
+            int act = 0;
+            double shx = 0.0, shy = 0.0, shz = 0.0;
+            uint32_t ncount = 0, nchild = 0, child = 0;
+            if (has) {
+                const uint64_t c = A.cap;
+                const double bnx = A.nd_bmin[node], bny = A.nd_bmin[c + node], bnz = A.nd_bmin[2 * c + node];
+                const double bxx = A.nd_bmax[node], bxy = A.nd_bmax[c + node], bxz = A.nd_bmax[2 * c + node];
+                double dcx = 0.5 * (bnx + bxx) - gcx, dcy = 0.5 * (bny + bxy) - gcy,
+                       dcz = 0.5 * (bnz + bxz) - gcz;
+                shx = dcx > A.halfL ? -A.L : (dcx < -A.halfL ? A.L : 0.0);
+                shy = dcy > A.halfL ? -A.L : (dcy < -A.halfL ? A.L : 0.0);
+                shz = dcz > A.halfL ? -A.L : (dcz < -A.halfL ? A.L : 0.0);
+                dcx += shx; dcy += shy; dcz += shz;
+                const double gx_ = fmax(0.0, fabs(dcx) - 0.5 * (bxx - bnx) - ghx);
+                const double gy_ = fmax(0.0, fabs(dcy) - 0.5 * (bxy - bny) - ghy);
+                const double gz_ = fmax(0.0, fabs(dcz) - 0.5 * (bxz - bnz) - ghz);
+                const double dist2 = gx_ * gx_ + gy_ * gy_ + gz_ * gz_;
+                nchild = A.nd_nchild[node];
+                ncount = A.nd_count[node];
+                if (dist2 >= A.rcut2) {
+                    act = 0;
+                } else if (nchild == 0) {
+                    act = 1;
+                } else {
+                    act = 3;
+                    if (A.theta2 > 0.0) {
+                        const double cx = A.nd_com[node] + shx - gcx;
+                        const double cy = A.nd_com[c + node] + shy - gcy;
+                        const double cz = A.nd_com[2 * c + node] + shz - gcz;
+                        const double ex = fmax(0.0, fabs(cx) - ghx);
+                        const double ey = fmax(0.0, fabs(cy) - ghy);
+                        const double ez = fmax(0.0, fabs(cz) - ghz);
+                        const double d2 = ex * ex + ey * ey + ez * ez;
+                        const double side = ldexp(A.L, -(int)A.nd_level[node]);
+                        if (side * side < A.theta2 * d2)
+                            act = 2;
+                    }
+                    child = A.nd_child[node];
+                }
+            }
+            // ---- pushes
+            const uint32_t npush = act == 3 ? nchild : 0u;
+            const uint32_t pincl = dzs_wave_incl_scan(npush);
+            const uint32_t ptot = __shfl(pincl, 63, 64);
+            if (sp + ptot > A.depth) {
+                overflow = true;
+                break;
+            }
+            for (uint32_t j = 0; j < npush; ++j)
+                stk[sp + pincl - npush + j] = child + j;
+            sp += ptot;
+            __threadfence_block();
+            // ---- monopoles
+            const uint64_t mono = __ballot(act == 2);
+            const uint32_t nmono = (uint32_t)__popcll(mono);
+            if (nmono > 0) {
+                if (nlist + nmono > WALK_LIST)
+                    flush();
+                if (act == 2) {
+                    const uint32_t slot = nlist + (uint32_t)__popcll(mono & lt_mask);
+                    const uint64_t c = A.cap;
+                    sx[slot] = A.nd_com[node] + shx;
+                    sy[slot] = A.nd_com[c + node] + shy;
+                    sz[slot] = A.nd_com[2 * c + node] + shz;
+                    sm[slot] = A.nd_mass[node];
+                    sh[slot] = A.nd_hmax[node];
+                }
+                nlist += nmono;
+            }
+            // ---- leaves: queue, then stream their particles into the list
+            const uint64_t lmask = __ballot(act == 1);
+            const uint32_t nq = (uint32_t)__popcll(lmask);
+            if (nq > 0) {
+                const uint32_t lc = act == 1 ? ncount : 0u;
+                const uint32_t lincl = dzs_wave_incl_scan(lc);
+                const uint32_t P = __shfl(lincl, 63, 64);
+                __syncthreads();
+                if (act == 1) {
+                    const uint32_t q = (uint32_t)__popcll(lmask & lt_mask);
+                    q_node[q] = node;
+                    q_pref[q] = lincl - lc;
+                    q_shift[0][q] = shx;
+                    q_shift[1][q] = shy;
+                    q_shift[2][q] = shz;
+                }
+                if (lane == 0)
+                    q_pref[nq] = P;
+                __syncthreads();
+                uint32_t done = 0;
+                while (done < P) {
+                    uint32_t space = WALK_LIST - nlist;
+                    if (space == 0) {
+                        flush();
+                        space = WALK_LIST;
+                    }
+                    const uint32_t chunk = (P - done) < space ? (P - done) : space;
+                    for (uint32_t q = lane; q < chunk; q += 64) {
+                        const uint32_t f = done + q;
+                        uint32_t lo = 0, hi2 = nq - 1;
+                        while (lo < hi2) {
+                            uint32_t mid = (lo + hi2 + 1) >> 1;
+                            if (q_pref[mid] <= f)
+                                lo = mid;
+                            else
+                                hi2 = mid - 1;
+                        }
+                        const uint32_t j = A.nd_first[q_node[lo]] + (f - q_pref[lo]);
+                        const double mj = (double)A.mult[j];
+                        sx[nlist + q] = A.x[j] + q_shift[0][lo];
+                        sy[nlist + q] = A.y[j] + q_shift[1][lo];
+                        sz[nlist + q] = A.z[j] + q_shift[2][lo];
+                        sm[nlist + q] = A.m0 * mj;
+                        sh[nlist + q] = A.h0 * cbrt(mj);
+                    }
+                    nlist += chunk;
+                    done += chunk;
+                    __syncthreads();
+                }
+            }
+        }
+        if (overflow) {
+            if (lane == 0)
+                atomicOr(&A.counter[1], 1u);
+        }
+        flush();
+        {
+            uint64_t cnt_pairs = valid ? n_pairs : 0u;
+            for (int o = 32; o >= 1; o >>= 1)
+                cnt_pairs += __shfl_xor(cnt_pairs, o, 64);
+            if (lane == 0)
+                atomicAdd(A.pair_count, (unsigned long long)cnt_pairs);
+        }
+        if (valid) {
+            const double gxv = A.G * ax, gyv = A.G * ay, gzv = A.G * az;
+            if (A.accumulate) {
+                A.gx[i] += gxv;
+                A.gy[i] += gyv;
+                A.gz[i] += gzv;
+            } else {
+                A.gx[i] = gxv;
+                A.gy[i] = gyv;
+                A.gz[i] = gzv;
+            }
+        }
+    }
+}
+
+dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                         const double *y, const double *z, const uint32_t *mult, double *gx,
+                         double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s) {
+    if (n == 0 || ctx->n_groups == 0)
+        return DZS_OK;
+    walk_args A;
+    A.grp_first = ctx->grp_first;
+    A.n_groups = ctx->n_groups;
+    A.x = x; A.y = y; A.z = z; A.mult = mult;
+    A.nd_first = ctx->nd_first; A.nd_count = ctx->nd_count; A.nd_child = ctx->nd_child;
+    A.nd_nchild = ctx->nd_nchild; A.nd_level = ctx->nd_level;
+    A.nd_mass = ctx->nd_mass; A.nd_com = ctx->nd_com; A.nd_bmin = ctx->nd_bmin;
+    A.nd_bmax = ctx->nd_bmax; A.nd_hmax = ctx->nd_hmax;
+    A.cap = ctx->cap_nodes;
+    A.L = box->L;
+    A.halfL = 0.5 * box->L;
+    A.rcut2 = prm->r_cut * prm->r_cut;
+    A.theta2 = prm->theta * prm->theta;
+    A.rs_inv = 1.0 / prm->r_s;
+    A.G = box->G;
+    A.m0 = box->m0;
+    A.h0 = 2.8 * box->eps0;
+    A.gx = gx; A.gy = gy; A.gz = gz;
+    A.accumulate = prm->accumulate;
+    A.stack = ctx->walk_stack;
+    A.depth = (uint32_t)ctx->walk_stack_depth;
+    A.counter = ctx->walk_counter;
+    A.pair_count = (unsigned long long *)(ctx->walk_counter + 8);
+    uint32_t slots = ctx->n_groups < ctx->walk_stack_slots ? ctx->n_groups
+                                                           : (uint32_t)ctx->walk_stack_slots;
+    DZS_HIP(ctx, hipMemsetAsync(ctx->walk_counter, 0, 2 * sizeof(uint32_t), s));
+    {
+        dzs_timed t(ctx, KC_TREE_WALK, s);
+        hipLaunchKernelGGL(k_tree_walk, dim3(slots), dim3(64), 0, s, A);
+        DZS_TRY(dzs_check_launch(ctx, "tree_walk"));
+    }
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 4, ctx->walk_counter + 1, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+    DZS_HIP(ctx, hipStreamSynchronize(s));
+    if (ctx->h_small[4])
+        return dzs_fail(ctx, DZS_ECAPACITY, "tree walk stack overflow (depth %u)", A.depth);
+    return DZS_OK;
+}
