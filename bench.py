@@ -61,7 +61,8 @@ def make_params(dz, W, do_coarsen):
     for s in range(W["n_steps"]):
         sp = dz.step_factors(float(a[s]), float(a[s + 1]), 0.3)
         sp.do_lightcone = 1
-        sp.do_coarsen = 1 if do_coarsen else 0
+        # DZS acts at a step boundary only when another step follows it
+        sp.do_coarsen = 1 if (do_coarsen and s + 1 < W["n_steps"]) else 0
         sp.coarsen.R_lc = math.sqrt(sp.lc.chi2_1)
         sp.coarsen.b = W["b"]
         sp.coarsen.theta = W["theta_dzs"]
