@@ -45,7 +45,7 @@ def workload(n_side=128, L=256.0, ng=256):
     return dict(n_side=n_side, N=n_side ** 3, L=L, ng=ng, r_s=1.25 * L / ng,
                 r_cut=4.5 * 1.25 * L / ng, eps0=lam / 40, m0=dzs_ics.particle_mass(L, n_side ** 3),
                 lam=lam, a_init=1.0 / 50.0, n_steps=50, theta_tree=0.5, theta_dzs=0.1,
-                b=5 * lam, lmax_over_lambda=2, seed=20050529)
+                b=5 * lam, lmax_over_lambda=2, seed=20050529, leaf=8, group=16)
 
 
 def k_min_for(n_side, j):
@@ -68,7 +68,8 @@ def make_params(dz, W, do_coarsen):
         sp.coarsen.theta = W["theta_dzs"]
         sp.coarsen.k_min = k_min_for(W["n_side"], W["lmax_over_lambda"])
         sp.pm = dz.PMParams(W["ng"], dz.DZS_FP64, W["r_s"], 0, 0)
-        sp.tree = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], 8, 64, dz.DZS_FP64, 0)
+        sp.tree = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"], W["group"],
+                                dz.DZS_FP64, 0)
         out.append(sp)
     return out
 
@@ -118,6 +119,8 @@ def main():
     ap.add_argument("--n-side", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-twin", action="store_true")
+    ap.add_argument("--group", type=int, default=0, help="targets per wave group (power of 2)")
+    ap.add_argument("--leaf", type=int, default=0, help="particles per tree leaf")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -129,6 +132,10 @@ def main():
     import paper_2005_05328_amd as dz
 
     W = workload(n_side=args.n_side, L=256.0 * args.n_side / 128, ng=2 * args.n_side)
+    if args.group:
+        W["group"] = args.group
+    if args.leaf:
+        W["leaf"] = args.leaf
     K = max(1, min(args.steps, W["n_steps"]))
     log(f"workload N={W['N']} L={W['L']} ng={W['ng']} steps={K} warmup={args.warmup}")
     ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
@@ -136,8 +143,8 @@ def main():
     ctx = dz.Context(W["N"], W["ng"])
     st0 = dz.State.from_host(ics)
     ctx.pm_force(box, st0, dz.PMParams(W["ng"], dz.DZS_FP64, W["r_s"], 0, 0))
-    ctx.tree_force(box, st0, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], 8, 64,
-                                           dz.DZS_FP64, 1))
+    ctx.tree_force(box, st0, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"],
+                                           W["group"], dz.DZS_FP64, 1))
     torch.cuda.synchronize()
     params_dzs = make_params(dz, W, True)
     params_std = make_params(dz, W, False)

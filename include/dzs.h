@@ -116,10 +116,11 @@ typedef struct {
  * satisfies l < theta * d (d = distance from the target group's bounding box to the node
  * centre of mass) act as monopoles.  theta = 0 opens every node (exact direct sum). */
 typedef struct {
-    double r_s, r_cut;   /* split scale and cutoff (r_cut < L/2) */
+    double r_s, r_cut;   /* split scale and cutoff (r_cut < L/2, r_cut <= 5 r_s) */
     double theta;        /* opening angle, >= 0 */
     int32_t leaf_size;   /* particles per tree leaf, 1..64 (0 = default 8) */
-    int32_t group_size;  /* targets per wavefront group, 1..64 (0 = default 64) */
+    int32_t group_size;  /* targets per wave64 group, a power of two <= 64 (0 = default
+                            16); each target is served by 64/group_size lanes */
     int32_t precision;   /* DZS_FP64 (plain form) */
     int32_t accumulate;  /* 0: g = g_short, 1: g += g_short */
 } dzs_tree_params;

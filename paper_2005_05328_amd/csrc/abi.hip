@@ -297,11 +297,15 @@ static dzs_status check_tree(dzs_ctx *ctx, const dzs_box *box, const dzs_tree_pa
     if (out->leaf_size == 0)
         out->leaf_size = 8;
     if (out->group_size == 0)
-        out->group_size = 64;
+        out->group_size = 16;
     if (!(t->r_s > 0.0) || !(t->r_cut > 0.0) || !(t->r_cut < 0.5 * box->L) || !(t->theta >= 0.0))
         return dzs_fail(ctx, DZS_EINVAL, "tree: need r_s > 0, 0 < r_cut < L/2, theta >= 0");
-    if (out->leaf_size < 1 || out->leaf_size > 64 || out->group_size < 1 || out->group_size > 64)
-        return dzs_fail(ctx, DZS_EINVAL, "tree: leaf_size and group_size must be in 1..64");
+    if (out->leaf_size < 1 || out->leaf_size > 64 || out->group_size < 1 ||
+        out->group_size > 64 || (out->group_size & (out->group_size - 1)) != 0)
+        return dzs_fail(ctx, DZS_EINVAL,
+                        "tree: leaf_size must be in 1..64, group_size a power of two <= 64");
+    if (t->r_cut > 5.0 * t->r_s)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: r_cut must not exceed 5 r_s");
     if (t->precision != DZS_FP64)
         return dzs_fail(ctx, DZS_EINVAL, "tree: only the FP64 form is available");
     return DZS_OK;

@@ -79,7 +79,10 @@ struct dzs_ctx {
     uint32_t *grp_flag = nullptr, *grp_scan = nullptr, *grp_first = nullptr;
     uint32_t *walk_stack = nullptr;
     uint64_t walk_stack_slots = 0, walk_stack_depth = 0;
-    uint32_t *walk_counter = nullptr;  // [0] work counter, [1] overflow flag
+    uint32_t *walk_counter = nullptr;  // [0] work counter, [1] overflow flag, [8..9] pair count
+    double q_coef[32] = {0};           // split-factor polynomial (see tree.hip)
+    double q_wmax = -1.0;
+    double q_err = 1.0;
     uint32_t level_start[DZS_KEY_BITS + 3] = {0};
     int n_levels = 0;
     uint32_t n_nodes = 0, n_groups = 0;

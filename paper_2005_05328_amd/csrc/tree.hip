@@ -18,7 +18,7 @@
 #include "internal.h"
 
 #define TB_THREADS 256
-#define WALK_LIST 256
+#define WALK_LIST 128
 #define WALK_DEPTH 8192u
 #define WALK_SLOTS_MAX 4096u
 
@@ -303,7 +303,21 @@ dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const 
 
 // ---------------------------------------------------------------------------------------
 // walk + pair evaluation (FP64)
+//
+// Lane layout: a wave holds G = 64/P targets; lane = t + G*s serves target t and evaluates
+// every P-th list entry starting at s, so a group of G targets is served by all 64 lanes and
+// a smaller G wastes fewer evaluations on sources inside the group's cutoff region but
+// outside the target's cutoff sphere.  The P partial sums of a target are added in a fixed
+// order at the end (deterministic).
+//
+// Split factor: S(u) = erfc(u/2) + u/sqrt(pi) exp(-u^2/4) = 1 - u w q(w), w = u^2, where
+// q(w) = (erf(u/2) - u/sqrt(pi) e^{-u^2/4}) / u^3 is an entire function of w.  The host fits q
+// on [0, (r_cut/r_s)^2] by a Chebyshev series (from its Taylor series in long double) and
+// passes the monomial coefficients in t = 2 w / w_max - 1; the kernel evaluates it by Horner.
+// The fit is checked on the host to 1e-12 relative error in S.
 // ---------------------------------------------------------------------------------------
+#define WALK_QN 20  // split-factor polynomial coefficients (Horner, fully unrolled)
+
 struct walk_args {
     const uint32_t *grp_first;
     uint32_t n_groups;
@@ -313,13 +327,15 @@ struct walk_args {
     const uint8_t *nd_nchild, *nd_level;
     const double *nd_mass, *nd_com, *nd_bmin, *nd_bmax, *nd_hmax;
     uint64_t cap;
-    double L, halfL, rcut2, theta2, rs_inv, G, m0, h0;
+    double L, halfL, rcut2, rcut, theta2, rs_inv, rs_inv2, G, m0, h0, t_scale;
     double *gx, *gy, *gz;
     int accumulate;
+    int G_lanes;  // targets per wave (64 / phases)
     uint32_t *stack;
     uint32_t depth;
     uint32_t *counter;  // [0] next group, [1] overflow flag
     unsigned long long *pair_count;
+    double q[WALK_QN];
 };
 
 // Cubic-spline softened 1/r^3 (enclosed-mass force / r), r < h.
@@ -328,22 +344,76 @@ __device__ __forceinline__ double gsoft_inner(double r, double h) {
     const double u = r * hinv;
     const double h3 = hinv * hinv * hinv;
     if (u < 0.5)
-        return h3 * (10.666666666666666 + u * u * (32.0 * u - 38.4));
-    return h3 * (21.333333333333332 - 48.0 * u + 38.4 * u * u - 10.666666666666666 * u * u * u -
-                 0.066666666666666666 / (u * u * u));
+        return h3 * (32.0 / 3.0 + u * u * (32.0 * u - 192.0 / 5.0));
+    return h3 * (64.0 / 3.0 - 48.0 * u + 192.0 / 5.0 * u * u - 32.0 / 3.0 * u * u * u -
+                 1.0 / (15.0 * u * u * u));
+}
+
+// One interaction-list entry in LDS: position (shifted to the image nearest the group),
+// mass, spline support; 48 bytes, read as two 16-byte and one 8-byte LDS load.
+struct src_entry {
+    double x, y, z, m;
+    double h, pad;
+};
+
+template <bool MINIMG>
+__device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry *src,
+                                          uint32_t nlist, uint32_t s, uint32_t P, double xi,
+                                          double yi, double zi, double hi, double &ax,
+                                          double &ay, double &az, uint32_t &n_pairs) {
+    for (uint32_t jj = 0; jj < nlist; jj += P) {
+        const uint32_t j = jj + s;
+        if (j >= nlist)
+            break;
+        const double2 xy = *(const double2 *)&src[j].x;
+        const double2 zm = *(const double2 *)&src[j].z;
+        double dx = xy.x - xi, dy = xy.y - yi, dz = zm.x - zi;
+        if (MINIMG) {
+            dx = dzs_min_image(dx, A.L);
+            dy = dzs_min_image(dy, A.L);
+            dz = dzs_min_image(dz, A.L);
+        }
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < A.rcut2 && r2 > 0.0) {
+            ++n_pairs;
+            const double rinv = rsqrt(r2);
+            const double w = r2 * A.rs_inv2;
+            const double t = fma(w, A.t_scale, -1.0);
+            double q = A.q[WALK_QN - 1];
+#pragma unroll
+            for (int k = WALK_QN - 2; k >= 0; --k)
+                q = fma(q, t, A.q[k]);
+            const double u = r2 * rinv * A.rs_inv;
+            const double S = 1.0 - u * w * q;
+            const double h = fmax(src[j].h, hi);
+            double ker = rinv * rinv * rinv;
+            if (r2 < h * h)
+                ker = gsoft_inner(r2 * rinv, h);
+            const double f = zm.y * ker * S;
+            ax = fma(f, dx, ax);
+            ay = fma(f, dy, ay);
+            az = fma(f, dz, az);
+        }
+    }
 }
 
 __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
-    __shared__ double sx[WALK_LIST], sy[WALK_LIST], sz[WALK_LIST], sm[WALK_LIST], sh[WALK_LIST];
+    __shared__ src_entry src[WALK_LIST];
     __shared__ uint32_t q_node[64];
     __shared__ uint32_t q_pref[65];
     __shared__ double q_shift[3][64];
     __shared__ uint32_t s_g;
 
     const uint32_t lane = threadIdx.x;
+    const uint32_t G = (uint32_t)A.G_lanes;
+    const uint32_t P = 64u / G;
+    const uint32_t tl = lane % G, ph = lane / G;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t *stk = A.stack + (uint64_t)blockIdx.x * A.depth;
-    const double inv_sqrt_pi = 0.56418958354775628;
+    // a source node and the group may be wide enough that the image nearest the group centre
+    // is not every pair's nearest image; above this half-extent sum the pair loop reduces
+    // each separation to the minimum image
+    const double wide_limit = A.halfL - A.rcut;
 
     for (;;) {
         if (lane == 0)
@@ -355,8 +425,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             break;
         const uint32_t first = A.grp_first[g];
         const uint32_t cnt = A.grp_first[g + 1] - first;
-        const bool valid = lane < cnt;
-        const uint32_t i = valid ? first + lane : first;
+        const bool valid = tl < cnt;
+        const uint32_t i = valid ? first + tl : first;
         const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
         const double hi = A.h0 * cbrt((double)A.mult[i]);
         // group bounding box
@@ -371,34 +441,19 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         }
         const double gcx = 0.5 * (mnx + mxx), gcy = 0.5 * (mny + mxy), gcz = 0.5 * (mnz + mxz);
         const double ghx = 0.5 * (mxx - mnx), ghy = 0.5 * (mxy - mny), ghz = 0.5 * (mxz - mnz);
+        const double ghmax = fmax(ghx, fmax(ghy, ghz));
 
         double ax = 0.0, ay = 0.0, az = 0.0;
         uint32_t nlist = 0;
-        uint32_t n_pairs = 0;  // interactions inside the cutoff (algorithmic work)
+        uint32_t n_pairs = 0;
+        bool wide = false;
 
         auto flush = [&]() {
             __syncthreads();
-            for (uint32_t j = 0; j < nlist; ++j) {
-                // sources were shifted to the image nearest the group's centre; for groups
-                // or leaves wide compared with L/2 - r_cut that is not every pair's nearest
-                // image, so the separation is reduced to the minimum image here as well
-                const double dx = dzs_min_image(sx[j] - xi, A.L);
-                const double dy = dzs_min_image(sy[j] - yi, A.L);
-                const double dz = dzs_min_image(sz[j] - zi, A.L);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < A.rcut2 && r2 > 0.0) {
-                    ++n_pairs;
-                    const double r = sqrt(r2);
-                    const double u = r * A.rs_inv;
-                    const double S = erfc(0.5 * u) + u * inv_sqrt_pi * exp(-0.25 * u * u);
-                    const double h = fmax(sh[j], hi);
-                    const double f = r >= h ? 1.0 / (r2 * r) : gsoft_inner(r, h);
-                    const double w = sm[j] * f * S;
-                    ax += w * dx;
-                    ay += w * dy;
-                    az += w * dz;
-                }
-            }
+            if (wide)
+                pair_loop<true>(A, src, nlist, ph, P, xi, yi, zi, hi, ax, ay, az, n_pairs);
+            else
+                pair_loop<false>(A, src, nlist, ph, P, xi, yi, zi, hi, ax, ay, az, n_pairs);
             nlist = 0;
             __syncthreads();
         };
@@ -417,6 +472,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             int act = 0;
             double shx = 0.0, shy = 0.0, shz = 0.0;
             uint32_t ncount = 0, nchild = 0, child = 0;
+            bool node_wide = false;
             if (has) {
                 const uint64_t c = A.cap;
                 const double bnx = A.nd_bmin[node], bny = A.nd_bmin[c + node], bnz = A.nd_bmin[2 * c + node];
@@ -427,10 +483,12 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 shy = dcy > A.halfL ? -A.L : (dcy < -A.halfL ? A.L : 0.0);
                 shz = dcz > A.halfL ? -A.L : (dcz < -A.halfL ? A.L : 0.0);
                 dcx += shx; dcy += shy; dcz += shz;
-                const double gx_ = fmax(0.0, fabs(dcx) - 0.5 * (bxx - bnx) - ghx);
-                const double gy_ = fmax(0.0, fabs(dcy) - 0.5 * (bxy - bny) - ghy);
-                const double gz_ = fmax(0.0, fabs(dcz) - 0.5 * (bxz - bnz) - ghz);
+                const double nhx = 0.5 * (bxx - bnx), nhy = 0.5 * (bxy - bny), nhz = 0.5 * (bxz - bnz);
+                const double gx_ = fmax(0.0, fabs(dcx) - nhx - ghx);
+                const double gy_ = fmax(0.0, fabs(dcy) - nhy - ghy);
+                const double gz_ = fmax(0.0, fabs(dcz) - nhz - ghz);
                 const double dist2 = gx_ * gx_ + gy_ * gy_ + gz_ * gz_;
+                node_wide = fmax(nhx, fmax(nhy, nhz)) + ghmax > wide_limit;
                 nchild = A.nd_nchild[node];
                 ncount = A.nd_count[node];
                 if (dist2 >= A.rcut2) {
@@ -454,6 +512,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                     child = A.nd_child[node];
                 }
             }
+            if (__ballot((act == 1 || act == 2) && node_wide) != 0ull)
+                wide = true;
             // ---- pushes
             const uint32_t npush = act == 3 ? nchild : 0u;
             const uint32_t pincl = dzs_wave_incl_scan(npush);
@@ -475,11 +535,11 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 if (act == 2) {
                     const uint32_t slot = nlist + (uint32_t)__popcll(mono & lt_mask);
                     const uint64_t c = A.cap;
-                    sx[slot] = A.nd_com[node] + shx;
-                    sy[slot] = A.nd_com[c + node] + shy;
-                    sz[slot] = A.nd_com[2 * c + node] + shz;
-                    sm[slot] = A.nd_mass[node];
-                    sh[slot] = A.nd_hmax[node];
+                    src[slot].x = A.nd_com[node] + shx;
+                    src[slot].y = A.nd_com[c + node] + shy;
+                    src[slot].z = A.nd_com[2 * c + node] + shz;
+                    src[slot].m = A.nd_mass[node];
+                    src[slot].h = A.nd_hmax[node];
                 }
                 nlist += nmono;
             }
@@ -489,7 +549,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             if (nq > 0) {
                 const uint32_t lc = act == 1 ? ncount : 0u;
                 const uint32_t lincl = dzs_wave_incl_scan(lc);
-                const uint32_t P = __shfl(lincl, 63, 64);
+                const uint32_t Ptot = __shfl(lincl, 63, 64);
                 __syncthreads();
                 if (act == 1) {
                     const uint32_t q = (uint32_t)__popcll(lmask & lt_mask);
@@ -500,16 +560,16 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                     q_shift[2][q] = shz;
                 }
                 if (lane == 0)
-                    q_pref[nq] = P;
+                    q_pref[nq] = Ptot;
                 __syncthreads();
                 uint32_t done = 0;
-                while (done < P) {
+                while (done < Ptot) {
                     uint32_t space = WALK_LIST - nlist;
                     if (space == 0) {
                         flush();
                         space = WALK_LIST;
                     }
-                    const uint32_t chunk = (P - done) < space ? (P - done) : space;
+                    const uint32_t chunk = (Ptot - done) < space ? (Ptot - done) : space;
                     for (uint32_t q = lane; q < chunk; q += 64) {
                         const uint32_t f = done + q;
                         uint32_t lo = 0, hi2 = nq - 1;
@@ -522,11 +582,12 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                         }
                         const uint32_t j = A.nd_first[q_node[lo]] + (f - q_pref[lo]);
                         const double mj = (double)A.mult[j];
-                        sx[nlist + q] = A.x[j] + q_shift[0][lo];
-                        sy[nlist + q] = A.y[j] + q_shift[1][lo];
-                        sz[nlist + q] = A.z[j] + q_shift[2][lo];
-                        sm[nlist + q] = A.m0 * mj;
-                        sh[nlist + q] = A.h0 * cbrt(mj);
+                        src_entry &e = src[nlist + q];
+                        e.x = A.x[j] + q_shift[0][lo];
+                        e.y = A.y[j] + q_shift[1][lo];
+                        e.z = A.z[j] + q_shift[2][lo];
+                        e.m = A.m0 * mj;
+                        e.h = A.h0 * cbrt(mj);
                     }
                     nlist += chunk;
                     done += chunk;
@@ -539,6 +600,12 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 atomicOr(&A.counter[1], 1u);
         }
         flush();
+        // fixed-order sum of the P partial accelerations of each target
+        for (uint32_t o = G; o < 64; o <<= 1) {
+            ax += __shfl_xor(ax, o, 64);
+            ay += __shfl_xor(ay, o, 64);
+            az += __shfl_xor(az, o, 64);
+        }
         {
             uint64_t cnt_pairs = valid ? n_pairs : 0u;
             for (int o = 32; o >= 1; o >>= 1)
@@ -546,7 +613,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             if (lane == 0)
                 atomicAdd(A.pair_count, (unsigned long long)cnt_pairs);
         }
-        if (valid) {
+        if (valid && ph == 0) {
             const double gxv = A.G * ax, gyv = A.G * ay, gzv = A.G * az;
             if (A.accumulate) {
                 A.gx[i] += gxv;
@@ -561,12 +628,95 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     }
 }
 
+// ---- host: the split-factor polynomial ------------------------------------------------
+namespace {
+
+// q(w) = (erf(u/2) - u/sqrt(pi) exp(-u^2/4)) / u^3 from its Taylor series:
+// q(w) = (1/sqrt(pi)) sum_{n>=1} (-1)^(n+1) 2n w^(n-1) / ((2n+1) 4^n n!)
+long double q_taylor(long double w) {
+    const long double inv_sqrt_pi = 0.564189583547756286948079451560772586L;
+    long double term = 1.0L;  // w^(n-1) / (4^n n!) * 4, starts at n = 1 as 1/4 * 4 ... kept as ratio
+    long double sum = 0.0L;
+    long double pw = 1.0L;     // w^(n-1)
+    long double fac = 1.0L;    // 4^n n!
+    for (int n = 1; n < 200; ++n) {
+        fac *= 4.0L * n;
+        term = (n % 2 ? 1.0L : -1.0L) * 2.0L * n * pw / ((2.0L * n + 1.0L) * fac);
+        sum += term;
+        if (n > 4 && fabsl(term) < 1e-24L * fabsl(sum))
+            break;
+        pw *= w;
+    }
+    return sum * inv_sqrt_pi;
+}
+
+// Chebyshev fit of q on [0, wmax] with n coefficients, converted to monomials in t.
+void fit_q(long double wmax, int n, long double *mono) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    long double f[WALK_QN], c[WALK_QN];
+    for (int j = 0; j < n; ++j) {
+        long double t = cosl(pi * (j + 0.5L) / n);
+        f[j] = q_taylor(0.5L * (t + 1.0L) * wmax);
+    }
+    for (int k = 0; k < n; ++k) {
+        long double s = 0.0L;
+        for (int j = 0; j < n; ++j)
+            s += f[j] * cosl(pi * k * (j + 0.5L) / n);
+        c[k] = s * (k == 0 ? 1.0L : 2.0L) / n;
+    }
+    // T_k as monomial vectors: T_0 = 1, T_1 = t, T_{k+1} = 2 t T_k - T_{k-1}
+    long double Tm[WALK_QN], T0[WALK_QN], T1[WALK_QN];
+    for (int i = 0; i < n; ++i)
+        mono[i] = T0[i] = T1[i] = 0.0L;
+    T0[0] = 1.0L;
+    T1[1 < n ? 1 : 0] += (n > 1) ? 1.0L : 0.0L;
+    for (int i = 0; i < n; ++i)
+        mono[i] += c[0] * T0[i];
+    if (n > 1)
+        for (int i = 0; i < n; ++i)
+            mono[i] += c[1] * T1[i];
+    for (int k = 2; k < n; ++k) {
+        for (int i = 0; i < n; ++i)
+            Tm[i] = -T0[i] + (i > 0 ? 2.0L * T1[i - 1] : 0.0L);
+        for (int i = 0; i < n; ++i) {
+            mono[i] += c[k] * Tm[i];
+            T0[i] = T1[i];
+            T1[i] = Tm[i];
+        }
+    }
+}
+
+}  // namespace
+
+// The WALK_QN-coefficient fit and its worst relative error in S on [0, wmax].
+static double split_poly(double wmax, double *q) {
+    long double mono[WALK_QN];
+    fit_q(wmax, WALK_QN, mono);
+    long double worst = 0.0L;
+    for (int k = 0; k <= 800; ++k) {
+        long double w = wmax * k / 800.0L;
+        long double t = 2.0L * w / wmax - 1.0L;
+        long double qa = 0.0L;
+        for (int i = WALK_QN - 1; i >= 0; --i)
+            qa = qa * t + mono[i];
+        long double qe = q_taylor(w);
+        long double u = sqrtl(w);
+        long double S = 1.0L - u * w * qe;
+        long double err = fabsl(u * w * (qa - qe)) / fabsl(S);
+        worst = err > worst ? err : worst;
+    }
+    for (int i = 0; i < WALK_QN; ++i)
+        q[i] = (double)mono[i];
+    return (double)worst;
+}
+
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
                          double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s) {
     if (n == 0 || ctx->n_groups == 0)
         return DZS_OK;
     walk_args A;
+    memset(&A, 0, sizeof(A));
     A.grp_first = ctx->grp_first;
     A.n_groups = ctx->n_groups;
     A.x = x; A.y = y; A.z = z; A.mult = mult;
@@ -577,14 +727,28 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
     A.cap = ctx->cap_nodes;
     A.L = box->L;
     A.halfL = 0.5 * box->L;
+    A.rcut = prm->r_cut;
     A.rcut2 = prm->r_cut * prm->r_cut;
     A.theta2 = prm->theta * prm->theta;
     A.rs_inv = 1.0 / prm->r_s;
+    A.rs_inv2 = A.rs_inv * A.rs_inv;
     A.G = box->G;
     A.m0 = box->m0;
     A.h0 = 2.8 * box->eps0;
     A.gx = gx; A.gy = gy; A.gz = gz;
     A.accumulate = prm->accumulate;
+    A.G_lanes = prm->group_size;
+    const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
+    if (ctx->q_wmax != wmax) {
+        ctx->q_err = split_poly(wmax, ctx->q_coef);
+        ctx->q_wmax = wmax;
+    }
+    if (!(ctx->q_err < 1e-10))
+        return dzs_fail(ctx, DZS_EINVAL, "tree: split-factor fit error %.2e for r_cut/r_s = %.3f",
+                        ctx->q_err, sqrt(wmax));
+    for (int k = 0; k < WALK_QN; ++k)
+        A.q[k] = ctx->q_coef[k];
+    A.t_scale = 2.0 / wmax;
     A.stack = ctx->walk_stack;
     A.depth = (uint32_t)ctx->walk_stack_depth;
     A.counter = ctx->walk_counter;

@@ -207,21 +207,22 @@ def test_pm_force_matches_oracle(dz, ctx, kind, n):
     assert np.array_equal(st.gx[: ps.n].cpu().numpy(), g[0])
 
 
-@pytest.mark.parametrize("kind,n,theta,tol", [("clustered", 20000, 0.0, 1e-10),
-                                              ("merged", 30001, 0.0, 1e-10),
-                                              ("zeldovich", 32768, 0.0, 1e-10),
-                                              ("clustered", 20000, 0.5, 5e-3),
-                                              ("merged", 30001, 0.5, 5e-3)])
-def test_tree_force_matches_direct_sum(dz, ctx, kind, n, theta, tol):
+@pytest.mark.parametrize("kind,n,theta,tol,gsize", [("clustered", 20000, 0.0, 1e-10, 64),
+                                                    ("merged", 30001, 0.0, 1e-10, 16),
+                                                    ("zeldovich", 32768, 0.0, 1e-10, 8),
+                                                    ("clustered", 20000, 0.0, 1e-10, 32),
+                                                    ("clustered", 20000, 0.5, 5e-3, 16),
+                                                    ("merged", 30001, 0.5, 5e-3, 64)])
+def test_tree_force_matches_direct_sum(dz, ctx, kind, n, theta, tol, gsize):
     import torch
     L, ng = 100.0, 64
     r_s = 1.25 * L / ng
     r_cut = 4.5 * r_s
     ps = _force_case(kind, n, L, 21)
-    _log(f"tree kind={kind} n={ps.n} theta={theta}")
+    _log(f"tree kind={kind} n={ps.n} theta={theta} group={gsize}")
     box, obox = _box(dz, L, ps.n, 32)
     st = dz.State.from_host(ps)
-    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, theta, 8, 64, dz.DZS_FP64, 0))
+    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, theta, 8, gsize, dz.DZS_FP64, 0))
     torch.cuda.synchronize()
     g = np.stack([st.gx[: ps.n].cpu().numpy(), st.gy[: ps.n].cpu().numpy(),
                   st.gz[: ps.n].cpu().numpy()])
@@ -229,7 +230,7 @@ def test_tree_force_matches_direct_sum(dz, ctx, kind, n, theta, tol):
     err = _rms_rel(g, ref)
     _log(f"  tree rms rel err {err:.3e}")
     assert err <= tol
-    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, theta, 8, 64, dz.DZS_FP64, 0))
+    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, theta, 8, gsize, dz.DZS_FP64, 0))
     torch.cuda.synchronize()
     assert np.array_equal(st.gx[: ps.n].cpu().numpy(), g[0])
 
