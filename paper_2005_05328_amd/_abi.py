@@ -86,6 +86,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libdzs.so not found at {LIB_PATH}: build it with "
                           "`python -m paper_2005_05328_amd.build` (the GPU path has no fallback)")
+    # torch ships its own HIP runtime under the same soname as /opt/rocm's; the first one loaded
+    # serves the whole process, so torch is imported before the library resolves its runtime
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, i32, st = C.c_void_p, C.c_int32, C.c_int32
     L.dzs_ctx_create.argtypes = [C.POINTER(P), i32, C.POINTER(Capacity)]

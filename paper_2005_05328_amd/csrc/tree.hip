@@ -402,6 +402,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     __shared__ uint32_t q_node[64];
     __shared__ uint32_t q_pref[65];
     __shared__ double q_shift[3][64];
+    __shared__ uint32_t q_wide[64];
     __shared__ uint32_t s_g;
 
     const uint32_t lane = threadIdx.x;
@@ -543,7 +544,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 }
                 nlist += nmono;
             }
-            // ---- leaves: queue, then stream their particles into the list
+            // ---- leaves: queue, then stream their particles into the list, keeping only the
+            //      particles within r_cut of the group's bounding box
             const uint64_t lmask = __ballot(act == 1);
             const uint32_t nq = (uint32_t)__popcll(lmask);
             if (nq > 0) {
@@ -558,20 +560,17 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                     q_shift[0][q] = shx;
                     q_shift[1][q] = shy;
                     q_shift[2][q] = shz;
+                    q_wide[q] = node_wide ? 1u : 0u;
                 }
                 if (lane == 0)
                     q_pref[nq] = Ptot;
                 __syncthreads();
-                uint32_t done = 0;
-                while (done < Ptot) {
-                    uint32_t space = WALK_LIST - nlist;
-                    if (space == 0) {
-                        flush();
-                        space = WALK_LIST;
-                    }
-                    const uint32_t chunk = (Ptot - done) < space ? (Ptot - done) : space;
-                    for (uint32_t q = lane; q < chunk; q += 64) {
-                        const uint32_t f = done + q;
+                for (uint32_t done = 0; done < Ptot; done += 64) {
+                    const uint32_t f = done + lane;
+                    bool keep = false;
+                    double ex_ = 0.0, ey_ = 0.0, ez_ = 0.0;
+                    uint32_t mj = 0;
+                    if (f < Ptot) {
                         uint32_t lo = 0, hi2 = nq - 1;
                         while (lo < hi2) {
                             uint32_t mid = (lo + hi2 + 1) >> 1;
@@ -581,18 +580,33 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                                 hi2 = mid - 1;
                         }
                         const uint32_t j = A.nd_first[q_node[lo]] + (f - q_pref[lo]);
-                        const double mj = (double)A.mult[j];
-                        src_entry &e = src[nlist + q];
-                        e.x = A.x[j] + q_shift[0][lo];
-                        e.y = A.y[j] + q_shift[1][lo];
-                        e.z = A.z[j] + q_shift[2][lo];
-                        e.m = A.m0 * mj;
-                        e.h = A.h0 * cbrt(mj);
+                        ex_ = A.x[j] + q_shift[0][lo];
+                        ey_ = A.y[j] + q_shift[1][lo];
+                        ez_ = A.z[j] + q_shift[2][lo];
+                        mj = A.mult[j];
+                        const double cx = fmax(0.0, fabs(ex_ - gcx) - ghx);
+                        const double cy = fmax(0.0, fabs(ey_ - gcy) - ghy);
+                        const double cz = fmax(0.0, fabs(ez_ - gcz) - ghz);
+                        keep = q_wide[lo] != 0u || cx * cx + cy * cy + cz * cz < A.rcut2;
                     }
-                    nlist += chunk;
-                    done += chunk;
-                    __syncthreads();
+                    const uint64_t kmask = __ballot(keep);
+                    const uint32_t nk = (uint32_t)__popcll(kmask);
+                    if (nk > 0) {
+                        if (nlist + nk > WALK_LIST)
+                            flush();
+                        if (keep) {
+                            src_entry &e = src[nlist + (uint32_t)__popcll(kmask & lt_mask)];
+                            const double md = (double)mj;
+                            e.x = ex_;
+                            e.y = ey_;
+                            e.z = ez_;
+                            e.m = A.m0 * md;
+                            e.h = A.h0 * cbrt(md);
+                        }
+                        nlist += nk;
+                    }
                 }
+                __syncthreads();
             }
         }
         if (overflow) {
