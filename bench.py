@@ -45,7 +45,7 @@ def workload(n_side=128, L=256.0, ng=256):
     return dict(n_side=n_side, N=n_side ** 3, L=L, ng=ng, r_s=1.25 * L / ng,
                 r_cut=4.5 * 1.25 * L / ng, eps0=lam / 40, m0=dzs_ics.particle_mass(L, n_side ** 3),
                 lam=lam, a_init=1.0 / 50.0, n_steps=50, theta_tree=0.5, theta_dzs=0.1,
-                b=5 * lam, lmax_over_lambda=2, seed=20050529, leaf=8, group=16)
+                b=5 * lam, lmax_over_lambda=2, seed=20050529, leaf=16, group=32)
 
 
 def k_min_for(n_side, j):
