@@ -30,6 +30,7 @@ METRIC = "particle force updates/sec on 1 GPU; DZS vs full-res wall time at equa
 UNIT = "particle force updates/s"
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 FLOP_PER_INTERACTION = 24
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -67,9 +68,9 @@ def make_params(dz, W, do_coarsen):
         sp.coarsen.b = W["b"]
         sp.coarsen.theta = W["theta_dzs"]
         sp.coarsen.k_min = k_min_for(W["n_side"], W["lmax_over_lambda"])
-        sp.pm = dz.PMParams(W["ng"], dz.DZS_FP64, W["r_s"], 0, 0)
+        sp.pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, 0)
         sp.tree = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"], W["group"],
-                                dz.DZS_FP64, 0)
+                                W["prec"], 0)
         out.append(sp)
     return out
 
@@ -121,6 +122,8 @@ def main():
     ap.add_argument("--no-twin", action="store_true")
     ap.add_argument("--group", type=int, default=0, help="targets per wave group (power of 2)")
     ap.add_argument("--leaf", type=int, default=0, help="particles per tree leaf")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="fp64: plain form; fp32: FP32 pair, mesh and FFT arithmetic")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -136,15 +139,16 @@ def main():
         W["group"] = args.group
     if args.leaf:
         W["leaf"] = args.leaf
+    W["prec"] = dz.DZS_FP32 if args.precision == "fp32" else dz.DZS_FP64
     K = max(1, min(args.steps, W["n_steps"]))
     log(f"workload N={W['N']} L={W['L']} ng={W['ng']} steps={K} warmup={args.warmup}")
     ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
     box = dz.make_box(W["L"], W["m0"], W["eps0"])
     ctx = dz.Context(W["N"], W["ng"])
     st0 = dz.State.from_host(ics)
-    ctx.pm_force(box, st0, dz.PMParams(W["ng"], dz.DZS_FP64, W["r_s"], 0, 0))
+    ctx.pm_force(box, st0, dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, 0))
     ctx.tree_force(box, st0, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"],
-                                           W["group"], dz.DZS_FP64, 1))
+                                           W["group"], W["prec"], 1))
     torch.cuda.synchronize()
     params_dzs = make_params(dz, W, True)
     params_std = make_params(dz, W, False)
@@ -189,11 +193,13 @@ def main():
     totals = {c: ms * calls for c, (ms, calls) in kern.items() if calls}
     dom = max(totals, key=totals.get)
     avg_ms, calls = kern[dom]
+    fp32 = W["prec"] == dz.DZS_FP32
     if dom == "tree_walk":
         flops = FLOP_PER_INTERACTION * pairs / calls
         achieved = flops / (avg_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+        peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+        roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
+                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                     "kernel": dom, "avg_ms": avg_ms,
                     "work_per_launch": f"{pairs / calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP"}
     else:
@@ -214,11 +220,14 @@ def main():
     out = {
         "metric": METRIC, "value": N * K / t_dzs, "unit": UNIT, "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if fp32 else "f64",
+        "data": "synthetic",
         "config": {"workload": (f"{W['n_side']}^3 particles, L={W['L']:g} Mpc/h, mesh "
                                 f"{W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, "
                                 f"{K} of 50 log KDK steps to z=0, DZS 2x2x2 + lightcone, "
-                                f"tree theta {W['theta_tree']}, FP64 plain form"),
+                                f"tree theta {W['theta_tree']}, "
+                                + ("precision form (FP32 pair/mesh/FFT, FP64 state)" if fp32
+                                   else "FP64 plain form")),
                    "particles": N, "mesh": W["ng"], "box": W["L"], "parallelism": "1 GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "dzs_twin": twin,
         "pair_interactions_per_step": pairs / K, "lightcone_records": n_records,

@@ -98,14 +98,18 @@ typedef struct {
 } dzs_coarsen_report;
 
 #define DZS_FP64 0        /* plain form: every step in FP64 */
-#define DZS_FP32 1        /* precision form: pair and mesh arithmetic in FP32 */
+#define DZS_FP32 1        /* precision form: pair, mesh and FFT arithmetic in FP32 with FP32
+                             accumulation; positions, momenta, the stored force, the
+                             deposit (fixed point), kicks, drifts, crossing times and merge
+                             sums stay FP64 */
 
 /* PM (long-range) parameters: mesh points at j*Delta, Delta = L/ng; cloud-in-cell
  * assignment; Green's function -4 pi G exp(-k^2 r_s^2) / (k^2 W(k)^2) with the CIC window
  * W deconvolved twice; 4-point finite-difference gradient; CIC interpolation. */
 typedef struct {
     int32_t ng;          /* mesh side */
-    int32_t precision;   /* DZS_FP64 (the only form implemented for the mesh so far) */
+    int32_t precision;   /* DZS_FP64, or DZS_FP32: FFT, Green's function product, gradient
+                            and interpolation in FP32 (rms error ~1e-6 of the force) */
     double r_s;          /* split scale */
     int32_t accumulate;  /* 0: g = g_long, 1: g += g_long */
     int32_t reserved;
@@ -121,7 +125,11 @@ typedef struct {
     int32_t leaf_size;   /* particles per tree leaf, 1..64 (0 = default 8) */
     int32_t group_size;  /* targets per wave64 group, a power of two <= 64 (0 = default
                             16); each target is served by 64/group_size lanes */
-    int32_t precision;   /* DZS_FP64 (plain form) */
+    int32_t precision;   /* DZS_FP64, or DZS_FP32: interaction list and pair arithmetic in
+                            FP32 on coordinates relative to the group centre (rms error
+                            ~1e-6; a pair within FP32 rounding of r_cut may be kept or
+                            dropped, a jump of G m S(r_cut/r_s)/r_cut^2 in that target's
+                            force) */
     int32_t accumulate;  /* 0: g = g_short, 1: g += g_short */
 } dzs_tree_params;
 

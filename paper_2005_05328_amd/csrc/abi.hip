@@ -306,8 +306,8 @@ static dzs_status check_tree(dzs_ctx *ctx, const dzs_box *box, const dzs_tree_pa
                         "tree: leaf_size must be in 1..64, group_size a power of two <= 64");
     if (t->r_cut > 5.0 * t->r_s)
         return dzs_fail(ctx, DZS_EINVAL, "tree: r_cut must not exceed 5 r_s");
-    if (t->precision != DZS_FP64)
-        return dzs_fail(ctx, DZS_EINVAL, "tree: only the FP64 form is available");
+    if (t->precision != DZS_FP64 && t->precision != DZS_FP32)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: precision must be DZS_FP64 or DZS_FP32");
     return DZS_OK;
 }
 
@@ -321,8 +321,8 @@ static dzs_status check_pm(dzs_ctx *ctx, const dzs_pm_params *m) {
                         ctx->cap_ng);
     if (!(m->r_s > 0.0))
         return dzs_fail(ctx, DZS_EINVAL, "pm: r_s must be positive");
-    if (m->precision != DZS_FP64)
-        return dzs_fail(ctx, DZS_EINVAL, "pm: only the FP64 form is available");
+    if (m->precision != DZS_FP64 && m->precision != DZS_FP32)
+        return dzs_fail(ctx, DZS_EINVAL, "pm: precision must be DZS_FP64 or DZS_FP32");
     return DZS_OK;
 }
 

@@ -83,6 +83,8 @@ struct dzs_ctx {
     double q_coef[32] = {0};           // split-factor polynomial (see tree.hip)
     double q_wmax = -1.0;
     double q_err = 1.0;
+    float qf_coef[16] = {0};           // its FP32 fit (precision form)
+    double qf_err = 1.0;
     uint32_t level_start[DZS_KEY_BITS + 3] = {0};
     int n_levels = 0;
     uint32_t n_nodes = 0, n_groups = 0;

@@ -37,33 +37,35 @@ struct fft_plan {
 // ---------------------------------------------------------------------------------------
 // LDS line FFT
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// C is double2 (plain form) or float2 (precision form); R its component type.
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
 
-template <int R, bool INV>
-__device__ __forceinline__ void dft_small(double2 *v) {
+template <int R, bool INV, typename C>
+__device__ __forceinline__ void dft_small(C *v) {
+    typedef decltype(v[0].x) Rt;
     if (R == 2) {
-        double2 a = v[0], b = v[1];
+        C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     } else if (R == 4) {
-        double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-        double2 c = cadd(v[1], v[3]), t = csub(v[1], v[3]);
+        C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        C c = cadd(v[1], v[3]), t = csub(v[1], v[3]);
         // forward: t * (-i) = (t.y, -t.x); inverse: t * (+i) = (-t.y, t.x)
-        double2 d = INV ? make_double2(-t.y, t.x) : make_double2(t.y, -t.x);
+        C d = INV ? C{-t.y, t.x} : C{t.y, -t.x};
         v[0] = cadd(a, c);
         v[1] = cadd(b, d);
         v[2] = csub(a, c);
         v[3] = csub(b, d);
     } else {  // R == 3
-        const double s3 = 0.86602540378443865;  // sqrt(3)/2
-        double2 t = cadd(v[1], v[2]), s = csub(v[1], v[2]);
-        double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+        const Rt s3 = Rt(0.86602540378443865);  // sqrt(3)/2
+        C t = cadd(v[1], v[2]), s = csub(v[1], v[2]);
+        C m = C{v[0].x - Rt(0.5) * t.x, v[0].y - Rt(0.5) * t.y};
         // forward: X1 = m - i s3 s, X2 = m + i s3 s ; inverse swaps the sign of i
-        double2 is = INV ? make_double2(-s3 * s.y, s3 * s.x) : make_double2(s3 * s.y, -s3 * s.x);
+        C is = INV ? C{-s3 * s.y, s3 * s.x} : C{s3 * s.y, -s3 * s.x};
         v[0] = cadd(v[0], t);
         v[1] = cadd(m, is);
         v[2] = csub(m, is);
@@ -73,13 +75,12 @@ __device__ __forceinline__ void dft_small(double2 *v) {
 // One Stockham stage over TL lines held in LDS.  Element e of line l lives at
 // buf[e * se + l * sl].  All loads of the stage complete before any store (barrier), so the
 // stage runs in place.
-template <int R, bool INV>
-__device__ void fft_stage(double2 *buf, const double2 *tw, int n, int TL, int se, int sl,
-                          int Ns) {
+template <int R, bool INV, typename C>
+__device__ void fft_stage(C *buf, const C *tw, int n, int TL, int se, int sl, int Ns) {
     const int nb = n / R;
     const int total = TL * nb;
     const int step = n / (Ns * R);
-    double2 v[FFT_MAX_SLOTS][R];
+    C v[FFT_MAX_SLOTS][R];
 #pragma unroll
     for (int q = 0; q < FFT_MAX_SLOTS; ++q) {
         const int b = threadIdx.x + q * FFT_THREADS;
@@ -113,7 +114,7 @@ __device__ void fft_stage(double2 *buf, const double2 *tw, int n, int TL, int se
             const int k = j % Ns;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                double2 w = tw[r * k * step];
+                C w = tw[r * k * step];
                 if (INV)
                     w.y = -w.y;
                 v[q][r] = cmul(v[q][r], w);
@@ -128,9 +129,8 @@ __device__ void fft_stage(double2 *buf, const double2 *tw, int n, int TL, int se
     __syncthreads();
 }
 
-template <bool INV>
-__device__ void fft_lines(double2 *buf, const double2 *tw, const fft_plan &P, int TL, int se,
-                          int sl) {
+template <bool INV, typename C>
+__device__ void fft_lines(C *buf, const C *tw, const fft_plan &P, int TL, int se, int sl) {
     int Ns = 1;
     for (int s = 0; s < P.n_stages; ++s) {
         const int R = P.radix[s];
@@ -144,9 +144,12 @@ __device__ void fft_lines(double2 *buf, const double2 *tw, const fft_plan &P, in
     }
 }
 
-__device__ __forceinline__ void load_twiddles(double2 *s_tw, const double2 *tw, int n) {
+// twiddles e^{-2 pi i m / n} from the FP64 host table, rounded to the form's precision
+template <typename C>
+__device__ __forceinline__ void load_twiddles(C *s_tw, const double2 *tw, int n) {
+    typedef decltype(s_tw[0].x) Rt;
     for (int i = threadIdx.x; i < n; i += FFT_THREADS)
-        s_tw[i] = tw[i];
+        s_tw[i] = C{Rt(tw[i].x), Rt(tw[i].y)};
 }
 
 // ---------------------------------------------------------------------------------------
@@ -198,12 +201,15 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit(uint64_t n, const dou
 // strided passes (x or y): a tile is TZ consecutive iz values x all n positions along the
 // axis, for a fixed other index.  stride_axis = N_g^2 (x) or N_g (y).
 // ---------------------------------------------------------------------------------------
-template <int MODE>  // 0: x forward from fixed point, 1: y forward, 2: y inverse, 3: x inverse to phi
+template <int MODE, typename C>  // 0: x forward from fixed point, 1: y forward, 2: y inverse,
+                                 // 3: x inverse to phi
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
-    const unsigned long long *__restrict__ q, double2 *__restrict__ c, double *__restrict__ phi,
-    const double2 *__restrict__ tw, fft_plan P, int TZ, double q_scale) {
-    __shared__ double2 s_buf[FFT_ELEMS];
-    __shared__ double2 s_tw[1024];
+    const unsigned long long *__restrict__ q, C *__restrict__ c,
+    decltype(C::x) *__restrict__ phi, const double2 *__restrict__ tw, fft_plan P, int TZ,
+    double q_scale) {
+    typedef decltype(C::x) Rt;
+    __shared__ C s_buf[FFT_ELEMS];
+    __shared__ C s_tw[1024];
     const int n = P.n;
     const int tiles_z = n / TZ;
     const int other = blockIdx.x / tiles_z;  // iy for the x pass, ix for the y pass
@@ -216,9 +222,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
     for (int e = threadIdx.x; e < total; e += FFT_THREADS) {
         const int t = e % TZ, a = e / TZ;
         const uint64_t gi = base + (uint64_t)a * stride_axis + t;
-        double2 v;
+        C v;
         if (MODE == 0)
-            v = make_double2((double)(long long)q[gi] * q_scale, 0.0);
+            v = C{Rt((double)(long long)q[gi] * q_scale), Rt(0.0)};
         else
             v = c[gi];
         s_buf[a * TZ + t] = v;
@@ -240,13 +246,15 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
 
 // z pass: TL whole contiguous lines (fixed ix, consecutive iy): forward FFT, Green's
 // function, inverse FFT.
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(double2 *__restrict__ c,
+template <typename C>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(C *__restrict__ c,
                                                               const double2 *__restrict__ tw,
                                                               const double *__restrict__ gt,
                                                               const double *__restrict__ k2t,
                                                               fft_plan P, int TL, double gconst) {
-    __shared__ double2 s_buf[FFT_ELEMS];
-    __shared__ double2 s_tw[1024];
+    typedef decltype(C::x) Rt;
+    __shared__ C s_buf[FFT_ELEMS];
+    __shared__ C s_tw[1024];
     const int n = P.n;
     const int tiles_y = n / TL;
     const int ix = blockIdx.x / tiles_y;
@@ -265,8 +273,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(double2 *__restrict
         double gk = 0.0;
         if (k2 > 0.0)
             gk = gconst * gt[ix] * gt[iy] * gt[iz] / k2;
-        double2 v = s_buf[e];
-        s_buf[e] = make_double2(v.x * gk, v.y * gk);
+        const Rt g = Rt(gk);
+        C v = s_buf[e];
+        s_buf[e] = C{v.x * g, v.y * g};
     }
     __syncthreads();
     fft_lines<true>(s_buf, s_tw, P, TL, 1, n);
@@ -277,9 +286,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(double2 *__restrict
 // ---------------------------------------------------------------------------------------
 // gradient + interpolation
 // ---------------------------------------------------------------------------------------
+template <typename Rt>
 __global__ __launch_bounds__(PM_THREADS) void k_pm_interp(
     uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ phi, double delta, int ng,
+    const double *__restrict__ z, const Rt *__restrict__ phi, double delta, int ng,
     double *__restrict__ gx, double *__restrict__ gy, double *__restrict__ gz, int accumulate) {
     uint64_t p = (uint64_t)blockIdx.x * PM_THREADS + threadIdx.x;
     if (p >= n)
@@ -290,37 +300,38 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_interp(
     cic_axis(y[p], delta, ng, iy[0], iy[1], wy[0], wy[1]);
     cic_axis(z[p], delta, ng, iz[0], iz[1], wz[0], wz[1]);
     const uint64_t N = (uint64_t)ng;
-    auto at = [&](int a, int b, int c) -> double {
+    auto at = [&](int a, int b, int c) -> Rt {
         a = (a % ng + ng) % ng;
         b = (b % ng + ng) % ng;
         c = (c % ng + ng) % ng;
         return phi[((uint64_t)a * N + b) * N + c];
     };
-    double sx = 0.0, sy = 0.0, sz = 0.0;
+    const Rt c1 = Rt(2.0 / 3.0), c2 = Rt(1.0 / 12.0);
+    Rt sx = Rt(0.0), sy = Rt(0.0), sz = Rt(0.0);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < 2; ++c) {
-                const double w = wx[a] * wy[b] * wz[c];
+                const Rt w = Rt(wx[a] * wy[b] * wz[c]);
                 const int i = ix[a], j = iy[b], k = iz[c];
-                const double dxp = 2.0 / 3.0 * (at(i + 1, j, k) - at(i - 1, j, k)) -
-                                   1.0 / 12.0 * (at(i + 2, j, k) - at(i - 2, j, k));
-                const double dyp = 2.0 / 3.0 * (at(i, j + 1, k) - at(i, j - 1, k)) -
-                                   1.0 / 12.0 * (at(i, j + 2, k) - at(i, j - 2, k));
-                const double dzp = 2.0 / 3.0 * (at(i, j, k + 1) - at(i, j, k - 1)) -
-                                   1.0 / 12.0 * (at(i, j, k + 2) - at(i, j, k - 2));
+                const Rt dxp = c1 * (at(i + 1, j, k) - at(i - 1, j, k)) -
+                               c2 * (at(i + 2, j, k) - at(i - 2, j, k));
+                const Rt dyp = c1 * (at(i, j + 1, k) - at(i, j - 1, k)) -
+                               c2 * (at(i, j + 2, k) - at(i, j - 2, k));
+                const Rt dzp = c1 * (at(i, j, k + 1) - at(i, j, k - 1)) -
+                               c2 * (at(i, j, k + 2) - at(i, j, k - 2));
                 sx += w * dxp;
                 sy += w * dyp;
                 sz += w * dzp;
             }
     const double s = -1.0 / delta;
     if (accumulate) {
-        gx[p] += s * sx;
-        gy[p] += s * sy;
-        gz[p] += s * sz;
+        gx[p] += s * (double)sx;
+        gy[p] += s * (double)sy;
+        gz[p] += s * (double)sz;
     } else {
-        gx[p] = s * sx;
-        gy[p] = s * sy;
-        gz[p] = s * sz;
+        gx[p] = s * (double)sx;
+        gy[p] = s * (double)sy;
+        gz[p] = s * (double)sz;
     }
 }
 
@@ -384,6 +395,61 @@ static dzs_status upload_tables(dzs_ctx *ctx, int ng, double L, double r_s, hipS
     return DZS_OK;
 }
 
+// The Poisson solve (x, y passes forward, z pass with the Green's function, y, x passes
+// inverse) and the gradient interpolation, in the complex type C of the form.
+template <typename C>
+static dzs_status pm_solve_interp(dzs_ctx *ctx, const dzs_particles *p, const dzs_pm_params *prm,
+                                  const fft_plan &P, const double2 *tw, const double *gt,
+                                  const double *k2t, int TZ, int TL, double delta,
+                                  double q_scale, double gconst, hipStream_t s) {
+    typedef decltype(C::x) Rt;
+    const int ng = P.n;
+    const uint32_t strided_blocks = (uint32_t)((uint64_t)ng * (ng / TZ));
+    const uint32_t z_blocks = (uint32_t)((uint64_t)ng * (ng / TL));
+    const unsigned long long *mq = (const unsigned long long *)ctx->mesh_q;
+    C *mc = (C *)ctx->mesh_c;
+    Rt *phi = (Rt *)ctx->mesh_phi;
+    {
+        dzs_timed t(ctx, KC_PM_FFT_X, s);
+        hipLaunchKernelGGL((k_fft_strided<0, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
+                           mc, phi, tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_x_fwd"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_Y, s);
+        hipLaunchKernelGGL((k_fft_strided<1, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
+                           mc, phi, tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_y_fwd"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_Z_GREEN, s);
+        hipLaunchKernelGGL(k_fft_z_green<C>, dim3(z_blocks), dim3(FFT_THREADS), 0, s, mc, tw, gt,
+                           k2t, P, TL, gconst);
+        DZS_TRY(dzs_check_launch(ctx, "fft_z_green"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_Y, s);
+        hipLaunchKernelGGL((k_fft_strided<2, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
+                           mc, phi, tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_y_inv"));
+    }
+    {
+        dzs_timed t(ctx, KC_PM_FFT_X, s);
+        hipLaunchKernelGGL((k_fft_strided<3, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
+                           mc, phi, tw, P, TZ, q_scale);
+        DZS_TRY(dzs_check_launch(ctx, "fft_x_inv"));
+    }
+    if (p->n > 0) {
+        dzs_timed t(ctx, KC_PM_INTERP, s);
+        hipLaunchKernelGGL(k_pm_interp<Rt>, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS),
+                           0, s, p->n, (const double *)p->x, (const double *)p->y,
+                           (const double *)p->z, (const Rt *)phi, delta, ng, p->gx,
+                           p->gy, p->gz, prm->accumulate);
+        DZS_TRY(dzs_check_launch(ctx, "pm_interp"));
+    }
+    return DZS_OK;
+}
+
 dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                       const dzs_pm_params *prm, hipStream_t s) {
     const int ng = prm->ng;
@@ -414,51 +480,9 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
     }
     const int TZ = tile_lines(ng, 16);
     const int TL = tile_lines(ng, FFT_ELEMS);
-    const uint32_t strided_blocks = (uint32_t)((uint64_t)ng * (ng / TZ));
-    const uint32_t z_blocks = (uint32_t)((uint64_t)ng * (ng / TL));
     const double q_scale = box->m0 / (DEP_FRAC * delta * delta * delta);
     const double gconst = -4.0 * 3.14159265358979323846 * box->G / (double)ng3;
-    {
-        dzs_timed t(ctx, KC_PM_FFT_X, s);
-        hipLaunchKernelGGL(k_fft_strided<0>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
-                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
-                           tw, P, TZ, q_scale);
-        DZS_TRY(dzs_check_launch(ctx, "fft_x_fwd"));
-    }
-    {
-        dzs_timed t(ctx, KC_PM_FFT_Y, s);
-        hipLaunchKernelGGL(k_fft_strided<1>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
-                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
-                           tw, P, TZ, q_scale);
-        DZS_TRY(dzs_check_launch(ctx, "fft_y_fwd"));
-    }
-    {
-        dzs_timed t(ctx, KC_PM_FFT_Z_GREEN, s);
-        hipLaunchKernelGGL(k_fft_z_green, dim3(z_blocks), dim3(FFT_THREADS), 0, s, ctx->mesh_c, tw,
-                           gt, k2t, P, TL, gconst);
-        DZS_TRY(dzs_check_launch(ctx, "fft_z_green"));
-    }
-    {
-        dzs_timed t(ctx, KC_PM_FFT_Y, s);
-        hipLaunchKernelGGL(k_fft_strided<2>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
-                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
-                           tw, P, TZ, q_scale);
-        DZS_TRY(dzs_check_launch(ctx, "fft_y_inv"));
-    }
-    {
-        dzs_timed t(ctx, KC_PM_FFT_X, s);
-        hipLaunchKernelGGL(k_fft_strided<3>, dim3(strided_blocks), dim3(FFT_THREADS), 0, s,
-                           (const unsigned long long *)ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
-                           tw, P, TZ, q_scale);
-        DZS_TRY(dzs_check_launch(ctx, "fft_x_inv"));
-    }
-    if (p->n > 0) {
-        dzs_timed t(ctx, KC_PM_INTERP, s);
-        hipLaunchKernelGGL(k_pm_interp, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0, s,
-                           p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,
-                           (const double *)ctx->mesh_phi, delta, ng, p->gx, p->gy, p->gz,
-                           prm->accumulate);
-        DZS_TRY(dzs_check_launch(ctx, "pm_interp"));
-    }
-    return DZS_OK;
+    if (prm->precision == DZS_FP32)
+        return pm_solve_interp<float2>(ctx, p, prm, P, tw, gt, k2t, TZ, TL, delta, q_scale, gconst, s);
+    return pm_solve_interp<double2>(ctx, p, prm, P, tw, gt, k2t, TZ, TL, delta, q_scale, gconst, s);
 }

@@ -15,6 +15,8 @@
 // shifted to the periodic image nearest the group, to an interaction list staged in LDS.
 // When the list fills, every lane sums its target's interactions with the whole list
 // (LDS broadcast reads).
+#include <type_traits>
+
 #include "internal.h"
 
 #define TB_THREADS 256
@@ -317,6 +319,7 @@ dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const 
 // The fit is checked on the host to 1e-12 relative error in S.
 // ---------------------------------------------------------------------------------------
 #define WALK_QN 20  // split-factor polynomial coefficients (Horner, fully unrolled)
+#define WALK_QF 12  // the same for FP32 evaluation
 
 struct walk_args {
     const uint32_t *grp_first;
@@ -336,69 +339,100 @@ struct walk_args {
     uint32_t *counter;  // [0] next group, [1] overflow flag
     unsigned long long *pair_count;
     double q[WALK_QN];
+    float qf[WALK_QF];  // the same split factor fitted for FP32 evaluation
 };
 
-// Cubic-spline softened 1/r^3 (enclosed-mass force / r), r < h.
-__device__ __forceinline__ double gsoft_inner(double r, double h) {
-    const double hinv = 1.0 / h;
-    const double u = r * hinv;
-    const double h3 = hinv * hinv * hinv;
-    if (u < 0.5)
-        return h3 * (32.0 / 3.0 + u * u * (32.0 * u - 192.0 / 5.0));
-    return h3 * (64.0 / 3.0 - 48.0 * u + 192.0 / 5.0 * u * u - 32.0 / 3.0 * u * u * u -
-                 1.0 / (15.0 * u * u * u));
+// Arithmetic of the pair loop in the precision T of the form: FP64 (plain) or FP32
+// (precision form; coordinates relative to the group centre, so FP32 keeps ~1e-7 of r_cut).
+__device__ __forceinline__ double wfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float wfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double wrsqrt(double a) { return rsqrt(a); }
+__device__ __forceinline__ float wrsqrt(float a) { return rsqrtf(a); }
+__device__ __forceinline__ double wmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float wmax(float a, float b) { return fmaxf(a, b); }
+template <typename T> __device__ __forceinline__ T wmin_image(T d, T L) {
+    if (d >= T(0.5) * L)
+        d -= L;
+    else if (d < T(-0.5) * L)
+        d += L;
+    return d;
 }
 
-// One interaction-list entry in LDS: position (shifted to the image nearest the group),
-// mass, spline support; 48 bytes, read as two 16-byte and one 8-byte LDS load.
-struct src_entry {
-    double x, y, z, m;
-    double h, pad;
+// Cubic-spline softened 1/r^3 (enclosed-mass force / r), r < h.
+template <typename T> __device__ __forceinline__ T gsoft_inner(T r, T h) {
+    const T hinv = T(1.0) / h;
+    const T u = r * hinv;
+    const T h3 = hinv * hinv * hinv;
+    if (u < T(0.5))
+        return h3 * (T(32.0 / 3.0) + u * u * (T(32.0) * u - T(192.0 / 5.0)));
+    return h3 * (T(64.0 / 3.0) - T(48.0) * u + T(192.0 / 5.0) * u * u - T(32.0 / 3.0) * u * u * u -
+                 T(1.0) / (T(15.0) * u * u * u));
+}
+
+// One interaction-list entry in LDS: position (shifted to the image nearest the group; in
+// FP32 relative to the group centre), mass, spline support.
+template <typename T> struct src_entry {
+    T x, y, z, m;
+    T h, pad;
 };
 
-template <bool MINIMG>
-__device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry *src,
-                                          uint32_t nlist, uint32_t s, uint32_t P, double xi,
-                                          double yi, double zi, double hi, double &ax,
-                                          double &ay, double &az, uint32_t &n_pairs) {
+template <typename T> struct split_coef;
+template <> struct split_coef<double> {
+    static constexpr int N = WALK_QN;
+    static __device__ __forceinline__ double at(const walk_args &A, int k) { return A.q[k]; }
+};
+template <> struct split_coef<float> {
+    static constexpr int N = WALK_QF;
+    static __device__ __forceinline__ float at(const walk_args &A, int k) { return A.qf[k]; }
+};
+
+template <typename T, bool MINIMG>
+__device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry<T> *src,
+                                          uint32_t nlist, uint32_t s, uint32_t P, T xi, T yi,
+                                          T zi, T hi, T &ax, T &ay, T &az, uint32_t &n_pairs) {
+    typedef typename std::conditional<sizeof(T) == 8, double2, float2>::type T2;
+    const T rcut2 = T(A.rcut2), rs_inv = T(A.rs_inv), rs_inv2 = T(A.rs_inv2);
+    const T t_scale = T(A.t_scale), L = T(A.L);
+    constexpr int QN = split_coef<T>::N;
     for (uint32_t jj = 0; jj < nlist; jj += P) {
         const uint32_t j = jj + s;
         if (j >= nlist)
             break;
-        const double2 xy = *(const double2 *)&src[j].x;
-        const double2 zm = *(const double2 *)&src[j].z;
-        double dx = xy.x - xi, dy = xy.y - yi, dz = zm.x - zi;
+        const T2 xy = *(const T2 *)&src[j].x;
+        const T2 zm = *(const T2 *)&src[j].z;
+        T dx = xy.x - xi, dy = xy.y - yi, dz = zm.x - zi;
         if (MINIMG) {
-            dx = dzs_min_image(dx, A.L);
-            dy = dzs_min_image(dy, A.L);
-            dz = dzs_min_image(dz, A.L);
+            dx = wmin_image(dx, L);
+            dy = wmin_image(dy, L);
+            dz = wmin_image(dz, L);
         }
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < A.rcut2 && r2 > 0.0) {
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < rcut2 && r2 > T(0.0)) {
             ++n_pairs;
-            const double rinv = rsqrt(r2);
-            const double w = r2 * A.rs_inv2;
-            const double t = fma(w, A.t_scale, -1.0);
-            double q = A.q[WALK_QN - 1];
+            const T rinv = wrsqrt(r2);
+            const T w = r2 * rs_inv2;
+            const T t = wfma(w, t_scale, T(-1.0));
+            T q = split_coef<T>::at(A, QN - 1);
 #pragma unroll
-            for (int k = WALK_QN - 2; k >= 0; --k)
-                q = fma(q, t, A.q[k]);
-            const double u = r2 * rinv * A.rs_inv;
-            const double S = 1.0 - u * w * q;
-            const double h = fmax(src[j].h, hi);
-            double ker = rinv * rinv * rinv;
+            for (int k = QN - 2; k >= 0; --k)
+                q = wfma(q, t, split_coef<T>::at(A, k));
+            const T u = r2 * rinv * rs_inv;
+            const T S = T(1.0) - u * w * q;
+            const T h = wmax(src[j].h, hi);
+            T ker = rinv * rinv * rinv;
             if (r2 < h * h)
                 ker = gsoft_inner(r2 * rinv, h);
-            const double f = zm.y * ker * S;
-            ax = fma(f, dx, ax);
-            ay = fma(f, dy, ay);
-            az = fma(f, dz, az);
+            const T f = zm.y * ker * S;
+            ax = wfma(f, dx, ax);
+            ay = wfma(f, dy, ay);
+            az = wfma(f, dz, az);
         }
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
-    __shared__ src_entry src[WALK_LIST];
+    __shared__ src_entry<T> src[WALK_LIST];
     __shared__ uint32_t q_node[64];
     __shared__ uint32_t q_pref[65];
     __shared__ double q_shift[3][64];
@@ -443,8 +477,12 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         const double gcx = 0.5 * (mnx + mxx), gcy = 0.5 * (mny + mxy), gcz = 0.5 * (mnz + mxz);
         const double ghx = 0.5 * (mxx - mnx), ghy = 0.5 * (mxy - mny), ghz = 0.5 * (mxz - mnz);
         const double ghmax = fmax(ghx, fmax(ghy, ghz));
+        // list coordinates: absolute in FP64, relative to the group centre in FP32
+        const bool rel = sizeof(T) == 4;
+        const double ox = rel ? gcx : 0.0, oy = rel ? gcy : 0.0, oz = rel ? gcz : 0.0;
+        const T txi = T(xi - ox), tyi = T(yi - oy), tzi = T(zi - oz), thi = T(hi);
 
-        double ax = 0.0, ay = 0.0, az = 0.0;
+        T ax = T(0.0), ay = T(0.0), az = T(0.0);
         uint32_t nlist = 0;
         uint32_t n_pairs = 0;
         bool wide = false;
@@ -452,9 +490,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         auto flush = [&]() {
             __syncthreads();
             if (wide)
-                pair_loop<true>(A, src, nlist, ph, P, xi, yi, zi, hi, ax, ay, az, n_pairs);
+                pair_loop<T, true>(A, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
             else
-                pair_loop<false>(A, src, nlist, ph, P, xi, yi, zi, hi, ax, ay, az, n_pairs);
+                pair_loop<T, false>(A, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
             nlist = 0;
             __syncthreads();
         };
@@ -536,11 +574,11 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 if (act == 2) {
                     const uint32_t slot = nlist + (uint32_t)__popcll(mono & lt_mask);
                     const uint64_t c = A.cap;
-                    src[slot].x = A.nd_com[node] + shx;
-                    src[slot].y = A.nd_com[c + node] + shy;
-                    src[slot].z = A.nd_com[2 * c + node] + shz;
-                    src[slot].m = A.nd_mass[node];
-                    src[slot].h = A.nd_hmax[node];
+                    src[slot].x = T(A.nd_com[node] + shx - ox);
+                    src[slot].y = T(A.nd_com[c + node] + shy - oy);
+                    src[slot].z = T(A.nd_com[2 * c + node] + shz - oz);
+                    src[slot].m = T(A.nd_mass[node]);
+                    src[slot].h = T(A.nd_hmax[node]);
                 }
                 nlist += nmono;
             }
@@ -595,13 +633,13 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                         if (nlist + nk > WALK_LIST)
                             flush();
                         if (keep) {
-                            src_entry &e = src[nlist + (uint32_t)__popcll(kmask & lt_mask)];
+                            src_entry<T> &e = src[nlist + (uint32_t)__popcll(kmask & lt_mask)];
                             const double md = (double)mj;
-                            e.x = ex_;
-                            e.y = ey_;
-                            e.z = ez_;
-                            e.m = A.m0 * md;
-                            e.h = A.h0 * cbrt(md);
+                            e.x = T(ex_ - ox);
+                            e.y = T(ey_ - oy);
+                            e.z = T(ez_ - oz);
+                            e.m = T(A.m0 * md);
+                            e.h = T(A.h0 * cbrt(md));
                         }
                         nlist += nk;
                     }
@@ -628,7 +666,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 atomicAdd(A.pair_count, (unsigned long long)cnt_pairs);
         }
         if (valid && ph == 0) {
-            const double gxv = A.G * ax, gyv = A.G * ay, gzv = A.G * az;
+            const double gxv = A.G * (double)ax, gyv = A.G * (double)ay, gzv = A.G * (double)az;
             if (A.accumulate) {
                 A.gx[i] += gxv;
                 A.gy[i] += gyv;
@@ -724,6 +762,27 @@ static double split_poly(double wmax, double *q) {
     return (double)worst;
 }
 
+// The WALK_QF-coefficient fit for FP32 evaluation, its coefficients rounded to FP32, and its
+// worst absolute error in S on [0, wmax] (S is 1 at contact: FP32 resolves ~1e-7 of it).
+static double split_poly_f32(double wmax, float *qf) {
+    long double mono[WALK_QF];
+    fit_q(wmax, WALK_QF, mono);
+    for (int i = 0; i < WALK_QF; ++i)
+        qf[i] = (float)mono[i];
+    long double worst = 0.0L;
+    for (int k = 0; k <= 800; ++k) {
+        long double w = wmax * k / 800.0L;
+        long double t = 2.0L * w / wmax - 1.0L;
+        long double qa = 0.0L;
+        for (int i = WALK_QF - 1; i >= 0; --i)
+            qa = qa * t + (long double)qf[i];
+        long double u = sqrtl(w);
+        long double err = fabsl(u * w * (qa - q_taylor(w)));
+        worst = err > worst ? err : worst;
+    }
+    return (double)worst;
+}
+
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
                          double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s) {
@@ -755,13 +814,17 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
     const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
     if (ctx->q_wmax != wmax) {
         ctx->q_err = split_poly(wmax, ctx->q_coef);
+        ctx->qf_err = split_poly_f32(wmax, ctx->qf_coef);
         ctx->q_wmax = wmax;
     }
-    if (!(ctx->q_err < 1e-10))
-        return dzs_fail(ctx, DZS_EINVAL, "tree: split-factor fit error %.2e for r_cut/r_s = %.3f",
-                        ctx->q_err, sqrt(wmax));
+    const bool fp32 = prm->precision == DZS_FP32;
+    if (!(ctx->q_err < 1e-10) || (fp32 && !(ctx->qf_err < 1e-6)))
+        return dzs_fail(ctx, DZS_EINVAL, "tree: split-factor fit error %.2e / %.2e (FP32) for "
+                        "r_cut/r_s = %.3f", ctx->q_err, ctx->qf_err, sqrt(wmax));
     for (int k = 0; k < WALK_QN; ++k)
         A.q[k] = ctx->q_coef[k];
+    for (int k = 0; k < WALK_QF; ++k)
+        A.qf[k] = ctx->qf_coef[k];
     A.t_scale = 2.0 / wmax;
     A.stack = ctx->walk_stack;
     A.depth = (uint32_t)ctx->walk_stack_depth;
@@ -772,7 +835,10 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
     DZS_HIP(ctx, hipMemsetAsync(ctx->walk_counter, 0, 2 * sizeof(uint32_t), s));
     {
         dzs_timed t(ctx, KC_TREE_WALK, s);
-        hipLaunchKernelGGL(k_tree_walk, dim3(slots), dim3(64), 0, s, A);
+        if (fp32)
+            hipLaunchKernelGGL(k_tree_walk<float>, dim3(slots), dim3(64), 0, s, A);
+        else
+            hipLaunchKernelGGL(k_tree_walk<double>, dim3(slots), dim3(64), 0, s, A);
         DZS_TRY(dzs_check_launch(ctx, "tree_walk"));
     }
     DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 4, ctx->walk_counter + 1, sizeof(uint32_t),
