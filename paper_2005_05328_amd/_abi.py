@@ -85,7 +85,7 @@ assert C.sizeof(LCRecord) == 64
 def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libdzs.so not found at {LIB_PATH}: build it with "
-                          "`python -m paper_2005_05328_amd.build` (the GPU path has no fallback)")
+                          "`python paper_2005_05328_amd/build.py` (the GPU path has no fallback)")
     # torch ships its own HIP runtime under the same soname as /opt/rocm's; the first one loaded
     # serves the whole process, so torch is imported before the library resolves its runtime
     import torch  # noqa: F401

@@ -386,43 +386,65 @@ template <> struct split_coef<float> {
     static __device__ __forceinline__ float at(const walk_args &A, int k) { return A.qf[k]; }
 };
 
+// Separation of a list entry from the target (minimum image for wide groups).
+template <typename T, bool MINIMG>
+__device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T L, T &dx,
+                                      T &dy, T &dz) {
+    dx = e.x - xi;
+    dy = e.y - yi;
+    dz = e.z - zi;
+    if (MINIMG) {
+        dx = wmin_image(dx, L);
+        dy = wmin_image(dy, L);
+        dz = wmin_image(dz, L);
+    }
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// The lane's share of the list (entries s, s + P, s + 2P, ...) in two passes per block of 64
+// of its entries: a cheap pass marks the entries inside r_cut in a 64-bit mask, then the lane
+// evaluates only the marked pairs, in ascending order.  A list culled against the group's box
+// holds several times more entries than any one target's cutoff sphere; without the mask the
+// whole wave would step through the force arithmetic for every entry some lane accepts.
 template <typename T, bool MINIMG>
 __device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry<T> *src,
                                           uint32_t nlist, uint32_t s, uint32_t P, T xi, T yi,
                                           T zi, T hi, T &ax, T &ay, T &az, uint32_t &n_pairs) {
-    typedef typename std::conditional<sizeof(T) == 8, double2, float2>::type T2;
     const T rcut2 = T(A.rcut2), rs_inv = T(A.rs_inv), rs_inv2 = T(A.rs_inv2);
     const T t_scale = T(A.t_scale), L = T(A.L);
     constexpr int QN = split_coef<T>::N;
-    for (uint32_t jj = 0; jj < nlist; jj += P) {
-        const uint32_t j = jj + s;
-        if (j >= nlist)
-            break;
-        const T2 xy = *(const T2 *)&src[j].x;
-        const T2 zm = *(const T2 *)&src[j].z;
-        T dx = xy.x - xi, dy = xy.y - yi, dz = zm.x - zi;
-        if (MINIMG) {
-            dx = wmin_image(dx, L);
-            dy = wmin_image(dy, L);
-            dz = wmin_image(dz, L);
+    for (uint32_t base = s; base < nlist; base += 64u * P) {
+        uint64_t mask = 0;
+        for (uint32_t k = 0; k < 64u; ++k) {
+            const uint32_t j = base + k * P;
+            if (j >= nlist)
+                break;
+            T dx, dy, dz;
+            const T r2 = pair_sep<T, MINIMG>(src[j], xi, yi, zi, L, dx, dy, dz);
+            if (r2 < rcut2 && r2 > T(0.0))
+                mask |= 1ull << k;
         }
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < rcut2 && r2 > T(0.0)) {
-            ++n_pairs;
+        n_pairs += (uint32_t)__popcll(mask);
+        while (mask) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(mask);
+            mask &= mask - 1ull;
+            const src_entry<T> &e = src[base + k * P];
+            T dx, dy, dz;
+            const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
             const T rinv = wrsqrt(r2);
             const T w = r2 * rs_inv2;
             const T t = wfma(w, t_scale, T(-1.0));
             T q = split_coef<T>::at(A, QN - 1);
 #pragma unroll
-            for (int k = QN - 2; k >= 0; --k)
-                q = wfma(q, t, split_coef<T>::at(A, k));
+            for (int c = QN - 2; c >= 0; --c)
+                q = wfma(q, t, split_coef<T>::at(A, c));
             const T u = r2 * rinv * rs_inv;
             const T S = T(1.0) - u * w * q;
-            const T h = wmax(src[j].h, hi);
+            const T h = wmax(e.h, hi);
             T ker = rinv * rinv * rinv;
             if (r2 < h * h)
                 ker = gsoft_inner(r2 * rinv, h);
-            const T f = zm.y * ker * S;
+            const T f = e.m * ker * S;
             ax = wfma(f, dx, ax);
             ay = wfma(f, dy, ay);
             az = wfma(f, dz, az);
