@@ -138,7 +138,7 @@ static void release(dzs_ctx *ctx) {
                     ctx->nd_bmax, ctx->nd_hmax, ctx->frontier, ctx->frontier_next,
                     ctx->fr_nchild, ctx->fr_ninternal, ctx->fr_child_off, ctx->fr_int_off,
                     ctx->child_bounds, ctx->grp_flag, ctx->grp_scan, ctx->grp_first,
-                    ctx->walk_stack, ctx->walk_counter, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                    ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
                     ctx->pm_tables, ctx->dz_head, ctx->dz_flag, ctx->dz_scan, ctx->dz_new,
                     ctx->dz_newmult, ctx->dz_newid, ctx->dz_perm, ctx->d_small};
     for (void *p : ptrs)
@@ -208,6 +208,8 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->walk_stack, c->walk_stack_slots * c->walk_stack_depth));
     DZS_TRY(alloc(c, &c->walk_counter, 64));
     DZS_HIP(c, hipMemset(c->walk_counter, 0, 64 * sizeof(uint32_t)));
+    DZS_TRY(alloc(c, &c->cell_node, 1ull << (3 * DZS_CELL_K_MAX)));
+    DZS_TRY(alloc(c, &c->cell_dl, 1ull << (3 * DZS_CELL_K_MAX)));
     if (ng > 0) {
         DZS_TRY(alloc(c, &c->mesh_q, ng3));
         DZS_TRY(alloc(c, &c->mesh_c, ng3));

@@ -10,6 +10,7 @@
 #include "../../include/dzs.h"
 
 #define DZS_KEY_BITS 21
+#define DZS_CELL_K_MAX 7  // deepest level of the walk start cells (8^7 cells, 10 MB)
 #define DZS_KEY_SIDE 2097152.0
 
 // ---------------------------------------------------------------------------------------
@@ -84,6 +85,8 @@ struct dzs_ctx {
     double q_wmax = -1.0;
     double q_err = 1.0;
     float qf_coef[16] = {0};           // its FP32 fit (precision form)
+    uint32_t *cell_node = nullptr;     // walk start cells: [8^DZS_CELL_K_MAX] node ids
+    uint8_t *cell_dl = nullptr;        // and the level offset of each
     double qf_err = 1.0;
     uint32_t level_start[DZS_KEY_BITS + 3] = {0};
     int n_levels = 0;

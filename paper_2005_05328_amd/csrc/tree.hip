@@ -340,7 +340,45 @@ struct walk_args {
     unsigned long long *pair_count;
     double q[WALK_QN];
     float qf[WALK_QF];  // the same split factor fitted for FP32 evaluation
+    // start cells: the walk of a group begins at the level-K nodes (and shallower leaves) of
+    // the cells that meet its bounding box grown by r_cut, instead of at the root
+    const uint32_t *cell_node;  // [8^K] node covering each level-K cell (Morton order)
+    const uint8_t *cell_dl;     // [8^K] K - level of that node
+    int cell_K;                 // 0: start at the root
 };
+
+// ---------------------------------------------------------------------------------------
+// start cells
+// ---------------------------------------------------------------------------------------
+#define CELL_EMPTY 0xffffffffu
+
+__global__ __launch_bounds__(TB_THREADS) void k_cell_clear(uint64_t n, uint32_t *cell_node) {
+    const uint64_t i = (uint64_t)blockIdx.x * TB_THREADS + threadIdx.x;
+    if (i < n)
+        cell_node[i] = CELL_EMPTY;
+}
+
+// Every node at level K, and every leaf above level K, claims the level-K cells of its cube:
+// in Morton order these form the contiguous range [P 8^(K-l), (P+1) 8^(K-l)), P = the node's
+// key prefix.  The claimed ranges are disjoint; cells no node claims hold no particle.
+__global__ __launch_bounds__(TB_THREADS) void k_cell_fill(
+    uint32_t n_nodes, int K, const uint64_t *__restrict__ key, const uint32_t *__restrict__ nd_first,
+    const uint8_t *__restrict__ nd_nchild, const uint8_t *__restrict__ nd_level,
+    uint32_t *__restrict__ cell_node, uint8_t *__restrict__ cell_dl) {
+    const uint32_t node = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (node >= n_nodes)
+        return;
+    const int l = nd_level[node];
+    if (l > K || (l < K && nd_nchild[node] != 0))
+        return;
+    const uint64_t P = key[nd_first[node]] >> (3 * (DZS_KEY_BITS - l));
+    const int dl = K - l;
+    const uint64_t lo = P << (3 * dl), hi = (P + 1) << (3 * dl);
+    for (uint64_t m = lo; m < hi; ++m) {
+        cell_node[m] = node;
+        cell_dl[m] = (uint8_t)dl;
+    }
+}
 
 // Arithmetic of the pair loop in the precision T of the form: FP64 (plain) or FP32
 // (precision form; coordinates relative to the group centre, so FP32 keeps ~1e-7 of r_cut).
@@ -455,7 +493,7 @@ __device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry<T>
 template <typename T>
 __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     __shared__ src_entry<T> src[WALK_LIST];
-    __shared__ uint32_t q_node[64];
+    __shared__ uint32_t q_first[64];
     __shared__ uint32_t q_pref[65];
     __shared__ double q_shift[3][64];
     __shared__ uint32_t q_wide[64];
@@ -519,12 +557,69 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             __syncthreads();
         };
 
-        uint32_t sp = 1;
-        if (lane == 0)
-            stk[0] = 0;
-        __threadfence_block();
+        uint32_t sp = 0;
         bool overflow = false;
-        while (sp > 0) {
+        if (A.cell_K == 0) {
+            if (lane == 0)
+                stk[0] = 0;
+            sp = 1;
+        } else {
+            // cells of level K met by the bounding box grown by r_cut (plus a margin far above
+            // rounding, so that every particle in it is found in a listed cell), wrapped
+            const int K = A.cell_K;
+            const int64_t side = 1ll << K, kmask = side - 1;
+            const double inv = (double)side / A.L, margin = 1e-9 * A.L;
+            const int64_t lox = (int64_t)floor((mnx - A.rcut - margin) * inv);
+            const int64_t loy = (int64_t)floor((mny - A.rcut - margin) * inv);
+            const int64_t loz = (int64_t)floor((mnz - A.rcut - margin) * inv);
+            int64_t nx = (int64_t)floor((mxx + A.rcut + margin) * inv) - lox + 1;
+            int64_t ny = (int64_t)floor((mxy + A.rcut + margin) * inv) - loy + 1;
+            int64_t nz = (int64_t)floor((mxz + A.rcut + margin) * inv) - loz + 1;
+            nx = nx < side ? nx : side;
+            ny = ny < side ? ny : side;
+            nz = nz < side ? nz : side;
+            const uint64_t total = (uint64_t)(nx * ny * nz);
+            for (uint64_t c0 = 0; c0 < total; c0 += 64) {
+                const uint64_t c = c0 + lane;
+                uint32_t node = CELL_EMPTY;
+                if (c < total) {
+                    const int64_t cz = loz + (int64_t)(c % (uint64_t)nz);
+                    const int64_t cy = loy + (int64_t)((c / (uint64_t)nz) % (uint64_t)ny);
+                    const int64_t cx = lox + (int64_t)(c / (uint64_t)(nz * ny));
+                    const uint64_t wx = (uint64_t)(cx & kmask), wy = (uint64_t)(cy & kmask),
+                                   wz = (uint64_t)(cz & kmask);
+                    const uint64_t m =
+                        (dzs_spread3(wx) << 2) | (dzs_spread3(wy) << 1) | dzs_spread3(wz);
+                    node = A.cell_node[m];
+                    const int dl = A.cell_dl[m];
+                    if (node != CELL_EMPTY && dl > 0) {
+                        // a leaf above level K covers 2^dl cells per axis: only the first
+                        // listed cell inside its cube (per axis, in listing order) pushes it
+                        const int64_t span = 1ll << dl;
+                        auto first = [&](int64_t lo, uint64_t w) -> int64_t {
+                            const int64_t n0 = (int64_t)w & ~(span - 1);
+                            const int64_t wlo = lo & kmask;
+                            const bool in = ((wlo - n0) & kmask) < span;
+                            return in ? lo : lo + ((n0 - wlo) & kmask);
+                        };
+                        if (cx != first(lox, wx) || cy != first(loy, wy) || cz != first(loz, wz))
+                            node = CELL_EMPTY;
+                    }
+                }
+                const uint32_t put = node != CELL_EMPTY ? 1u : 0u;
+                const uint32_t incl = dzs_wave_incl_scan(put);
+                const uint32_t tot = __shfl(incl, 63, 64);
+                if (sp + tot > A.depth) {
+                    overflow = true;
+                    break;
+                }
+                if (put)
+                    stk[sp + incl - 1] = node;
+                sp += tot;
+            }
+        }
+        __threadfence_block();
+        while (sp > 0 && !overflow) {
             const uint32_t take = sp < 64 ? sp : 64;
             sp -= take;
             const bool has = lane < take;
@@ -532,12 +627,22 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             // classify: 0 skip, 1 leaf, 2 monopole, 3 open
             int act = 0;
             double shx = 0.0, shy = 0.0, shz = 0.0;
-            uint32_t ncount = 0, nchild = 0, child = 0;
+            uint32_t ncount = 0, nchild = 0, child = 0, nfirst = 0;
+            double comx = 0.0, comy = 0.0, comz = 0.0;
             bool node_wide = false;
             if (has) {
                 const uint64_t c = A.cap;
+                // every field the classification may need, in one round of loads
                 const double bnx = A.nd_bmin[node], bny = A.nd_bmin[c + node], bnz = A.nd_bmin[2 * c + node];
                 const double bxx = A.nd_bmax[node], bxy = A.nd_bmax[c + node], bxz = A.nd_bmax[2 * c + node];
+                comx = A.nd_com[node];
+                comy = A.nd_com[c + node];
+                comz = A.nd_com[2 * c + node];
+                const int nlev = A.nd_level[node];
+                nchild = A.nd_nchild[node];
+                ncount = A.nd_count[node];
+                nfirst = A.nd_first[node];
+                child = A.nd_child[node];
                 double dcx = 0.5 * (bnx + bxx) - gcx, dcy = 0.5 * (bny + bxy) - gcy,
                        dcz = 0.5 * (bnz + bxz) - gcz;
                 shx = dcx > A.halfL ? -A.L : (dcx < -A.halfL ? A.L : 0.0);
@@ -550,8 +655,6 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 const double gz_ = fmax(0.0, fabs(dcz) - nhz - ghz);
                 const double dist2 = gx_ * gx_ + gy_ * gy_ + gz_ * gz_;
                 node_wide = fmax(nhx, fmax(nhy, nhz)) + ghmax > wide_limit;
-                nchild = A.nd_nchild[node];
-                ncount = A.nd_count[node];
                 if (dist2 >= A.rcut2) {
                     act = 0;
                 } else if (nchild == 0) {
@@ -559,18 +662,17 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 } else {
                     act = 3;
                     if (A.theta2 > 0.0) {
-                        const double cx = A.nd_com[node] + shx - gcx;
-                        const double cy = A.nd_com[c + node] + shy - gcy;
-                        const double cz = A.nd_com[2 * c + node] + shz - gcz;
+                        const double cx = comx + shx - gcx;
+                        const double cy = comy + shy - gcy;
+                        const double cz = comz + shz - gcz;
                         const double ex = fmax(0.0, fabs(cx) - ghx);
                         const double ey = fmax(0.0, fabs(cy) - ghy);
                         const double ez = fmax(0.0, fabs(cz) - ghz);
                         const double d2 = ex * ex + ey * ey + ez * ez;
-                        const double side = ldexp(A.L, -(int)A.nd_level[node]);
+                        const double side = ldexp(A.L, -nlev);
                         if (side * side < A.theta2 * d2)
                             act = 2;
                     }
-                    child = A.nd_child[node];
                 }
             }
             if (__ballot((act == 1 || act == 2) && node_wide) != 0ull)
@@ -596,9 +698,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 if (act == 2) {
                     const uint32_t slot = nlist + (uint32_t)__popcll(mono & lt_mask);
                     const uint64_t c = A.cap;
-                    src[slot].x = T(A.nd_com[node] + shx - ox);
-                    src[slot].y = T(A.nd_com[c + node] + shy - oy);
-                    src[slot].z = T(A.nd_com[2 * c + node] + shz - oz);
+                    src[slot].x = T(comx + shx - ox);
+                    src[slot].y = T(comy + shy - oy);
+                    src[slot].z = T(comz + shz - oz);
                     src[slot].m = T(A.nd_mass[node]);
                     src[slot].h = T(A.nd_hmax[node]);
                 }
@@ -615,7 +717,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 __syncthreads();
                 if (act == 1) {
                     const uint32_t q = (uint32_t)__popcll(lmask & lt_mask);
-                    q_node[q] = node;
+                    q_first[q] = nfirst;
                     q_pref[q] = lincl - lc;
                     q_shift[0][q] = shx;
                     q_shift[1][q] = shy;
@@ -639,7 +741,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                             else
                                 hi2 = mid - 1;
                         }
-                        const uint32_t j = A.nd_first[q_node[lo]] + (f - q_pref[lo]);
+                        const uint32_t j = q_first[lo] + (f - q_pref[lo]);
                         ex_ = A.x[j] + q_shift[0][lo];
                         ey_ = A.y[j] + q_shift[1][lo];
                         ez_ = A.z[j] + q_shift[2][lo];
@@ -852,6 +954,28 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
     A.depth = (uint32_t)ctx->walk_stack_depth;
     A.counter = ctx->walk_counter;
     A.pair_count = (unsigned long long *)(ctx->walk_counter + 8);
+    // start level K: the deepest level whose cells are at least r_cut wide (so no node above
+    // it can be a monopole while theta <= 1), at most DZS_CELL_K_MAX
+    int K = 0;
+    if (prm->theta <= 1.0)
+        while (K < DZS_CELL_K_MAX && ldexp(box->L, -(K + 1)) >= prm->r_cut)
+            ++K;
+    A.cell_K = K;
+    A.cell_node = ctx->cell_node;
+    A.cell_dl = ctx->cell_dl;
+    if (K > 0) {
+        dzs_timed t(ctx, KC_TREE_BUILD, s);
+        const uint64_t n_cells = 1ull << (3 * K);
+        hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(n_cells, TB_THREADS)), dim3(TB_THREADS),
+                           0, s, n_cells, ctx->cell_node);
+        DZS_TRY(dzs_check_launch(ctx, "cell_clear"));
+        const int top = K + 1 < ctx->n_levels ? K + 1 : ctx->n_levels;
+        const uint32_t n_top = ctx->level_start[top];
+        hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(n_top, TB_THREADS)), dim3(TB_THREADS), 0,
+                           s, n_top, K, (const uint64_t *)ctx->key, ctx->nd_first, ctx->nd_nchild,
+                           ctx->nd_level, ctx->cell_node, ctx->cell_dl);
+        DZS_TRY(dzs_check_launch(ctx, "cell_fill"));
+    }
     uint32_t slots = ctx->n_groups < ctx->walk_stack_slots ? ctx->n_groups
                                                            : (uint32_t)ctx->walk_stack_slots;
     DZS_HIP(ctx, hipMemsetAsync(ctx->walk_counter, 0, 2 * sizeof(uint32_t), s));
