@@ -490,7 +490,7 @@ __device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry<T>
     }
 }
 
-template <typename T>
+template <typename T, bool CELLS>
 __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     __shared__ src_entry<T> src[WALK_LIST];
     __shared__ uint32_t q_first[64];
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
 
         uint32_t sp = 0;
         bool overflow = false;
-        if (A.cell_K == 0) {
+        if (!CELLS) {
             if (lane == 0)
                 stk[0] = 0;
             sp = 1;
@@ -567,40 +567,36 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             // cells of level K met by the bounding box grown by r_cut (plus a margin far above
             // rounding, so that every particle in it is found in a listed cell), wrapped
             const int K = A.cell_K;
-            const int64_t side = 1ll << K, kmask = side - 1;
+            const int side = 1 << K, kmask = side - 1;
             const double inv = (double)side / A.L, margin = 1e-9 * A.L;
-            const int64_t lox = (int64_t)floor((mnx - A.rcut - margin) * inv);
-            const int64_t loy = (int64_t)floor((mny - A.rcut - margin) * inv);
-            const int64_t loz = (int64_t)floor((mnz - A.rcut - margin) * inv);
-            int64_t nx = (int64_t)floor((mxx + A.rcut + margin) * inv) - lox + 1;
-            int64_t ny = (int64_t)floor((mxy + A.rcut + margin) * inv) - loy + 1;
-            int64_t nz = (int64_t)floor((mxz + A.rcut + margin) * inv) - loz + 1;
-            nx = nx < side ? nx : side;
-            ny = ny < side ? ny : side;
-            nz = nz < side ? nz : side;
-            const uint64_t total = (uint64_t)(nx * ny * nz);
-            for (uint64_t c0 = 0; c0 < total; c0 += 64) {
-                const uint64_t c = c0 + lane;
+            const int lox = (int)floor((mnx - A.rcut - margin) * inv);
+            const int loy = (int)floor((mny - A.rcut - margin) * inv);
+            const int loz = (int)floor((mnz - A.rcut - margin) * inv);
+            const int nx = min((int)floor((mxx + A.rcut + margin) * inv) - lox + 1, side);
+            const int ny = min((int)floor((mxy + A.rcut + margin) * inv) - loy + 1, side);
+            const int nz = min((int)floor((mxz + A.rcut + margin) * inv) - loz + 1, side);
+            const uint32_t nyz = (uint32_t)(ny * nz), total = (uint32_t)nx * nyz;
+            for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+                const uint32_t c = c0 + lane;
                 uint32_t node = CELL_EMPTY;
                 if (c < total) {
-                    const int64_t cz = loz + (int64_t)(c % (uint64_t)nz);
-                    const int64_t cy = loy + (int64_t)((c / (uint64_t)nz) % (uint64_t)ny);
-                    const int64_t cx = lox + (int64_t)(c / (uint64_t)(nz * ny));
-                    const uint64_t wx = (uint64_t)(cx & kmask), wy = (uint64_t)(cy & kmask),
-                                   wz = (uint64_t)(cz & kmask);
-                    const uint64_t m =
-                        (dzs_spread3(wx) << 2) | (dzs_spread3(wy) << 1) | dzs_spread3(wz);
+                    const uint32_t cxo = c / nyz, rem = c - cxo * nyz;
+                    const uint32_t cyo = rem / (uint32_t)nz, czo = rem - cyo * (uint32_t)nz;
+                    const int cx = lox + (int)cxo, cy = loy + (int)cyo, cz = loz + (int)czo;
+                    const uint32_t wx = (uint32_t)(cx & kmask), wy = (uint32_t)(cy & kmask),
+                                   wz = (uint32_t)(cz & kmask);
+                    const uint32_t m = (uint32_t)((dzs_spread3(wx) << 2) | (dzs_spread3(wy) << 1) |
+                                                  dzs_spread3(wz));
                     node = A.cell_node[m];
                     const int dl = A.cell_dl[m];
                     if (node != CELL_EMPTY && dl > 0) {
                         // a leaf above level K covers 2^dl cells per axis: only the first
                         // listed cell inside its cube (per axis, in listing order) pushes it
-                        const int64_t span = 1ll << dl;
-                        auto first = [&](int64_t lo, uint64_t w) -> int64_t {
-                            const int64_t n0 = (int64_t)w & ~(span - 1);
-                            const int64_t wlo = lo & kmask;
-                            const bool in = ((wlo - n0) & kmask) < span;
-                            return in ? lo : lo + ((n0 - wlo) & kmask);
+                        const int span = 1 << dl;
+                        auto first = [&](int lo, uint32_t w) -> int {
+                            const int n0 = (int)w & ~(span - 1);
+                            const int wlo = lo & kmask;
+                            return ((wlo - n0) & kmask) < span ? lo : lo + ((n0 - wlo) & kmask);
                         };
                         if (cx != first(lox, wx) || cy != first(loy, wy) || cz != first(loz, wz))
                             node = CELL_EMPTY;
@@ -957,7 +953,7 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
     // start level K: the deepest level whose cells are at least r_cut wide (so no node above
     // it can be a monopole while theta <= 1), at most DZS_CELL_K_MAX
     int K = 0;
-    if (prm->theta <= 1.0)
+    if (prm->theta <= 1.0 && prm->precision == DZS_FP32)
         while (K < DZS_CELL_K_MAX && ldexp(box->L, -(K + 1)) >= prm->r_cut)
             ++K;
     A.cell_K = K;
@@ -981,10 +977,14 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
     DZS_HIP(ctx, hipMemsetAsync(ctx->walk_counter, 0, 2 * sizeof(uint32_t), s));
     {
         dzs_timed t(ctx, KC_TREE_WALK, s);
-        if (fp32)
-            hipLaunchKernelGGL(k_tree_walk<float>, dim3(slots), dim3(64), 0, s, A);
+        // the start-cell variant carries more scalar state; in FP64 its register pressure
+        // costs more than the shorter traversal saves, so the plain form starts at the root
+        if (fp32 && K > 0)
+            hipLaunchKernelGGL((k_tree_walk<float, true>), dim3(slots), dim3(64), 0, s, A);
+        else if (fp32)
+            hipLaunchKernelGGL((k_tree_walk<float, false>), dim3(slots), dim3(64), 0, s, A);
         else
-            hipLaunchKernelGGL(k_tree_walk<double>, dim3(slots), dim3(64), 0, s, A);
+            hipLaunchKernelGGL((k_tree_walk<double, false>), dim3(slots), dim3(64), 0, s, A);
         DZS_TRY(dzs_check_launch(ctx, "tree_walk"));
     }
     DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 4, ctx->walk_counter + 1, sizeof(uint32_t),
