@@ -81,35 +81,75 @@ def copy_state(dst, src):
     dst.n = src.n
 
 
-# algorithmic bytes moved per launch, by kernel class (per particle N, per mesh cell C)
-def algorithmic_bytes(cls, N, C):
+# algorithmic bytes moved per launch, by kernel class (N particles, C mesh cells); in the
+# precision form mesh values are 4-byte reals / 8-byte complex instead of 8 / 16
+def algorithmic_bytes(cls, N, C, fp32=False):
+    r, c = (4, 8) if fp32 else (8, 16)
     return {
         "kick": 72 * N, "drift_lightcone": 72 * N, "morton_keys": 36 * N,
-        "pm_deposit": 28 * N + 8 * C, "pm_fft_x": 24 * C, "pm_fft_y": 32 * C,
-        "pm_fft_z_green": 32 * C, "pm_interp": 48 * N + 8 * C,
+        "pm_deposit": 28 * N + 8 * C,
+        # x pass: forward reads the 8-byte fixed-point mesh and writes complex; inverse reads
+        # complex and writes the real potential (the class averages both launches)
+        "pm_fft_x": ((8 + c) + (c + r)) * C // 2,
+        "pm_fft_y": 2 * c * C, "pm_fft_z_green": 2 * c * C,
+        "pm_interp": 48 * N + r * C,
     }.get(cls)
 
 
-def cpu_baseline(W, ics, box_o):
-    """The oracle timed on the host: one full force evaluation (PM on the full mesh plus the
-    direct-sum short range for a bounded sample of targets, extrapolated to N)."""
+HBM_CLASSES = ("pm_deposit", "pm_fft_x", "pm_fft_y", "pm_fft_z_green", "pm_interp", "kick",
+               "drift_lightcone")
+TRAFFIC_SOURCES = {"tree_walk": "tree.hip", "kick": "particles.hip",
+                   "drift_lightcone": "particles.hip"}
+
+
+def measured_traffic(prec_name, workload_is_default):
+    """Counter-measured HBM bytes per launch from the committed rocprofv3 summary, by kernel
+    class, for the default 128^3 workload only; a class whose sources changed since the
+    counters were taken gets None."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_128cube.md")
+    if not workload_is_default or not os.path.exists(path):
+        return {}
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return {}
+    doc = json.loads(m.group(1))
+    csrc = os.path.join(ROOT, "paper_2005_05328_amd", "csrc")
+
+    def same(f):
+        h = hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
+        return doc["source_sha256_16"].get(f) == h
+    out = {}
+    for cls, b in doc["bytes_per_launch"].get(prec_name, {}).items():
+        src = TRAFFIC_SOURCES.get(cls, "pm.hip")
+        out[cls] = b if (same(src) and same("internal.h")) else None
+    return out
+
+
+def cpu_baseline(W, ics, box_o, n_steps=8):
+    """The oracle timed on the host: its kick-drift-kick step (FP64 PM on the full mesh plus
+    the direct-sum short range for every particle, lightcone test) over the first n_steps
+    steps of the same schedule, on all particles."""
     import oracle
     oracle.build(force=False)
-    n_sample = 100000
-    rng = np.random.default_rng(1)
-    targets = np.sort(rng.choice(W["N"], n_sample, replace=False))
+    a = np.exp(np.linspace(math.log(W["a_init"]), 0.0, W["n_steps"] + 1))
+    g = oracle.total_force(ics.x, ics.y, ics.z, ics.mult, box_o, W["ng"], W["r_s"], W["r_cut"])
+    ps = ics
     t0 = time.perf_counter()
-    oracle.pm_force(ics.x, ics.y, ics.z, ics.mult, box_o, W["ng"], W["r_s"])
-    t_pm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.short_range(ics.x, ics.y, ics.z, ics.mult, box_o, W["r_s"], W["r_cut"], targets)
-    t_sr = time.perf_counter() - t0
-    t_total = t_pm + t_sr * W["N"] / n_sample
+    for s in range(n_steps):
+        fac = oracle.step_factors(float(a[s]), float(a[s + 1]))
+        fac.update(a0=float(a[s]), a1=float(a[s + 1]))
+        ps, g, _, _ = oracle.kdk_step(ps, g, box_o, fac, W["ng"], W["r_s"], W["r_cut"],
+                                      [0.0, 0.0, 0.0])
+    t = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": W["N"] / t_total, "unit": UNIT, "cores": cores, "kind": "oracle",
-            "sample": (f"one force evaluation of the z=49 initial state: full PM {W['ng']}^3 "
-                       f"({t_pm:.2f} s) + direct-sum short range on {n_sample} of {W['N']} "
-                       f"targets ({t_sr:.2f} s), extrapolated to all targets; FP64")}
+    return {"value": W["N"] * n_steps / t, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": (f"the oracle's FP64 kick-drift-kick step (full PM {W['ng']}^3, direct-sum "
+                       f"short range for all {W['N']} particles, lightcone test) over the first "
+                       f"{n_steps} of the 50 steps (z = 49 to {1 / a[n_steps] - 1:.1f}), "
+                       f"{t:.1f} s; OpenMP short range, single-threaded numpy FFT; the GPU "
+                       f"figure averages all 50 steps")}
 
 
 def main():
@@ -122,6 +162,9 @@ def main():
     ap.add_argument("--no-twin", action="store_true")
     ap.add_argument("--group", type=int, default=0, help="targets per wave group (power of 2)")
     ap.add_argument("--leaf", type=int, default=0, help="particles per tree leaf")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (the reference "
+                         "for scaling HBM byte counters), then exit")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp64: plain form; fp32: FP32 pair, mesh and FFT arithmetic")
     args = ap.parse_args()
@@ -130,6 +173,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}), flush=True)
+        return
     sys.path.insert(0, ROOT)
     import dzs_ics
     import paper_2005_05328_amd as dz
@@ -194,20 +246,36 @@ def main():
     dom = max(totals, key=totals.get)
     avg_ms, calls = kern[dom]
     fp32 = W["prec"] == dz.DZS_FP32
+    default = (args.n_side == 128 and K == 50 and args.warmup == 2 and not args.group
+               and not args.leaf)
+    traffic = measured_traffic(args.precision, default)
     if dom == "tree_walk":
         flops = FLOP_PER_INTERACTION * pairs / calls
         achieved = flops / (avg_ms * 1e-3) / 1e12
         peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
         roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
-                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic.get(dom),
                     "kernel": dom, "avg_ms": avg_ms,
                     "work_per_launch": f"{pairs / calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP"}
     else:
-        b = algorithmic_bytes(dom, N, C)
+        b = algorithmic_bytes(dom, N, C, fp32)
         achieved = (b / (avg_ms * 1e-3) / 1e9) if b else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
-                    "kernel": dom, "avg_ms": avg_ms}
+                    "frac": achieved / PEAK_HBM_GBS if achieved else None,
+                    "traffic": traffic.get(dom), "kernel": dom, "avg_ms": avg_ms}
+    # the HBM-bound kernels beside it: algorithmic GB/s against the 8 TB/s peak, and the
+    # counter-measured bytes where available
+    hbm = {}
+    for cls in HBM_CLASSES:
+        if cls not in kern or not kern[cls][1]:
+            continue
+        ms = kern[cls][0]
+        b = algorithmic_bytes(cls, N, C, fp32)
+        t = traffic.get(cls)
+        hbm[cls] = {"avg_ms": ms, "achieved_GBps": b / (ms * 1e-3) / 1e9,
+                    "frac": b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                    "traffic_bytes": t,
+                    "traffic_GBps": (t / (ms * 1e-3) / 1e9) if t else None}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -229,7 +297,7 @@ def main():
                                 + ("precision form (FP32 pair/mesh/FFT, FP64 state)" if fp32
                                    else "FP64 plain form")),
                    "particles": N, "mesh": W["ng"], "box": W["L"], "parallelism": "1 GPU"},
-        "roofline": roofline, "cpu_baseline": cpu, "dzs_twin": twin,
+        "roofline": roofline, "hbm_kernels": hbm, "cpu_baseline": cpu, "dzs_twin": twin,
         "pair_interactions_per_step": pairs / K, "lightcone_records": n_records,
         "particles_final": n_final,
         "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
