@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X DZS gravity step.
 
-Workload (the 128^3 configuration): 128^3 particles, periodic box L = 256 Mpc/h, PM mesh 256^3,
-split scale r_s = 1.25 mesh cells, cutoff 4.5 r_s, Zel'dovich start at z = 49 from a seeded
-Gaussian random field with a LCDM-shaped (BBKS, Omega_m = 0.3, sigma_8 = 0.8) spectrum,
-observer at the box corner, 50 log-spaced KDK steps to z = 0, all in the FP64 plain form.
-Each step is one kdk_step call: kick, drift + lightcone crossing output, DZS coarsening
-(2x2x2, theta = 0.1, b = 5 lambda; the host check skips the merge kernels at boundaries where
-no node can qualify), Morton sort, tree build, PM force, tree force (opening angle 0.5), kick.
+Default workload (the 128^3 configuration, `--workload c2`): 128^3 particles, periodic box
+L = 256 Mpc/h, PM mesh 256^3, split scale r_s = 1.25 mesh cells, cutoff 4.5 r_s, Zel'dovich start
+at z = 49 from a seeded Gaussian random field with a LCDM-shaped (BBKS, Omega_m = 0.3,
+sigma_8 = 0.8) spectrum, observer at the box corner, 50 log-spaced KDK steps to z = 0, all in
+the FP64 plain form.  Each step is one kdk_step call: kick, drift + lightcone crossing output,
+DZS coarsening (2x2x2, theta = 0.1, b = 5 lambda, l_max = 2 lambda; the host check skips the
+merge kernels at boundaries where no node can qualify), Morton sort, tree build, PM force,
+tree force (opening angle 0.5), kick.
 
 value = particle force updates per second = N * K / wall time of the K timed steps (inputs
-resident in HBM; the timed region is bracketed by torch.cuda.synchronize()).  The same K steps
-are then run as the full-resolution twin (no DZS) for the DZS/full-resolution wall-time ratio.
+resident in HBM; the timed region is bracketed by torch.cuda.synchronize()).  A twin run
+follows: the full-resolution run (no DZS) for the DZS/full-resolution wall-time ratio and the
+lightcone comparison, or (`--workload c3`) the FP64 plain form against the timed precision
+form, with force errors at the initial and final states.
+
+Other workloads: c3 = 512^3, L = 1000, mesh 512^3, precision form vs plain form (l_max =
+4 lambda); c5s = 256^3, L = 2000, mesh 256^3, 100 steps, precision form, DZS vs full
+resolution (the DZS geometry of the 1024^3 configuration at lower resolution); c5 = 1024^3,
+L = 2000, mesh 1024^3, 100 steps (use --steps to bound it).
 
 Prints ONE JSON line.  `--gpus N` with N > 1 is refused: this build runs on one GPU.
 """
@@ -40,13 +48,27 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def workload(n_side=128, L=256.0, ng=256):
+# workload presets: particles per side, box, mesh, seed, steps, l_max / lambda, form, twin
+PRESETS = {
+    "c2": dict(n_side=128, L=256.0, ng=256, seed=20050529, n_steps=50, lmax_over_lambda=2,
+               precision="fp64", twin="dzs"),
+    "c3": dict(n_side=512, L=1000.0, ng=512, seed=20050530, n_steps=50, lmax_over_lambda=4,
+               precision="fp32", twin="precision"),
+    "c5s": dict(n_side=256, L=2000.0, ng=256, seed=20050532, n_steps=100, lmax_over_lambda=4,
+                precision="fp32", twin="dzs"),
+    "c5": dict(n_side=1024, L=2000.0, ng=1024, seed=20050532, n_steps=100, lmax_over_lambda=4,
+               precision="fp32", twin="dzs"),
+}
+
+
+def workload(n_side=128, L=256.0, ng=256, seed=20050529, n_steps=50, lmax_over_lambda=2,
+             **_):
     import dzs_ics
     lam = L / n_side
     return dict(n_side=n_side, N=n_side ** 3, L=L, ng=ng, r_s=1.25 * L / ng,
                 r_cut=4.5 * 1.25 * L / ng, eps0=lam / 40, m0=dzs_ics.particle_mass(L, n_side ** 3),
-                lam=lam, a_init=1.0 / 50.0, n_steps=50, theta_tree=0.5, theta_dzs=0.1,
-                b=5 * lam, lmax_over_lambda=2, seed=20050529, leaf=16, group=32)
+                lam=lam, a_init=1.0 / 50.0, n_steps=n_steps, theta_tree=0.5, theta_dzs=0.1,
+                b=5 * lam, lmax_over_lambda=lmax_over_lambda, seed=seed, leaf=16, group=32)
 
 
 def k_min_for(n_side, j):
@@ -147,17 +169,117 @@ def cpu_baseline(W, ics, box_o, n_steps=8):
     return {"value": W["N"] * n_steps / t, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": (f"the oracle's FP64 kick-drift-kick step (full PM {W['ng']}^3, direct-sum "
                        f"short range for all {W['N']} particles, lightcone test) over the first "
-                       f"{n_steps} of the 50 steps (z = 49 to {1 / a[n_steps] - 1:.1f}), "
-                       f"{t:.1f} s; OpenMP short range, single-threaded numpy FFT; the GPU "
-                       f"figure averages all 50 steps")}
+                       f"{n_steps} of the {W['n_steps']} steps (z = 49 to "
+                       f"{1 / a[n_steps] - 1:.1f}), {t:.1f} s; OpenMP short range, "
+                       f"single-threaded numpy FFT; the GPU figure averages all timed steps")}
+
+
+# ---- twin-run diagnostics (measurement only: they run after the timed region) -------------
+
+def lightcone_records(ring):
+    """Device views of the records in a ring: ids, multiplicities, offsets d (n x 3)."""
+    import torch
+    n = min(int(ring.count.item()), ring.capacity)
+    rec = ring.buf[: 8 * n].view(n, 8)
+    ints = rec.view(torch.int32)[:, :2]
+    return ints[:, 0], ints[:, 1].to(torch.float64), rec[:, 2:5]
+
+
+def lightcone_density(ring, L, M):
+    """Mass (in particle masses) of the lightcone records deposited by cloud-in-cell onto an
+    M^3 mesh, each record at its crossing position wrapped into the box (observer at 0)."""
+    import torch
+    _, mult, d = lightcone_records(ring)
+    u = torch.remainder(d, L) * (M / L)
+    i0 = torch.floor(u)
+    f = u - i0
+    i0 = i0.to(torch.int64) % M
+    rho = torch.zeros(M ** 3, dtype=torch.float64, device=d.device)
+    for cx in (0, 1):
+        wx = f[:, 0] if cx else 1 - f[:, 0]
+        ix = (i0[:, 0] + cx) % M
+        for cy in (0, 1):
+            wy = f[:, 1] if cy else 1 - f[:, 1]
+            iy = (i0[:, 1] + cy) % M
+            for cz in (0, 1):
+                wz = f[:, 2] if cz else 1 - f[:, 2]
+                iz = (i0[:, 2] + cz) % M
+                rho.index_add_(0, (ix * M + iy) * M + iz, mult * wx * wy * wz)
+    return rho.view(M, M, M)
+
+
+def power_spectrum(rho, L, n_bins=16):
+    """P(k) of the density contrast in logarithmic bins from the fundamental mode to half
+    the Nyquist frequency (bin centres, power, mode counts)."""
+    import torch
+    M = rho.shape[0]
+    delta = rho / rho.mean() - 1.0
+    dk = torch.fft.rfftn(delta)
+    pk = (dk.real ** 2 + dk.imag ** 2) * (L ** 3 / M ** 6)
+    kf = 2 * math.pi / L
+    n1 = torch.fft.fftfreq(M, 1.0 / M, device=rho.device, dtype=torch.float64)
+    n3 = torch.fft.rfftfreq(M, 1.0 / M, device=rho.device, dtype=torch.float64)
+    kk = kf * torch.sqrt(n1[:, None, None] ** 2 + n1[None, :, None] ** 2 + n3[None, None, :] ** 2)
+    edges = torch.logspace(math.log10(kf), math.log10(kf * M / 4), n_bins + 1,
+                           dtype=torch.float64, device=rho.device)
+    idx = torch.bucketize(kk.flatten(), edges) - 1
+    ok = (idx >= 0) & (idx < n_bins) & (kk.flatten() > 0)
+    p = torch.zeros(n_bins, dtype=torch.float64, device=rho.device)
+    c = torch.zeros(n_bins, dtype=torch.float64, device=rho.device)
+    p.index_add_(0, idx[ok], pk.flatten()[ok])
+    c.index_add_(0, idx[ok], torch.ones_like(pk.flatten()[ok]))
+    keep = c > 0
+    kc = torch.sqrt(edges[:-1] * edges[1:])
+    return kc[keep].cpu().numpy(), (p[keep] / c[keep]).cpu().numpy(), c[keep].cpu().numpy()
+
+
+def compare_lightcones(ring_a, rho_a, ring_b, rho_b, L, eps0):
+    """M-LC (max |P_a/P_b - 1| over the bins), rms pixel density difference, and the
+    displacement percentiles of records present in both runs, in units of eps0."""
+    import torch
+    k, pa, _ = power_spectrum(rho_a, L)
+    _, pb, _ = power_spectrum(rho_b, L)
+    ratio = pa / pb - 1.0
+    rms = float(torch.sqrt(torch.mean((rho_a - rho_b) ** 2)) / rho_b.mean())
+    ia, _, da = lightcone_records(ring_a)
+    ib, _, db = lightcone_records(ring_b)
+    sa, oa = torch.sort(ia.to(torch.int64))
+    sb, ob = torch.sort(ib.to(torch.int64))
+    common = torch.isin(sa, sb)
+    pos = torch.searchsorted(sb, sa[common])
+    dx = da[oa[common]] - db[ob[pos]]
+    dx = dx - L * torch.round(dx / L)
+    r = (torch.sqrt((dx ** 2).sum(1)) / eps0).cpu().numpy()
+    pct = {f"p{q}": float(np.percentile(r, q)) for q in (50, 99, 99.9)} if r.size else {}
+    pct["max"] = float(r.max()) if r.size else None
+    return {"M_LC_max_abs_P_ratio_minus_1": float(np.abs(ratio).max()),
+            "P_ratio_minus_1_by_bin": [round(float(v), 8) for v in ratio],
+            "k_bins_h_per_Mpc": [round(float(v), 5) for v in k],
+            "rms_pixel_density_difference": rms,
+            "records": [int(ia.numel()), int(ib.numel())], "records_matched": int(r.size),
+            "displacement_over_eps0": pct}
+
+
+def force_error(g, ref):
+    """rms relative error over particles and the 99th percentile of the per-particle
+    relative error |g - ref| / |ref|."""
+    import torch
+    e = torch.sqrt(((g - ref) ** 2).sum(0))
+    m = torch.sqrt((ref ** 2).sum(0))
+    rms = float(torch.sqrt((e ** 2).mean() / (m ** 2).mean()))
+    rel = (e / torch.clamp(m, min=1e-300)).cpu().numpy()
+    return {"rms_rel": rms, "p99_rel": float(np.percentile(rel, 99)),
+            "max_rel": float(rel.max())}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--workload", choices=sorted(PRESETS), default="c2")
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the whole run)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n-side", type=int, default=128)
+    ap.add_argument("--n-side", type=int, default=0,
+                    help="particles per side (box and mesh scaled with it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-twin", action="store_true")
     ap.add_argument("--group", type=int, default=0, help="targets per wave group (power of 2)")
@@ -165,8 +287,9 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "for scaling HBM byte counters), then exit")
-    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
-                    help="fp64: plain form; fp32: FP32 pair, mesh and FFT arithmetic")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default=None,
+                    help="fp64: plain form; fp32: FP32 pair, mesh and FFT arithmetic "
+                         "(default: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -186,69 +309,109 @@ def main():
     import dzs_ics
     import paper_2005_05328_amd as dz
 
-    W = workload(n_side=args.n_side, L=256.0 * args.n_side / 128, ng=2 * args.n_side)
+    P = dict(PRESETS[args.workload])
+    if args.n_side:
+        f = args.n_side / P["n_side"]
+        P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
+    W = workload(**P)
     if args.group:
         W["group"] = args.group
     if args.leaf:
         W["leaf"] = args.leaf
-    W["prec"] = dz.DZS_FP32 if args.precision == "fp32" else dz.DZS_FP64
-    K = max(1, min(args.steps, W["n_steps"]))
-    log(f"workload N={W['N']} L={W['L']} ng={W['ng']} steps={K} warmup={args.warmup}")
+    prec_name = args.precision or P["precision"]
+    W["prec"] = dz.DZS_FP32 if prec_name == "fp32" else dz.DZS_FP64
+    fp32 = W["prec"] == dz.DZS_FP32
+    twin_kind = None if args.no_twin else P["twin"]
+    K = max(1, min(args.steps or W["n_steps"], W["n_steps"]))
+    log(f"workload {args.workload}: N={W['N']} L={W['L']} ng={W['ng']} {prec_name} steps={K} "
+        f"warmup={args.warmup} twin={twin_kind}")
     ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
+    log("initial conditions ready")
     box = dz.make_box(W["L"], W["m0"], W["eps0"])
     ctx = dz.Context(W["N"], W["ng"])
     st0 = dz.State.from_host(ics)
-    ctx.pm_force(box, st0, dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, 0))
-    ctx.tree_force(box, st0, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"],
-                                           W["group"], W["prec"], 1))
-    torch.cuda.synchronize()
-    params_dzs = make_params(dz, W, True)
-    params_std = make_params(dz, W, False)
+
+    def force(state, prec):
+        ctx.pm_force(box, state, dz.PMParams(W["ng"], prec, W["r_s"], 0, 0))
+        ctx.tree_force(box, state, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"],
+                                                 W["leaf"], W["group"], prec, 1))
+        torch.cuda.synchronize()
+        return torch.stack([state.gx[: state.n], state.gy[: state.n], state.gz[: state.n]]).clone()
+
+    g0 = force(st0, W["prec"])
+    twin_prec = W["prec"]
+    if twin_kind == "precision":
+        twin_prec = dz.DZS_FP64
+    g0_twin = force(st0, twin_prec) if twin_prec != W["prec"] else g0
+    ic_force_error = force_error(g0, g0_twin) if twin_kind == "precision" else None
+    params_main = make_params(dz, W, True)
+    W_twin = dict(W, prec=twin_prec)
+    params_twin = make_params(dz, W_twin, twin_kind != "dzs")
     st = dz.State(W["N"])
     ring = dz.LCRing(W["N"])
+    ring_twin = dz.LCRing(W["N"]) if twin_kind else None
 
-    def run(params, steps, timed):
+    def run(params, steps, timed, g_init, rg):
         copy_state(st, st0)
-        ring.reset()
+        for a_, k in enumerate(("gx", "gy", "gz")):
+            getattr(st, k)[: st0.n].copy_(g_init[a_])
+        rg.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         merged = 0
-        for s in range(steps):
-            rep = ctx.kdk_step(box, st, params[s], ring)
+        for s_ in range(steps):
+            rep = ctx.kdk_step(box, st, params[s_], rg)
             merged += int(rep.n_groups)
-            if timed and (s + 1) % 10 == 0:
-                log(f"  step {s + 1}/{steps}")
+            if timed and (s_ + 1) % 10 == 0:
+                log(f"  step {s_ + 1}/{steps}")
         torch.cuda.synchronize()
         return time.perf_counter() - t0, merged
 
     log("warmup")
-    run(params_dzs, args.warmup, False)
-    log("timed DZS run")
+    run(params_main, args.warmup, False, g0, ring)
+    log("timed run")
     ctx.timing(enable=True, reset=True)
     ctx.pair_interactions(reset=True)
-    t_dzs, merged = run(params_dzs, K, True)
+    t_main, merged = run(params_main, K, True, g0, ring)
     kern = ctx.timing(enable=False, reset=True)
     pairs = ctx.pair_interactions(reset=True)
     n_records = int(ring.count.item())
-    final_dzs = {k: getattr(st, k)[: st.n].clone() for k in ("x", "y", "z", "px", "py", "pz")}
     n_final = st.n
+    M = min(W["ng"], 256)
     twin = None
-    if not args.no_twin:
-        log("timed full-resolution twin")
-        t_std, _ = run(params_std, K, True)
-        same = n_final == st.n and all(torch.equal(final_dzs[k], getattr(st, k)[: st.n])
-                                       for k in final_dzs)
-        twin = {"std_s": t_std, "dzs_s": t_dzs, "dzs_over_std": t_dzs / t_std,
-                "twins_bitwise_identical": bool(same), "merged_nodes": merged}
+    if twin_kind:
+        final_main = {k: getattr(st, k)[: st.n].clone() for k in ("x", "y", "z", "px", "py", "pz")}
+        rho_main = lightcone_density(ring, W["L"], M)
+        log(f"timed twin ({'full resolution' if twin_kind == 'dzs' else 'FP64 plain form'})")
+        t_twin, merged_twin = run(params_twin, K, True, g0_twin, ring_twin)
+        rho_twin = lightcone_density(ring_twin, W["L"], M)
+        lc = compare_lightcones(ring, rho_main, ring_twin, rho_twin, W["L"], W["eps0"])
+        if twin_kind == "dzs":
+            same = n_final == st.n and all(torch.equal(final_main[k], getattr(st, k)[: st.n])
+                                           for k in final_main)
+            twin = {"kind": "DZS vs full resolution", "std_s": t_twin, "dzs_s": t_main,
+                    "dzs_over_std": t_main / t_twin, "twins_bitwise_identical": bool(same),
+                    "merged_nodes": merged, "particles_final": [n_final, st.n],
+                    "lightcone": lc}
+        else:
+            del final_main
+            log("forces on the final plain-form state in both forms")
+            g64 = force(st, dz.DZS_FP64)
+            g32 = force(st, dz.DZS_FP32)
+            twin = {"kind": "precision form vs FP64 plain form", "precision_s": t_main,
+                    "plain_s": t_twin, "precision_over_plain": t_main / t_twin,
+                    "merged_nodes": [merged, merged_twin],
+                    "force_error_initial": ic_force_error,
+                    "force_error_final_state": force_error(g32, g64),
+                    "lightcone": lc}
 
     N, C = W["N"], W["ng"] ** 3
     totals = {c: ms * calls for c, (ms, calls) in kern.items() if calls}
     dom = max(totals, key=totals.get)
     avg_ms, calls = kern[dom]
-    fp32 = W["prec"] == dz.DZS_FP32
-    default = (args.n_side == 128 and K == 50 and args.warmup == 2 and not args.group
-               and not args.leaf)
-    traffic = measured_traffic(args.precision, default)
+    default = (args.workload == "c2" and not args.n_side and K == 50 and args.warmup == 2
+               and not args.group and not args.leaf)
+    traffic = measured_traffic(prec_name, default)
     if dom == "tree_walk":
         flops = FLOP_PER_INTERACTION * pairs / calls
         achieved = flops / (avg_ms * 1e-3) / 1e12
@@ -284,20 +447,22 @@ def main():
         box_o = oracle.Box(L=W["L"], m0=W["m0"], eps0=W["eps0"])
         cpu = cpu_baseline(W, ics, box_o)
 
-    ms_per_step = 1e3 * t_dzs / K
+    ms_per_step = 1e3 * t_main / K
     out = {
-        "metric": METRIC, "value": N * K / t_dzs, "unit": UNIT, "n_gpus": 1, "steps": K,
+        "metric": METRIC, "value": N * K / t_main, "unit": UNIT, "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": (f"{W['n_side']}^3 particles, L={W['L']:g} Mpc/h, mesh "
                                 f"{W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, "
-                                f"{K} of 50 log KDK steps to z=0, DZS 2x2x2 + lightcone, "
+                                f"{K} of {W['n_steps']} log KDK steps to z=0, DZS 2x2x2 "
+                                f"(l_max {W['lmax_over_lambda']} lambda) + lightcone, "
                                 f"tree theta {W['theta_tree']}, "
                                 + ("precision form (FP32 pair/mesh/FFT, FP64 state)" if fp32
                                    else "FP64 plain form")),
-                   "particles": N, "mesh": W["ng"], "box": W["L"], "parallelism": "1 GPU"},
-        "roofline": roofline, "hbm_kernels": hbm, "cpu_baseline": cpu, "dzs_twin": twin,
+                   "preset": args.workload, "particles": N, "mesh": W["ng"], "box": W["L"],
+                   "parallelism": "1 GPU"},
+        "roofline": roofline, "hbm_kernels": hbm, "cpu_baseline": cpu, "twin": twin,
         "pair_interactions_per_step": pairs / K, "lightcone_records": n_records,
         "particles_final": n_final,
         "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
