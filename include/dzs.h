@@ -134,8 +134,10 @@ typedef struct {
 } dzs_tree_params;
 
 /* Lightcone crossing over one drift a0 -> a1 (positions at a0, momenta constant).
- * d0 = min-image(x - x_obs); d1 = d0 + p D.  A particle is emitted iff
- * |d0|^2 - chi2_0 < 0 <= |d1|^2 - chi2_1 (the sphere of radius chi(a) shrinks with a).
+ * d0 = min-image(x - x_obs); d1 = min-image(wrap(x + p D) - x_obs), the offset the next
+ * drift starts from.  A particle is emitted iff |d0|^2 - chi2_0 < 0 <= |d1|^2 - chi2_1 (the
+ * sphere of radius chi(a) shrinks with a); since one drift's end test is the next drift's
+ * start test, a particle is emitted once over a run of consecutive drifts.
  * The crossing time solves |d0 + p D(a0,a)| = chi(a) on [a0, a1] using the Chebyshev
  * series of chi(a) and D(a0,a) on [a0, a1] (dzs_step_factors fills all of this). */
 typedef struct {

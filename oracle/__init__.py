@@ -335,13 +335,16 @@ def lightcone_select(x, y, z, px, py, pz, L, x_obs, D, chi2_0, chi2_1):
 
     The lightcone sphere (radius chi(a), the comoving distance the light reaching the observer
     at a = 1 left from at a) shrinks as a grows.  With d0 the minimum-image offset from the
-    observer at a_n, and d1 = d0 + p D at a_{n+1}, a particle is on the past lightcone when
+    observer at a_n, and d1 the minimum-image offset of the drifted, wrapped position at
+    a_{n+1} (exactly the next drift's d0), a particle is on the past lightcone when
     f = |d|^2 - chi^2 changes sign from negative to non-negative: emit iff f0 < 0 <= f1.
+    Because f1 of one drift is f0 of the next, each particle is emitted once.
     Returns (mask, d0 (3,n), f0, f1).
     """
     d0 = np.stack([min_image(_f64(c) - xo, L) for c, xo in zip((x, y, z), x_obs)])
     pp = np.stack([_f64(px), _f64(py), _f64(pz)])
-    d1 = d0 + pp * D
+    d1 = np.stack([min_image(drift(_f64(c), pc, D, L) - xo, L)
+                   for c, pc, xo in zip((x, y, z), pp, x_obs)])
     f0 = (d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2]) - chi2_0
     f1 = (d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]) - chi2_1
     mask = (f0 < 0) & (f1 >= 0)

@@ -96,12 +96,17 @@ __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
     const double xi = x[i], yi = y[i], zi = z[i];
     const double pxi = px[i], pyi = py[i], pzi = pz[i];
     const double sx = pxi * A.D, sy = pyi * A.D, sz = pzi * A.D;
+    const double nx = dzs_wrap(xi + sx, L), ny = dzs_wrap(yi + sy, L), nz = dzs_wrap(zi + sz, L);
     if (do_lc) {
         const double dx = dzs_min_image(xi - A.xo[0], L);
         const double dy = dzs_min_image(yi - A.xo[1], L);
         const double dz = dzs_min_image(zi - A.xo[2], L);
         const double f0 = (dx * dx + dy * dy + dz * dz) - A.chi2_0;
-        const double ex = dx + sx, ey = dy + sy, ez = dz + sz;
+        // the end-of-drift test uses the offset the next drift starts from (the drifted,
+        // wrapped position, minimum image): f1 here is f0 there, so a particle is emitted once
+        const double ex = dzs_min_image(nx - A.xo[0], L);
+        const double ey = dzs_min_image(ny - A.xo[1], L);
+        const double ez = dzs_min_image(nz - A.xo[2], L);
         const double f1 = (ex * ex + ey * ey + ez * ez) - A.chi2_1;
         if (f0 < 0.0 && f1 >= 0.0) {
             double cx, cy, cz;
@@ -125,9 +130,9 @@ __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
         }
     }
     if (do_drift) {
-        x[i] = dzs_wrap(xi + sx, L);
-        y[i] = dzs_wrap(yi + sy, L);
-        z[i] = dzs_wrap(zi + sz, L);
+        x[i] = nx;
+        y[i] = ny;
+        z[i] = nz;
     }
 }
 

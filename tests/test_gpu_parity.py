@@ -467,3 +467,44 @@ def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
             dp = dp - fac["K2"] * (gg[a] - ref_g[a, r])
         assert np.abs(dp).max() <= 1e-9 * scale
     assert ring.records()["count"] == 0   # chi(z=49) >> L: no particle on the lightcone
+
+
+@pytest.mark.parametrize("coarsen", [False, True])
+def test_lightcone_emits_every_particle_once_over_a_run(dz, ctx, coarsen):
+    """A 32^3 box (L = 1000, observer at the corner) run through 50 log steps to z = 0: the
+    shrinking sphere passes every particle once, so every id is emitted exactly once with its
+    own multiplicity 1; with DZS the merged particles lie outside the sphere when they form
+    and never cross again."""
+    import torch
+    n_side, L, ng = 32, 1000.0, 64
+    ps = dzs_ics.zeldovich(n_side, L, 0.02, seed=20050533, spectrum="bbks")
+    lam = L / n_side
+    box, _ = _box(dz, L, ps.n, n_side)
+    r_s = 1.25 * L / ng
+    a = np.exp(np.linspace(math.log(0.02), 0.0, 51))
+    st = dz.State.from_host(ps)
+    ctx.pm_force(box, st, dz.PMParams(ng, dz.DZS_FP64, r_s, 0, 0))
+    ctx.tree_force(box, st, dz.TreeParams(r_s, 4.5 * r_s, 0.5, 8, 32, dz.DZS_FP64, 1))
+    ring = dz.LCRing(2 * ps.n)
+    ring.reset()
+    merged = 0
+    for s in range(50):
+        sp = dz.step_factors(float(a[s]), float(a[s + 1]), 0.3)
+        sp.do_lightcone = 1
+        sp.do_coarsen = 1 if (coarsen and s < 49) else 0
+        sp.coarsen.R_lc = math.sqrt(sp.lc.chi2_1)
+        sp.coarsen.b, sp.coarsen.theta, sp.coarsen.k_min = 5 * lam, 1.0, 4
+        sp.pm = dz.PMParams(ng, dz.DZS_FP64, r_s, 0, 0)
+        sp.tree = dz.TreeParams(r_s, 4.5 * r_s, 0.5, 8, 32, dz.DZS_FP64, 0)
+        merged += int(ctx.kdk_step(box, st, sp, ring).n_groups)
+    torch.cuda.synchronize()
+    rec = ring.records()
+    _log(f"lightcone run coarsen={coarsen}: {rec['count']} records, merged nodes {merged}, "
+         f"final n {st.n}")
+    assert rec["overflow"] == 0
+    if coarsen:
+        assert merged > 0 and st.n < ps.n
+    ids = np.sort(rec["id"])
+    assert np.array_equal(ids, np.sort(ps.id))
+    assert np.all(rec["mult"] == 1)
+    assert np.all((rec["a_cross"] >= 0.02) & (rec["a_cross"] <= 1.0))

@@ -168,3 +168,27 @@ def test_lightcone_moving_particles_record_consistency():
         assert a0 <= ac <= a1
         dn = np.linalg.norm(rec["d"][r])
         assert abs(dn - chi_closed(ac)) <= 1e-9 * dn
+
+
+def test_lightcone_particle_moving_through_the_antipode_is_emitted_once():
+    """A particle that drifts across the face of the periodic cell opposite the observer just
+    as the sphere reaches it: its minimum-image distance shrinks from 49.9 to 49.9 via 50.
+    Unwrapped, the end-of-drift distance would be 50.1 (outside a sphere of radius 50): it
+    would be emitted in the first drift and again in the second, when the sphere passes its
+    true distance.  Each particle crosses the past lightcone once (Sec. 3.1.3), so the test at
+    the end of a drift must be the test at the start of the next."""
+    L = 100.0
+    x, y, z = np.array([49.9]), np.array([0.0]), np.array([0.0])
+    px, py, pz = np.array([1.0]), np.array([0.0]), np.array([0.0])
+    D = 0.2                          # one drift moves the particle by 0.2 along x
+    chis = [50.05, 50.0, 49.6]
+    emitted = 0
+    for n in range(2):
+        mask, _, f0, f1 = oracle.lightcone_select(x, y, z, px, py, pz, L, [0.0, 0.0, 0.0], D,
+                                                  chis[n] ** 2, chis[n + 1] ** 2)
+        emitted += int(mask[0])
+        x = oracle.drift(x, px, D, L)
+        # the next drift starts from exactly this end-of-drift test value
+        d_next = oracle.min_image(x, L)
+        assert float(d_next[0] ** 2 - chis[n + 1] ** 2) == float(f1[0])
+    assert emitted == 1
