@@ -229,6 +229,39 @@ dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *state,
                     const dzs_step_params *prm, dzs_lc_ring *ring, dzs_coarsen_report *report,
                     void *stream);
 
+/* ---- many boxes in one step ----------------------------------------------------------- */
+
+#define DZS_BATCH_MAX 512
+
+/* A batch of independent periodic boxes (an ensemble of uneven particle counts, e.g. after
+ * per-box DZS coarsening) advanced together: box b owns particles [first[b], first[b+1]) of
+ * one state.  All host arrays, read during the call only. */
+typedef struct {
+    uint32_t n_boxes;       /* 1 .. DZS_BATCH_MAX */
+    uint32_t reserved;
+    const dzs_box *boxes;   /* [n_boxes]: L, m0, eps0 of each box; G equal for all */
+    const uint64_t *first;  /* [n_boxes + 1]: first[0] = 0, non-decreasing, first[n_boxes] =
+                               state->n */
+    const int32_t *ng;      /* [n_boxes]: PM mesh side of each box (2^a 3^b, 8 .. 1024); the
+                               meshes together need sum ng^3 <= max_mesh_side^3 of the context */
+    const double *r_s;      /* [n_boxes]: split scale of each box */
+    const double *r_cut;    /* [n_boxes]: cutoff, r_cut < L/2, r_cut <= 5 r_s, the same
+                               r_cut / r_s for every box */
+} dzs_batch;
+
+/* One kick-drift-kick step a0 -> a1 of every box of a batch, as kdk_step does for one box
+ * (the per-box physics is the same), with one launch of each kernel for all boxes: one
+ * sort of keys that carry the box in their top three octal digits (2^18 cells per side
+ * below them), one tree over all boxes (each box below the node of its digits), one walk
+ * over every box's target groups, one deposit and one interpolation, and one set of FFT
+ * launches per distinct mesh side.  prm supplies K1, K2, the lightcone drift (x_obs, chi^2,
+ * Chebyshev series; every box's particles are tested against the same sphere), the PM
+ * precision and the tree's opening angle, leaf and group size and precision (r_s and r_cut
+ * come from the batch); do_coarsen must be 0 (coarsen each box with dzs_coarsen).  Each
+ * box's particles are left Morton-sorted within its range.  Synchronises the stream. */
+dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_particles *state,
+                          const dzs_step_params *prm, dzs_lc_ring *ring, void *stream);
+
 /* ---- parts of the path, exposed for testing and measurement --------------------------- */
 
 /* Morton keys (21 bits per dimension, x in the highest bit of each triple) of the

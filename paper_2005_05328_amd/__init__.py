@@ -207,6 +207,22 @@ class Context:
         st.n = int(v.n)
         return rep
 
+    def kdk_step_batch(self, boxes, first, ng, r_s, r_cut, st: State, prm: StepParams,
+                       ring: LCRing | None = None, stream=None):
+        """One step of every box of a batch; box b owns st's particles first[b]:first[b+1]."""
+        nb = len(boxes)
+        arr_box = (Box * nb)(*boxes)
+        arr_first = (C.c_uint64 * (nb + 1))(*[int(v) for v in first])
+        arr_ng = (C.c_int32 * nb)(*[int(v) for v in ng])
+        arr_rs = (C.c_double * nb)(*[float(v) for v in r_s])
+        arr_rc = (C.c_double * nb)(*[float(v) for v in r_cut])
+        b = _abi.Batch(nb, 0, arr_box, arr_first, arr_ng, arr_rs, arr_rc)
+        v = st.view()
+        rv = C.byref(ring.view()) if ring is not None else None
+        self._check("kdk_step_batch", _lib.kdk_step_batch(self._h, C.byref(b), C.byref(v),
+                                                          C.byref(prm), rv,
+                                                          _stream_handle(stream)))
+
     # ---- parts of the path
     def morton_keys(self, box: Box, st: State, keys, stream=None):
         v = st.view()

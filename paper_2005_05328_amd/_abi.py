@@ -18,7 +18,8 @@ DZS_FP64, DZS_FP32 = 0, 1
 # every entry point include/dzs.h declares
 EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_factors",
            "dzs_coarsen", "pm_force", "tree_force", "lightcone_emit", "kdk_step",
-           "dzs_morton_keys", "dzs_sort_state", "dzs_counters", "dzs_timing")
+           "kdk_step_batch", "dzs_morton_keys", "dzs_sort_state", "dzs_counters", "dzs_timing")
+DZS_BATCH_MAX = 512
 
 
 class Capacity(C.Structure):
@@ -79,6 +80,12 @@ class StepParams(C.Structure):
                 ("coarsen", CoarsenParams), ("pm", PMParams), ("tree", TreeParams)]
 
 
+class Batch(C.Structure):
+    _fields_ = [("n_boxes", C.c_uint32), ("reserved", C.c_uint32), ("boxes", C.POINTER(Box)),
+                ("first", C.POINTER(C.c_uint64)), ("ng", C.POINTER(C.c_int32)),
+                ("r_s", C.POINTER(C.c_double)), ("r_cut", C.POINTER(C.c_double))]
+
+
 assert C.sizeof(LCRecord) == 64
 
 
@@ -104,13 +111,16 @@ def load():
                                  C.POINTER(LCRing), P]
     L.kdk_step.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(StepParams),
                            C.POINTER(LCRing), C.POINTER(CoarsenReport), P]
+    L.kdk_step_batch.argtypes = [P, C.POINTER(Batch), C.POINTER(Particles), C.POINTER(StepParams),
+                                 C.POINTER(LCRing), P]
     L.dzs_morton_keys.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), P, P]
     L.dzs_sort_state.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), i32, P, P]
     L.dzs_counters.argtypes = [P, i32, C.POINTER(C.c_uint64)]
     L.dzs_timing.argtypes = [P, i32, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                              C.POINTER(C.c_uint64), i32]
     for name in ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_step_factors", "dzs_coarsen",
-                 "pm_force", "tree_force", "lightcone_emit", "kdk_step", "dzs_morton_keys",
+                 "pm_force", "tree_force", "lightcone_emit", "kdk_step", "kdk_step_batch",
+                 "dzs_morton_keys",
                  "dzs_sort_state", "dzs_counters", "dzs_timing"):
         getattr(L, name).restype = st
     return L

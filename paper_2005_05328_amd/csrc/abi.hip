@@ -138,7 +138,8 @@ static void release(dzs_ctx *ctx) {
                     ctx->nd_bmax, ctx->nd_hmax, ctx->frontier, ctx->frontier_next,
                     ctx->fr_nchild, ctx->fr_ninternal, ctx->fr_child_off, ctx->fr_int_off,
                     ctx->child_bounds, ctx->grp_flag, ctx->grp_scan, ctx->grp_first,
-                    ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                    ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl,
+                    ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
                     ctx->pm_tables, ctx->dz_head, ctx->dz_flag, ctx->dz_scan, ctx->dz_new,
                     ctx->dz_newmult, ctx->dz_newid, ctx->dz_perm, ctx->d_small};
     for (void *p : ptrs)
@@ -146,6 +147,8 @@ static void release(dzs_ctx *ctx) {
             (void)hipFree(p);
     if (ctx->h_small)
         (void)hipHostFree(ctx->h_small);
+    if (ctx->batch_box_h)
+        (void)hipHostFree(ctx->batch_box_h);
     if (ctx->timers) {
         for (int i = 0; i < dzs_timer_pool::CAP; ++i) {
             (void)hipEventDestroy(ctx->timers->start[i]);
@@ -209,6 +212,14 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->walk_counter, 64));
     DZS_HIP(c, hipMemset(c->walk_counter, 0, 64 * sizeof(uint32_t)));
     DZS_TRY(alloc(c, &c->cell_node, 1ull << (3 * DZS_CELL_K_MAX)));
+    DZS_TRY(alloc(c, &c->batch_box, DZS_BATCH_MAX));
+    DZS_TRY(alloc(c, &c->batch_first, DZS_BATCH_MAX + 1));
+    DZS_TRY(alloc(c, &c->batch_members, DZS_BATCH_MAX));
+    {
+        void *hb = nullptr;
+        DZS_HIP(c, hipHostMalloc(&hb, sizeof(dzs_bbox) * DZS_BATCH_MAX, hipHostMallocDefault));
+        c->batch_box_h = (dzs_bbox *)hb;
+    }
     DZS_TRY(alloc(c, &c->cell_dl, 1ull << (3 * DZS_CELL_K_MAX)));
     if (ng > 0) {
         DZS_TRY(alloc(c, &c->mesh_q, ng3));
@@ -501,4 +512,99 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
         DZS_TRY(dzs_launch_kick(ctx, st, prm->K2, s));
     }
     return DZS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// batched step
+// ---------------------------------------------------------------------------------------
+extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_particles *st,
+                                     const dzs_step_params *prm, dzs_lc_ring *ring,
+                                     void *stream) {
+    if (!ctx)
+        return DZS_EINVAL;
+    ctx->err[0] = 0;
+    if (!batch || !st || !prm || !batch->boxes || !batch->first || !batch->ng || !batch->r_s ||
+        !batch->r_cut)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: null argument");
+    const uint32_t nb = batch->n_boxes;
+    if (nb < 1 || nb > DZS_BATCH_MAX)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: need 1 <= n_boxes <= %d", DZS_BATCH_MAX);
+    if (batch->first[0] != 0 || batch->first[nb] != st->n)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: first[0] must be 0 and first[n_boxes] = n");
+    if (st->n > st->capacity || st->n > ctx->cap_n || st->n >= (1ull << 32))
+        return dzs_fail(ctx, DZS_ECAPACITY, "batch: %llu particles exceed the capacity",
+                        (unsigned long long)st->n);
+    if (st->n > 0 && (!st->x || !st->y || !st->z || !st->px || !st->py || !st->pz || !st->gx ||
+                      !st->gy || !st->gz || !st->mult || !st->id || !st->type))
+        return dzs_fail(ctx, DZS_EINVAL, "batch: null state array");
+    if (prm->do_coarsen)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: coarsening runs per box (dzs_coarsen), not in "
+                        "the batched step");
+    dzs_tree_params t, t_in = prm->tree;
+    t_in.r_s = batch->r_s[0];
+    t_in.r_cut = batch->r_cut[0];
+    DZS_TRY(check_tree(ctx, &batch->boxes[0], &t_in, &t));
+    if (prm->pm.precision != DZS_FP64 && prm->pm.precision != DZS_FP32)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: PM precision must be DZS_FP64 or DZS_FP32");
+    if (prm->do_lightcone)
+        DZS_TRY(check_lc(ctx, &prm->lc, ring));
+    const double ratio = batch->r_cut[0] / batch->r_s[0];
+    dzs_bbox *hb = ctx->batch_box_h;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const dzs_box &bx = batch->boxes[b];
+        const double rs = batch->r_s[b], rc = batch->r_cut[b];
+        if (batch->first[b + 1] < batch->first[b])
+            return dzs_fail(ctx, DZS_EINVAL, "batch: first[] must not decrease");
+        if (!(bx.L > 0.0) || !(bx.m0 > 0.0) || !(bx.eps0 > 0.0) || bx.G != batch->boxes[0].G)
+            return dzs_fail(ctx, DZS_EINVAL, "batch: box %u needs L, m0, eps0 > 0 and the same G "
+                            "as box 0", b);
+        if (!(rs > 0.0) || !(rc > 0.0) || !(rc < 0.5 * bx.L) || rc > 5.0 * rs ||
+            fabs(rc / rs - ratio) > 1e-12 * ratio)
+            return dzs_fail(ctx, DZS_EINVAL, "batch: box %u needs 0 < r_cut < L/2, r_cut <= 5 r_s "
+                            "and the r_cut / r_s of box 0", b);
+        dzs_bbox &h = hb[b];
+        memset(&h, 0, sizeof(h));
+        h.L = bx.L;
+        h.halfL = 0.5 * bx.L;
+        h.m0 = bx.m0;
+        h.h0 = 2.8 * bx.eps0;
+        h.G = bx.G;
+        h.r_s = rs;
+        h.r_cut = rc;
+        h.rcut2 = rc * rc;
+        h.rs_inv = 1.0 / rs;
+        h.rs_inv2 = h.rs_inv * h.rs_inv;
+        h.wide_limit = h.halfL - rc;
+        h.first = batch->first[b];
+        h.count = batch->first[b + 1] - batch->first[b];
+        h.ng = batch->ng[b];
+        h.root = 0xffffffffu;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    DZS_TRY(dzs_pm_batch_prepare(ctx, nb, hb, s));
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_box, hb, sizeof(dzs_bbox) * nb, hipMemcpyHostToDevice,
+                                s));
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_first, batch->first, sizeof(uint64_t) * (nb + 1),
+                                hipMemcpyHostToDevice, s));
+    if (st->n == 0)
+        return DZS_OK;
+
+    DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s));
+    DZS_TRY(dzs_launch_drift_lc(ctx, &batch->boxes[0], st, &prm->lc, ring, prm->do_lightcone, 1,
+                                s, true, nb));
+    // keys with the box on top, one sort for every box: each box stays in its range
+    DZS_TRY(dzs_launch_keys(ctx, st->x, st->y, st->z, st->n, 1.0, ctx->key, ctx->idx, s, true,
+                            nb));
+    DZS_TRY(dzs_radix_sort(ctx, st->n, s));
+    DZS_TRY(dzs_permute_state(ctx, st, ctx->idx, 0, s));
+    DZS_TRY(dzs_tree_build_ex(ctx, &batch->boxes[0], st->n, st->x, st->y, st->z, st->mult,
+                              t.leaf_size, t.group_size, DZS_BATCH_LEVELS, ctx->batch_box, s));
+    DZS_TRY(dzs_batch_roots(ctx, ctx->batch_box, s));
+    DZS_TRY(dzs_pm_run_batch(ctx, st, prm->pm.precision, ctx->batch_box, batch->boxes[0].G, s));
+    t.r_s = batch->r_s[0];
+    t.r_cut = batch->r_cut[0];
+    t.accumulate = 1;
+    DZS_TRY(dzs_tree_walk_ex(ctx, &batch->boxes[0], st->n, st->x, st->y, st->z, st->mult, st->gx,
+                             st->gy, st->gz, &t, ctx->batch_box, s));
+    return dzs_launch_kick(ctx, st, prm->K2, s);
 }

@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -47,6 +49,26 @@ struct dzs_timer_pool {
     bool created = false;
 };
 
+// A batched step (many independent boxes in one particle array): box b's particles carry
+// Morton keys prefixed by b in their top DZS_BATCH_LEVELS octal digits, so one sort keeps each
+// box contiguous and one tree holds every box below the node of its prefix.
+#define DZS_BATCH_LEVELS 3                       // 8^3 = 512 boxes at most
+#define DZS_BATCH_SHIFT (3 * (DZS_KEY_BITS - DZS_BATCH_LEVELS))  // 54: box id = key >> 54
+#define DZS_BATCH_SIDE 262144.0                  // 2^18 cells per side below the box digits
+
+// per-box parameters of a batched step, in device memory
+struct dzs_bbox {
+    double L, halfL;
+    double m0, h0, G;                 // mass unit, spline support of mult 1, gravity
+    double r_s, r_cut, rcut2, rs_inv, rs_inv2, wide_limit;
+    double delta, q_scale;            // PM mesh spacing, fixed-point deposit scale
+    uint64_t first, count;            // particle range of the box
+    uint64_t mesh_off;                // first cell of the box's mesh in the mesh arrays
+    uint64_t tab_off;                 // first entry of its Green's function tables
+    int32_t ng;
+    uint32_t root;                    // tree node of the box (its key prefix)
+};
+
 struct dzs_ctx {
     int device = 0;
     uint64_t cap_n = 0;
@@ -85,6 +107,16 @@ struct dzs_ctx {
     double q_wmax = -1.0;
     double q_err = 1.0;
     float qf_coef[16] = {0};           // its FP32 fit (precision form)
+    dzs_bbox *batch_box = nullptr;     // batched step: per-box table [DZS_BATCH_MAX]
+    dzs_bbox *batch_box_h = nullptr;   // pinned host staging of the same
+    double *batch_tab = nullptr;       // Green's function tables of every box
+    uint64_t batch_tab_cap = 0;
+    uint64_t *batch_first = nullptr;   // [DZS_BATCH_MAX + 1] particle offsets of the boxes
+    uint32_t *batch_members = nullptr; // [DZS_BATCH_MAX] boxes grouped by mesh side
+    std::vector<int> batch_sides;      // distinct mesh sides of the prepared batch
+    std::vector<size_t> batch_tw_off;  // their twiddle tables in batch_tab
+    std::vector<uint32_t> batch_cls_first;  // their member ranges in batch_members
+    uint64_t batch_cells = 0;          // mesh cells of all boxes
     uint32_t *cell_node = nullptr;     // walk start cells: [8^DZS_CELL_K_MAX] node ids
     uint8_t *cell_dl = nullptr;        // and the level offset of each
     double qf_err = 1.0;
@@ -226,11 +258,13 @@ dzs_status dzs_fix_ties(dzs_ctx *ctx, uint64_t n, const uint32_t *id, hipStream_
 
 // particles.hip
 dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipStream_t s);
+// batch = true: the box of each particle (its L) from ctx->batch_first / ctx->batch_box (nb boxes)
 dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                                const dzs_lc_params *lc, dzs_lc_ring *ring, int do_lc,
-                               int do_drift, hipStream_t s);
+                               int do_drift, hipStream_t s, bool batch = false, uint32_t nb = 0);
 dzs_status dzs_launch_keys(dzs_ctx *ctx, const double *x, const double *y, const double *z,
-                           uint64_t n, double L, uint64_t *key, uint32_t *idx, hipStream_t s);
+                           uint64_t n, double L, uint64_t *key, uint32_t *idx, hipStream_t s,
+                           bool batch = false, uint32_t nb = 0);
 dzs_status dzs_permute_state(dzs_ctx *ctx, dzs_particles *p, const uint32_t *perm,
                              int with_g, hipStream_t s);
 dzs_status dzs_gather_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm, double *dst,
@@ -244,14 +278,27 @@ dzs_status dzs_scatter_add_f64(dzs_ctx *ctx, const double *src, const uint32_t *
 dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                           const double *y, const double *z, const uint32_t *mult,
                           int leaf_size, int group_size, hipStream_t s);
+dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                             const double *y, const double *z, const uint32_t *mult,
+                             int leaf_size, int group_size, int KB, const dzs_bbox *boxes,
+                             hipStream_t s);
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
                          double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s);
+
+dzs_status dzs_batch_roots(dzs_ctx *ctx, dzs_bbox *boxes, hipStream_t s);
+dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                            const double *y, const double *z, const uint32_t *mult, double *gx,
+                            double *gy, double *gz, const dzs_tree_params *prm,
+                            const dzs_bbox *boxes, hipStream_t s);
 
 // pm.hip
 bool dzs_pm_mesh_ok(int ng);
 dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                       const dzs_pm_params *prm, hipStream_t s);
+dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStream_t s);
+dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision, const dzs_bbox *db,
+                            double G, hipStream_t s);
 
 // coarsen.hip
 dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p,

@@ -34,6 +34,19 @@ dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipSt
     return dzs_check_launch(ctx, "kick");
 }
 
+// box of particle i in a batch: the last b with first[b] <= i (first[] ascending, nb entries)
+__device__ __forceinline__ uint32_t batch_box_of(const uint64_t *first, uint32_t nb, uint64_t i) {
+    uint32_t lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------------------
 // drift + lightcone
 // ---------------------------------------------------------------------------------------
@@ -89,10 +102,13 @@ __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
     const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
     const uint32_t *__restrict__ id, const uint32_t *__restrict__ mult, double L, lc_args A,
     int do_lc, int do_drift, dzs_lc_record *__restrict__ rec, uint64_t rec_cap,
-    unsigned long long *__restrict__ rec_count, uint32_t *__restrict__ overflow) {
+    unsigned long long *__restrict__ rec_count, uint32_t *__restrict__ overflow,
+    const uint64_t *__restrict__ bfirst, const dzs_bbox *__restrict__ boxes, uint32_t nb) {
     uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
     if (i >= n)
         return;
+    if (boxes)
+        L = boxes[batch_box_of(bfirst, nb, i)].L;
     const double xi = x[i], yi = y[i], zi = z[i];
     const double pxi = px[i], pyi = py[i], pzi = pz[i];
     const double sx = pxi * A.D, sy = pyi * A.D, sz = pzi * A.D;
@@ -138,7 +154,7 @@ __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
 
 dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                                const dzs_lc_params *lc, dzs_lc_ring *ring, int do_lc,
-                               int do_drift, hipStream_t s) {
+                               int do_drift, hipStream_t s, bool batch, uint32_t nb) {
     if (p->n == 0)
         return DZS_OK;
     lc_args A;
@@ -170,7 +186,8 @@ dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_parti
                        p->n, p->x, p->y, p->z, (const double *)p->px, (const double *)p->py,
                        (const double *)p->pz, (const uint32_t *)p->id,
                        (const uint32_t *)p->mult, box->L, A, do_lc, do_drift, rec, cap, cnt,
-                       ovf);
+                       ovf, (const uint64_t *)ctx->batch_first, batch ? ctx->batch_box : nullptr,
+                       nb);
     return dzs_check_launch(ctx, "drift_lc");
 }
 
@@ -181,23 +198,41 @@ __global__ __launch_bounds__(PT_THREADS) void k_keys(uint64_t n, const double *_
                                                      const double *__restrict__ y,
                                                      const double *__restrict__ z, double s,
                                                      uint64_t *__restrict__ key,
-                                                     uint32_t *__restrict__ idx) {
+                                                     uint32_t *__restrict__ idx,
+                                                     const uint64_t *__restrict__ bfirst,
+                                                     const dzs_bbox *__restrict__ boxes,
+                                                     uint32_t nb) {
     uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
     if (i >= n)
         return;
-    key[i] = dzs_morton(x[i], y[i], z[i], s);
+    if (boxes) {
+        // a batch: the box in the top DZS_BATCH_LEVELS digits, 2^18 cells per side below
+        const uint64_t b = batch_box_of(bfirst, nb, i);
+        const double sb = DZS_BATCH_SIDE / boxes[b].L;
+        auto cell = [&](double v) -> uint64_t {
+            double t = floor(v * sb);
+            t = t < 0.0 ? 0.0 : (t > DZS_BATCH_SIDE - 1.0 ? DZS_BATCH_SIDE - 1.0 : t);
+            return (uint64_t)t;
+        };
+        key[i] = (b << DZS_BATCH_SHIFT) | (dzs_spread3(cell(x[i])) << 2) |
+                 (dzs_spread3(cell(y[i])) << 1) | dzs_spread3(cell(z[i]));
+    } else {
+        key[i] = dzs_morton(x[i], y[i], z[i], s);
+    }
     if (idx)
         idx[i] = (uint32_t)i;
 }
 
 dzs_status dzs_launch_keys(dzs_ctx *ctx, const double *x, const double *y, const double *z,
-                           uint64_t n, double L, uint64_t *key, uint32_t *idx, hipStream_t s) {
+                           uint64_t n, double L, uint64_t *key, uint32_t *idx, hipStream_t s,
+                           bool batch, uint32_t nb) {
     if (n == 0)
         return DZS_OK;
     const double scale = DZS_KEY_SIDE / L;
     dzs_timed t(ctx, KC_KEYS, s);
     hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n, x, y,
-                       z, scale, key, idx);
+                       z, scale, key, idx, (const uint64_t *)ctx->batch_first,
+                       batch ? ctx->batch_box : nullptr, nb);
     return dzs_check_launch(ctx, "keys");
 }
 

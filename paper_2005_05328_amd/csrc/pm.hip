@@ -34,6 +34,16 @@ struct fft_plan {
     int radix[FFT_MAX_STAGES];
 };
 
+// A batch of boxes, each with its own mesh at its own offset of the mesh arrays.  Deposit and
+// interpolation find a particle's box from its key prefix; the FFT kernels of one mesh-size
+// class run blocks_per_mesh blocks for each member box.  boxes == nullptr: a single box.
+struct pm_batch {
+    const dzs_bbox *boxes;
+    const uint32_t *members;
+    int blocks_per_mesh;
+    const uint64_t *key;
+};
+
 // ---------------------------------------------------------------------------------------
 // LDS line FFT
 // ---------------------------------------------------------------------------------------
@@ -174,10 +184,17 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit(uint64_t n, const dou
                                                            const double *__restrict__ z,
                                                            const uint32_t *__restrict__ mult,
                                                            double delta, int ng,
-                                                           unsigned long long *__restrict__ q) {
+                                                           unsigned long long *__restrict__ q,
+                                                           pm_batch B) {
     uint64_t p = (uint64_t)blockIdx.x * PM_THREADS + threadIdx.x;
     if (p >= n)
         return;
+    if (B.boxes) {
+        const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
+        delta = bx.delta;
+        ng = bx.ng;
+        q += bx.mesh_off;
+    }
     int ix[2], iy[2], iz[2];
     double wx[2], wy[2], wz[2];
     cic_axis(x[p], delta, ng, ix[0], ix[1], wx[0], wx[1]);
@@ -206,14 +223,23 @@ template <int MODE, typename C>  // 0: x forward from fixed point, 1: y forward,
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
     const unsigned long long *__restrict__ q, C *__restrict__ c,
     decltype(C::x) *__restrict__ phi, const double2 *__restrict__ tw, fft_plan P, int TZ,
-    double q_scale) {
+    double q_scale, pm_batch B) {
     typedef decltype(C::x) Rt;
     __shared__ C s_buf[FFT_ELEMS];
     __shared__ C s_tw[1024];
     const int n = P.n;
     const int tiles_z = n / TZ;
-    const int other = blockIdx.x / tiles_z;  // iy for the x pass, ix for the y pass
-    const int iz0 = (blockIdx.x % tiles_z) * TZ;
+    uint32_t blk = blockIdx.x;
+    if (B.boxes) {
+        const dzs_bbox &bx = B.boxes[B.members[blk / (uint32_t)B.blocks_per_mesh]];
+        blk %= (uint32_t)B.blocks_per_mesh;
+        q += bx.mesh_off;
+        c += bx.mesh_off;
+        phi += bx.mesh_off;
+        q_scale = bx.q_scale;
+    }
+    const int other = blk / tiles_z;  // iy for the x pass, ix for the y pass
+    const int iz0 = (blk % tiles_z) * TZ;
     const bool xpass = (MODE == 0 || MODE == 3);
     const uint64_t stride_axis = xpass ? (uint64_t)n * n : (uint64_t)n;
     const uint64_t base = xpass ? (uint64_t)other * n + iz0 : (uint64_t)other * n * n + iz0;
@@ -251,14 +277,23 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(C *__restrict__ c,
                                                               const double2 *__restrict__ tw,
                                                               const double *__restrict__ gt,
                                                               const double *__restrict__ k2t,
-                                                              fft_plan P, int TL, double gconst) {
+                                                              fft_plan P, int TL, double gconst,
+                                                              pm_batch B) {
     typedef decltype(C::x) Rt;
     __shared__ C s_buf[FFT_ELEMS];
     __shared__ C s_tw[1024];
     const int n = P.n;
     const int tiles_y = n / TL;
-    const int ix = blockIdx.x / tiles_y;
-    const int iy0 = (blockIdx.x % tiles_y) * TL;
+    uint32_t blk = blockIdx.x;
+    if (B.boxes) {
+        const dzs_bbox &bx = B.boxes[B.members[blk / (uint32_t)B.blocks_per_mesh]];
+        blk %= (uint32_t)B.blocks_per_mesh;
+        c += bx.mesh_off;
+        gt += bx.tab_off;
+        k2t += bx.tab_off + (uint64_t)n;
+    }
+    const int ix = blk / tiles_y;
+    const int iy0 = (blk % tiles_y) * TL;
     const uint64_t base = ((uint64_t)ix * n + iy0) * n;
     load_twiddles(s_tw, tw, n);
     const int total = n * TL;
@@ -290,10 +325,17 @@ template <typename Rt>
 __global__ __launch_bounds__(PM_THREADS) void k_pm_interp(
     uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const Rt *__restrict__ phi, double delta, int ng,
-    double *__restrict__ gx, double *__restrict__ gy, double *__restrict__ gz, int accumulate) {
+    double *__restrict__ gx, double *__restrict__ gy, double *__restrict__ gz, int accumulate,
+    pm_batch B) {
     uint64_t p = (uint64_t)blockIdx.x * PM_THREADS + threadIdx.x;
     if (p >= n)
         return;
+    if (B.boxes) {
+        const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
+        delta = bx.delta;
+        ng = bx.ng;
+        phi += bx.mesh_off;
+    }
     int ix[2], iy[2], iz[2];
     double wx[2], wy[2], wz[2];
     cic_axis(x[p], delta, ng, ix[0], ix[1], wx[0], wx[1]);
@@ -396,56 +438,77 @@ static dzs_status upload_tables(dzs_ctx *ctx, int ng, double L, double r_s, hipS
 }
 
 // The Poisson solve (x, y passes forward, z pass with the Green's function, y, x passes
-// inverse) and the gradient interpolation, in the complex type C of the form.
+// inverse) over n_meshes meshes of side P.n, in the complex type C of the form.
 template <typename C>
-static dzs_status pm_solve_interp(dzs_ctx *ctx, const dzs_particles *p, const dzs_pm_params *prm,
-                                  const fft_plan &P, const double2 *tw, const double *gt,
-                                  const double *k2t, int TZ, int TL, double delta,
-                                  double q_scale, double gconst, hipStream_t s) {
+static dzs_status pm_solve(dzs_ctx *ctx, const fft_plan &P, const double2 *tw, const double *gt,
+                           const double *k2t, int TZ, int TL, double q_scale, double gconst,
+                           uint32_t n_meshes, pm_batch B, hipStream_t s) {
     typedef decltype(C::x) Rt;
     const int ng = P.n;
-    const uint32_t strided_blocks = (uint32_t)((uint64_t)ng * (ng / TZ));
-    const uint32_t z_blocks = (uint32_t)((uint64_t)ng * (ng / TL));
+    const uint32_t strided_per = (uint32_t)((uint64_t)ng * (ng / TZ));
+    const uint32_t z_per = (uint32_t)((uint64_t)ng * (ng / TL));
     const unsigned long long *mq = (const unsigned long long *)ctx->mesh_q;
     C *mc = (C *)ctx->mesh_c;
     Rt *phi = (Rt *)ctx->mesh_phi;
+    pm_batch Bs = B, Bz = B;
+    Bs.blocks_per_mesh = (int)strided_per;
+    Bz.blocks_per_mesh = (int)z_per;
+    const dim3 gs(strided_per * n_meshes), gz(z_per * n_meshes);
     {
         dzs_timed t(ctx, KC_PM_FFT_X, s);
-        hipLaunchKernelGGL((k_fft_strided<0, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
-                           mc, phi, tw, P, TZ, q_scale);
+        hipLaunchKernelGGL((k_fft_strided<0, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
+                           TZ, q_scale, Bs);
         DZS_TRY(dzs_check_launch(ctx, "fft_x_fwd"));
     }
     {
         dzs_timed t(ctx, KC_PM_FFT_Y, s);
-        hipLaunchKernelGGL((k_fft_strided<1, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
-                           mc, phi, tw, P, TZ, q_scale);
+        hipLaunchKernelGGL((k_fft_strided<1, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
+                           TZ, q_scale, Bs);
         DZS_TRY(dzs_check_launch(ctx, "fft_y_fwd"));
     }
     {
         dzs_timed t(ctx, KC_PM_FFT_Z_GREEN, s);
-        hipLaunchKernelGGL(k_fft_z_green<C>, dim3(z_blocks), dim3(FFT_THREADS), 0, s, mc, tw, gt,
-                           k2t, P, TL, gconst);
+        hipLaunchKernelGGL(k_fft_z_green<C>, gz, dim3(FFT_THREADS), 0, s, mc, tw, gt, k2t, P, TL,
+                           gconst, Bz);
         DZS_TRY(dzs_check_launch(ctx, "fft_z_green"));
     }
     {
         dzs_timed t(ctx, KC_PM_FFT_Y, s);
-        hipLaunchKernelGGL((k_fft_strided<2, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
-                           mc, phi, tw, P, TZ, q_scale);
+        hipLaunchKernelGGL((k_fft_strided<2, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
+                           TZ, q_scale, Bs);
         DZS_TRY(dzs_check_launch(ctx, "fft_y_inv"));
     }
     {
         dzs_timed t(ctx, KC_PM_FFT_X, s);
-        hipLaunchKernelGGL((k_fft_strided<3, C>), dim3(strided_blocks), dim3(FFT_THREADS), 0, s, mq,
-                           mc, phi, tw, P, TZ, q_scale);
+        hipLaunchKernelGGL((k_fft_strided<3, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
+                           TZ, q_scale, Bs);
         DZS_TRY(dzs_check_launch(ctx, "fft_x_inv"));
     }
+    return DZS_OK;
+}
+
+template <typename Rt>
+static dzs_status pm_interp(dzs_ctx *ctx, const dzs_particles *p, int accumulate, double delta,
+                            int ng, pm_batch B, hipStream_t s) {
+    if (p->n == 0)
+        return DZS_OK;
+    dzs_timed t(ctx, KC_PM_INTERP, s);
+    hipLaunchKernelGGL(k_pm_interp<Rt>, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0,
+                       s, p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,
+                       (const Rt *)ctx->mesh_phi, delta, ng, p->gx, p->gy, p->gz, accumulate, B);
+    return dzs_check_launch(ctx, "pm_interp");
+}
+
+static dzs_status pm_deposit(dzs_ctx *ctx, const dzs_particles *p, uint64_t cells, double delta,
+                             int ng, pm_batch B, hipStream_t s) {
+    dzs_timed t(ctx, KC_PM_DEPOSIT, s);
+    DZS_HIP(ctx, hipMemsetAsync(ctx->mesh_q, 0, sizeof(long long) * cells, s));
     if (p->n > 0) {
-        dzs_timed t(ctx, KC_PM_INTERP, s);
-        hipLaunchKernelGGL(k_pm_interp<Rt>, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS),
-                           0, s, p->n, (const double *)p->x, (const double *)p->y,
-                           (const double *)p->z, (const Rt *)phi, delta, ng, p->gx,
-                           p->gy, p->gz, prm->accumulate);
-        DZS_TRY(dzs_check_launch(ctx, "pm_interp"));
+        hipLaunchKernelGGL(k_pm_deposit, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0, s,
+                           p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,
+                           (const uint32_t *)p->mult, delta, ng, (unsigned long long *)ctx->mesh_q,
+                           B);
+        DZS_TRY(dzs_check_launch(ctx, "pm_deposit"));
     }
     return DZS_OK;
 }
@@ -467,22 +530,124 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
     const double2 *tw = (const double2 *)ctx->pm_tables;
     const double *gt = ctx->pm_tables + 2 * ng;
     const double *k2t = ctx->pm_tables + 3 * ng;
-    {
-        dzs_timed t(ctx, KC_PM_DEPOSIT, s);
-        DZS_HIP(ctx, hipMemsetAsync(ctx->mesh_q, 0, sizeof(long long) * ng3, s));
-        if (p->n > 0) {
-            hipLaunchKernelGGL(k_pm_deposit, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS),
-                               0, s, p->n, (const double *)p->x, (const double *)p->y,
-                               (const double *)p->z, (const uint32_t *)p->mult, delta, ng,
-                               (unsigned long long *)ctx->mesh_q);
-            DZS_TRY(dzs_check_launch(ctx, "pm_deposit"));
-        }
-    }
+    const pm_batch none{nullptr, nullptr, 0, nullptr};
+    DZS_TRY(pm_deposit(ctx, p, ng3, delta, ng, none, s));
     const int TZ = tile_lines(ng, 16);
     const int TL = tile_lines(ng, FFT_ELEMS);
     const double q_scale = box->m0 / (DEP_FRAC * delta * delta * delta);
     const double gconst = -4.0 * 3.14159265358979323846 * box->G / (double)ng3;
-    if (prm->precision == DZS_FP32)
-        return pm_solve_interp<float2>(ctx, p, prm, P, tw, gt, k2t, TZ, TL, delta, q_scale, gconst, s);
-    return pm_solve_interp<double2>(ctx, p, prm, P, tw, gt, k2t, TZ, TL, delta, q_scale, gconst, s);
+    if (prm->precision == DZS_FP32) {
+        DZS_TRY(pm_solve<float2>(ctx, P, tw, gt, k2t, TZ, TL, q_scale, gconst, 1, none, s));
+        return pm_interp<float>(ctx, p, prm->accumulate, delta, ng, none, s);
+    }
+    DZS_TRY(pm_solve<double2>(ctx, P, tw, gt, k2t, TZ, TL, q_scale, gconst, 1, none, s));
+    return pm_interp<double>(ctx, p, prm->accumulate, delta, ng, none, s);
+}
+
+// A batch: every box's mesh at its offset of the mesh arrays.  dzs_pm_batch_prepare fills
+// each box's mesh offset, spacing, deposit scale and table offset in the host table hb[] and
+// uploads the twiddle and Green's function tables of every box and mesh size; the caller
+// uploads hb[] to the device table.  Boxes of one mesh size share each FFT launch.
+dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStream_t s) {
+    ctx->batch_sides.clear();
+    uint64_t cells = 0;
+    for (uint32_t b = 0; b < nb; ++b) {
+        fft_plan P;
+        if (!make_plan(hb[b].ng, &P) || hb[b].ng > 1024 || hb[b].ng < 8)
+            return dzs_fail(ctx, DZS_EINVAL, "batch: box %u mesh side %d is not 2^a 3^b in "
+                            "[8, 1024]", b, hb[b].ng);
+        hb[b].mesh_off = cells;
+        cells += (uint64_t)hb[b].ng * hb[b].ng * hb[b].ng;
+        bool seen = false;
+        for (int v : ctx->batch_sides)
+            seen |= v == hb[b].ng;
+        if (!seen)
+            ctx->batch_sides.push_back(hb[b].ng);
+    }
+    const uint64_t cap_cells = (uint64_t)ctx->cap_ng * ctx->cap_ng * ctx->cap_ng;
+    if (cells > cap_cells)
+        return dzs_fail(ctx, DZS_ECAPACITY, "batch: meshes need %llu cells, the context holds %llu",
+                        (unsigned long long)cells, (unsigned long long)cap_cells);
+    ctx->batch_cells = cells;
+    // tables: per box [Green factor (ng), k^2 (ng)], then per mesh side twiddles (2 ng)
+    std::vector<double> tab;
+    const long double pi = 3.14159265358979323846264338327950288L;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const int ng = hb[b].ng;
+        const double L = hb[b].L, delta = L / ng;
+        hb[b].delta = delta;
+        hb[b].q_scale = hb[b].m0 / (DEP_FRAC * delta * delta * delta);
+        hb[b].tab_off = tab.size();
+        tab.resize(tab.size() + 2 * (size_t)ng);
+        double *gt = tab.data() + hb[b].tab_off, *k2 = gt + ng;
+        for (int m = 0; m < ng; ++m) {
+            const int nn = m < ng / 2 ? m : m - ng;
+            const long double k = 2.0L * pi * nn / L;
+            const long double hh = 0.5L * k * delta;
+            const long double sinc = hh == 0.0L ? 1.0L : sinl(hh) / hh;
+            const long double w2 = sinc * sinc * sinc * sinc;
+            gt[m] = (double)(expl(-k * k * (long double)hb[b].r_s * hb[b].r_s) / w2);
+            k2[m] = (double)(k * k);
+        }
+    }
+    ctx->batch_tw_off.clear();
+    ctx->batch_cls_first.clear();
+    std::vector<uint32_t> members;
+    for (int ng : ctx->batch_sides) {
+        ctx->batch_tw_off.push_back(tab.size());
+        tab.resize(tab.size() + 2 * (size_t)ng);
+        for (int m = 0; m < ng; ++m) {
+            const long double ang = -2.0L * pi * m / ng;
+            tab[ctx->batch_tw_off.back() + 2 * m] = (double)cosl(ang);
+            tab[ctx->batch_tw_off.back() + 2 * m + 1] = (double)sinl(ang);
+        }
+        ctx->batch_cls_first.push_back((uint32_t)members.size());
+        for (uint32_t b = 0; b < nb; ++b)
+            if (hb[b].ng == ng)
+                members.push_back(b);
+    }
+    ctx->batch_cls_first.push_back((uint32_t)members.size());
+    if (tab.size() > ctx->batch_tab_cap) {
+        if (ctx->batch_tab)
+            DZS_HIP(ctx, hipFree(ctx->batch_tab));
+        ctx->batch_tab = nullptr;
+        ctx->batch_tab_cap = 0;
+        DZS_HIP(ctx, hipMalloc(&ctx->batch_tab, sizeof(double) * tab.size()));
+        ctx->batch_tab_cap = tab.size();
+    }
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_tab, tab.data(), sizeof(double) * tab.size(),
+                                hipMemcpyHostToDevice, s));
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_members, members.data(),
+                                sizeof(uint32_t) * members.size(), hipMemcpyHostToDevice, s));
+    // the staging vectors die here: wait for the copies
+    DZS_HIP(ctx, hipStreamSynchronize(s));
+    return DZS_OK;
+}
+
+// The long-range force of every box of a prepared batch into g (g = g_long); db is the device
+// box table and ctx->key the sorted keys (box in the top digits) of the particles.
+dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision, const dzs_bbox *db,
+                            double G, hipStream_t s) {
+    const pm_batch all{db, nullptr, 0, (const uint64_t *)ctx->key};
+    DZS_TRY(pm_deposit(ctx, p, ctx->batch_cells, 0.0, 0, all, s));
+    for (size_t c = 0; c < ctx->batch_sides.size(); ++c) {
+        const int ng = ctx->batch_sides[c];
+        fft_plan P;
+        make_plan(ng, &P);
+        const uint32_t nm = ctx->batch_cls_first[c + 1] - ctx->batch_cls_first[c];
+        const pm_batch B{db, ctx->batch_members + ctx->batch_cls_first[c], 0,
+                         (const uint64_t *)ctx->key};
+        const double2 *tw = (const double2 *)(ctx->batch_tab + ctx->batch_tw_off[c]);
+        const double gconst = -4.0 * 3.14159265358979323846 * G / ((double)ng * ng * ng);
+        const int TZ = tile_lines(ng, 16), TL = tile_lines(ng, FFT_ELEMS);
+        if (precision == DZS_FP32)
+            DZS_TRY(pm_solve<float2>(ctx, P, tw, ctx->batch_tab, ctx->batch_tab, TZ, TL, 0.0,
+                                     gconst, nm, B, s));
+        else
+            DZS_TRY(pm_solve<double2>(ctx, P, tw, ctx->batch_tab, ctx->batch_tab, TZ, TL, 0.0,
+                                      gconst, nm, B, s));
+    }
+    if (precision == DZS_FP32)
+        return pm_interp<float>(ctx, p, 0, 0.0, 0, all, s);
+    return pm_interp<double>(ctx, p, 0, 0.0, 0, all, s);
 }

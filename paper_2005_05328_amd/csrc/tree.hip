@@ -45,7 +45,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_split(
     const uint32_t *__restrict__ frontier, uint32_t nf, int k, const uint64_t *__restrict__ key,
     const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     uint32_t *__restrict__ bounds, uint32_t *__restrict__ nchild, uint32_t *__restrict__ ninternal,
-    uint32_t leaf) {
+    uint32_t leaf, int KB) {
     uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
     if (f >= nf)
         return;
@@ -73,7 +73,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_split(
         uint32_t c = b[d + 1] - b[d];
         bounds[(uint64_t)f * 9 + d] = b[d];
         nc += c > 0;
-        ni += (c > leaf && k + 1 < DZS_KEY_BITS);
+        // nodes above level KB (the box digits of a batch) always split
+        ni += c > 0 && (c > leaf || k + 1 < KB) && k + 1 < DZS_KEY_BITS;
     }
     bounds[(uint64_t)f * 9 + 8] = e;
     nchild[f] = nc;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
     const uint32_t *__restrict__ child_off, const uint32_t *__restrict__ int_off, uint32_t base,
     uint32_t *__restrict__ nd_first, uint32_t *__restrict__ nd_count, uint32_t *__restrict__ nd_child,
     uint8_t *__restrict__ nd_nchild, uint8_t *__restrict__ nd_level,
-    uint32_t *__restrict__ frontier_next, uint32_t leaf) {
+    uint32_t *__restrict__ frontier_next, uint32_t leaf, int KB) {
     uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
     if (f >= nf)
         return;
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
         nd_child[c] = 0;
         nd_nchild[c] = 0;
         nd_level[c] = (uint8_t)(k + 1);
-        if (e - s > leaf && k + 1 < DZS_KEY_BITS)
+        if ((e - s > leaf || k + 1 < KB) && k + 1 < DZS_KEY_BITS)
             frontier_next[q++] = c;
         ++c;
         ++nc;
@@ -118,10 +119,17 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
     double m0, double h0, const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild,
     double *__restrict__ nd_mass, double *__restrict__ nd_com, double *__restrict__ nd_bmin,
-    double *__restrict__ nd_bmax, double *__restrict__ nd_hmax) {
+    double *__restrict__ nd_bmax, double *__restrict__ nd_hmax, const uint64_t *__restrict__ key,
+    const dzs_bbox *__restrict__ boxes) {
     uint32_t v = lo + blockIdx.x * TB_THREADS + threadIdx.x;
     if (v >= hi)
         return;
+    if (boxes && nd_nchild[v] == 0) {
+        // a batch: the leaf's box (its key prefix) sets the mass unit and the softening
+        const uint64_t b = key[nd_first[v]] >> DZS_BATCH_SHIFT;
+        m0 = boxes[b].m0;
+        h0 = boxes[b].h0;
+    }
     double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, hmax = 0.0;
     double mnx = 1e300, mny = 1e300, mnz = 1e300, mxx = -1e300, mxy = -1e300, mxz = -1e300;
     const uint32_t nc = nd_nchild[v];
@@ -170,11 +178,25 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
 __global__ __launch_bounds__(TB_THREADS) void k_tree_groups(
     uint32_t n_nodes, const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild, uint32_t G,
-    uint32_t *__restrict__ flag) {
+    uint32_t *__restrict__ flag, const uint8_t *__restrict__ nd_level, int KB) {
     uint32_t v = blockIdx.x * TB_THREADS + threadIdx.x;
     if (v >= n_nodes)
         return;
     const uint32_t cnt = nd_count[v];
+    if (KB > 0) {
+        // a batch: nothing above the box nodes (level KB) is a group, and the box nodes of at
+        // most G particles are groups of their own
+        const int lev = nd_level[v];
+        if (lev + 1 < KB)
+            return;
+        if (lev + 1 == KB) {
+            const uint32_t c0 = nd_child[v];
+            for (uint32_t c = c0; c < c0 + nd_nchild[v]; ++c)
+                if (nd_count[c] <= G)
+                    flag[nd_first[c]] = 1u;
+            return;
+        }
+    }
     if (v == 0 && cnt <= G) {
         flag[0] = 1u;
         return;
@@ -216,6 +238,15 @@ __global__ __launch_bounds__(TB_THREADS) void k_group_compact(uint32_t n,
 dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const double *x,
                           const double *y, const double *z, const uint32_t *mult, int leaf_size,
                           int group_size, hipStream_t s) {
+    return dzs_tree_build_ex(ctx, box, n64, x, y, z, mult, leaf_size, group_size, 0, nullptr, s);
+}
+
+// KB > 0: a batch whose keys carry the box in their top KB digits; the nodes above level KB
+// always split, the box table supplies each leaf's mass unit and softening.
+dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const double *x,
+                             const double *y, const double *z, const uint32_t *mult,
+                             int leaf_size, int group_size, int KB, const dzs_bbox *boxes,
+                             hipStream_t s) {
     const uint32_t n = (uint32_t)n64;
     ctx->n_nodes = 0;
     ctx->n_groups = 0;
@@ -233,14 +264,14 @@ dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const 
     ctx->level_start[0] = 0;
     ctx->level_start[1] = 1;
     int n_levels = 1;
-    uint32_t nf = n > leaf ? 1u : 0u;
+    uint32_t nf = (n > leaf || KB > 0) ? 1u : 0u;
     uint32_t *fr = ctx->frontier, *fr_next = ctx->frontier_next;
     for (int k = 0; nf > 0 && k < DZS_KEY_BITS; ++k) {
         {
             dzs_timed t(ctx, KC_TREE_BUILD, s);
             hipLaunchKernelGGL(k_tree_split, dim3(blocks_for(nf, TB_THREADS)), dim3(TB_THREADS), 0,
                                s, fr, nf, k, ctx->key, ctx->nd_first, ctx->nd_count,
-                               ctx->child_bounds, ctx->fr_nchild, ctx->fr_ninternal, leaf);
+                               ctx->child_bounds, ctx->fr_nchild, ctx->fr_ninternal, leaf, KB);
             DZS_TRY(dzs_check_launch(ctx, "tree_split"));
             DZS_TRY(dzs_scan_u32(ctx, ctx->fr_nchild, ctx->fr_child_off, nf, ctx->d_small, s));
             DZS_TRY(dzs_scan_u32(ctx, ctx->fr_ninternal, ctx->fr_int_off, nf, ctx->d_small + 1, s));
@@ -257,7 +288,7 @@ dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const 
             hipLaunchKernelGGL(k_tree_emit, dim3(blocks_for(nf, TB_THREADS)), dim3(TB_THREADS), 0,
                                s, fr, nf, k, ctx->child_bounds, ctx->fr_child_off,
                                ctx->fr_int_off, n_nodes, ctx->nd_first, ctx->nd_count,
-                               ctx->nd_child, ctx->nd_nchild, ctx->nd_level, fr_next, leaf);
+                               ctx->nd_child, ctx->nd_nchild, ctx->nd_level, fr_next, leaf, KB);
             DZS_TRY(dzs_check_launch(ctx, "tree_emit"));
         }
         n_nodes += n_children;
@@ -280,7 +311,7 @@ dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const 
                                dim3(TB_THREADS), 0, s, lo, hi, cap, x, y, z, mult, box->m0,
                                2.8 * box->eps0, ctx->nd_first, ctx->nd_count, ctx->nd_child,
                                ctx->nd_nchild, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
-                               ctx->nd_bmax, ctx->nd_hmax);
+                               ctx->nd_bmax, ctx->nd_hmax, (const uint64_t *)ctx->key, boxes);
             DZS_TRY(dzs_check_launch(ctx, "tree_moments"));
         }
     }
@@ -289,7 +320,8 @@ dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const 
         DZS_HIP(ctx, hipMemsetAsync(ctx->grp_flag, 0, sizeof(uint32_t) * n, s));
         hipLaunchKernelGGL(k_tree_groups, dim3(blocks_for(n_nodes, TB_THREADS)), dim3(TB_THREADS),
                            0, s, n_nodes, ctx->nd_first, ctx->nd_count, ctx->nd_child,
-                           ctx->nd_nchild, (uint32_t)group_size, ctx->grp_flag);
+                           ctx->nd_nchild, (uint32_t)group_size, ctx->grp_flag, ctx->nd_level,
+                           KB);
         DZS_TRY(dzs_check_launch(ctx, "tree_groups"));
         DZS_TRY(dzs_scan_u32(ctx, ctx->grp_flag, ctx->grp_scan, n, ctx->d_small + 2, s));
         hipLaunchKernelGGL(k_group_compact, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s,
@@ -345,7 +377,41 @@ struct walk_args {
     const uint32_t *cell_node;  // [8^K] node covering each level-K cell (Morton order)
     const uint8_t *cell_dl;     // [8^K] K - level of that node
     int cell_K;                 // 0: start at the root
+    // a batch: the box of a group is its first particle's key prefix
+    const uint64_t *key;
+    const dzs_bbox *boxes;
 };
+
+// Geometry and constants of the box a group lives in.
+struct walk_geom {
+    double L, halfL, rcut, rcut2, rs_inv, rs_inv2, Gc, m0, h0, wide;
+    uint32_t root;
+};
+
+// ---------------------------------------------------------------------------------------
+// batch: the node of each box (the level-KB node with the box's key prefix)
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(TB_THREADS) void k_batch_roots(uint32_t lo, uint32_t hi,
+                                                            const uint64_t *__restrict__ key,
+                                                            const uint32_t *__restrict__ nd_first,
+                                                            dzs_bbox *__restrict__ boxes) {
+    const uint32_t v = lo + blockIdx.x * TB_THREADS + threadIdx.x;
+    if (v < hi)
+        boxes[key[nd_first[v]] >> DZS_BATCH_SHIFT].root = v;
+}
+
+dzs_status dzs_batch_roots(dzs_ctx *ctx, dzs_bbox *boxes, hipStream_t s) {
+    const int KB = DZS_BATCH_LEVELS;
+    if (ctx->n_levels <= KB)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: the tree has no box level");
+    const uint32_t lo = ctx->level_start[KB], hi = ctx->level_start[KB + 1];
+    if (hi > lo) {
+        hipLaunchKernelGGL(k_batch_roots, dim3(blocks_for(hi - lo, TB_THREADS)), dim3(TB_THREADS),
+                           0, s, lo, hi, (const uint64_t *)ctx->key, ctx->nd_first, boxes);
+        DZS_TRY(dzs_check_launch(ctx, "batch_roots"));
+    }
+    return DZS_OK;
+}
 
 // ---------------------------------------------------------------------------------------
 // start cells
@@ -445,11 +511,12 @@ __device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T
 // holds several times more entries than any one target's cutoff sphere; without the mask the
 // whole wave would step through the force arithmetic for every entry some lane accepts.
 template <typename T, bool MINIMG>
-__device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry<T> *src,
-                                          uint32_t nlist, uint32_t s, uint32_t P, T xi, T yi,
-                                          T zi, T hi, T &ax, T &ay, T &az, uint32_t &n_pairs) {
-    const T rcut2 = T(A.rcut2), rs_inv = T(A.rs_inv), rs_inv2 = T(A.rs_inv2);
-    const T t_scale = T(A.t_scale), L = T(A.L);
+__device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W,
+                                          const src_entry<T> *src, uint32_t nlist, uint32_t s,
+                                          uint32_t P, T xi, T yi, T zi, T hi, T &ax, T &ay,
+                                          T &az, uint32_t &n_pairs) {
+    const T rcut2 = T(W.rcut2), rs_inv = T(W.rs_inv), rs_inv2 = T(W.rs_inv2);
+    const T t_scale = T(A.t_scale), L = T(W.L);
     constexpr int QN = split_coef<T>::N;
     for (uint32_t base = s; base < nlist; base += 64u * P) {
         uint64_t mask = 0;
@@ -490,8 +557,10 @@ __device__ __forceinline__ void pair_loop(const walk_args &A, const src_entry<T>
     }
 }
 
-template <typename T, bool CELLS>
+template <typename T, bool CELLS, bool BATCH>
 __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
+    static_assert(!(CELLS && BATCH), "a batch walk starts at the box nodes");
+    constexpr int KBL = BATCH ? DZS_BATCH_LEVELS : 0;  // tree levels above a box
     __shared__ src_entry<T> src[WALK_LIST];
     __shared__ uint32_t q_first[64];
     __shared__ uint32_t q_pref[65];
@@ -505,10 +574,6 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     const uint32_t tl = lane % G, ph = lane / G;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t *stk = A.stack + (uint64_t)blockIdx.x * A.depth;
-    // a source node and the group may be wide enough that the image nearest the group centre
-    // is not every pair's nearest image; above this half-extent sum the pair loop reduces
-    // each separation to the minimum image
-    const double wide_limit = A.halfL - A.rcut;
 
     for (;;) {
         if (lane == 0)
@@ -520,10 +585,22 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             break;
         const uint32_t first = A.grp_first[g];
         const uint32_t cnt = A.grp_first[g + 1] - first;
+        // a source node and the group may be wide enough that the image nearest the group
+        // centre is not every pair's nearest image; above W.wide (half-extent sum) the pair
+        // loop reduces each separation to the minimum image
+        walk_geom W;
+        if (BATCH) {
+            const dzs_bbox &bx = A.boxes[A.key[first] >> DZS_BATCH_SHIFT];
+            W = walk_geom{bx.L,      bx.halfL,   bx.r_cut, bx.rcut2, bx.rs_inv, bx.rs_inv2,
+                          bx.G,      bx.m0,      bx.h0,    bx.wide_limit, bx.root};
+        } else {
+            W = walk_geom{A.L,  A.halfL, A.rcut, A.rcut2, A.rs_inv, A.rs_inv2,
+                          A.G,  A.m0,    A.h0,   A.halfL - A.rcut, 0u};
+        }
         const bool valid = tl < cnt;
         const uint32_t i = valid ? first + tl : first;
         const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
-        const double hi = A.h0 * cbrt((double)A.mult[i]);
+        const double hi = W.h0 * cbrt((double)A.mult[i]);
         // group bounding box
         double mnx = xi, mny = yi, mnz = zi, mxx = xi, mxy = yi, mxz = zi;
         for (int o = 32; o >= 1; o >>= 1) {
@@ -550,9 +627,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         auto flush = [&]() {
             __syncthreads();
             if (wide)
-                pair_loop<T, true>(A, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
+                pair_loop<T, true>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
             else
-                pair_loop<T, false>(A, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
+                pair_loop<T, false>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
             nlist = 0;
             __syncthreads();
         };
@@ -561,20 +638,20 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         bool overflow = false;
         if (!CELLS) {
             if (lane == 0)
-                stk[0] = 0;
+                stk[0] = W.root;
             sp = 1;
         } else {
             // cells of level K met by the bounding box grown by r_cut (plus a margin far above
             // rounding, so that every particle in it is found in a listed cell), wrapped
             const int K = A.cell_K;
             const int side = 1 << K, kmask = side - 1;
-            const double inv = (double)side / A.L, margin = 1e-9 * A.L;
-            const int lox = (int)floor((mnx - A.rcut - margin) * inv);
-            const int loy = (int)floor((mny - A.rcut - margin) * inv);
-            const int loz = (int)floor((mnz - A.rcut - margin) * inv);
-            const int nx = min((int)floor((mxx + A.rcut + margin) * inv) - lox + 1, side);
-            const int ny = min((int)floor((mxy + A.rcut + margin) * inv) - loy + 1, side);
-            const int nz = min((int)floor((mxz + A.rcut + margin) * inv) - loz + 1, side);
+            const double inv = (double)side / W.L, margin = 1e-9 * W.L;
+            const int lox = (int)floor((mnx - W.rcut - margin) * inv);
+            const int loy = (int)floor((mny - W.rcut - margin) * inv);
+            const int loz = (int)floor((mnz - W.rcut - margin) * inv);
+            const int nx = min((int)floor((mxx + W.rcut + margin) * inv) - lox + 1, side);
+            const int ny = min((int)floor((mxy + W.rcut + margin) * inv) - loy + 1, side);
+            const int nz = min((int)floor((mxz + W.rcut + margin) * inv) - loz + 1, side);
             const uint32_t nyz = (uint32_t)(ny * nz), total = (uint32_t)nx * nyz;
             for (uint32_t c0 = 0; c0 < total; c0 += 64) {
                 const uint32_t c = c0 + lane;
@@ -641,17 +718,17 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 child = A.nd_child[node];
                 double dcx = 0.5 * (bnx + bxx) - gcx, dcy = 0.5 * (bny + bxy) - gcy,
                        dcz = 0.5 * (bnz + bxz) - gcz;
-                shx = dcx > A.halfL ? -A.L : (dcx < -A.halfL ? A.L : 0.0);
-                shy = dcy > A.halfL ? -A.L : (dcy < -A.halfL ? A.L : 0.0);
-                shz = dcz > A.halfL ? -A.L : (dcz < -A.halfL ? A.L : 0.0);
+                shx = dcx > W.halfL ? -W.L : (dcx < -W.halfL ? W.L : 0.0);
+                shy = dcy > W.halfL ? -W.L : (dcy < -W.halfL ? W.L : 0.0);
+                shz = dcz > W.halfL ? -W.L : (dcz < -W.halfL ? W.L : 0.0);
                 dcx += shx; dcy += shy; dcz += shz;
                 const double nhx = 0.5 * (bxx - bnx), nhy = 0.5 * (bxy - bny), nhz = 0.5 * (bxz - bnz);
                 const double gx_ = fmax(0.0, fabs(dcx) - nhx - ghx);
                 const double gy_ = fmax(0.0, fabs(dcy) - nhy - ghy);
                 const double gz_ = fmax(0.0, fabs(dcz) - nhz - ghz);
                 const double dist2 = gx_ * gx_ + gy_ * gy_ + gz_ * gz_;
-                node_wide = fmax(nhx, fmax(nhy, nhz)) + ghmax > wide_limit;
-                if (dist2 >= A.rcut2) {
+                node_wide = fmax(nhx, fmax(nhy, nhz)) + ghmax > W.wide;
+                if (dist2 >= W.rcut2) {
                     act = 0;
                 } else if (nchild == 0) {
                     act = 1;
@@ -665,7 +742,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                         const double ey = fmax(0.0, fabs(cy) - ghy);
                         const double ez = fmax(0.0, fabs(cz) - ghz);
                         const double d2 = ex * ex + ey * ey + ez * ez;
-                        const double side = ldexp(A.L, -nlev);
+                        const double side = ldexp(W.L, -(nlev - KBL));
                         if (side * side < A.theta2 * d2)
                             act = 2;
                     }
@@ -745,7 +822,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                         const double cx = fmax(0.0, fabs(ex_ - gcx) - ghx);
                         const double cy = fmax(0.0, fabs(ey_ - gcy) - ghy);
                         const double cz = fmax(0.0, fabs(ez_ - gcz) - ghz);
-                        keep = q_wide[lo] != 0u || cx * cx + cy * cy + cz * cz < A.rcut2;
+                        keep = q_wide[lo] != 0u || cx * cx + cy * cy + cz * cz < W.rcut2;
                     }
                     const uint64_t kmask = __ballot(keep);
                     const uint32_t nk = (uint32_t)__popcll(kmask);
@@ -758,8 +835,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                             e.x = T(ex_ - ox);
                             e.y = T(ey_ - oy);
                             e.z = T(ez_ - oz);
-                            e.m = T(A.m0 * md);
-                            e.h = T(A.h0 * cbrt(md));
+                            e.m = T(W.m0 * md);
+                            e.h = T(W.h0 * cbrt(md));
                         }
                         nlist += nk;
                     }
@@ -786,7 +863,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 atomicAdd(A.pair_count, (unsigned long long)cnt_pairs);
         }
         if (valid && ph == 0) {
-            const double gxv = A.G * (double)ax, gyv = A.G * (double)ay, gzv = A.G * (double)az;
+            const double gxv = W.Gc * (double)ax, gyv = W.Gc * (double)ay, gzv = W.Gc * (double)az;
             if (A.accumulate) {
                 A.gx[i] += gxv;
                 A.gy[i] += gyv;
@@ -906,6 +983,15 @@ static double split_poly_f32(double wmax, float *qf) {
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
                          double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s) {
+    return dzs_tree_walk_ex(ctx, box, n, x, y, z, mult, gx, gy, gz, prm, nullptr, s);
+}
+
+// boxes != nullptr: a batch (device table of the boxes; the keys in ctx->key carry the box);
+// every box must share r_cut / r_s, the ratio the split-factor polynomial is fitted for.
+dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                            const double *y, const double *z, const uint32_t *mult, double *gx,
+                            double *gy, double *gz, const dzs_tree_params *prm,
+                            const dzs_bbox *boxes, hipStream_t s) {
     if (n == 0 || ctx->n_groups == 0)
         return DZS_OK;
     walk_args A;
@@ -952,8 +1038,10 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
     A.pair_count = (unsigned long long *)(ctx->walk_counter + 8);
     // start level K: the deepest level whose cells are at least r_cut wide (so no node above
     // it can be a monopole while theta <= 1), at most DZS_CELL_K_MAX
+    A.key = (const uint64_t *)ctx->key;
+    A.boxes = boxes;
     int K = 0;
-    if (prm->theta <= 1.0 && prm->precision == DZS_FP32)
+    if (prm->theta <= 1.0 && prm->precision == DZS_FP32 && !boxes)
         while (K < DZS_CELL_K_MAX && ldexp(box->L, -(K + 1)) >= prm->r_cut)
             ++K;
     A.cell_K = K;
@@ -979,12 +1067,16 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
         dzs_timed t(ctx, KC_TREE_WALK, s);
         // the start-cell variant carries more scalar state; in FP64 its register pressure
         // costs more than the shorter traversal saves, so the plain form starts at the root
-        if (fp32 && K > 0)
-            hipLaunchKernelGGL((k_tree_walk<float, true>), dim3(slots), dim3(64), 0, s, A);
+        if (boxes && fp32)
+            hipLaunchKernelGGL((k_tree_walk<float, false, true>), dim3(slots), dim3(64), 0, s, A);
+        else if (boxes)
+            hipLaunchKernelGGL((k_tree_walk<double, false, true>), dim3(slots), dim3(64), 0, s, A);
+        else if (fp32 && K > 0)
+            hipLaunchKernelGGL((k_tree_walk<float, true, false>), dim3(slots), dim3(64), 0, s, A);
         else if (fp32)
-            hipLaunchKernelGGL((k_tree_walk<float, false>), dim3(slots), dim3(64), 0, s, A);
+            hipLaunchKernelGGL((k_tree_walk<float, false, false>), dim3(slots), dim3(64), 0, s, A);
         else
-            hipLaunchKernelGGL((k_tree_walk<double, false>), dim3(slots), dim3(64), 0, s, A);
+            hipLaunchKernelGGL((k_tree_walk<double, false, false>), dim3(slots), dim3(64), 0, s, A);
         DZS_TRY(dzs_check_launch(ctx, "tree_walk"));
     }
     DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 4, ctx->walk_counter + 1, sizeof(uint32_t),

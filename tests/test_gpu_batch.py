@@ -1,0 +1,149 @@
+"""GPU parity of the batched step: several independent boxes of different sizes, masses and
+meshes advanced by one kdk_step_batch call, each box against the FP64 oracle's step of that
+box alone.  Bars: drifted positions bit-exact (the drift is the same FP64 arithmetic per
+box); forces at opening angle 0 within rms 1e-9 (plain form) of the oracle's direct sum +
+PM; momenta within 1e-9 of their scale; the precision form within the 1e-5 force bar."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import dzs_ics
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+# (particles per side, box side, mesh side, seed): uneven counts, masses and meshes
+BOXES = [(16, 50.0, 32, 301), (24, 80.0, 48, 302), (32, 120.0, 64, 303), (12, 40.0, 24, 304),
+         (20, 70.0, 48, 305)]
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dz():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2005_05328_amd as dz
+    return dz
+
+
+def _setup(dz):
+    sets, boxes, oboxes, first, ng, r_s, r_cut = [], [], [], [0], [], [], []
+    id_base = 0
+    for n_side, L, g, seed in BOXES:
+        ps = dzs_ics.zeldovich(n_side, L, 0.02, seed=seed, spectrum="bbks")
+        ps.id = ps.id + np.uint32(id_base)
+        id_base += ps.n
+        lam = L / n_side
+        m0 = dzs_ics.particle_mass(L, ps.n)
+        boxes.append(dz.make_box(L, m0, lam / 40))
+        oboxes.append(oracle.Box(L=L, m0=m0, eps0=lam / 40))
+        sets.append(ps)
+        first.append(first[-1] + ps.n)
+        ng.append(g)
+        r_s.append(1.25 * L / g)
+        r_cut.append(4.5 * 1.25 * L / g)
+    return sets, boxes, oboxes, first, ng, r_s, r_cut
+
+
+def _concat(sets):
+    class _P:
+        pass
+    out = _P()
+    for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+        setattr(out, k, np.concatenate([getattr(p, k) for p in sets]))
+    return out
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_batched_step_matches_the_oracle_per_box(dz, fp32):
+    import torch
+    sets, boxes, oboxes, first, ng, r_s, r_cut = _setup(dz)
+    prec = dz.DZS_FP32 if fp32 else dz.DZS_FP64
+    a0, a1 = 0.02, 0.02 * math.exp(0.07824)
+    fac = oracle.step_factors(a0, a1)
+    fac.update(a0=a0, a1=a1)
+    g0s, refs = [], []
+    for ps, ob, g, rs, rc in zip(sets, oboxes, ng, r_s, r_cut):
+        g0 = oracle.total_force(ps.x, ps.y, ps.z, ps.mult, ob, g, rs, rc)
+        ref, ref_g, _, _ = oracle.kdk_step(ps, g0, ob, fac, g, rs, rc, [0.0, 0.0, 0.0],
+                                           solve=False)
+        g0s.append(g0)
+        refs.append((ref, ref_g))
+    allp = _concat(sets)
+    st = dz.State.from_host(allp, g=np.concatenate(g0s, axis=1))
+    sp = dz.step_factors(a0, a1, 0.3)
+    sp.K1, sp.K2 = fac["K1"], fac["K2"]
+    sp.lc.D, sp.lc.chi2_0, sp.lc.chi2_1 = fac["D"], fac["chi2_0"], fac["chi2_1"]
+    sp.do_lightcone, sp.do_coarsen = 1, 0
+    sp.pm = dz.PMParams(0, prec, 0.0, 0, 0)
+    sp.tree = dz.TreeParams(0.0, 0.0, 0.0, 8, 32, prec, 0)
+    ring = dz.LCRing(1000)
+    ring.reset()
+    ctx = dz.Context(max_particles=first[-1] + 64, max_mesh_side=81)
+    _log(f"batch of {len(BOXES)} boxes, {first[-1]} particles, fp32={fp32}")
+    ctx.kdk_step_batch(boxes, first, ng, r_s, r_cut, st, sp, ring)
+    torch.cuda.synchronize()
+    out = st.to_host()
+    ctx.close()
+    assert ring.records()["count"] == 0          # chi(z = 49) >> L
+    for b, (ps, ob) in enumerate(zip(sets, oboxes)):
+        lo, hi = first[b], first[b + 1]
+        ref, ref_g = refs[b]
+        o = np.argsort(out["id"][lo:hi]) + lo
+        r = np.argsort(ref.id)
+        # each box keeps its own particles in its own range
+        assert np.array_equal(out["id"][o], ref.id[r])
+        for k in ("x", "y", "z", "mult", "type"):
+            assert np.array_equal(out[k][o], getattr(ref, k)[r]), (b, k)
+        g = np.stack([out["gx"][o], out["gy"][o], out["gz"][o]])
+        rg = ref_g[:, r]
+        err = math.sqrt(((g - rg) ** 2).sum(0).mean() / (rg ** 2).sum(0).mean())
+        # the force of a z = 49 lattice is a small residual: scale by the parts' magnitude
+        gp = oracle.pm_force(ref.x, ref.y, ref.z, ref.mult, ob, ng[b], r_s[b])[:, r]
+        gs = oracle.short_range(ref.x, ref.y, ref.z, ref.mult, ob, r_s[b], r_cut[b])[:, r]
+        parts = np.sqrt((gp ** 2).sum(0)) + np.sqrt((gs ** 2).sum(0))
+        err_p = math.sqrt(((g - rg) ** 2).sum(0).mean() / (parts ** 2).mean())
+        _log(f"  box {b}: n={hi - lo} force rms rel {err:.3e}, of the parts {err_p:.3e}")
+        if fp32:
+            assert err_p <= 1e-5
+        else:
+            assert err <= 1e-9
+        for a, k in enumerate(("px", "py", "pz")):
+            dp = out[k][o] - getattr(ref, k)[r] - fac["K2"] * (g[a] - rg[a])
+            assert np.abs(dp).max() <= 1e-9 * np.abs(getattr(ref, k)).max()
+
+
+def test_batched_step_rejects_bad_batches(dz):
+    sets, boxes, _, first, ng, r_s, r_cut = _setup(dz)
+    st = dz.State.from_host(_concat(sets))
+    sp = dz.step_factors(0.5, 0.51, 0.3)
+    sp.do_lightcone, sp.do_coarsen = 0, 0
+    sp.pm = dz.PMParams(0, dz.DZS_FP64, 0.0, 0, 0)
+    sp.tree = dz.TreeParams(0.0, 0.0, 0.5, 8, 32, dz.DZS_FP64, 0)
+    ctx = dz.Context(max_particles=first[-1] + 64, max_mesh_side=81)
+    bad_first = list(first)
+    bad_first[-1] -= 1
+    with pytest.raises(dz.DZSError):
+        ctx.kdk_step_batch(boxes, bad_first, ng, r_s, r_cut, st, sp)
+    bad_rc = list(r_cut)
+    bad_rc[1] *= 1.1                               # a different r_cut / r_s
+    with pytest.raises(dz.DZSError):
+        ctx.kdk_step_batch(boxes, first, ng, r_s, bad_rc, st, sp)
+    bad_ng = list(ng)
+    bad_ng[0] = 35                                 # not 2^a 3^b
+    with pytest.raises(dz.DZSError):
+        ctx.kdk_step_batch(boxes, first, bad_ng, r_s, r_cut, st, sp)
+    big = dz.Context(max_particles=first[-1] + 64, max_mesh_side=36)
+    with pytest.raises(dz.DZSError):               # meshes exceed the context
+        big.kdk_step_batch(boxes, first, ng, r_s, r_cut, st, sp)
+    sp.do_coarsen = 1
+    with pytest.raises(dz.DZSError):
+        ctx.kdk_step_batch(boxes, first, ng, r_s, r_cut, st, sp)
+    ctx.close()
+    big.close()
