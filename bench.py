@@ -58,7 +58,168 @@ PRESETS = {
                 precision="fp32", twin="dzs"),
     "c5": dict(n_side=1024, L=2000.0, ng=1024, seed=20050532, n_steps=100, lmax_over_lambda=4,
                precision="fp32", twin="dzs"),
+    # the 64-box ensemble: run by run_ensemble(), not by the single-box path
+    "c4": dict(n_side=0, L=0.0, ng=0, seed=20051000, n_steps=10, lmax_over_lambda=0,
+               precision="fp32", twin=None),
 }
+
+
+def ensemble_boxes():
+    """The 64-box ensemble: box i has side 128 + 256 (i mod 8) / 7 Mpc/h, 32^3, 48^3, 64^3 or
+    96^3 particles (i // 16), a mesh of twice the particles per side, seed 20051000 + i, and is
+    coarsened once at DZS level 1 + (i mod 3) (l_max = 2^level lambda)."""
+    out = []
+    for i in range(64):
+        n_side = [32, 48, 64, 96][i // 16]
+        L = 128.0 + 256.0 * (i % 8) / 7.0
+        out.append(dict(i=i, n_side=n_side, L=L, ng=2 * n_side, seed=20051000 + i,
+                        level=1 + i % 3))
+    return out
+
+
+def run_ensemble(args, dz, torch, dzs_ics):
+    """Config 4: 64 independent boxes (Zel'dovich at z = 9), each coarsened once outside a
+    prescribed lightcone radius R_lc = L/4 (theta 1, b = 0, l_max = 2^level lambda), then
+    advanced together by kdk_step_batch in the precision form; the same steps run box by box
+    with kdk_step for the launch-overhead comparison.  A short autotuning pass picks the
+    walk's group and leaf sizes first."""
+    K = max(1, min(args.steps or 10, 10))
+    prec = dz.DZS_FP64 if args.precision == "fp64" else dz.DZS_FP32
+    a = np.exp(np.linspace(math.log(0.1), math.log(0.1) + 0.05 * 10, 11))
+    specs = ensemble_boxes()
+    big = max(sp_["n_side"] for sp_ in specs) ** 3
+    cctx = dz.Context(big, 2 * max(sp_["n_side"] for sp_ in specs))
+    parts, boxes, first, ngs, rss, rcs = [], [], [0], [], [], []
+    id_base = 0
+    log("ensemble: initial conditions and per-box coarsening")
+    for b in specs:
+        ps = dzs_ics.zeldovich(b["n_side"], b["L"], 0.1, seed=b["seed"], spectrum="bbks")
+        lam = b["L"] / b["n_side"]
+        m0 = dzs_ics.particle_mass(b["L"], ps.n)
+        box = dz.make_box(b["L"], m0, lam / 40)
+        st = dz.State.from_host(ps)
+        cp = dz.CoarsenParams()
+        cp.R_lc, cp.b, cp.theta = 0.25 * b["L"], 0.0, 1.0
+        cp.k_min = k_min_for(b["n_side"], 2 ** b["level"])
+        cctx.dzs_coarsen(box, st, cp)
+        torch.cuda.synchronize()
+        h = st.to_host()
+        h["id"] = h["id"] + np.uint32(id_base)
+        id_base += b["n_side"] ** 3
+        parts.append(h)
+        boxes.append(box)
+        first.append(first[-1] + h["x"].shape[0])
+        ngs.append(b["ng"])
+        rss.append(1.25 * b["L"] / b["ng"])
+        rcs.append(4.5 * 1.25 * b["L"] / b["ng"])
+    cctx.close()
+    N = first[-1]
+    log(f"ensemble: {N} particles in 64 boxes after coarsening "
+        f"({sum(sp_['n_side'] ** 3 for sp_ in specs)} before)")
+
+    class _P:
+        pass
+    allp = _P()
+    for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+        setattr(allp, k, np.concatenate([h[k] for h in parts]))
+    cells = sum(g ** 3 for g in ngs)
+    side = 8
+    while side ** 3 < cells or not _smooth(side):
+        side += 1
+    ctx = dz.Context(N + 64, side)
+    st0 = dz.State.from_host(allp, capacity=N + 64)
+    st = dz.State(N + 64)
+    ring = dz.LCRing(1024)
+
+    def params(s_, group, leaf):
+        sp_ = dz.step_factors(float(a[s_]), float(a[s_ + 1]), 0.3)
+        sp_.do_lightcone, sp_.do_coarsen = 1, 0
+        sp_.pm = dz.PMParams(0, prec, 0.0, 0, 0)
+        sp_.tree = dz.TreeParams(0.0, 0.0, 0.5, leaf, group, prec, 0)
+        return sp_
+
+    def batch_run(steps, group, leaf):
+        copy_state(st, st0)
+        ring.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(steps):
+            ctx.kdk_step_batch(boxes, first, ngs, rss, rcs, st, params(s_, group, leaf), ring)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # autotuning: one step per candidate (after one warm-up step), fastest wins
+    tune = {}
+    batch_run(1, 32, 16)
+    for group in (16, 32, 64):
+        for leaf in (8, 16, 32):
+            tune[f"group {group} leaf {leaf}"] = (batch_run(1, group, leaf), group, leaf)
+    best = min(tune.values())
+    group, leaf = best[1], best[2]
+    log(f"autotune: group {group}, leaf {leaf}")
+    batch_run(args.warmup, group, leaf)
+    ctx.timing(enable=True, reset=True)
+    ctx.pair_interactions(reset=True)
+    t_batch = batch_run(K, group, leaf)
+    kern = ctx.timing(enable=False, reset=True)
+    pairs = ctx.pair_interactions(reset=True)
+    ctx.close()
+
+    # the same steps box by box with the single-box call
+    log("box-by-box comparison")
+    bctx = dz.Context(max(first[b + 1] - first[b] for b in range(64)) + 64, max(ngs))
+    states = []
+    for b in range(64):
+        lo, hi = first[b], first[b + 1]
+        sub = _P()
+        for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+            setattr(sub, k, getattr(allp, k)[lo:hi])
+        states.append(dz.State.from_host(sub))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(K):
+        for b in range(64):
+            sp_ = params(s_, group, leaf)
+            sp_.pm = dz.PMParams(ngs[b], prec, rss[b], 0, 0)
+            sp_.tree = dz.TreeParams(rss[b], rcs[b], 0.5, leaf, group, prec, 0)
+            bctx.kdk_step(boxes[b], states[b], sp_, ring)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    bctx.close()
+    totals = {c: ms * calls for c, (ms, calls) in kern.items() if calls}
+    avg_ms, calls = kern["tree_walk"]
+    flops = FLOP_PER_INTERACTION * pairs / calls
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if prec == dz.DZS_FP32 else PEAK_FP64_TFLOPS
+    return {
+        "metric": METRIC, "value": N * K / t_batch, "unit": UNIT, "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_batch / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == dz.DZS_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"64-box ensemble (L 128-384 Mpc/h, 32^3-96^3 particles, "
+                                f"meshes 64^3-192^3, Zel'dovich z=9, each coarsened once at "
+                                f"level 1-3), {N} particles, {K} log KDK steps in one batched "
+                                f"call per step"),
+                   "preset": "c4", "particles": N, "boxes": 64, "parallelism": "1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": "tree_walk",
+                     "avg_ms": avg_ms,
+                     "work_per_launch": f"{pairs / calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP"},
+        "cpu_baseline": None,
+        "ensemble": {"batched_s": t_batch, "box_by_box_s": t_loop,
+                     "batched_speedup": t_loop / t_batch, "autotuned": {"group": group, "leaf": leaf},
+                     "autotune_s_per_step": {k: v[0] for k, v in tune.items()}},
+        "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
+                                                                    key=lambda kv: -kv[1])},
+    }
+
+
+def _smooth(n):
+    while n % 2 == 0:
+        n //= 2
+    while n % 3 == 0:
+        n //= 3
+    return n == 1
 
 
 def workload(n_side=128, L=256.0, ng=256, seed=20050529, n_steps=50, lmax_over_lambda=2,
@@ -309,6 +470,9 @@ def main():
     import dzs_ics
     import paper_2005_05328_amd as dz
 
+    if args.workload == "c4":
+        print(json.dumps(run_ensemble(args, dz, torch, dzs_ics)), flush=True)
+        return
     P = dict(PRESETS[args.workload])
     if args.n_side:
         f = args.n_side / P["n_side"]
