@@ -258,9 +258,23 @@ typedef struct {
  * Chebyshev series; every box's particles are tested against the same sphere), the PM
  * precision and the tree's opening angle, leaf and group size and precision (r_s and r_cut
  * come from the batch); do_coarsen must be 0 (coarsen each box with dzs_coarsen).  Each
- * box's particles are left Morton-sorted within its range.  Synchronises the stream. */
+ * box's particles are left Morton-sorted within its range.
+ * Synchronises the stream only when the batch differs from the previous call (its tables are
+ * then rebuilt and uploaded); otherwise the call only enqueues work, so it can be captured
+ * into a HIP graph once and replayed for every step: K1, K2 and the lightcone drift are read
+ * when the step runs from a device block filled from the context's pinned host staging, which
+ * this call and kdk_step_batch_stage write.  The tree's node capacity and the walk's stack
+ * depth are checked on the device; dzs_check reports an overflow. */
 dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_particles *state,
                           const dzs_step_params *prm, dzs_lc_ring *ring, void *stream);
+
+/* Stage K1, K2 and the lightcone drift of prm for the next replay of a captured
+ * kdk_step_batch (host memory only; call after the previous replay has finished). */
+dzs_status kdk_step_batch_stage(dzs_ctx *ctx, const dzs_step_params *prm);
+
+/* Synchronise the stream and report (and clear) a tree node-capacity or walk stack-depth
+ * overflow left by calls that do not check it themselves (kdk_step_batch): DZS_ECAPACITY. */
+dzs_status dzs_check(dzs_ctx *ctx, void *stream);
 
 /* ---- parts of the path, exposed for testing and measurement --------------------------- */
 

@@ -223,6 +223,14 @@ class Context:
                                                           C.byref(prm), rv,
                                                           _stream_handle(stream)))
 
+    def kdk_step_batch_stage(self, prm: StepParams):
+        """Stage the factors of the next replay of a captured kdk_step_batch."""
+        self._check("kdk_step_batch_stage", _lib.kdk_step_batch_stage(self._h, C.byref(prm)))
+
+    def check(self, stream=None):
+        """Report a deferred tree-capacity or walk-stack overflow (synchronises)."""
+        self._check("dzs_check", _lib.dzs_check(self._h, _stream_handle(stream)))
+
     # ---- parts of the path
     def morton_keys(self, box: Box, st: State, keys, stream=None):
         v = st.view()

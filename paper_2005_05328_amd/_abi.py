@@ -18,7 +18,8 @@ DZS_FP64, DZS_FP32 = 0, 1
 # every entry point include/dzs.h declares
 EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_factors",
            "dzs_coarsen", "pm_force", "tree_force", "lightcone_emit", "kdk_step",
-           "kdk_step_batch", "dzs_morton_keys", "dzs_sort_state", "dzs_counters", "dzs_timing")
+           "kdk_step_batch", "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
+           "dzs_sort_state", "dzs_counters", "dzs_timing")
 DZS_BATCH_MAX = 512
 
 
@@ -113,6 +114,8 @@ def load():
                            C.POINTER(LCRing), C.POINTER(CoarsenReport), P]
     L.kdk_step_batch.argtypes = [P, C.POINTER(Batch), C.POINTER(Particles), C.POINTER(StepParams),
                                  C.POINTER(LCRing), P]
+    L.kdk_step_batch_stage.argtypes = [P, C.POINTER(StepParams)]
+    L.dzs_check.argtypes = [P, P]
     L.dzs_morton_keys.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), P, P]
     L.dzs_sort_state.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), i32, P, P]
     L.dzs_counters.argtypes = [P, i32, C.POINTER(C.c_uint64)]
@@ -120,7 +123,7 @@ def load():
                              C.POINTER(C.c_uint64), i32]
     for name in ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_step_factors", "dzs_coarsen",
                  "pm_force", "tree_force", "lightcone_emit", "kdk_step", "kdk_step_batch",
-                 "dzs_morton_keys",
+                 "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
                  "dzs_sort_state", "dzs_counters", "dzs_timing"):
         getattr(L, name).restype = st
     return L

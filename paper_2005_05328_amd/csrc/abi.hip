@@ -135,11 +135,13 @@ static void release(dzs_ctx *ctx) {
                     ctx->scan_tmp, ctx->gather_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult,
                     ctx->sgx, ctx->sgy, ctx->sgz, ctx->nd_first, ctx->nd_count, ctx->nd_child,
                     ctx->nd_nchild, ctx->nd_level, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
-                    ctx->nd_bmax, ctx->nd_hmax, ctx->frontier, ctx->frontier_next,
+                    ctx->nd_bmax, ctx->nd_hmax, ctx->nd_parent, ctx->nd_arrive, ctx->bstate,
+                    ctx->frontier, ctx->frontier_next,
                     ctx->fr_nchild, ctx->fr_ninternal, ctx->fr_child_off, ctx->fr_int_off,
                     ctx->child_bounds, ctx->grp_flag, ctx->grp_scan, ctx->grp_first,
                     ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl,
-                    ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
+                    ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members,
+                    ctx->step_dev, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
                     ctx->pm_tables, ctx->dz_head, ctx->dz_flag, ctx->dz_scan, ctx->dz_new,
                     ctx->dz_newmult, ctx->dz_newid, ctx->dz_perm, ctx->d_small};
     for (void *p : ptrs)
@@ -149,6 +151,10 @@ static void release(dzs_ctx *ctx) {
         (void)hipHostFree(ctx->h_small);
     if (ctx->batch_box_h)
         (void)hipHostFree(ctx->batch_box_h);
+    if (ctx->batch_first_h)
+        (void)hipHostFree(ctx->batch_first_h);
+    if (ctx->step_h)
+        (void)hipHostFree(ctx->step_h);
     if (ctx->timers) {
         for (int i = 0; i < dzs_timer_pool::CAP; ++i) {
             (void)hipEventDestroy(ctx->timers->start[i]);
@@ -196,6 +202,10 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->nd_bmin, 3 * nn));
     DZS_TRY(alloc(c, &c->nd_bmax, 3 * nn));
     DZS_TRY(alloc(c, &c->nd_hmax, nn));
+    DZS_TRY(alloc(c, &c->nd_parent, nn));
+    DZS_TRY(alloc(c, &c->nd_arrive, nn));
+    DZS_TRY(alloc(c, &c->bstate, 64));
+    DZS_HIP(c, hipMemset(c->bstate, 0, 64 * sizeof(uint32_t)));
     DZS_TRY(alloc(c, &c->frontier, n));
     DZS_TRY(alloc(c, &c->frontier_next, n));
     DZS_TRY(alloc(c, &c->fr_nchild, n));
@@ -215,10 +225,16 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->batch_box, DZS_BATCH_MAX));
     DZS_TRY(alloc(c, &c->batch_first, DZS_BATCH_MAX + 1));
     DZS_TRY(alloc(c, &c->batch_members, DZS_BATCH_MAX));
+    DZS_TRY(alloc(c, &c->step_dev, 1));
     {
-        void *hb = nullptr;
+        void *hb = nullptr, *hf = nullptr, *hs = nullptr;
         DZS_HIP(c, hipHostMalloc(&hb, sizeof(dzs_bbox) * DZS_BATCH_MAX, hipHostMallocDefault));
         c->batch_box_h = (dzs_bbox *)hb;
+        DZS_HIP(c, hipHostMalloc(&hf, sizeof(uint64_t) * (DZS_BATCH_MAX + 1),
+                                 hipHostMallocDefault));
+        c->batch_first_h = (uint64_t *)hf;
+        DZS_HIP(c, hipHostMalloc(&hs, sizeof(dzs_step_block), hipHostMallocDefault));
+        c->step_h = (dzs_step_block *)hs;
     }
     DZS_TRY(alloc(c, &c->cell_dl, 1ull << (3 * DZS_CELL_K_MAX)));
     if (ng > 0) {
@@ -549,7 +565,7 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     if (prm->do_lightcone)
         DZS_TRY(check_lc(ctx, &prm->lc, ring));
     const double ratio = batch->r_cut[0] / batch->r_s[0];
-    dzs_bbox *hb = ctx->batch_box_h;
+    std::vector<dzs_bbox> tb(nb);
     for (uint32_t b = 0; b < nb; ++b) {
         const dzs_box &bx = batch->boxes[b];
         const double rs = batch->r_s[b], rc = batch->r_cut[b];
@@ -562,7 +578,7 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
             fabs(rc / rs - ratio) > 1e-12 * ratio)
             return dzs_fail(ctx, DZS_EINVAL, "batch: box %u needs 0 < r_cut < L/2, r_cut <= 5 r_s "
                             "and the r_cut / r_s of box 0", b);
-        dzs_bbox &h = hb[b];
+        dzs_bbox &h = tb[b];
         memset(&h, 0, sizeof(h));
         h.L = bx.L;
         h.halfL = 0.5 * bx.L;
@@ -581,17 +597,47 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
         h.root = 0xffffffffu;
     }
     hipStream_t s = (hipStream_t)stream;
-    DZS_TRY(dzs_pm_batch_prepare(ctx, nb, hb, s));
-    DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_box, hb, sizeof(dzs_bbox) * nb, hipMemcpyHostToDevice,
-                                s));
-    DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_first, batch->first, sizeof(uint64_t) * (nb + 1),
+    // the box tables, particle offsets and mesh tables are uploaded when the batch changes;
+    // a repeated batch (the steps of one run, or a captured step) reuses them without any
+    // host synchronisation
+    bool same = ctx->batch_ready && ctx->batch_nb == nb;
+    for (uint32_t b = 0; same && b < nb; ++b) {
+        const dzs_bbox &o = ctx->batch_box_h[b], &n = tb[b];
+        same = o.L == n.L && o.m0 == n.m0 && o.h0 == n.h0 && o.G == n.G && o.r_s == n.r_s &&
+               o.r_cut == n.r_cut && o.first == n.first && o.count == n.count && o.ng == n.ng;
+    }
+    if (!same) {
+        ctx->batch_ready = false;
+        DZS_HIP(ctx, hipStreamSynchronize(s));  // the staging buffers may be in use
+        memcpy(ctx->batch_box_h, tb.data(), sizeof(dzs_bbox) * nb);
+        DZS_TRY(dzs_pm_batch_prepare(ctx, nb, ctx->batch_box_h, s));
+        for (uint32_t b = 0; b <= nb; ++b)
+            ctx->batch_first_h[b] = batch->first[b];
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_box, ctx->batch_box_h, sizeof(dzs_bbox) * nb,
+                                    hipMemcpyHostToDevice, s));
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_first, ctx->batch_first_h,
+                                    sizeof(uint64_t) * (nb + 1), hipMemcpyHostToDevice, s));
+        DZS_HIP(ctx, hipStreamSynchronize(s));
+        ctx->batch_nb = nb;
+        ctx->batch_ready = true;
+    }
+    // this step's factors: staged on the host, copied to the device block by the stream
+    ctx->step_h->K1 = prm->K1;
+    ctx->step_h->K2 = prm->K2;
+    dzs_make_lc_args(&prm->lc, &ctx->step_h->lc);
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->step_dev, ctx->step_h, sizeof(dzs_step_block),
                                 hipMemcpyHostToDevice, s));
     if (st->n == 0)
         return DZS_OK;
+    struct defer_guard {
+        dzs_ctx *c;
+        ~defer_guard() { c->defer_checks = false; }
+    } guard{ctx};
+    ctx->defer_checks = true;
 
-    DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s));
+    DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s, &ctx->step_dev->K1));
     DZS_TRY(dzs_launch_drift_lc(ctx, &batch->boxes[0], st, &prm->lc, ring, prm->do_lightcone, 1,
-                                s, true, nb));
+                                s, true, nb, &ctx->step_dev->lc));
     // keys with the box on top, one sort for every box: each box stays in its range
     DZS_TRY(dzs_launch_keys(ctx, st->x, st->y, st->z, st->n, 1.0, ctx->key, ctx->idx, s, true,
                             nb));
@@ -606,5 +652,26 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     t.accumulate = 1;
     DZS_TRY(dzs_tree_walk_ex(ctx, &batch->boxes[0], st->n, st->x, st->y, st->z, st->mult, st->gx,
                              st->gy, st->gz, &t, ctx->batch_box, s));
-    return dzs_launch_kick(ctx, st, prm->K2, s);
+    return dzs_launch_kick(ctx, st, prm->K2, s, &ctx->step_dev->K2);
+}
+
+extern "C" dzs_status kdk_step_batch_stage(dzs_ctx *ctx, const dzs_step_params *prm) {
+    if (!ctx)
+        return DZS_EINVAL;
+    ctx->err[0] = 0;
+    if (!prm)
+        return dzs_fail(ctx, DZS_EINVAL, "null step parameters");
+    if (prm->lc.n_cheb < 1 || prm->lc.n_cheb > DZS_CHEB_MAX)
+        return dzs_fail(ctx, DZS_EINVAL, "step: need 1 <= n_cheb <= %d", DZS_CHEB_MAX);
+    ctx->step_h->K1 = prm->K1;
+    ctx->step_h->K2 = prm->K2;
+    dzs_make_lc_args(&prm->lc, &ctx->step_h->lc);
+    return DZS_OK;
+}
+
+extern "C" dzs_status dzs_check(dzs_ctx *ctx, void *stream) {
+    if (!ctx)
+        return DZS_EINVAL;
+    ctx->err[0] = 0;
+    return dzs_tree_check(ctx, (hipStream_t)stream);
 }

@@ -56,6 +56,22 @@ struct dzs_timer_pool {
 #define DZS_BATCH_SHIFT (3 * (DZS_KEY_BITS - DZS_BATCH_LEVELS))  // 54: box id = key >> 54
 #define DZS_BATCH_SIDE 262144.0                  // 2^18 cells per side below the box digits
 
+// drift and lightcone parameters of one drift (kernel argument or device block)
+struct lc_args {
+    double xo[3];
+    double chi2_0, chi2_1, D, a0, a1;
+    int n_cheb;
+    double cchi[DZS_CHEB_MAX];
+    double cdrift[DZS_CHEB_MAX];
+};
+
+// the factors of one batched step, in a device block (and its pinned host staging): a
+// captured step reads them when it runs
+struct dzs_step_block {
+    double K1, K2;
+    lc_args lc;
+};
+
 // per-box parameters of a batched step, in device memory
 struct dzs_bbox {
     double L, halfL;
@@ -117,12 +133,19 @@ struct dzs_ctx {
     std::vector<size_t> batch_tw_off;  // their twiddle tables in batch_tab
     std::vector<uint32_t> batch_cls_first;  // their member ranges in batch_members
     uint64_t batch_cells = 0;          // mesh cells of all boxes
+    bool batch_ready = false;          // batch tables match batch_box_h
+    uint32_t batch_nb = 0;
+    uint64_t *batch_first_h = nullptr; // pinned staging of the particle offsets
+    dzs_step_block *step_dev = nullptr, *step_h = nullptr;
     uint32_t *cell_node = nullptr;     // walk start cells: [8^DZS_CELL_K_MAX] node ids
     uint8_t *cell_dl = nullptr;        // and the level offset of each
     double qf_err = 1.0;
-    uint32_t level_start[DZS_KEY_BITS + 3] = {0};
-    int n_levels = 0;
-    uint32_t n_nodes = 0, n_groups = 0;
+    uint32_t *bstate = nullptr;        // tree build state on the device (counts, level starts)
+    uint32_t *nd_parent = nullptr;     // parent of each node (bottom-up moments)
+    uint32_t *nd_arrive = nullptr;     // children counted in at each node (bottom-up moments)
+    bool tree_built = false;           // a tree for tree_n particles is in the node arrays
+    uint32_t tree_n = 0;
+    bool defer_checks = false;         // skip the synchronising overflow checks (batched step)
 
     // ---- PM mesh
     long long *mesh_q = nullptr;  // fixed-point density accumulator, ng^3
@@ -252,16 +275,22 @@ __device__ __forceinline__ uint32_t dzs_wave_incl_scan(uint32_t v) {
 uint64_t dzs_scan_tmp_words(uint64_t n);
 dzs_status dzs_scan_u32(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n,
                         uint32_t *total_dev, hipStream_t s);
+// the same over min(n_max, *n_dev) elements, the count read on the device
+dzs_status dzs_scan_u32_dev(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n_max,
+                            const uint32_t *n_dev, uint32_t *total_dev, hipStream_t s);
 uint64_t dzs_sort_hist_words(uint64_t n);
 dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s);  // ctx->key/idx in+out
 dzs_status dzs_fix_ties(dzs_ctx *ctx, uint64_t n, const uint32_t *id, hipStream_t s);
 
 // particles.hip
-dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipStream_t s);
+dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipStream_t s,
+                           const double *K_dev = nullptr);
+void dzs_make_lc_args(const dzs_lc_params *lc, lc_args *A);
 // batch = true: the box of each particle (its L) from ctx->batch_first / ctx->batch_box (nb boxes)
 dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                                const dzs_lc_params *lc, dzs_lc_ring *ring, int do_lc,
-                               int do_drift, hipStream_t s, bool batch = false, uint32_t nb = 0);
+                               int do_drift, hipStream_t s, bool batch = false, uint32_t nb = 0,
+                               const lc_args *A_dev = nullptr);
 dzs_status dzs_launch_keys(dzs_ctx *ctx, const double *x, const double *y, const double *z,
                            uint64_t n, double L, uint64_t *key, uint32_t *idx, hipStream_t s,
                            bool batch = false, uint32_t nb = 0);
@@ -287,6 +316,7 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
                          double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s);
 
 dzs_status dzs_batch_roots(dzs_ctx *ctx, dzs_bbox *boxes, hipStream_t s);
+dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s);
 dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                             const double *y, const double *z, const uint32_t *mult, double *gx,
                             double *gy, double *gz, const dzs_tree_params *prm,

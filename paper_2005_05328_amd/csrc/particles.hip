@@ -15,22 +15,26 @@ __global__ __launch_bounds__(PT_THREADS) void k_kick(uint64_t n, double *__restr
                                                      double *__restrict__ pz,
                                                      const double *__restrict__ gx,
                                                      const double *__restrict__ gy,
-                                                     const double *__restrict__ gz, double K) {
+                                                     const double *__restrict__ gz, double K,
+                                                     const double *__restrict__ Kp) {
     uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
     if (i >= n)
         return;
+    if (Kp)
+        K = *Kp;  // the step's factor from a device parameter block
     px[i] = px[i] + gx[i] * K;
     py[i] = py[i] + gy[i] * K;
     pz[i] = pz[i] + gz[i] * K;
 }
 
-dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipStream_t s) {
+dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipStream_t s,
+                           const double *K_dev) {
     if (p->n == 0)
         return DZS_OK;
     dzs_timed t(ctx, KC_KICK, s);
     hipLaunchKernelGGL(k_kick, dim3(blocks_for(p->n, PT_THREADS)), dim3(PT_THREADS), 0, s, p->n,
                        p->px, p->py, p->pz, (const double *)p->gx, (const double *)p->gy,
-                       (const double *)p->gz, K);
+                       (const double *)p->gz, K, K_dev);
     return dzs_check_launch(ctx, "kick");
 }
 
@@ -50,14 +54,6 @@ __device__ __forceinline__ uint32_t batch_box_of(const uint64_t *first, uint32_t
 // ---------------------------------------------------------------------------------------
 // drift + lightcone
 // ---------------------------------------------------------------------------------------
-struct lc_args {
-    double xo[3];
-    double chi2_0, chi2_1, D, a0, a1;
-    int n_cheb;
-    double cchi[DZS_CHEB_MAX];
-    double cdrift[DZS_CHEB_MAX];
-};
-
 __device__ __forceinline__ double cheb_eval(const double *c, int n, double t) {
     // Clenshaw recurrence for sum_k c_k T_k(t)
     double b1 = 0.0, b2 = 0.0;
@@ -97,11 +93,14 @@ __device__ double lc_solve(const lc_args &A, double d0x, double d0y, double d0z,
     return t;
 }
 
+// PBLOCK: the drift and lightcone parameters come from a device block (*Ap) rather than the
+// kernel arguments, so that a captured launch can be replayed for another step.
+template <bool PBLOCK>
 __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
     uint64_t n, double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
     const double *__restrict__ px, const double *__restrict__ py, const double *__restrict__ pz,
-    const uint32_t *__restrict__ id, const uint32_t *__restrict__ mult, double L, lc_args A,
-    int do_lc, int do_drift, dzs_lc_record *__restrict__ rec, uint64_t rec_cap,
+    const uint32_t *__restrict__ id, const uint32_t *__restrict__ mult, double L, lc_args A_arg,
+    const lc_args *__restrict__ Ap, int do_lc, int do_drift, dzs_lc_record *__restrict__ rec, uint64_t rec_cap,
     unsigned long long *__restrict__ rec_count, uint32_t *__restrict__ overflow,
     const uint64_t *__restrict__ bfirst, const dzs_bbox *__restrict__ boxes, uint32_t nb) {
     uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
@@ -109,6 +108,7 @@ __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
         return;
     if (boxes)
         L = boxes[batch_box_of(bfirst, nb, i)].L;
+    const lc_args &A = PBLOCK ? *Ap : A_arg;
     const double xi = x[i], yi = y[i], zi = z[i];
     const double pxi = px[i], pyi = py[i], pzi = pz[i];
     const double sx = pxi * A.D, sy = pyi * A.D, sz = pzi * A.D;
@@ -152,25 +152,30 @@ __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
     }
 }
 
+void dzs_make_lc_args(const dzs_lc_params *lc, lc_args *A) {
+    memset(A, 0, sizeof(*A));
+    for (int d = 0; d < 3; ++d)
+        A->xo[d] = lc->x_obs[d];
+    A->chi2_0 = lc->chi2_0;
+    A->chi2_1 = lc->chi2_1;
+    A->D = lc->D;
+    A->a0 = lc->a0;
+    A->a1 = lc->a1;
+    A->n_cheb = lc->n_cheb;
+    for (int k = 0; k < DZS_CHEB_MAX; ++k) {
+        A->cchi[k] = lc->cheb_chi[k];
+        A->cdrift[k] = lc->cheb_drift[k];
+    }
+}
+
 dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                                const dzs_lc_params *lc, dzs_lc_ring *ring, int do_lc,
-                               int do_drift, hipStream_t s, bool batch, uint32_t nb) {
+                               int do_drift, hipStream_t s, bool batch, uint32_t nb,
+                               const lc_args *A_dev) {
     if (p->n == 0)
         return DZS_OK;
     lc_args A;
-    memset(&A, 0, sizeof(A));
-    for (int d = 0; d < 3; ++d)
-        A.xo[d] = lc->x_obs[d];
-    A.chi2_0 = lc->chi2_0;
-    A.chi2_1 = lc->chi2_1;
-    A.D = lc->D;
-    A.a0 = lc->a0;
-    A.a1 = lc->a1;
-    A.n_cheb = lc->n_cheb;
-    for (int k = 0; k < DZS_CHEB_MAX; ++k) {
-        A.cchi[k] = lc->cheb_chi[k];
-        A.cdrift[k] = lc->cheb_drift[k];
-    }
+    dzs_make_lc_args(lc, &A);
     dzs_lc_record *rec = nullptr;
     uint64_t cap = 0;
     unsigned long long *cnt = nullptr;
@@ -182,12 +187,22 @@ dzs_status dzs_launch_drift_lc(dzs_ctx *ctx, const dzs_box *box, const dzs_parti
         ovf = ring->overflow;
     }
     dzs_timed t(ctx, KC_DRIFT_LC, s);
-    hipLaunchKernelGGL(k_drift_lc, dim3(blocks_for(p->n, PT_THREADS)), dim3(PT_THREADS), 0, s,
-                       p->n, p->x, p->y, p->z, (const double *)p->px, (const double *)p->py,
-                       (const double *)p->pz, (const uint32_t *)p->id,
-                       (const uint32_t *)p->mult, box->L, A, do_lc, do_drift, rec, cap, cnt,
-                       ovf, (const uint64_t *)ctx->batch_first, batch ? ctx->batch_box : nullptr,
-                       nb);
+    if (A_dev)
+        hipLaunchKernelGGL(k_drift_lc<true>, dim3(blocks_for(p->n, PT_THREADS)), dim3(PT_THREADS),
+                           0, s, p->n, p->x, p->y, p->z, (const double *)p->px,
+                           (const double *)p->py, (const double *)p->pz,
+                           (const uint32_t *)p->id, (const uint32_t *)p->mult, box->L, A, A_dev,
+                           do_lc, do_drift, rec, cap, cnt, ovf,
+                           (const uint64_t *)ctx->batch_first, batch ? ctx->batch_box : nullptr,
+                           nb);
+    else
+        hipLaunchKernelGGL(k_drift_lc<false>, dim3(blocks_for(p->n, PT_THREADS)),
+                           dim3(PT_THREADS), 0, s, p->n, p->x, p->y, p->z,
+                           (const double *)p->px, (const double *)p->py,
+                           (const double *)p->pz, (const uint32_t *)p->id,
+                           (const uint32_t *)p->mult, box->L, A, A_dev, do_lc, do_drift, rec,
+                           cap, cnt, ovf, (const uint64_t *)ctx->batch_first,
+                           batch ? ctx->batch_box : nullptr, nb);
     return dzs_check_launch(ctx, "drift_lc");
 }
 

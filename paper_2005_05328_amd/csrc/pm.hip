@@ -499,10 +499,20 @@ static dzs_status pm_interp(dzs_ctx *ctx, const dzs_particles *p, int accumulate
     return dzs_check_launch(ctx, "pm_interp");
 }
 
+// zero fill by a kernel (a memset node in a captured graph is avoided)
+__global__ __launch_bounds__(PM_THREADS) void k_zero_u64(uint64_t n, unsigned long long *a) {
+    for (uint64_t i = (uint64_t)blockIdx.x * PM_THREADS + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * PM_THREADS)
+        a[i] = 0ull;
+}
+
 static dzs_status pm_deposit(dzs_ctx *ctx, const dzs_particles *p, uint64_t cells, double delta,
                              int ng, pm_batch B, hipStream_t s) {
     dzs_timed t(ctx, KC_PM_DEPOSIT, s);
-    DZS_HIP(ctx, hipMemsetAsync(ctx->mesh_q, 0, sizeof(long long) * cells, s));
+    const uint64_t zb = (cells + PM_THREADS - 1) / PM_THREADS;
+    hipLaunchKernelGGL(k_zero_u64, dim3((uint32_t)(zb < 65536 ? zb : 65536)), dim3(PM_THREADS), 0,
+                       s, cells, (unsigned long long *)ctx->mesh_q);
+    DZS_TRY(dzs_check_launch(ctx, "mesh_clear"));
     if (p->n > 0) {
         hipLaunchKernelGGL(k_pm_deposit, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0, s,
                            p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,

@@ -37,10 +37,15 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_
     return off + incl - v;
 }
 
+// n_dev (optional): the element count is min(n, *n_dev), read on the device, so that a
+// launch sized for an upper bound needs no host copy of the count.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *__restrict__ in,
                                                               uint64_t n,
-                                                              uint32_t *__restrict__ part) {
+                                                              uint32_t *__restrict__ part,
+                                                              const uint32_t *__restrict__ n_dev) {
     __shared__ uint32_t s_wave[4];
+    if (n_dev && *n_dev < n)
+        n = *n_dev;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
     uint32_t sum = 0;
     for (int r = 0; r < SCAN_ITEMS; ++r) {
@@ -59,8 +64,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile(const uint32_t *__re
                                                             uint32_t *__restrict__ out,
                                                             uint64_t n,
                                                             const uint32_t *__restrict__ offs,
-                                                            uint32_t *__restrict__ total) {
+                                                            uint32_t *__restrict__ total,
+                                                            const uint32_t *__restrict__ n_dev) {
     __shared__ uint32_t s_wave[4];
+    if (n_dev && *n_dev < n)
+        n = *n_dev;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     uint32_t sum = 0;
@@ -96,19 +104,22 @@ uint64_t dzs_scan_tmp_words(uint64_t n) {
 }
 
 static dzs_status scan_rec(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n,
-                           uint32_t *total_dev, uint32_t *tmp, hipStream_t s) {
+                           uint32_t *total_dev, uint32_t *tmp, const uint32_t *n_dev,
+                           hipStream_t s) {
     uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb <= 1) {
         hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SCAN_THREADS), 0, s, in, out, n,
-                           (const uint32_t *)nullptr, total_dev);
+                           (const uint32_t *)nullptr, total_dev, n_dev);
         return dzs_check_launch(ctx, "scan_tile");
     }
+    // tiles past the device count sum to zero, so the partial sums need no count of their own
     uint32_t *part = tmp, *part_scan = tmp + nb;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, n, part,
+                       n_dev);
     DZS_TRY(dzs_check_launch(ctx, "scan_reduce"));
-    DZS_TRY(scan_rec(ctx, part, part_scan, nb, nullptr, tmp + 2 * nb, s));
+    DZS_TRY(scan_rec(ctx, part, part_scan, nb, nullptr, tmp + 2 * nb, nullptr, s));
     hipLaunchKernelGGL(k_scan_tile, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, out, n,
-                       (const uint32_t *)part_scan, total_dev);
+                       (const uint32_t *)part_scan, total_dev, n_dev);
     return dzs_check_launch(ctx, "scan_tile");
 }
 
@@ -122,7 +133,17 @@ dzs_status dzs_scan_u32(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_
     if (dzs_scan_tmp_words(n) > ctx->scan_tmp_cap)
         return dzs_fail(ctx, DZS_ECAPACITY, "scan of %llu elements exceeds scratch",
                         (unsigned long long)n);
-    return scan_rec(ctx, in, out, n, total_dev, ctx->scan_tmp, s);
+    return scan_rec(ctx, in, out, n, total_dev, ctx->scan_tmp, nullptr, s);
+}
+
+dzs_status dzs_scan_u32_dev(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n_max,
+                            const uint32_t *n_dev, uint32_t *total_dev, hipStream_t s) {
+    if (n_max == 0)
+        n_max = 1;
+    if (dzs_scan_tmp_words(n_max) > ctx->scan_tmp_cap)
+        return dzs_fail(ctx, DZS_ECAPACITY, "scan of %llu elements exceeds scratch",
+                        (unsigned long long)n_max);
+    return scan_rec(ctx, in, out, n_max, total_dev, ctx->scan_tmp, n_dev, s);
 }
 
 // ---------------------------------------------------------------------------------------

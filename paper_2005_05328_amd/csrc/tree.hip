@@ -29,25 +29,60 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n
 // ---------------------------------------------------------------------------------------
 // build
 // ---------------------------------------------------------------------------------------
+// Build state in device memory (ctx->bstate): the counts of the level-synchronous build stay
+// on the device, so the build needs no host synchronisation (and can be graph-captured).
+#define BS_NF 0         // frontier nodes at the current level
+#define BS_NODES 1      // nodes so far
+#define BS_GROUPS 2     // target groups
+#define BS_OVERFLOW 3   // sticky: the tree needed more than the node capacity
+#define BS_CHILDREN 4   // scan totals of the current level
+#define BS_INTERNAL 5
+#define BS_LEVEL 8      // [BS_LEVEL + k]: first node of level k (k <= DZS_KEY_BITS + 1)
+
 __global__ void k_tree_root(uint32_t n, uint32_t *nd_first, uint32_t *nd_count,
                             uint32_t *nd_child, uint8_t *nd_nchild, uint8_t *nd_level,
-                            uint32_t *frontier) {
+                            uint32_t *nd_parent, uint32_t *nd_arrive, uint32_t *frontier,
+                            uint32_t *bs, uint32_t leaf, int KB) {
     nd_first[0] = 0;
     nd_count[0] = n;
     nd_child[0] = 0;
     nd_nchild[0] = 0;
     nd_level[0] = 0;
+    nd_parent[0] = 0xffffffffu;
+    nd_arrive[0] = 0;
     frontier[0] = 0;
+    bs[BS_NF] = (n > leaf || KB > 0) ? 1u : 0u;
+    bs[BS_NODES] = 1;
+    bs[BS_GROUPS] = 0;
+    bs[BS_LEVEL + 0] = 0;
+    for (int k = 1; k <= DZS_KEY_BITS + 1; ++k)
+        bs[BS_LEVEL + k] = 1;
+}
+
+// After the emit of level k: advance the node count and the frontier; a level that would
+// exceed the node capacity stops the build (its nodes were not written) and flags it.
+__global__ void k_tree_level(uint32_t *bs, int k, uint64_t cap) {
+    const uint64_t nodes = (uint64_t)bs[BS_NODES] + bs[BS_CHILDREN];
+    if (nodes > cap) {
+        bs[BS_OVERFLOW] = 1u;
+        bs[BS_NF] = 0;
+    } else {
+        bs[BS_NODES] = (uint32_t)nodes;
+        bs[BS_NF] = bs[BS_INTERNAL];
+    }
+    for (int j = k + 2; j <= DZS_KEY_BITS + 1; ++j)
+        bs[BS_LEVEL + j] = bs[BS_NODES];
 }
 
 // For each frontier node at level k: the 9 bounds of its 8 octant sub-ranges.
 __global__ __launch_bounds__(TB_THREADS) void k_tree_split(
-    const uint32_t *__restrict__ frontier, uint32_t nf, int k, const uint64_t *__restrict__ key,
+    const uint32_t *__restrict__ frontier, const uint32_t *__restrict__ bs, int k,
+    const uint64_t *__restrict__ key,
     const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     uint32_t *__restrict__ bounds, uint32_t *__restrict__ nchild, uint32_t *__restrict__ ninternal,
     uint32_t leaf, int KB) {
     uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
-    if (f >= nf)
+    if (f >= bs[BS_NF])
         return;
     const uint32_t node = frontier[f];
     const uint32_t s = nd_first[node], e = s + nd_count[node];
@@ -82,16 +117,21 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_split(
 }
 
 __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
-    const uint32_t *__restrict__ frontier, uint32_t nf, int k, const uint32_t *__restrict__ bounds,
-    const uint32_t *__restrict__ child_off, const uint32_t *__restrict__ int_off, uint32_t base,
-    uint32_t *__restrict__ nd_first, uint32_t *__restrict__ nd_count, uint32_t *__restrict__ nd_child,
+    const uint32_t *__restrict__ frontier, const uint32_t *__restrict__ bs, int k,
+    const uint32_t *__restrict__ bounds, const uint32_t *__restrict__ child_off,
+    const uint32_t *__restrict__ int_off, uint64_t cap, uint32_t *__restrict__ nd_first,
+    uint32_t *__restrict__ nd_count, uint32_t *__restrict__ nd_child,
     uint8_t *__restrict__ nd_nchild, uint8_t *__restrict__ nd_level,
+    uint32_t *__restrict__ nd_parent, uint32_t *__restrict__ nd_arrive,
     uint32_t *__restrict__ frontier_next, uint32_t leaf, int KB) {
     uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
-    if (f >= nf)
+    if (f >= bs[BS_NF])
+        return;
+    // the whole level is dropped when it does not fit (k_tree_level flags it)
+    if ((uint64_t)bs[BS_NODES] + bs[BS_CHILDREN] > cap)
         return;
     const uint32_t node = frontier[f];
-    uint32_t c = base + child_off[f];
+    uint32_t c = bs[BS_NODES] + child_off[f];
     uint32_t q = int_off[f];
     nd_child[node] = c;
     uint32_t nc = 0;
@@ -104,6 +144,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
         nd_child[c] = 0;
         nd_nchild[c] = 0;
         nd_level[c] = (uint8_t)(k + 1);
+        nd_parent[c] = node;
+        nd_arrive[c] = 0;
         if ((e - s > leaf || k + 1 < KB) && k + 1 < DZS_KEY_BITS)
             frontier_next[q++] = c;
         ++c;
@@ -112,18 +154,15 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
     nd_nchild[node] = (uint8_t)nc;
 }
 
-// Bottom-up moments of the nodes [lo, hi) (one level).
-__global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
-    uint32_t lo, uint32_t hi, uint64_t cap, const double *__restrict__ x,
-    const double *__restrict__ y, const double *__restrict__ z, const uint32_t *__restrict__ mult,
-    double m0, double h0, const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
+// Moments of node v (mass, centre of mass, particle bounding box, largest softening): of its
+// particles for a leaf, of its children (already complete) otherwise.
+__device__ __forceinline__ void node_moments(
+    uint32_t v, uint64_t cap, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const uint32_t *__restrict__ mult, double m0, double h0,
+    const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild,
-    double *__restrict__ nd_mass, double *__restrict__ nd_com, double *__restrict__ nd_bmin,
-    double *__restrict__ nd_bmax, double *__restrict__ nd_hmax, const uint64_t *__restrict__ key,
-    const dzs_bbox *__restrict__ boxes) {
-    uint32_t v = lo + blockIdx.x * TB_THREADS + threadIdx.x;
-    if (v >= hi)
-        return;
+    double *nd_mass, double *nd_com, double *nd_bmin, double *nd_bmax, double *nd_hmax,
+    const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes) {
     if (boxes && nd_nchild[v] == 0) {
         // a batch: the leaf's box (its key prefix) sets the mass unit and the softening
         const uint64_t b = key[nd_first[v]] >> DZS_BATCH_SHIFT;
@@ -171,16 +210,47 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
     nd_hmax[v] = hmax;
 }
 
+// All moments in one launch, bottom-up: a thread starts at each leaf; after writing a node
+// it counts itself in at the parent, and the last child to arrive goes on to compute the
+// parent (from its children in their stored order, so the result does not depend on the
+// order of arrival).  The fences order a node's stores before its arrival and the parent's
+// loads after it.
+__global__ __launch_bounds__(TB_THREADS) void k_tree_refit(
+    const uint32_t *__restrict__ bs, uint64_t cap, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const uint32_t *__restrict__ mult,
+    double m0, double h0, const uint32_t *__restrict__ nd_first,
+    const uint32_t *__restrict__ nd_count, const uint32_t *__restrict__ nd_child,
+    const uint8_t *__restrict__ nd_nchild, const uint32_t *__restrict__ nd_parent,
+    uint32_t *nd_arrive, double *nd_mass, double *nd_com, double *nd_bmin, double *nd_bmax,
+    double *nd_hmax, const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes) {
+    uint32_t v = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (v >= bs[BS_NODES] || nd_nchild[v] != 0)
+        return;
+    for (;;) {
+        node_moments(v, cap, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild,
+                     nd_mass, nd_com, nd_bmin, nd_bmax, nd_hmax, key, boxes);
+        __threadfence();
+        const uint32_t p = nd_parent[v];
+        if (p == 0xffffffffu)
+            return;
+        if (atomicAdd(&nd_arrive[p], 1u) + 1u != (uint32_t)nd_nchild[p])
+            return;
+        __threadfence();
+        v = p;
+    }
+}
+
 // Target groups: each node with more than G particles packs its consecutive children that
 // hold at most G particles into bins of at most G (greedy, Morton order); a bin starts a
 // group.  Leaves with more than G particles (coincident particles at the finest level) are
 // cut into chunks of G.
 __global__ __launch_bounds__(TB_THREADS) void k_tree_groups(
-    uint32_t n_nodes, const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
+    const uint32_t *__restrict__ bs, const uint32_t *__restrict__ nd_first,
+    const uint32_t *__restrict__ nd_count,
     const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild, uint32_t G,
     uint32_t *__restrict__ flag, const uint8_t *__restrict__ nd_level, int KB) {
     uint32_t v = blockIdx.x * TB_THREADS + threadIdx.x;
-    if (v >= n_nodes)
+    if (v >= bs[BS_NODES])
         return;
     const uint32_t cnt = nd_count[v];
     if (KB > 0) {
@@ -241,97 +311,115 @@ dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const 
     return dzs_tree_build_ex(ctx, box, n64, x, y, z, mult, leaf_size, group_size, 0, nullptr, s);
 }
 
+__global__ __launch_bounds__(TB_THREADS) void k_fill_u32(uint64_t n, uint32_t *a, uint32_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * TB_THREADS + threadIdx.x;
+    if (i < n)
+        a[i] = v;
+}
+
 // KB > 0: a batch whose keys carry the box in their top KB digits; the nodes above level KB
 // always split, the box table supplies each leaf's mass unit and softening.
+//
+// Every level runs whether or not the tree is that deep (an empty frontier makes its kernels
+// return at once): the counts stay on the device and nothing here waits for the host.  The
+// launches of level k are sized for the largest frontier it can have: 8^k nodes, and below
+// the forced levels the internal nodes of more than `leaf` particles, at most n / (leaf + 1).
 dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const double *x,
                              const double *y, const double *z, const uint32_t *mult,
                              int leaf_size, int group_size, int KB, const dzs_bbox *boxes,
                              hipStream_t s) {
     const uint32_t n = (uint32_t)n64;
-    ctx->n_nodes = 0;
-    ctx->n_groups = 0;
+    ctx->tree_built = false;
     if (n == 0)
         return DZS_OK;
     const uint32_t leaf = (uint32_t)leaf_size;
     const uint64_t cap = ctx->cap_nodes;
+    uint32_t *bs = ctx->bstate;
     {
         dzs_timed t(ctx, KC_TREE_BUILD, s);
         hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, n, ctx->nd_first, ctx->nd_count,
-                           ctx->nd_child, ctx->nd_nchild, ctx->nd_level, ctx->frontier);
+                           ctx->nd_child, ctx->nd_nchild, ctx->nd_level, ctx->nd_parent,
+                           ctx->nd_arrive, ctx->frontier, bs, leaf, KB);
         DZS_TRY(dzs_check_launch(ctx, "tree_root"));
-    }
-    uint32_t n_nodes = 1;
-    ctx->level_start[0] = 0;
-    ctx->level_start[1] = 1;
-    int n_levels = 1;
-    uint32_t nf = (n > leaf || KB > 0) ? 1u : 0u;
-    uint32_t *fr = ctx->frontier, *fr_next = ctx->frontier_next;
-    for (int k = 0; nf > 0 && k < DZS_KEY_BITS; ++k) {
-        {
-            dzs_timed t(ctx, KC_TREE_BUILD, s);
-            hipLaunchKernelGGL(k_tree_split, dim3(blocks_for(nf, TB_THREADS)), dim3(TB_THREADS), 0,
-                               s, fr, nf, k, ctx->key, ctx->nd_first, ctx->nd_count,
-                               ctx->child_bounds, ctx->fr_nchild, ctx->fr_ninternal, leaf, KB);
+        uint32_t *fr = ctx->frontier, *fr_next = ctx->frontier_next;
+        for (int k = 0; k < DZS_KEY_BITS; ++k) {
+            uint64_t ub = k <= KB ? n : n / (leaf + 1) + 1;
+            if (k < 8 && (1ull << (3 * k)) < ub)
+                ub = 1ull << (3 * k);
+            hipLaunchKernelGGL(k_tree_split, dim3(blocks_for(ub, TB_THREADS)), dim3(TB_THREADS), 0,
+                               s, fr, (const uint32_t *)bs, k, ctx->key, ctx->nd_first,
+                               ctx->nd_count, ctx->child_bounds, ctx->fr_nchild,
+                               ctx->fr_ninternal, leaf, KB);
             DZS_TRY(dzs_check_launch(ctx, "tree_split"));
-            DZS_TRY(dzs_scan_u32(ctx, ctx->fr_nchild, ctx->fr_child_off, nf, ctx->d_small, s));
-            DZS_TRY(dzs_scan_u32(ctx, ctx->fr_ninternal, ctx->fr_int_off, nf, ctx->d_small + 1, s));
-            DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small, ctx->d_small, 2 * sizeof(uint32_t),
-                                        hipMemcpyDeviceToHost, s));
-        }
-        DZS_HIP(ctx, hipStreamSynchronize(s));
-        const uint32_t n_children = ctx->h_small[0], n_internal = ctx->h_small[1];
-        if ((uint64_t)n_nodes + n_children > cap)
-            return dzs_fail(ctx, DZS_ECAPACITY, "tree needs more than %llu nodes",
-                            (unsigned long long)cap);
-        {
-            dzs_timed t(ctx, KC_TREE_BUILD, s);
-            hipLaunchKernelGGL(k_tree_emit, dim3(blocks_for(nf, TB_THREADS)), dim3(TB_THREADS), 0,
-                               s, fr, nf, k, ctx->child_bounds, ctx->fr_child_off,
-                               ctx->fr_int_off, n_nodes, ctx->nd_first, ctx->nd_count,
-                               ctx->nd_child, ctx->nd_nchild, ctx->nd_level, fr_next, leaf, KB);
+            DZS_TRY(dzs_scan_u32_dev(ctx, ctx->fr_nchild, ctx->fr_child_off, ub, bs + BS_NF,
+                                     bs + BS_CHILDREN, s));
+            DZS_TRY(dzs_scan_u32_dev(ctx, ctx->fr_ninternal, ctx->fr_int_off, ub, bs + BS_NF,
+                                     bs + BS_INTERNAL, s));
+            hipLaunchKernelGGL(k_tree_emit, dim3(blocks_for(ub, TB_THREADS)), dim3(TB_THREADS), 0,
+                               s, fr, (const uint32_t *)bs, k, ctx->child_bounds,
+                               ctx->fr_child_off, ctx->fr_int_off, cap, ctx->nd_first,
+                               ctx->nd_count, ctx->nd_child, ctx->nd_nchild, ctx->nd_level,
+                               ctx->nd_parent, ctx->nd_arrive, fr_next, leaf, KB);
             DZS_TRY(dzs_check_launch(ctx, "tree_emit"));
+            hipLaunchKernelGGL(k_tree_level, dim3(1), dim3(1), 0, s, bs, k, cap);
+            DZS_TRY(dzs_check_launch(ctx, "tree_level"));
+            uint32_t *tmp = fr;
+            fr = fr_next;
+            fr_next = tmp;
         }
-        n_nodes += n_children;
-        ctx->level_start[k + 2] = n_nodes;
-        n_levels = k + 2;
-        uint32_t *tmp = fr;
-        fr = fr_next;
-        fr_next = tmp;
-        nf = n_internal;
     }
-    ctx->n_nodes = n_nodes;
-    ctx->n_levels = n_levels;
     {
         dzs_timed t(ctx, KC_TREE_MOMENTS, s);
-        for (int k = n_levels - 1; k >= 0; --k) {
-            const uint32_t lo = ctx->level_start[k], hi = ctx->level_start[k + 1];
-            if (hi <= lo)
-                continue;
-            hipLaunchKernelGGL(k_tree_moments, dim3(blocks_for(hi - lo, TB_THREADS)),
-                               dim3(TB_THREADS), 0, s, lo, hi, cap, x, y, z, mult, box->m0,
-                               2.8 * box->eps0, ctx->nd_first, ctx->nd_count, ctx->nd_child,
-                               ctx->nd_nchild, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
-                               ctx->nd_bmax, ctx->nd_hmax, (const uint64_t *)ctx->key, boxes);
-            DZS_TRY(dzs_check_launch(ctx, "tree_moments"));
-        }
+        hipLaunchKernelGGL(k_tree_refit, dim3(blocks_for(cap, TB_THREADS)), dim3(TB_THREADS), 0,
+                           s, (const uint32_t *)bs, cap, x, y, z, mult, box->m0, 2.8 * box->eps0,
+                           ctx->nd_first, ctx->nd_count, ctx->nd_child, ctx->nd_nchild,
+                           ctx->nd_parent, ctx->nd_arrive, ctx->nd_mass, ctx->nd_com,
+                           ctx->nd_bmin, ctx->nd_bmax, ctx->nd_hmax, (const uint64_t *)ctx->key,
+                           boxes);
+        DZS_TRY(dzs_check_launch(ctx, "tree_refit"));
     }
     {
         dzs_timed t(ctx, KC_TREE_GROUPS, s);
-        DZS_HIP(ctx, hipMemsetAsync(ctx->grp_flag, 0, sizeof(uint32_t) * n, s));
-        hipLaunchKernelGGL(k_tree_groups, dim3(blocks_for(n_nodes, TB_THREADS)), dim3(TB_THREADS),
-                           0, s, n_nodes, ctx->nd_first, ctx->nd_count, ctx->nd_child,
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s,
+                           (uint64_t)n, ctx->grp_flag, 0u);
+        DZS_TRY(dzs_check_launch(ctx, "group_clear"));
+        hipLaunchKernelGGL(k_tree_groups, dim3(blocks_for(cap, TB_THREADS)), dim3(TB_THREADS), 0,
+                           s, (const uint32_t *)bs, ctx->nd_first, ctx->nd_count, ctx->nd_child,
                            ctx->nd_nchild, (uint32_t)group_size, ctx->grp_flag, ctx->nd_level,
                            KB);
         DZS_TRY(dzs_check_launch(ctx, "tree_groups"));
-        DZS_TRY(dzs_scan_u32(ctx, ctx->grp_flag, ctx->grp_scan, n, ctx->d_small + 2, s));
+        DZS_TRY(dzs_scan_u32(ctx, ctx->grp_flag, ctx->grp_scan, n, bs + BS_GROUPS, s));
         hipLaunchKernelGGL(k_group_compact, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s,
                            n, ctx->grp_flag, ctx->grp_scan, ctx->grp_first);
         DZS_TRY(dzs_check_launch(ctx, "group_compact"));
-        DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 2, ctx->d_small + 2, sizeof(uint32_t),
-                                    hipMemcpyDeviceToHost, s));
     }
+    ctx->tree_built = true;
+    ctx->tree_n = n;
+    return DZS_OK;
+}
+
+// The sticky overflow flags of the tree build (node capacity) and of the walk (stack depth),
+// read back and cleared (synchronises the stream).
+dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s) {
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 8, ctx->bstate + BS_OVERFLOW, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 9, ctx->walk_counter + 2, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
     DZS_HIP(ctx, hipStreamSynchronize(s));
-    ctx->n_groups = ctx->h_small[2];
+    const uint32_t tree_over = ctx->h_small[8], walk_over = ctx->h_small[9];
+    if (tree_over || walk_over) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, (uint64_t)1,
+                           ctx->bstate + BS_OVERFLOW, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, (uint64_t)1,
+                           ctx->walk_counter + 2, 0u);
+        DZS_HIP(ctx, hipStreamSynchronize(s));
+    }
+    if (tree_over)
+        return dzs_fail(ctx, DZS_ECAPACITY, "tree needs more than %llu nodes",
+                        (unsigned long long)ctx->cap_nodes);
+    if (walk_over)
+        return dzs_fail(ctx, DZS_ECAPACITY, "tree walk stack overflow (depth %llu)",
+                        (unsigned long long)ctx->walk_stack_depth);
     return DZS_OK;
 }
 
@@ -355,7 +443,7 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
 
 struct walk_args {
     const uint32_t *grp_first;
-    uint32_t n_groups;
+    const uint32_t *n_groups;   // device: the build's group count
     const double *x, *y, *z;
     const uint32_t *mult;
     const uint32_t *nd_first, *nd_count, *nd_child;
@@ -391,26 +479,22 @@ struct walk_geom {
 // ---------------------------------------------------------------------------------------
 // batch: the node of each box (the level-KB node with the box's key prefix)
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(TB_THREADS) void k_batch_roots(uint32_t lo, uint32_t hi,
+__global__ __launch_bounds__(TB_THREADS) void k_batch_roots(const uint32_t *__restrict__ bs,
+                                                            int KB,
                                                             const uint64_t *__restrict__ key,
                                                             const uint32_t *__restrict__ nd_first,
                                                             dzs_bbox *__restrict__ boxes) {
-    const uint32_t v = lo + blockIdx.x * TB_THREADS + threadIdx.x;
-    if (v < hi)
+    const uint32_t v = bs[BS_LEVEL + KB] + blockIdx.x * TB_THREADS + threadIdx.x;
+    if (v < bs[BS_LEVEL + KB + 1])
         boxes[key[nd_first[v]] >> DZS_BATCH_SHIFT].root = v;
 }
 
 dzs_status dzs_batch_roots(dzs_ctx *ctx, dzs_bbox *boxes, hipStream_t s) {
     const int KB = DZS_BATCH_LEVELS;
-    if (ctx->n_levels <= KB)
-        return dzs_fail(ctx, DZS_EINVAL, "batch: the tree has no box level");
-    const uint32_t lo = ctx->level_start[KB], hi = ctx->level_start[KB + 1];
-    if (hi > lo) {
-        hipLaunchKernelGGL(k_batch_roots, dim3(blocks_for(hi - lo, TB_THREADS)), dim3(TB_THREADS),
-                           0, s, lo, hi, (const uint64_t *)ctx->key, ctx->nd_first, boxes);
-        DZS_TRY(dzs_check_launch(ctx, "batch_roots"));
-    }
-    return DZS_OK;
+    hipLaunchKernelGGL(k_batch_roots, dim3(blocks_for(1u << (3 * KB), TB_THREADS)),
+                       dim3(TB_THREADS), 0, s, (const uint32_t *)ctx->bstate, KB,
+                       (const uint64_t *)ctx->key, ctx->nd_first, boxes);
+    return dzs_check_launch(ctx, "batch_roots");
 }
 
 // ---------------------------------------------------------------------------------------
@@ -428,11 +512,12 @@ __global__ __launch_bounds__(TB_THREADS) void k_cell_clear(uint64_t n, uint32_t 
 // in Morton order these form the contiguous range [P 8^(K-l), (P+1) 8^(K-l)), P = the node's
 // key prefix.  The claimed ranges are disjoint; cells no node claims hold no particle.
 __global__ __launch_bounds__(TB_THREADS) void k_cell_fill(
-    uint32_t n_nodes, int K, const uint64_t *__restrict__ key, const uint32_t *__restrict__ nd_first,
-    const uint8_t *__restrict__ nd_nchild, const uint8_t *__restrict__ nd_level,
-    uint32_t *__restrict__ cell_node, uint8_t *__restrict__ cell_dl) {
+    const uint32_t *__restrict__ bs, int K, const uint64_t *__restrict__ key,
+    const uint32_t *__restrict__ nd_first, const uint8_t *__restrict__ nd_nchild,
+    const uint8_t *__restrict__ nd_level, uint32_t *__restrict__ cell_node,
+    uint8_t *__restrict__ cell_dl) {
     const uint32_t node = blockIdx.x * TB_THREADS + threadIdx.x;
-    if (node >= n_nodes)
+    if (node >= bs[BS_LEVEL + K + 1])  // the nodes of levels 0..K
         return;
     const int l = nd_level[node];
     if (l > K || (l < K && nd_nchild[node] != 0))
@@ -581,7 +666,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         __syncthreads();
         const uint32_t g = s_g;
         __syncthreads();
-        if (g >= A.n_groups)
+        if (g >= *A.n_groups)
             break;
         const uint32_t first = A.grp_first[g];
         const uint32_t cnt = A.grp_first[g + 1] - first;
@@ -846,7 +931,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         }
         if (overflow) {
             if (lane == 0)
-                atomicOr(&A.counter[1], 1u);
+                atomicOr(&A.counter[2], 1u);   // sticky until checked
         }
         flush();
         // fixed-order sum of the P partial accelerations of each target
@@ -992,12 +1077,12 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
                             const double *y, const double *z, const uint32_t *mult, double *gx,
                             double *gy, double *gz, const dzs_tree_params *prm,
                             const dzs_bbox *boxes, hipStream_t s) {
-    if (n == 0 || ctx->n_groups == 0)
+    if (n == 0 || !ctx->tree_built)
         return DZS_OK;
     walk_args A;
     memset(&A, 0, sizeof(A));
     A.grp_first = ctx->grp_first;
-    A.n_groups = ctx->n_groups;
+    A.n_groups = ctx->bstate + BS_GROUPS;
     A.x = x; A.y = y; A.z = z; A.mult = mult;
     A.nd_first = ctx->nd_first; A.nd_count = ctx->nd_count; A.nd_child = ctx->nd_child;
     A.nd_nchild = ctx->nd_nchild; A.nd_level = ctx->nd_level;
@@ -1053,16 +1138,22 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
         hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(n_cells, TB_THREADS)), dim3(TB_THREADS),
                            0, s, n_cells, ctx->cell_node);
         DZS_TRY(dzs_check_launch(ctx, "cell_clear"));
-        const int top = K + 1 < ctx->n_levels ? K + 1 : ctx->n_levels;
-        const uint32_t n_top = ctx->level_start[top];
+        // at most (8^(K+1) - 1) / 7 nodes sit on levels 0..K
+        uint64_t n_top = ((1ull << (3 * (K + 1))) - 1) / 7;
+        n_top = n_top < ctx->cap_nodes ? n_top : ctx->cap_nodes;
         hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(n_top, TB_THREADS)), dim3(TB_THREADS), 0,
-                           s, n_top, K, (const uint64_t *)ctx->key, ctx->nd_first, ctx->nd_nchild,
-                           ctx->nd_level, ctx->cell_node, ctx->cell_dl);
+                           s, (const uint32_t *)ctx->bstate, K, (const uint64_t *)ctx->key,
+                           ctx->nd_first, ctx->nd_nchild, ctx->nd_level, ctx->cell_node,
+                           ctx->cell_dl);
         DZS_TRY(dzs_check_launch(ctx, "cell_fill"));
     }
-    uint32_t slots = ctx->n_groups < ctx->walk_stack_slots ? ctx->n_groups
-                                                           : (uint32_t)ctx->walk_stack_slots;
-    DZS_HIP(ctx, hipMemsetAsync(ctx->walk_counter, 0, 2 * sizeof(uint32_t), s));
+    // persistent waves: each takes groups until the counter passes the device group count
+    uint32_t slots = (uint32_t)ctx->walk_stack_slots;
+    if (n < slots)
+        slots = (uint32_t)n;   // there are at most n groups
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(TB_THREADS), 0, s, (uint64_t)1, ctx->walk_counter,
+                       0u);
+    DZS_TRY(dzs_check_launch(ctx, "walk_counter_clear"));
     {
         dzs_timed t(ctx, KC_TREE_WALK, s);
         // the start-cell variant carries more scalar state; in FP64 its register pressure
@@ -1079,10 +1170,5 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
             hipLaunchKernelGGL((k_tree_walk<double, false, false>), dim3(slots), dim3(64), 0, s, A);
         DZS_TRY(dzs_check_launch(ctx, "tree_walk"));
     }
-    DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 4, ctx->walk_counter + 1, sizeof(uint32_t),
-                                hipMemcpyDeviceToHost, s));
-    DZS_HIP(ctx, hipStreamSynchronize(s));
-    if (ctx->h_small[4])
-        return dzs_fail(ctx, DZS_ECAPACITY, "tree walk stack overflow (depth %u)", A.depth);
-    return DZS_OK;
+    return ctx->defer_checks ? DZS_OK : dzs_tree_check(ctx, s);
 }
