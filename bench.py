@@ -163,6 +163,26 @@ def run_ensemble(args, dz, torch, dzs_ics):
     t_batch = batch_run(K, group, leaf)
     kern = ctx.timing(enable=False, reset=True)
     pairs = ctx.pair_interactions(reset=True)
+    final_eager = {k: getattr(st, k)[: st.n].clone() for k in ("x", "px", "gx")}
+
+    # the same K steps as replays of one captured step (factors staged before each replay)
+    log("graph capture and replays")
+    copy_state(st, st0)
+    ring.reset()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ctx.kdk_step_batch(boxes, first, ngs, rss, rcs, st, params(0, group, leaf), ring)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(K):
+        ctx.kdk_step_batch_stage(params(s_, group, leaf))
+        graph.replay()
+        torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    ctx.check()
+    graph_same = all(torch.equal(final_eager[k], getattr(st, k)[: st.n]) for k in final_eager)
+    del graph
     ctx.close()
 
     # the same steps box by box with the single-box call
@@ -206,8 +226,10 @@ def run_ensemble(args, dz, torch, dzs_ics):
                      "avg_ms": avg_ms,
                      "work_per_launch": f"{pairs / calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP"},
         "cpu_baseline": None,
-        "ensemble": {"batched_s": t_batch, "box_by_box_s": t_loop,
-                     "batched_speedup": t_loop / t_batch, "autotuned": {"group": group, "leaf": leaf},
+        "ensemble": {"batched_s": t_batch, "graph_replays_s": t_graph,
+                     "graph_matches_eager_bitwise": bool(graph_same), "box_by_box_s": t_loop,
+                     "batched_speedup": t_loop / t_batch, "graph_speedup": t_loop / t_graph,
+                     "autotuned": {"group": group, "leaf": leaf},
                      "autotune_s_per_step": {k: v[0] for k, v in tune.items()}},
         "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
                                                                     key=lambda kv: -kv[1])},

@@ -261,9 +261,10 @@ typedef struct {
  * box's particles are left Morton-sorted within its range.
  * Synchronises the stream only when the batch differs from the previous call (its tables are
  * then rebuilt and uploaded); otherwise the call only enqueues work, so it can be captured
- * into a HIP graph once and replayed for every step: K1, K2 and the lightcone drift are read
- * when the step runs from a device block filled from the context's pinned host staging, which
- * this call and kdk_step_batch_stage write.  The tree's node capacity and the walk's stack
+ * into a HIP graph once and replayed for every step: a captured call reads K1, K2 and the
+ * lightcone drift, when the graph runs, from a device block filled from the context's pinned
+ * host staging, which the capturing call and kdk_step_batch_stage write (eager calls pass
+ * them as kernel arguments).  The tree's node capacity and the walk's stack
  * depth are checked on the device; dzs_check reports an overflow. */
 dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_particles *state,
                           const dzs_step_params *prm, dzs_lc_ring *ring, void *stream);

@@ -135,7 +135,7 @@ static void release(dzs_ctx *ctx) {
                     ctx->scan_tmp, ctx->gather_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult,
                     ctx->sgx, ctx->sgy, ctx->sgz, ctx->nd_first, ctx->nd_count, ctx->nd_child,
                     ctx->nd_nchild, ctx->nd_level, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
-                    ctx->nd_bmax, ctx->nd_hmax, ctx->nd_parent, ctx->nd_arrive, ctx->bstate,
+                    ctx->nd_bmax, ctx->nd_hmax, ctx->bstate,
                     ctx->frontier, ctx->frontier_next,
                     ctx->fr_nchild, ctx->fr_ninternal, ctx->fr_child_off, ctx->fr_int_off,
                     ctx->child_bounds, ctx->grp_flag, ctx->grp_scan, ctx->grp_first,
@@ -202,8 +202,6 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->nd_bmin, 3 * nn));
     DZS_TRY(alloc(c, &c->nd_bmax, 3 * nn));
     DZS_TRY(alloc(c, &c->nd_hmax, nn));
-    DZS_TRY(alloc(c, &c->nd_parent, nn));
-    DZS_TRY(alloc(c, &c->nd_arrive, nn));
     DZS_TRY(alloc(c, &c->bstate, 64));
     DZS_HIP(c, hipMemset(c->bstate, 0, 64 * sizeof(uint32_t)));
     DZS_TRY(alloc(c, &c->frontier, n));
@@ -621,12 +619,23 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
         ctx->batch_nb = nb;
         ctx->batch_ready = true;
     }
-    // this step's factors: staged on the host, copied to the device block by the stream
-    ctx->step_h->K1 = prm->K1;
-    ctx->step_h->K2 = prm->K2;
-    dzs_make_lc_args(&prm->lc, &ctx->step_h->lc);
-    DZS_HIP(ctx, hipMemcpyAsync(ctx->step_dev, ctx->step_h, sizeof(dzs_step_block),
-                                hipMemcpyHostToDevice, s));
+    // Eager calls pass this step's factors as kernel arguments.  Under graph capture they are
+    // read from a device block that a captured copy fills, when the graph runs, from the
+    // pinned staging (written here and by kdk_step_batch_stage between replays); eager calls
+    // do not use the staging, whose copy could still be pending when the next call writes it.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DZS_HIP(ctx, hipStreamIsCapturing(s, &cs));
+    const bool captured = cs == hipStreamCaptureStatusActive;
+    if (captured) {
+        ctx->step_h->K1 = prm->K1;
+        ctx->step_h->K2 = prm->K2;
+        dzs_make_lc_args(&prm->lc, &ctx->step_h->lc);
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->step_dev, ctx->step_h, sizeof(dzs_step_block),
+                                    hipMemcpyHostToDevice, s));
+    }
+    const double *K1_dev = captured ? &ctx->step_dev->K1 : nullptr;
+    const double *K2_dev = captured ? &ctx->step_dev->K2 : nullptr;
+    const lc_args *lc_dev = captured ? &ctx->step_dev->lc : nullptr;
     if (st->n == 0)
         return DZS_OK;
     struct defer_guard {
@@ -635,9 +644,9 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     } guard{ctx};
     ctx->defer_checks = true;
 
-    DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s, &ctx->step_dev->K1));
+    DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s, K1_dev));
     DZS_TRY(dzs_launch_drift_lc(ctx, &batch->boxes[0], st, &prm->lc, ring, prm->do_lightcone, 1,
-                                s, true, nb, &ctx->step_dev->lc));
+                                s, true, nb, lc_dev));
     // keys with the box on top, one sort for every box: each box stays in its range
     DZS_TRY(dzs_launch_keys(ctx, st->x, st->y, st->z, st->n, 1.0, ctx->key, ctx->idx, s, true,
                             nb));
@@ -652,7 +661,7 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     t.accumulate = 1;
     DZS_TRY(dzs_tree_walk_ex(ctx, &batch->boxes[0], st->n, st->x, st->y, st->z, st->mult, st->gx,
                              st->gy, st->gz, &t, ctx->batch_box, s));
-    return dzs_launch_kick(ctx, st, prm->K2, s, &ctx->step_dev->K2);
+    return dzs_launch_kick(ctx, st, prm->K2, s, K2_dev);
 }
 
 extern "C" dzs_status kdk_step_batch_stage(dzs_ctx *ctx, const dzs_step_params *prm) {

@@ -141,8 +141,6 @@ struct dzs_ctx {
     uint8_t *cell_dl = nullptr;        // and the level offset of each
     double qf_err = 1.0;
     uint32_t *bstate = nullptr;        // tree build state on the device (counts, level starts)
-    uint32_t *nd_parent = nullptr;     // parent of each node (bottom-up moments)
-    uint32_t *nd_arrive = nullptr;     // children counted in at each node (bottom-up moments)
     bool tree_built = false;           // a tree for tree_n particles is in the node arrays
     uint32_t tree_n = 0;
     bool defer_checks = false;         // skip the synchronising overflow checks (batched step)

@@ -41,15 +41,13 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n
 
 __global__ void k_tree_root(uint32_t n, uint32_t *nd_first, uint32_t *nd_count,
                             uint32_t *nd_child, uint8_t *nd_nchild, uint8_t *nd_level,
-                            uint32_t *nd_parent, uint32_t *nd_arrive, uint32_t *frontier,
+                            uint32_t *frontier,
                             uint32_t *bs, uint32_t leaf, int KB) {
     nd_first[0] = 0;
     nd_count[0] = n;
     nd_child[0] = 0;
     nd_nchild[0] = 0;
     nd_level[0] = 0;
-    nd_parent[0] = 0xffffffffu;
-    nd_arrive[0] = 0;
     frontier[0] = 0;
     bs[BS_NF] = (n > leaf || KB > 0) ? 1u : 0u;
     bs[BS_NODES] = 1;
@@ -122,7 +120,6 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
     const uint32_t *__restrict__ int_off, uint64_t cap, uint32_t *__restrict__ nd_first,
     uint32_t *__restrict__ nd_count, uint32_t *__restrict__ nd_child,
     uint8_t *__restrict__ nd_nchild, uint8_t *__restrict__ nd_level,
-    uint32_t *__restrict__ nd_parent, uint32_t *__restrict__ nd_arrive,
     uint32_t *__restrict__ frontier_next, uint32_t leaf, int KB) {
     uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
     if (f >= bs[BS_NF])
@@ -144,8 +141,6 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
         nd_child[c] = 0;
         nd_nchild[c] = 0;
         nd_level[c] = (uint8_t)(k + 1);
-        nd_parent[c] = node;
-        nd_arrive[c] = 0;
         if ((e - s > leaf || k + 1 < KB) && k + 1 < DZS_KEY_BITS)
             frontier_next[q++] = c;
         ++c;
@@ -210,34 +205,21 @@ __device__ __forceinline__ void node_moments(
     nd_hmax[v] = hmax;
 }
 
-// All moments in one launch, bottom-up: a thread starts at each leaf; after writing a node
-// it counts itself in at the parent, and the last child to arrive goes on to compute the
-// parent (from its children in their stored order, so the result does not depend on the
-// order of arrival).  The fences order a node's stores before its arrival and the parent's
-// loads after it.
-__global__ __launch_bounds__(TB_THREADS) void k_tree_refit(
-    const uint32_t *__restrict__ bs, uint64_t cap, const double *__restrict__ x,
+// Moments of the nodes of level k, [level_start[k], level_start[k+1]) read on the device;
+// levels run bottom-up, so the children of every node are complete before it.
+__global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
+    const uint32_t *__restrict__ bs, int k, uint64_t cap, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const uint32_t *__restrict__ mult,
     double m0, double h0, const uint32_t *__restrict__ nd_first,
     const uint32_t *__restrict__ nd_count, const uint32_t *__restrict__ nd_child,
-    const uint8_t *__restrict__ nd_nchild, const uint32_t *__restrict__ nd_parent,
-    uint32_t *nd_arrive, double *nd_mass, double *nd_com, double *nd_bmin, double *nd_bmax,
-    double *nd_hmax, const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes) {
-    uint32_t v = blockIdx.x * TB_THREADS + threadIdx.x;
-    if (v >= bs[BS_NODES] || nd_nchild[v] != 0)
+    const uint8_t *__restrict__ nd_nchild, double *nd_mass, double *nd_com, double *nd_bmin,
+    double *nd_bmax, double *nd_hmax, const uint64_t *__restrict__ key,
+    const dzs_bbox *__restrict__ boxes) {
+    const uint32_t v = bs[BS_LEVEL + k] + blockIdx.x * TB_THREADS + threadIdx.x;
+    if (v >= bs[BS_LEVEL + k + 1])
         return;
-    for (;;) {
-        node_moments(v, cap, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild,
-                     nd_mass, nd_com, nd_bmin, nd_bmax, nd_hmax, key, boxes);
-        __threadfence();
-        const uint32_t p = nd_parent[v];
-        if (p == 0xffffffffu)
-            return;
-        if (atomicAdd(&nd_arrive[p], 1u) + 1u != (uint32_t)nd_nchild[p])
-            return;
-        __threadfence();
-        v = p;
-    }
+    node_moments(v, cap, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild, nd_mass,
+                 nd_com, nd_bmin, nd_bmax, nd_hmax, key, boxes);
 }
 
 // Target groups: each node with more than G particles packs its consecutive children that
@@ -338,8 +320,8 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
     {
         dzs_timed t(ctx, KC_TREE_BUILD, s);
         hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, n, ctx->nd_first, ctx->nd_count,
-                           ctx->nd_child, ctx->nd_nchild, ctx->nd_level, ctx->nd_parent,
-                           ctx->nd_arrive, ctx->frontier, bs, leaf, KB);
+                           ctx->nd_child, ctx->nd_nchild, ctx->nd_level, ctx->frontier, bs, leaf,
+                           KB);
         DZS_TRY(dzs_check_launch(ctx, "tree_root"));
         uint32_t *fr = ctx->frontier, *fr_next = ctx->frontier_next;
         for (int k = 0; k < DZS_KEY_BITS; ++k) {
@@ -359,7 +341,7 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
                                s, fr, (const uint32_t *)bs, k, ctx->child_bounds,
                                ctx->fr_child_off, ctx->fr_int_off, cap, ctx->nd_first,
                                ctx->nd_count, ctx->nd_child, ctx->nd_nchild, ctx->nd_level,
-                               ctx->nd_parent, ctx->nd_arrive, fr_next, leaf, KB);
+                               fr_next, leaf, KB);
             DZS_TRY(dzs_check_launch(ctx, "tree_emit"));
             hipLaunchKernelGGL(k_tree_level, dim3(1), dim3(1), 0, s, bs, k, cap);
             DZS_TRY(dzs_check_launch(ctx, "tree_level"));
@@ -370,13 +352,18 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
     }
     {
         dzs_timed t(ctx, KC_TREE_MOMENTS, s);
-        hipLaunchKernelGGL(k_tree_refit, dim3(blocks_for(cap, TB_THREADS)), dim3(TB_THREADS), 0,
-                           s, (const uint32_t *)bs, cap, x, y, z, mult, box->m0, 2.8 * box->eps0,
-                           ctx->nd_first, ctx->nd_count, ctx->nd_child, ctx->nd_nchild,
-                           ctx->nd_parent, ctx->nd_arrive, ctx->nd_mass, ctx->nd_com,
-                           ctx->nd_bmin, ctx->nd_bmax, ctx->nd_hmax, (const uint64_t *)ctx->key,
-                           boxes);
-        DZS_TRY(dzs_check_launch(ctx, "tree_refit"));
+        for (int k = DZS_KEY_BITS; k >= 0; --k) {
+            // at most 8^k nodes on level k, and never more than the particles
+            uint64_t ub = n;
+            if (k < 8 && (1ull << (3 * k)) < ub)
+                ub = 1ull << (3 * k);
+            hipLaunchKernelGGL(k_tree_moments, dim3(blocks_for(ub, TB_THREADS)), dim3(TB_THREADS),
+                               0, s, (const uint32_t *)bs, k, cap, x, y, z, mult, box->m0,
+                               2.8 * box->eps0, ctx->nd_first, ctx->nd_count, ctx->nd_child,
+                               ctx->nd_nchild, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
+                               ctx->nd_bmax, ctx->nd_hmax, (const uint64_t *)ctx->key, boxes);
+            DZS_TRY(dzs_check_launch(ctx, "tree_moments"));
+        }
     }
     {
         dzs_timed t(ctx, KC_TREE_GROUPS, s);
