@@ -210,7 +210,8 @@ dzs_status pm_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                     const dzs_pm_params *prm, void *stream);
 
 /* Tree short-range acceleration into g (or added to g).  Particle order is left unchanged
- * (the tree is built on a sorted copy).  Synchronises the stream during the tree build. */
+ * (the tree is built on a sorted copy).  Synchronises the stream at the end to check the
+ * tree's node capacity and the walk's stack depth (DZS_ECAPACITY). */
 dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                       const dzs_tree_params *prm, void *stream);
 
@@ -224,7 +225,7 @@ dzs_status lightcone_emit(dzs_ctx *ctx, const dzs_box *box, const dzs_particles 
  *   DZS coarsening at a1 (optional; skipped when R_lc + b >= sqrt(3)/2 L, where no node can
  *   qualify); reorder the state by Morton key; g = PM + tree; p += g K2.
  * The state is left sorted by Morton key.  report (optional) receives the coarsening
- * counts.  Synchronises the stream (tree build; coarsening). */
+ * counts.  Synchronises the stream (coarsening counts; the capacity check after the walk). */
 dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *state,
                     const dzs_step_params *prm, dzs_lc_ring *ring, dzs_coarsen_report *report,
                     void *stream);
