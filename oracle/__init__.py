@@ -66,8 +66,11 @@ def lib():
                                                ctypes.c_void_p, ctypes.c_void_p)
         L.orc_morton_keys.argtypes = [i64, dp, dp, dp, d, u64p]
         L.orc_coarsen.argtypes = [i64, dp, dp, dp, dp, dp, dp, u32p, u32p, u8p, d, dp, d, d, d,
-                                  ctypes.c_int, dp, dp, dp, dp, dp, dp, u32p, u32p, u8p, i64p, i64p]
+                                  ctypes.c_int, ctypes.c_int, d, d, dp, dp, dp, dp,
+                                  dp, dp, dp, dp, dp, dp, u32p, u32p, u8p, i64p, i64p]
         L.orc_coarsen.restype = i64
+        L.orc_a_min.argtypes = [i64, dp, dp, dp, dp, dp, dp, d, dp, d]
+        L.orc_a_min.restype = d
         L.orc_merge_thresholds.argtypes = [d, d, d, d, dp]
         L.orc_short_range.argtypes = [i64, dp, dp, dp, u32p, d, d, d, d, d, d, i64, i64p, dp, dp, dp]
         L.orc_cic_deposit.argtypes = [i64, dp, dp, dp, u32p, d, ctypes.c_int, d, dp]
@@ -129,8 +132,12 @@ def k_min_for(n_side: int, lmax_over_lambda: int) -> int:
     return k
 
 
-def coarsen(ps, x_obs, R_lc, b, theta, k_min):
-    """Top-down merge walk.  Returns (new particle dict, group_of[old] -> new, n_merged_nodes)."""
+def coarsen(ps, x_obs, R_lc, b, theta, k_min, alpha_dyn=None, g=None, Gm0=None):
+    """Top-down merge walk.  Returns (new particle dict, group_of[old] -> new, n_merged_nodes).
+
+    Geometric criterion (eq. 1 with eq. 3) by default; with `alpha_dyn` the dynamical one
+    (eq. 2 with eq. 3 and the in-lightcone minimum of the previous accelerations `g`, shape
+    (3, n), Sec. 2.2.1), which also needs Gm0 = G m0.  `theta` is ignored then."""
     n = ps.n
     outs = {k: np.empty(n, np.float64) for k in ("x", "y", "z", "px", "py", "pz")}
     omult = np.empty(n, np.uint32)
@@ -143,15 +150,36 @@ def coarsen(ps, x_obs, R_lc, b, theta, k_min):
     mult = np.ascontiguousarray(ps.mult, np.uint32)
     ids = np.ascontiguousarray(ps.id, np.uint32)
     typ = np.ascontiguousarray(ps.type, np.uint8)
+    amin = np.zeros(1, np.float64)
+    if alpha_dyn is None:
+        crit, alpha, gm0, gp = 0, 0.0, 0.0, [None, None, None]
+        theta = float(theta)
+    else:
+        if g is None or Gm0 is None:
+            raise ValueError("the dynamical criterion needs g and Gm0")
+        crit, alpha, gm0 = 1, float(alpha_dyn), float(Gm0)
+        gg = [_f64(g[0]), _f64(g[1]), _f64(g[2])]
+        gp = [_p(a) for a in gg]
+        theta = 1.0 if theta is None else float(theta)
     n_out = lib().orc_coarsen(n, *[_p(a) for a in arrs], _p(mult), _p(ids), _p(typ), float(ps.L),
-                              _p(xo), float(R_lc), float(b), float(theta), int(k_min),
+                              _p(xo), float(R_lc), float(b), theta, int(k_min),
+                              crit, alpha, gm0, *gp, _p(amin),
                               *[_p(outs[k]) for k in ("x", "y", "z", "px", "py", "pz")],
                               _p(omult), _p(oid), _p(otype), _p(group_of), _p(nm))
     res = {k: v[:n_out].copy() for k, v in outs.items()}
     res["mult"] = omult[:n_out].copy()
     res["id"] = oid[:n_out].copy()
     res["type"] = otype[:n_out].copy()
+    res["a_min"] = float(amin[0])
     return res, group_of, int(nm[0])
+
+
+def a_min_lightcone(x, y, z, g, L, x_obs, R_lc, b) -> float:
+    """Smallest |g| among particles within R_lc + b of the observer (min image); +inf if none."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    gg = [_f64(g[0]), _f64(g[1]), _f64(g[2])]
+    return lib().orc_a_min(x.shape[0], _p(x), _p(y), _p(z), *[_p(a) for a in gg], float(L),
+                           _p(_f64(x_obs)), float(R_lc) + float(b))
 
 
 # ======================================================================================
@@ -424,7 +452,10 @@ def kdk_step(ps, g, box: Box, fac, ng, r_s, r_cut, x_obs, coarsen_params=None, s
     s.z = drift(s.z, s.pz, fac["D"], s.L)
     cres = None
     if coarsen_params is not None:
-        out, group_of, nm = coarsen(s, x_obs, **coarsen_params)
+        extra = {}
+        if coarsen_params.get("alpha_dyn") is not None:
+            extra = {"g": g, "Gm0": box.G * box.m0}
+        out, group_of, nm = coarsen(s, x_obs, **coarsen_params, **extra)
         cres = (out, group_of, nm)
         for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
             setattr(s, k, out[k])

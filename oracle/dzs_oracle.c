@@ -102,6 +102,15 @@ void orc_morton_keys(int64_t n, const double *x, const double *y, const double *
 /*  - the new particle: mult = sum of mult, x = centre of mass (wrapped into [0,L)),       */
 /*    p = mass-weighted mean momentum (momentum conserved), id = smallest member id,       */
 /*    type = 1.                                                                           */
+/*                                                                                       */
+/* Dynamical criterion (eq. 2 made node-centric with eq. 3, Sec. 2.2.1): the force walk   */
+/* opens a node when G M_n l_n^2 / d^4 >= alpha |a_old|; DZS replaces d by D_n and |a_old| */
+/* by the smallest previous acceleration among the particles inside the lightcone plus    */
+/* buffer.  A node therefore merges when G M_n l_k^2 < alpha a_min D_n^4 with D_n > 0.    */
+/* Readings: "inside" is sqrt(|d_i|^2) < R_lc + b on the minimum-image offset; a_min is   */
+/* sqrt of the smallest g.g among those particles (+inf when none is inside, so every     */
+/* node with D_n > 0 qualifies); D_n = sqrt(|d|^2) - (R_lc + b); the comparison is        */
+/* evaluated as ((G m0) K) l_k^2 < (alpha a_min) ((D D)(D D)), l_k^2 = l_k l_k.            */
 /* ------------------------------------------------------------------------------------ */
 
 typedef struct {
@@ -130,6 +139,9 @@ typedef struct {
     double L, xobs[3];
     double T2[KEY_BITS + 1];
     int k_min;
+    /* dynamical criterion (crit == 1) */
+    int crit;
+    double Gm0, Rb, alpha_amin, lk2[KEY_BITS + 1];
     /* outputs */
     double *ox, *oy, *oz, *opx, *opy, *opz;
     uint32_t *omult, *oid;
@@ -179,8 +191,18 @@ static int try_merge(coarsen_ctx *c, int k, int64_t s, int64_t e)
         d[a] = min_image(X[a] - c->xobs[a], c->L);
     }
     double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (!(d2 > c->T2[k]))
-        return 0;
+    if (c->crit == 0) {
+        if (!(d2 > c->T2[k]))
+            return 0;
+    } else {
+        double D = sqrt(d2) - c->Rb;
+        if (!(D > 0.0))
+            return 0;
+        double lhs = (c->Gm0 * Kd) * c->lk2[k];
+        double rhs = c->alpha_amin * ((D * D) * (D * D));
+        if (!(lhs < rhs))
+            return 0;
+    }
     int64_t o = c->n_out++;
     c->ox[o] = X[0];
     c->oy[o] = X[1];
@@ -248,16 +270,43 @@ void orc_merge_thresholds(double L, double R_lc, double b, double theta, double 
     }
 }
 
+/* The smallest previous acceleration among the particles inside the lightcone plus buffer
+ * (the a_old replacement of Sec. 2.2.1): sqrt of min g.g over particles with
+ * sqrt(|min-image(x_i - x_obs)|^2) < R_lc + b; +inf when there is none. */
+double orc_a_min(int64_t n, const double *x, const double *y, const double *z,
+                 const double *gx, const double *gy, const double *gz, double L,
+                 const double *xobs, double Rb)
+{
+    double best = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = min_image(x[i] - xobs[0], L);
+        double dy = min_image(y[i] - xobs[1], L);
+        double dz = min_image(z[i] - xobs[2], L);
+        if (!(sqrt(dx * dx + dy * dy + dz * dz) < Rb))
+            continue;
+        double g2 = gx[i] * gx[i] + gy[i] * gy[i] + gz[i] * gz[i];
+        if (g2 < best)
+            best = g2;
+    }
+    return sqrt(best);
+}
+
+/* crit 0: geometric (theta).  crit 1: dynamical (alpha, with G m0 and the previous
+ * accelerations gx, gy, gz); *a_min_out (optional) receives the a_min used. */
 int64_t orc_coarsen(int64_t n, const double *x, const double *y, const double *z,
                     const double *px, const double *py, const double *pz,
                     const uint32_t *mult, const uint32_t *id, const uint8_t *type, double L,
                     const double *xobs, double R_lc, double b, double theta, int k_min,
+                    int crit, double alpha, double Gm0, const double *gx, const double *gy,
+                    const double *gz, double *a_min_out,
                     double *ox, double *oy, double *oz, double *opx, double *opy, double *opz,
                     uint32_t *omult, uint32_t *oid, uint8_t *otype, int64_t *group_of,
                     int64_t *n_merged_nodes)
 {
     if (n <= 0) {
         *n_merged_nodes = 0;
+        if (a_min_out)
+            *a_min_out = INFINITY;
         return 0;
     }
     uint64_t *key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
@@ -277,6 +326,21 @@ int64_t orc_coarsen(int64_t n, const double *x, const double *y, const double *z
     c.xobs[0] = xobs[0]; c.xobs[1] = xobs[1]; c.xobs[2] = xobs[2];
     orc_merge_thresholds(L, R_lc, b, theta, c.T2);
     c.k_min = k_min;
+    c.crit = crit;
+    if (crit == 1) {
+        c.Gm0 = Gm0;
+        c.Rb = R_lc + b;
+        for (int k = 0; k <= KEY_BITS; ++k) {
+            double lk = ldexp(L, -k);
+            c.lk2[k] = lk * lk;
+        }
+        double a_min = orc_a_min(n, x, y, z, gx, gy, gz, L, xobs, c.Rb);
+        c.alpha_amin = alpha * a_min;
+        if (a_min_out)
+            *a_min_out = a_min;
+    } else if (a_min_out) {
+        *a_min_out = NAN;
+    }
     c.ox = ox; c.oy = oy; c.oz = oz; c.opx = opx; c.opy = opy; c.opz = opz;
     c.omult = omult; c.oid = oid; c.otype = otype; c.group_of = group_of;
     visit(&c, 0, 0, n);
