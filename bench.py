@@ -236,6 +236,84 @@ def run_ensemble(args, dz, torch, dzs_ics):
     }
 
 
+def run_lean(args, dz, torch, dzs_ics):
+    """The 1024^3 configuration on one GPU: a single state (no twin, no copy of the initial
+    state), a context with meshes for the precision form only, a bounded lightcone ring; the
+    first `warmup` steps, then `steps` timed steps of the 100-step schedule (default 3)."""
+    P = dict(PRESETS["c5"])
+    if args.n_side:
+        f = args.n_side / P["n_side"]
+        P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
+    W = workload(**P)
+    W["prec"] = dz.DZS_FP32
+    K = max(1, min(args.steps or 3, W["n_steps"] - args.warmup))
+    log(f"c5: N={W['N']} L={W['L']} ng={W['ng']} warmup={args.warmup} timed={K}")
+    t0 = time.perf_counter()
+    ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
+    log(f"initial conditions ready ({time.perf_counter() - t0:.0f} s)")
+    box = dz.make_box(W["L"], W["m0"], W["eps0"])
+    ctx = dz.Context(W["N"], W["ng"], fp32_meshes=True)
+    st = dz.State.from_host(ics)
+    del ics
+    free, total = torch.cuda.mem_get_info()
+    log(f"state and context resident: {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f}")
+    params = make_params(dz, W, True)
+    # the initial force: a step with zero kicks and drift (sorts the state and computes g,
+    # without the sorted copies a standalone tree_force would allocate)
+    import copy
+    sp0 = copy.deepcopy(params[0])
+    sp0.K1 = sp0.K2 = 0.0
+    sp0.lc.D = 0.0
+    sp0.do_lightcone = sp0.do_coarsen = 0
+    ctx.kdk_step(box, st, sp0, None)
+    torch.cuda.synchronize()
+    log("initial force done")
+    ring = dz.LCRing(min(W["N"], 1 << 24))
+    ring.reset()
+    for s_ in range(args.warmup):
+        ctx.kdk_step(box, st, params[s_], ring)
+    torch.cuda.synchronize()
+    ctx.timing(enable=True, reset=True)
+    ctx.pair_interactions(reset=True)
+    t0 = time.perf_counter()
+    for s_ in range(args.warmup, args.warmup + K):
+        ctx.kdk_step(box, st, params[s_], ring)
+        torch.cuda.synchronize()
+        log(f"  step {s_ + 1}")
+    t = time.perf_counter() - t0
+    kern = ctx.timing(enable=False, reset=True)
+    pairs = ctx.pair_interactions(reset=True)
+    free, total = torch.cuda.mem_get_info()
+    peak = torch.cuda.max_memory_allocated()
+    ctx.close()
+    totals = {c: ms * calls for c, (ms, calls) in kern.items() if calls}
+    avg_ms, calls = kern["tree_walk"]
+    achieved = FLOP_PER_INTERACTION * pairs / calls / (avg_ms * 1e-3) / 1e12
+    N = W["N"]
+    return {
+        "metric": METRIC, "value": N * K / t, "unit": UNIT, "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{W['n_side']}^3 particles, L={W['L']:g} Mpc/h, mesh "
+                                f"{W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, steps "
+                                f"{args.warmup + 1}-{args.warmup + K} of {W['n_steps']} log KDK "
+                                f"steps, DZS + lightcone, tree theta {W['theta_tree']}, precision "
+                                f"form"),
+                   "preset": "c5", "particles": N, "mesh": W["ng"], "box": W["L"],
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "tree_walk", "avg_ms": avg_ms,
+                     "work_per_launch": f"{pairs / calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP"},
+        "cpu_baseline": None,
+        "memory": {"device_used_GiB_after": (total - free) / 2 ** 30,
+                   "device_total_GiB": total / 2 ** 30,
+                   "torch_peak_GiB": peak / 2 ** 30},
+        "kernels_ms_per_step": {c: round(v / K, 2) for c, v in sorted(totals.items(),
+                                                                    key=lambda kv: -kv[1])},
+    }
+
+
 def _smooth(n):
     while n % 2 == 0:
         n //= 2
@@ -494,6 +572,9 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(run_ensemble(args, dz, torch, dzs_ics)), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(run_lean(args, dz, torch, dzs_ics)), flush=True)
         return
     P = dict(PRESETS[args.workload])
     if args.n_side:

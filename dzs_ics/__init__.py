@@ -208,21 +208,22 @@ def zeldovich(n_side: int, L: float, a_init: float, seed: int, spectrum: str = "
     The white-noise field is drawn in real space on the n_side^3 grid (Philox), so the
     Fourier modes are Hermitian by construction; the Nyquist planes and k = 0 are zeroed.
     Displacement psi_k = i k delta_k / k^2 (so delta = -div psi), scaled by D(a)/D(1);
-    momentum p = a^2 H f psi.  Positions are wrapped into [0, L).
+    momentum p = a^2 H f psi.  Positions are wrapped into [0, L).  One displacement component
+    is held at a time (a 1024^3 lattice needs ~80 GB of host memory); FFTs use every core.
     """
+    import os
+    import scipy.fft as sfft
+    workers = os.cpu_count() or 1
     pk = {"bbks": power_bbks, "powerlaw": power_powerlaw}[spectrum]
     amp = (sigma8 / _sigma_r(pk)) ** 2
     g = rng(seed)
-    white = g.standard_normal((n_side, n_side, n_side))
-    wk = np.fft.rfftn(white)
+    dk = sfft.rfftn(g.standard_normal((n_side, n_side, n_side)), workers=workers)
     kf = 2 * np.pi / L
-    n1 = np.fft.fftfreq(n_side, 1.0 / n_side)
-    n3 = np.fft.rfftfreq(n_side, 1.0 / n_side)
-    KX, KY, KZ = np.meshgrid(n1 * kf, n1 * kf, n3 * kf, indexing="ij")
-    k2 = KX ** 2 + KY ** 2 + KZ ** 2
-    k = np.sqrt(k2)
+    k1 = np.fft.fftfreq(n_side, 1.0 / n_side) * kf
+    k3 = np.fft.rfftfreq(n_side, 1.0 / n_side) * kf
+    k2 = (k1 ** 2)[:, None, None] + (k1 ** 2)[None, :, None] + (k3 ** 2)[None, None, :]
     cell_vol = (L / n_side) ** 3
-    dk = wk * np.sqrt(amp * pk(k) / cell_vol)
+    dk *= np.sqrt(amp * pk(np.sqrt(k2)) / cell_vol)
     nyq = n_side // 2
     if n_side % 2 == 0:
         dk[nyq, :, :] = 0
@@ -230,15 +231,23 @@ def zeldovich(n_side: int, L: float, a_init: float, seed: int, spectrum: str = "
         dk[:, :, nyq] = 0
     dk[0, 0, 0] = 0
     k2[0, 0, 0] = 1.0
+    dk /= k2
+    del k2
     dfac = growth_factor(a_init, om)
-    psi = []
-    for kd in (KX, KY, KZ):
-        psi.append(np.fft.irfftn(1j * kd * dk / k2, s=(n_side,) * 3, axes=(0, 1, 2)).ravel() * dfac)
-    base = lattice(n_side, L)
     vfac = a_init ** 2 * hubble(a_init, om) * growth_rate(a_init, om)
-    x = _wrap(base.x + psi[0], L)
-    y = _wrap(base.y + psi[1], L)
-    z = _wrap(base.z + psi[2], L)
-    ps = _make(x, y, z, vfac * psi[0], vfac * psi[1], vfac * psi[2], L)
-    ps.max_disp = float(max(np.abs(p).max() for p in psi))  # type: ignore[attr-defined]
+    q = (np.arange(n_side, dtype=np.float64) + 0.5) * (L / n_side)
+    shape = (n_side, n_side, n_side)
+    pos, mom = [], []
+    max_disp = 0.0
+    for axis, kd in enumerate((k1[:, None, None], k1[None, :, None], k3[None, None, :])):
+        psi = sfft.irfftn(1j * kd * dk, s=shape, axes=(0, 1, 2), workers=workers).ravel()
+        psi *= dfac
+        max_disp = max(max_disp, float(np.abs(psi).max()))
+        base = np.broadcast_to(q.reshape([-1 if d == axis else 1 for d in range(3)]), shape)
+        pos.append(_wrap(base.ravel() + psi, L))
+        mom.append(vfac * psi)
+        del psi
+    del dk
+    ps = _make(pos[0], pos[1], pos[2], mom[0], mom[1], mom[2], L)
+    ps.max_disp = max_disp  # type: ignore[attr-defined]
     return ps

@@ -55,8 +55,13 @@ typedef struct dzs_ctx dzs_ctx;
 typedef struct {
     uint64_t max_particles;  /* largest particle count any call will see */
     uint32_t max_mesh_side;  /* largest PM mesh side N_g (N_g = 2^a 3^b, 8 <= N_g <= 1024) */
-    uint32_t reserved;
+    uint32_t flags;          /* DZS_CAP_* bits */
 } dzs_capacity;
+
+/* Capacity flag: size the meshes for the precision form only (8-byte complex cells that
+ * also hold the fixed-point deposit, 4-byte potential: 12 instead of 32 bytes per cell);
+ * plain-form PM calls on such a context fail with DZS_EINVAL. */
+#define DZS_CAP_FP32_MESHES 1u
 
 /* Periodic box. */
 typedef struct {
@@ -78,23 +83,34 @@ typedef struct {
     uint64_t capacity;
 } dzs_particles;
 
-/* DZS de-refinement parameters (Sec. 2.2.1).  Geometric criterion: a node of side l_k
- * (level k, l_k = L / 2^k) merges when l_k < theta * D_n with
- * D_n = max(|x_com - x_obs|_min-image - R_lc - b, 0) (eq. 3), when k >= k_min (l_k <= l_max)
- * and when it holds at least two particles.  Each particle joins its shallowest merging
- * node (top-down walk).  The node centre of mass is the Neumaier-compensated FP64 sum over
- * its members in ascending (Morton key, id) order divided by their total multiplicity. */
+/* DZS de-refinement parameters (Sec. 2.2.1).  A node of side l_k (level k, l_k = L / 2^k)
+ * may merge when k >= k_min (l_k <= l_max) and it holds at least two particles; its distance
+ * to the lightcone is D_n = max(|x_com - x_obs|_min-image - R_lc - b, 0) (eq. 3).
+ *  - geometric criterion (eq. 1): merge when l_k < theta * D_n, evaluated as
+ *    |d|^2 > (R_lc + b + l_k / theta)^2;
+ *  - dynamical criterion (eq. 2): merge when G M_n l_k^2 < alpha_dyn a_min D_n^4 and D_n > 0,
+ *    M_n = K m0 (K = summed multiplicity), a_min = the smallest |g| (the accelerations held in
+ *    the state, i.e. those of the previous force) over particles with |x - x_obs|_min-image
+ *    < R_lc + b, +inf when there is none.  Evaluated in FP64 as
+ *    ((G m0) K) l_k^2 < (alpha_dyn a_min) ((D D)(D D)), D = sqrt(|d|^2) - (R_lc + b).
+ * Each particle joins its shallowest merging node (top-down walk).  The node centre of mass
+ * is the Neumaier-compensated FP64 sum over its members in ascending (Morton key, id) order
+ * divided by their total multiplicity. */
+#define DZS_CRIT_GEOMETRIC 0
+#define DZS_CRIT_DYNAMICAL 1
 typedef struct {
-    double x_obs[3];  /* observer position */
-    double R_lc;      /* lightcone radius at the coarsening epoch */
-    double b;         /* buffer width */
-    double theta;     /* geometric de-refinement angle (> 0) */
-    int32_t k_min;    /* shallowest level allowed to merge, 1..21 */
-    int32_t reserved;
+    double x_obs[3];    /* observer position */
+    double R_lc;        /* lightcone radius at the coarsening epoch */
+    double b;           /* buffer width */
+    double theta;       /* geometric de-refinement angle (> 0; read by the geometric one) */
+    int32_t k_min;      /* shallowest level allowed to merge, 1..21 */
+    int32_t criterion;  /* DZS_CRIT_GEOMETRIC or DZS_CRIT_DYNAMICAL */
+    double alpha_dyn;   /* dynamical accuracy parameter (>= 0; read by the dynamical one) */
 } dzs_coarsen_params;
 
 typedef struct {
     uint64_t n_before, n_after, n_groups;  /* n_groups = merged nodes created */
+    double a_min;  /* dynamical criterion: the a_min used (+inf if none inside); else NaN */
 } dzs_coarsen_report;
 
 #define DZS_FP64 0        /* plain form: every step in FP64 */
@@ -181,8 +197,12 @@ typedef struct {
 
 /* ---- context ------------------------------------------------------------------------ */
 
-/* Create a context on HIP device `device` and allocate all its scratch for `cap`.
- * Returns DZS_ENOMEM if the device memory does not suffice. */
+/* Create a context on HIP device `device` and allocate its scratch for `cap`: about
+ * 117 bytes per particle (keys and sort indices 24; one arena of 89 shared by the tree, with
+ * node capacity max_particles/2 + 4096, and the DZS coarsening buffers; group starts 4) plus
+ * the meshes (32 bytes per cell, 12 with DZS_CAP_FP32_MESHES); tree_force adds 52 bytes per
+ * particle of sorted copies at its first call.  Returns DZS_ENOMEM if the device memory does
+ * not suffice. */
 dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap);
 dzs_status dzs_ctx_destroy(dzs_ctx *ctx);
 /* Text of the context's last failure ("" if none); valid until the next call. */
@@ -198,7 +218,7 @@ dzs_status dzs_step_factors(double a0, double a1, double omega_m, dzs_step_param
 /* DZS coarsening (Sec. 2.2).  Reorders the state in place to ascending (Morton key, id),
  * replaces each merging node's members by one particle (mult = sum, x = centre of mass,
  * p = mult-weighted mean momentum, id = smallest member id, type = 1) and updates inout->n.
- * g is not preserved.  group_of (optional, device, >= n entries) receives for each
+ * The dynamical criterion reads g (must be non-null); g is not preserved.  group_of (optional, device, >= n entries) receives for each
  * particle's index on entry the index of the particle representing it on exit.
  * Synchronises the stream (the new count is read back). */
 dzs_status dzs_coarsen(dzs_ctx *ctx, const dzs_box *box, dzs_particles *inout,

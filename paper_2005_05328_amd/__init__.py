@@ -14,13 +14,15 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (DZS_FP32, DZS_FP64, Box, CoarsenParams, CoarsenReport, LCParams, LCRecord,
-                   PMParams, StepParams, TreeParams)
+from ._abi import (DZS_CRIT_DYNAMICAL, DZS_CRIT_GEOMETRIC, DZS_FP32, DZS_FP64, Box,
+                   CoarsenParams, CoarsenReport, LCParams, LCRecord, PMParams, StepParams,
+                   TreeParams)
 
 _lib = _abi.load()
 
 __all__ = ["Context", "State", "Box", "CoarsenParams", "PMParams", "TreeParams", "LCParams",
-           "StepParams", "LCRing", "DZSError", "step_factors", "DZS_FP64", "DZS_FP32", "lib"]
+           "StepParams", "LCRing", "DZSError", "step_factors", "DZS_FP64", "DZS_FP32",
+           "DZS_CRIT_GEOMETRIC", "DZS_CRIT_DYNAMICAL", "lib"]
 
 
 def lib():
@@ -147,8 +149,10 @@ class Context:
     """A libdzs context: scratch for up to `max_particles` particles and a `max_mesh_side`
     mesh on one device."""
 
-    def __init__(self, max_particles: int, max_mesh_side: int, device: int = 0):
-        cap = _abi.Capacity(int(max_particles), int(max_mesh_side), 0)
+    def __init__(self, max_particles: int, max_mesh_side: int, device: int = 0,
+                 fp32_meshes: bool = False):
+        cap = _abi.Capacity(int(max_particles), int(max_mesh_side),
+                            _abi.DZS_CAP_FP32_MESHES if fp32_meshes else 0)
         h = C.c_void_p()
         rc = _lib.dzs_ctx_create(C.byref(h), int(device), C.byref(cap))
         if rc != 0:

@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(HERE, "libdzs.so")
 DZS_OK, DZS_EINVAL, DZS_ENOMEM, DZS_ECAPACITY, DZS_EHIP = 0, -1, -2, -3, -4
 DZS_CHEB_MAX = 24
 DZS_FP64, DZS_FP32 = 0, 1
+DZS_CAP_FP32_MESHES = 1
+DZS_CRIT_GEOMETRIC, DZS_CRIT_DYNAMICAL = 0, 1
 
 # every entry point include/dzs.h declares
 EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_factors",
@@ -25,7 +27,7 @@ DZS_BATCH_MAX = 512
 
 class Capacity(C.Structure):
     _fields_ = [("max_particles", C.c_uint64), ("max_mesh_side", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("flags", C.c_uint32)]
 
 
 class Box(C.Structure):
@@ -40,11 +42,13 @@ class Particles(C.Structure):
 
 class CoarsenParams(C.Structure):
     _fields_ = [("x_obs", C.c_double * 3), ("R_lc", C.c_double), ("b", C.c_double),
-                ("theta", C.c_double), ("k_min", C.c_int32), ("reserved", C.c_int32)]
+                ("theta", C.c_double), ("k_min", C.c_int32), ("criterion", C.c_int32),
+                ("alpha_dyn", C.c_double)]
 
 
 class CoarsenReport(C.Structure):
-    _fields_ = [("n_before", C.c_uint64), ("n_after", C.c_uint64), ("n_groups", C.c_uint64)]
+    _fields_ = [("n_before", C.c_uint64), ("n_after", C.c_uint64), ("n_groups", C.c_uint64),
+                ("a_min", C.c_double)]
 
 
 class PMParams(C.Structure):

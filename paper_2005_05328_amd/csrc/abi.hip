@@ -132,18 +132,13 @@ static dzs_status alloc(dzs_ctx *ctx, T **p, uint64_t count) {
 
 static void release(dzs_ctx *ctx) {
     void *ptrs[] = {ctx->key, ctx->key_alt, ctx->idx, ctx->idx_alt, ctx->hist, ctx->hist_scan,
-                    ctx->scan_tmp, ctx->gather_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult,
-                    ctx->sgx, ctx->sgy, ctx->sgz, ctx->nd_first, ctx->nd_count, ctx->nd_child,
-                    ctx->nd_nchild, ctx->nd_level, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
-                    ctx->nd_bmax, ctx->nd_hmax, ctx->bstate,
-                    ctx->frontier, ctx->frontier_next,
-                    ctx->fr_nchild, ctx->fr_ninternal, ctx->fr_child_off, ctx->fr_int_off,
-                    ctx->child_bounds, ctx->grp_flag, ctx->grp_scan, ctx->grp_first,
+                    ctx->scan_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult,
+                    ctx->sgx, ctx->sgy, ctx->sgz, ctx->arena, ctx->bstate, ctx->grp_first,
                     ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl,
                     ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members,
-                    ctx->step_dev, ctx->mesh_q, ctx->mesh_c, ctx->mesh_phi,
-                    ctx->pm_tables, ctx->dz_head, ctx->dz_flag, ctx->dz_scan, ctx->dz_new,
-                    ctx->dz_newmult, ctx->dz_newid, ctx->dz_perm, ctx->d_small};
+                    ctx->step_dev, ctx->fp32_meshes ? nullptr : (void *)ctx->mesh_q, ctx->mesh_c,
+                    ctx->mesh_phi,
+                    ctx->pm_tables, ctx->d_small};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -180,39 +175,65 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     uint64_t scan_n = n > c->hist_cap ? n : c->hist_cap;
     c->scan_tmp_cap = dzs_scan_tmp_words(scan_n);
     DZS_TRY(alloc(c, &c->scan_tmp, c->scan_tmp_cap));
-    double *gt = nullptr;
-    DZS_TRY(alloc(c, &gt, n));
-    c->gather_tmp = gt;
-    DZS_TRY(alloc(c, &c->sx, n));
-    DZS_TRY(alloc(c, &c->sy, n));
-    DZS_TRY(alloc(c, &c->sz, n));
-    DZS_TRY(alloc(c, &c->smult, n));
-    DZS_TRY(alloc(c, &c->sgx, n));
-    DZS_TRY(alloc(c, &c->sgy, n));
-    DZS_TRY(alloc(c, &c->sgz, n));
-    const uint64_t nn = n + 4096;
+    // the permutation scratch shares the sort's ping-pong keys (free once a sort returns)
+    c->gather_tmp = (double *)c->key_alt;
+    // One arena holds, at different times, the tree (nodes, which live from the build to the
+    // end of the walk, plus the build's frontier scratch and the group flags) and the DZS
+    // coarsening buffers (used before the tree of the same step is built).  Nodes: at most
+    // n/2 + 4096 (internal nodes hold more than one particle; the build flags an overflow).
+    const uint64_t nn = n / 2 + 4096;
     c->cap_nodes = nn;
-    DZS_TRY(alloc(c, &c->nd_first, nn));
-    DZS_TRY(alloc(c, &c->nd_count, nn));
-    DZS_TRY(alloc(c, &c->nd_child, nn));
-    DZS_TRY(alloc(c, &c->nd_nchild, nn));
-    DZS_TRY(alloc(c, &c->nd_level, nn));
-    DZS_TRY(alloc(c, &c->nd_mass, nn));
-    DZS_TRY(alloc(c, &c->nd_com, 3 * nn));
-    DZS_TRY(alloc(c, &c->nd_bmin, 3 * nn));
-    DZS_TRY(alloc(c, &c->nd_bmax, 3 * nn));
-    DZS_TRY(alloc(c, &c->nd_hmax, nn));
+    uint64_t off_t = 0, off_d = 0;
+    auto carve = [](uint64_t &off, uint64_t bytes) {
+        const uint64_t at = off;
+        off += (bytes + 255) & ~255ull;
+        return at;
+    };
+    const uint64_t o_first = carve(off_t, 4 * nn), o_count = carve(off_t, 4 * nn),
+                   o_child = carve(off_t, 4 * nn), o_nchild = carve(off_t, nn),
+                   o_level = carve(off_t, nn), o_mass = carve(off_t, 8 * nn),
+                   o_com = carve(off_t, 24 * nn), o_bmin = carve(off_t, 24 * nn),
+                   o_bmax = carve(off_t, 24 * nn), o_hmax = carve(off_t, 8 * nn),
+                   o_fr = carve(off_t, 4 * nn), o_frn = carve(off_t, 4 * nn),
+                   o_nc = carve(off_t, 4 * nn), o_ni = carve(off_t, 4 * nn),
+                   o_co = carve(off_t, 4 * nn), o_io = carve(off_t, 4 * nn),
+                   o_cb = carve(off_t, 36 * nn), o_gf = carve(off_t, 4 * n),
+                   o_gs = carve(off_t, 4 * n);
+    const uint64_t o_head = carve(off_d, 4 * n), o_flag = carve(off_d, 4 * n),
+                   o_scan = carve(off_d, 4 * n), o_new = carve(off_d, 48 * n),
+                   o_nmult = carve(off_d, 4 * n), o_nid = carve(off_d, 4 * n),
+                   o_perm = carve(off_d, 4 * n);
+    DZS_TRY(alloc(c, &c->arena, off_t > off_d ? off_t : off_d));
+    c->arena_bytes = off_t > off_d ? off_t : off_d;
+    char *A = c->arena;
+    c->nd_first = (uint32_t *)(A + o_first);
+    c->nd_count = (uint32_t *)(A + o_count);
+    c->nd_child = (uint32_t *)(A + o_child);
+    c->nd_nchild = (uint8_t *)(A + o_nchild);
+    c->nd_level = (uint8_t *)(A + o_level);
+    c->nd_mass = (double *)(A + o_mass);
+    c->nd_com = (double *)(A + o_com);
+    c->nd_bmin = (double *)(A + o_bmin);
+    c->nd_bmax = (double *)(A + o_bmax);
+    c->nd_hmax = (double *)(A + o_hmax);
+    c->frontier = (uint32_t *)(A + o_fr);
+    c->frontier_next = (uint32_t *)(A + o_frn);
+    c->fr_nchild = (uint32_t *)(A + o_nc);
+    c->fr_ninternal = (uint32_t *)(A + o_ni);
+    c->fr_child_off = (uint32_t *)(A + o_co);
+    c->fr_int_off = (uint32_t *)(A + o_io);
+    c->child_bounds = (uint32_t *)(A + o_cb);
+    c->grp_flag = (uint32_t *)(A + o_gf);
+    c->grp_scan = (uint32_t *)(A + o_gs);
+    c->dz_head = (uint32_t *)(A + o_head);
+    c->dz_flag = (uint32_t *)(A + o_flag);
+    c->dz_scan = (uint32_t *)(A + o_scan);
+    c->dz_new = (double *)(A + o_new);
+    c->dz_newmult = (uint32_t *)(A + o_nmult);
+    c->dz_newid = (uint32_t *)(A + o_nid);
+    c->dz_perm = (uint32_t *)(A + o_perm);
     DZS_TRY(alloc(c, &c->bstate, 64));
     DZS_HIP(c, hipMemset(c->bstate, 0, 64 * sizeof(uint32_t)));
-    DZS_TRY(alloc(c, &c->frontier, n));
-    DZS_TRY(alloc(c, &c->frontier_next, n));
-    DZS_TRY(alloc(c, &c->fr_nchild, n));
-    DZS_TRY(alloc(c, &c->fr_ninternal, n));
-    DZS_TRY(alloc(c, &c->fr_child_off, n));
-    DZS_TRY(alloc(c, &c->fr_int_off, n));
-    DZS_TRY(alloc(c, &c->child_bounds, 9 * n));
-    DZS_TRY(alloc(c, &c->grp_flag, n));
-    DZS_TRY(alloc(c, &c->grp_scan, n));
     DZS_TRY(alloc(c, &c->grp_first, n + 1));
     c->walk_stack_slots = 4096;
     c->walk_stack_depth = 8192;
@@ -236,18 +257,24 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     }
     DZS_TRY(alloc(c, &c->cell_dl, 1ull << (3 * DZS_CELL_K_MAX)));
     if (ng > 0) {
-        DZS_TRY(alloc(c, &c->mesh_q, ng3));
-        DZS_TRY(alloc(c, &c->mesh_c, ng3));
-        DZS_TRY(alloc(c, &c->mesh_phi, ng3));
+        c->fp32_meshes = (cap->flags & DZS_CAP_FP32_MESHES) != 0;
+        if (c->fp32_meshes) {
+            // precision form only: 8-byte complex cells hold the 8-byte fixed-point deposit
+            // in place (the first FFT pass reads a tile, then writes it), 4-byte potential
+            char *m = nullptr;
+            DZS_TRY(alloc(c, &m, 8 * ng3));
+            c->mesh_c = (double2 *)m;
+            c->mesh_q = (long long *)m;
+            char *ph = nullptr;
+            DZS_TRY(alloc(c, &ph, 4 * ng3));
+            c->mesh_phi = (double *)ph;
+        } else {
+            DZS_TRY(alloc(c, &c->mesh_q, ng3));
+            DZS_TRY(alloc(c, &c->mesh_c, ng3));
+            DZS_TRY(alloc(c, &c->mesh_phi, ng3));
+        }
         DZS_TRY(alloc(c, &c->pm_tables, 4 * ng));
     }
-    DZS_TRY(alloc(c, &c->dz_head, n));
-    DZS_TRY(alloc(c, &c->dz_flag, n));
-    DZS_TRY(alloc(c, &c->dz_scan, n));
-    DZS_TRY(alloc(c, &c->dz_new, 6 * n));
-    DZS_TRY(alloc(c, &c->dz_newmult, n));
-    DZS_TRY(alloc(c, &c->dz_newid, n));
-    DZS_TRY(alloc(c, &c->dz_perm, n));
     DZS_TRY(alloc(c, &c->d_small, 64));
     void *h = nullptr;
     DZS_HIP(c, hipHostMalloc(&h, 64 * sizeof(uint32_t), hipHostMallocDefault));
@@ -350,15 +377,24 @@ static dzs_status check_pm(dzs_ctx *ctx, const dzs_pm_params *m) {
         return dzs_fail(ctx, DZS_EINVAL, "pm: r_s must be positive");
     if (m->precision != DZS_FP64 && m->precision != DZS_FP32)
         return dzs_fail(ctx, DZS_EINVAL, "pm: precision must be DZS_FP64 or DZS_FP32");
+    if (m->precision == DZS_FP64 && ctx->fp32_meshes)
+        return dzs_fail(ctx, DZS_EINVAL, "pm: the context holds meshes for the precision form "
+                        "only (DZS_CAP_FP32_MESHES)");
     return DZS_OK;
 }
 
 static dzs_status check_coarsen(dzs_ctx *ctx, const dzs_coarsen_params *c) {
     if (!c)
         return dzs_fail(ctx, DZS_EINVAL, "null coarsening parameters");
-    if (!(c->theta > 0.0) || c->k_min < 1 || c->k_min > DZS_KEY_BITS || !(c->R_lc >= 0.0) ||
-        !(c->b >= 0.0))
-        return dzs_fail(ctx, DZS_EINVAL, "coarsen: need theta > 0, 1 <= k_min <= 21, R_lc, b >= 0");
+    if (c->criterion != DZS_CRIT_GEOMETRIC && c->criterion != DZS_CRIT_DYNAMICAL)
+        return dzs_fail(ctx, DZS_EINVAL, "coarsen: unknown criterion %d", c->criterion);
+    if (c->criterion == DZS_CRIT_GEOMETRIC && !(c->theta > 0.0))
+        return dzs_fail(ctx, DZS_EINVAL, "coarsen: the geometric criterion needs theta > 0");
+    if (c->criterion == DZS_CRIT_DYNAMICAL && !(c->alpha_dyn >= 0.0 && c->alpha_dyn < HUGE_VAL))
+        return dzs_fail(ctx, DZS_EINVAL, "coarsen: the dynamical criterion needs a finite "
+                        "alpha_dyn >= 0");
+    if (c->k_min < 1 || c->k_min > DZS_KEY_BITS || !(c->R_lc >= 0.0) || !(c->b >= 0.0))
+        return dzs_fail(ctx, DZS_EINVAL, "coarsen: need 1 <= k_min <= 21, R_lc, b >= 0");
     return DZS_OK;
 }
 
@@ -416,12 +452,17 @@ extern "C" dzs_status dzs_coarsen(dzs_ctx *ctx, const dzs_box *box, dzs_particle
     DZS_TRY(check_coarsen(ctx, prm));
     if (inout->n > 0 && (!inout->px || !inout->py || !inout->pz || !inout->id || !inout->type))
         return dzs_fail(ctx, DZS_EINVAL, "null state array");
+    const bool dyn = prm->criterion == DZS_CRIT_DYNAMICAL;
+    if (dyn && inout->n > 0 && (!inout->gx || !inout->gy || !inout->gz))
+        return dzs_fail(ctx, DZS_EINVAL, "coarsen: the dynamical criterion reads g (null)");
     hipStream_t s = (hipStream_t)stream;
     if (inout->n == 0) {
         if (report)
-            *report = dzs_coarsen_report{0, 0, 0};
+            *report = dzs_coarsen_report{0, 0, 0, dyn ? HUGE_VAL : NAN};
         return DZS_OK;
     }
+    if (dyn)  // before the sort, which leaves g behind
+        DZS_TRY(dzs_coarsen_amin(ctx, box, inout, prm, s));
     DZS_TRY(sort_state(ctx, box, inout, 1, 0, s));
     DZS_HIP(ctx, hipMemcpyAsync(ctx->dz_perm, ctx->idx, sizeof(uint32_t) * inout->n,
                                 hipMemcpyDeviceToDevice, s));
@@ -448,6 +489,16 @@ extern "C" dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_par
     if (n == 0)
         return DZS_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (!ctx->sx) {
+        // the sorted copies of a standalone force call, allocated at its first use
+        DZS_TRY(alloc(ctx, &ctx->sx, ctx->cap_n));
+        DZS_TRY(alloc(ctx, &ctx->sy, ctx->cap_n));
+        DZS_TRY(alloc(ctx, &ctx->sz, ctx->cap_n));
+        DZS_TRY(alloc(ctx, &ctx->smult, ctx->cap_n));
+        DZS_TRY(alloc(ctx, &ctx->sgx, ctx->cap_n));
+        DZS_TRY(alloc(ctx, &ctx->sgy, ctx->cap_n));
+        DZS_TRY(alloc(ctx, &ctx->sgz, ctx->cap_n));
+    }
     DZS_TRY(dzs_launch_keys(ctx, p->x, p->y, p->z, n, box->L, ctx->key, ctx->idx, s));
     DZS_TRY(dzs_radix_sort(ctx, n, s));
     {
@@ -501,13 +552,15 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
         DZS_TRY(check_coarsen(ctx, &prm->coarsen));
     hipStream_t s = (hipStream_t)stream;
     if (report)
-        *report = dzs_coarsen_report{st->n, st->n, 0};
+        *report = dzs_coarsen_report{st->n, st->n, 0, NAN};
 
     DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s));
     DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &prm->lc, ring, prm->do_lightcone, 1, s));
     const bool can_merge = prm->do_coarsen &&
                            prm->coarsen.R_lc + prm->coarsen.b < 0.5 * sqrt(3.0) * box->L;
     if (can_merge && st->n > 0) {
+        if (prm->coarsen.criterion == DZS_CRIT_DYNAMICAL)  // g is the previous force here
+            DZS_TRY(dzs_coarsen_amin(ctx, box, st, &prm->coarsen, s));
         DZS_TRY(sort_state(ctx, box, st, 1, 0, s));
         DZS_HIP(ctx, hipMemcpyAsync(ctx->dz_perm, ctx->idx, sizeof(uint32_t) * st->n,
                                     hipMemcpyDeviceToDevice, s));
@@ -560,6 +613,9 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     DZS_TRY(check_tree(ctx, &batch->boxes[0], &t_in, &t));
     if (prm->pm.precision != DZS_FP64 && prm->pm.precision != DZS_FP32)
         return dzs_fail(ctx, DZS_EINVAL, "batch: PM precision must be DZS_FP64 or DZS_FP32");
+    if (prm->pm.precision == DZS_FP64 && ctx->fp32_meshes)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: the context holds meshes for the precision "
+                        "form only (DZS_CAP_FP32_MESHES)");
     if (prm->do_lightcone)
         DZS_TRY(check_lc(ctx, &prm->lc, ring));
     const double ratio = batch->r_cut[0] / batch->r_s[0];

@@ -12,6 +12,11 @@
 // The node sums, the centre of mass, the minimum-image distance and the threshold comparison
 // use the exact operation sequence of the definition (no contraction), so the grouping is
 // bit-identical to any implementation that follows the same definition.
+//
+// Two criteria (Sec. 2.2.1): the geometric one (eq. 1 with eq. 3) compares |d|^2 with a
+// per-level threshold; the dynamical one (eq. 2 with eq. 3) compares G m0 K l_k^2 with
+// alpha a_min D^4, where a_min, the smallest previous acceleration inside the lightcone plus
+// buffer, is reduced on the device beforehand (an order-independent minimum, so exact).
 #include "internal.h"
 
 #define DZ_THREADS 256
@@ -36,8 +41,10 @@ __device__ __forceinline__ double nm_value(const neumaier &a) { return a.sum + a
 
 struct dz_level_args {
     uint64_t n;
-    int k;
+    int k, crit;
     double L, T2;
+    double Gm0, lk2, Rb, alpha;       // dynamical criterion
+    const unsigned long long *amin2;  // bits of min g.g inside the lightcone (device)
     double xo[3];
     const uint64_t *key;
     const double *x, *y, *z, *px, *py, *pz;
@@ -85,8 +92,19 @@ __global__ __launch_bounds__(DZ_THREADS) void k_dz_level(dz_level_args A) {
     const double dy = dzs_min_image(Y - A.xo[1], A.L);
     const double dz = dzs_min_image(Z - A.xo[2], A.L);
     const double d2 = dx * dx + dy * dy + dz * dz;
-    if (!(d2 > A.T2))
-        return;
+    if (A.crit == DZS_CRIT_GEOMETRIC) {
+        if (!(d2 > A.T2))
+            return;
+    } else {
+        const double D = sqrt(d2) - A.Rb;
+        if (!(D > 0.0))
+            return;
+        const double amin = sqrt(__longlong_as_double((long long)*A.amin2));
+        const double lhs = (A.Gm0 * Kd) * A.lk2;
+        const double rhs = (A.alpha * amin) * ((D * D) * (D * D));
+        if (!(lhs < rhs))
+            return;
+    }
     for (uint64_t r = i; r < e; ++r)
         A.head[r] = (uint32_t)i;
     A.nx[i] = X;
@@ -97,6 +115,63 @@ __global__ __launch_bounds__(DZ_THREADS) void k_dz_level(dz_level_args A) {
     A.npz[i] = nm_value(P[2]) / Kd;
     A.nmult[i] = (uint32_t)K;
     A.nid[i] = min_id;
+}
+
+// The smallest g.g among particles strictly inside R_lc + b of the observer (minimum image);
+// its bit pattern orders like the value because g.g >= 0, so blocks combine by an integer
+// atomic minimum on a slot preset to +inf.
+__global__ __launch_bounds__(1) void k_dz_amin_init(unsigned long long *out) {
+    *out = 0x7ff0000000000000ull;
+}
+
+__global__ __launch_bounds__(DZ_THREADS) void k_dz_amin(uint64_t n, const double *__restrict__ x,
+                                                       const double *__restrict__ y,
+                                                       const double *__restrict__ z,
+                                                       const double *__restrict__ gx,
+                                                       const double *__restrict__ gy,
+                                                       const double *__restrict__ gz, double L,
+                                                       double xo0, double xo1, double xo2,
+                                                       double Rb, unsigned long long *out) {
+    __shared__ double red[DZ_THREADS];
+    double best = __builtin_inf();
+    const uint64_t stride = (uint64_t)gridDim.x * DZ_THREADS;
+    for (uint64_t i = (uint64_t)blockIdx.x * DZ_THREADS + threadIdx.x; i < n; i += stride) {
+        const double dx = dzs_min_image(x[i] - xo0, L);
+        const double dy = dzs_min_image(y[i] - xo1, L);
+        const double dz = dzs_min_image(z[i] - xo2, L);
+        if (!(sqrt(dx * dx + dy * dy + dz * dz) < Rb))
+            continue;
+        const double g2 = gx[i] * gx[i] + gy[i] * gy[i] + gz[i] * gz[i];
+        best = g2 < best ? g2 : best;
+    }
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int h = DZ_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const double o = red[threadIdx.x + h];
+            red[threadIdx.x] = o < red[threadIdx.x] ? o : red[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        atomicMin(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+dzs_status dzs_coarsen_amin(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                            const dzs_coarsen_params *prm, hipStream_t s) {
+    unsigned long long *slot = (unsigned long long *)(ctx->d_small + DZS_SMALL_AMIN);
+    hipLaunchKernelGGL(k_dz_amin_init, dim3(1), dim3(1), 0, s, slot);
+    DZS_TRY(dzs_check_launch(ctx, "dz_amin_init"));
+    if (p->n == 0)
+        return DZS_OK;
+    const uint64_t want = (p->n + DZ_THREADS - 1) / DZ_THREADS;
+    const uint32_t blocks = (uint32_t)(want < 2048 ? want : 2048);
+    hipLaunchKernelGGL(k_dz_amin, dim3(blocks), dim3(DZ_THREADS), 0, s, p->n,
+                       (const double *)p->x, (const double *)p->y, (const double *)p->z,
+                       (const double *)p->gx, (const double *)p->gy, (const double *)p->gz,
+                       box->L, prm->x_obs[0], prm->x_obs[1], prm->x_obs[2], prm->R_lc + prm->b,
+                       slot);
+    return dzs_check_launch(ctx, "dz_amin");
 }
 
 __global__ __launch_bounds__(DZ_THREADS) void k_dz_init(uint64_t n, uint32_t *head) {
@@ -189,19 +264,26 @@ dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p
                               const dzs_coarsen_params *prm, uint32_t *group_of,
                               dzs_coarsen_report *report, hipStream_t s) {
     const uint64_t n = p->n;
+    const bool dyn = prm->criterion == DZS_CRIT_DYNAMICAL;
     if (report) {
         report->n_before = n;
         report->n_after = n;
         report->n_groups = 0;
+        report->a_min = dyn ? __builtin_inf() : __builtin_nan("");
     }
     if (n == 0)
         return DZS_OK;
     double T2[DZS_KEY_BITS + 1];
-    dzs_merge_thresholds(box->L, prm->R_lc, prm->b, prm->theta, T2);
+    dzs_merge_thresholds(box->L, prm->R_lc, prm->b, dyn ? 1.0 : prm->theta, T2);
     const uint64_t cap = ctx->cap_n;
     dz_level_args A;
     A.n = n;
     A.L = box->L;
+    A.crit = dyn ? DZS_CRIT_DYNAMICAL : DZS_CRIT_GEOMETRIC;
+    A.Gm0 = box->G * box->m0;
+    A.Rb = prm->R_lc + prm->b;
+    A.alpha = prm->alpha_dyn;
+    A.amin2 = (const unsigned long long *)(ctx->d_small + DZS_SMALL_AMIN);
     for (int d = 0; d < 3; ++d)
         A.xo[d] = prm->x_obs[d];
     A.key = ctx->key;
@@ -221,6 +303,8 @@ dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p
         for (int k = prm->k_min; k <= DZS_KEY_BITS; ++k) {
             A.k = k;
             A.T2 = T2[k];
+            const double lk = ldexp(box->L, -k);
+            A.lk2 = lk * lk;
             hipLaunchKernelGGL(k_dz_level, dim3(blocks), dim3(DZ_THREADS), 0, s, A);
             DZS_TRY(dzs_check_launch(ctx, "dz_level"));
         }
@@ -236,11 +320,19 @@ dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p
         hipLaunchKernelGGL(k_dz_count_heads, dim3(blocks), dim3(DZ_THREADS), 0, s, n,
                            (const uint32_t *)ctx->dz_head, ctx->d_small + 9);
         DZS_TRY(dzs_check_launch(ctx, "dz_count_heads"));
-        DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 8, ctx->d_small + 8, 2 * sizeof(uint32_t),
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 8, ctx->d_small + 8,
+                                    (DZS_SMALL_AMIN + 2 - 8) * sizeof(uint32_t),
                                     hipMemcpyDeviceToHost, s));
         DZS_HIP(ctx, hipStreamSynchronize(s));
         n_new = ctx->h_small[8];
         n_heads = ctx->h_small[9];
+        if (dyn && report) {
+            unsigned long long bits;
+            memcpy(&bits, ctx->h_small + DZS_SMALL_AMIN, sizeof(bits));
+            double g2;
+            memcpy(&g2, &bits, sizeof(g2));
+            report->a_min = sqrt(g2);
+        }
         if (group_of) {
             hipLaunchKernelGGL(k_dz_groupmap, dim3(blocks), dim3(DZ_THREADS), 0, s, n,
                                (const uint32_t *)ctx->dz_head, (const uint32_t *)ctx->dz_scan,

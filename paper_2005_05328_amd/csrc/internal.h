@@ -144,6 +144,9 @@ struct dzs_ctx {
     bool tree_built = false;           // a tree for tree_n particles is in the node arrays
     uint32_t tree_n = 0;
     bool defer_checks = false;         // skip the synchronising overflow checks (batched step)
+    char *arena = nullptr;             // tree and coarsening buffers (shared, see create())
+    uint64_t arena_bytes = 0;
+    bool fp32_meshes = false;          // meshes sized for the precision form only
 
     // ---- PM mesh
     long long *mesh_q = nullptr;  // fixed-point density accumulator, ng^3
@@ -161,7 +164,7 @@ struct dzs_ctx {
     uint32_t *dz_perm = nullptr;     // entry index of each sorted slot
 
     // ---- small device / host scalars
-    uint32_t *d_small = nullptr;  // 64 words of device scratch
+    uint32_t *d_small = nullptr;  // 64 words of device scratch (DZS_SMALL_* slots)
     uint32_t *h_small = nullptr;  // 64 words of pinned host memory
 
     // ---- timing
@@ -329,6 +332,13 @@ dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
                             double G, hipStream_t s);
 
 // coarsen.hip
+// d_small word slots: 8 the coarsening survivor count, 9 its head count, 16..17 the bits of
+// the dynamical criterion's min g.g (8-byte aligned).
+#define DZS_SMALL_AMIN 16
+// Reduce the dynamical criterion's a_min^2 over the state (before any reordering that leaves
+// g behind) into d_small[DZS_SMALL_AMIN].
+dzs_status dzs_coarsen_amin(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                            const dzs_coarsen_params *prm, hipStream_t s);
 dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p,
                               const dzs_coarsen_params *prm, uint32_t *group_of,
                               dzs_coarsen_report *report, hipStream_t s);

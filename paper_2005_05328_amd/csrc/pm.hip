@@ -221,9 +221,10 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit(uint64_t n, const dou
 template <int MODE, typename C>  // 0: x forward from fixed point, 1: y forward, 2: y inverse,
                                  // 3: x inverse to phi
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
-    const unsigned long long *__restrict__ q, C *__restrict__ c,
-    decltype(C::x) *__restrict__ phi, const double2 *__restrict__ tw, fft_plan P, int TZ,
-    double q_scale, pm_batch B) {
+    const unsigned long long *q, C *c, decltype(C::x) *__restrict__ phi,
+    const double2 *__restrict__ tw, fft_plan P, int TZ, double q_scale, pm_batch B) {
+    // q and c may be the same memory (meshes for the precision form only): every element of
+    // the tile is loaded before the first store
     typedef decltype(C::x) Rt;
     __shared__ C s_buf[FFT_ELEMS];
     __shared__ C s_tw[1024];

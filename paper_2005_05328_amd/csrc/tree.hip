@@ -317,6 +317,10 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
     const uint32_t leaf = (uint32_t)leaf_size;
     const uint64_t cap = ctx->cap_nodes;
     uint32_t *bs = ctx->bstate;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DZS_HIP(ctx, hipStreamIsCapturing(s, &cs));
+    const bool may_sync = !ctx->defer_checks && cs == hipStreamCaptureStatusNone;
+    int deepest = 0;  // the deepest level the build may have created
     {
         dzs_timed t(ctx, KC_TREE_BUILD, s);
         hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, n, ctx->nd_first, ctx->nd_count,
@@ -325,6 +329,7 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
         DZS_TRY(dzs_check_launch(ctx, "tree_root"));
         uint32_t *fr = ctx->frontier, *fr_next = ctx->frontier_next;
         for (int k = 0; k < DZS_KEY_BITS; ++k) {
+            deepest = k + 1;
             uint64_t ub = k <= KB ? n : n / (leaf + 1) + 1;
             if (k < 8 && (1ull << (3 * k)) < ub)
                 ub = 1ull << (3 * k);
@@ -348,11 +353,21 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
             uint32_t *tmp = fr;
             fr = fr_next;
             fr_next = tmp;
+            // Outside a captured or deferred-check call, stop once the frontier is empty: a
+            // read-back at a few depths costs less than the empty levels' launches.  The
+            // tree is the same either way.
+            if (may_sync && (k == 9 || k == 12 || k == 15)) {
+                DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 10, bs + BS_NF, sizeof(uint32_t),
+                                            hipMemcpyDeviceToHost, s));
+                DZS_HIP(ctx, hipStreamSynchronize(s));
+                if (ctx->h_small[10] == 0)
+                    break;
+            }
         }
     }
     {
         dzs_timed t(ctx, KC_TREE_MOMENTS, s);
-        for (int k = DZS_KEY_BITS; k >= 0; --k) {
+        for (int k = deepest; k >= 0; --k) {
             // at most 8^k nodes on level k, and never more than the particles
             uint64_t ub = n;
             if (k < 8 && (1ull << (3 * k)) < ub)

@@ -377,6 +377,72 @@ def test_coarsen_bit_exact(dz, ctx, case):
     assert np.array_equal(gof.cpu().numpy().astype(np.int64), group_of)
 
 
+@pytest.mark.parametrize("case", range(4))
+def test_coarsen_dynamical_bit_exact(dz, ctx, case):
+    """Dynamical criterion (eq. 2 with eq. 3): the same bit-exact bar as the geometric one,
+    including the reduced a_min; case 3 puts nobody inside (a_min = +inf)."""
+    import torch
+    L = [100.0, 256.0, 1.0, 64.0][case]
+    n = [20000, 40000, 7000, 12000][case]
+    ps = dzs_ics.merged_state(dzs_ics.clustered_random(n, L, seed=70 + case, r_clump=L / 30,
+                                                       vel=400.0), seed=case, max_mult=20)
+    ps.id = dzs_ics.rng(80 + case).permutation(ps.n).astype(np.uint32)
+    g = dzs_ics.rng(90 + case).standard_normal((3, ps.n)) * [1.0, 30.0, 1e-3, 5.0][case]
+    box, obox = _box(dz, L, ps.n, 32)
+    R = 0.0 if case == 3 else 0.15 * L
+    b = 1e-9 * L if case == 3 else 0.02 * L
+    prm = dict(x_obs=[0.1 * L * case, 0.0, 0.3 * L], R_lc=R, b=b, theta=None, k_min=2 + case % 3,
+               alpha_dyn=[3e-2, 1e-3, 1.0, 1e-6][case])
+    _log(f"coarsen dynamical case={case} n={ps.n}")
+    res, group_of, nm = oracle.coarsen(ps, **prm, g=g, Gm0=obox.G * obox.m0)
+    st = dz.State.from_host(ps, g=g)
+    cp = dz.CoarsenParams()
+    for d in range(3):
+        cp.x_obs[d] = prm["x_obs"][d]
+    cp.R_lc, cp.b, cp.k_min = prm["R_lc"], prm["b"], prm["k_min"]
+    cp.criterion, cp.alpha_dyn = dz.DZS_CRIT_DYNAMICAL, prm["alpha_dyn"]
+    gof = torch.zeros(ps.n, dtype=torch.int32, device="cuda")
+    rep = ctx.dzs_coarsen(box, st, cp, group_of=gof)
+    torch.cuda.synchronize()
+    out = st.to_host()
+    assert nm > 0 and 0 < res["x"].shape[0] < ps.n
+    assert rep.a_min == res["a_min"]
+    if case == 3:
+        assert rep.a_min == math.inf
+    assert rep.n_groups == nm and rep.n_after == res["x"].shape[0]
+    for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+        assert np.array_equal(out[k], res[k]), k
+    assert np.array_equal(gof.cpu().numpy().astype(np.int64), group_of)
+
+
+def test_coarsen_dynamical_zero_alpha_and_rejects(dz, ctx):
+    import torch
+    L = 100.0
+    ps = dzs_ics.clustered_random(8000, L, seed=61)
+    g = dzs_ics.rng(62).standard_normal((3, ps.n))
+    box, _ = _box(dz, L, ps.n, 20)
+    st = dz.State.from_host(ps, g=g)
+    cp = dz.CoarsenParams()
+    cp.R_lc, cp.b, cp.k_min = 10.0, 1.0, 2
+    cp.criterion, cp.alpha_dyn = dz.DZS_CRIT_DYNAMICAL, 0.0
+    rep = ctx.dzs_coarsen(box, st, cp)
+    torch.cuda.synchronize()
+    assert rep.n_groups == 0 and st.n == ps.n and rep.a_min > 0
+    for bad in (dict(criterion=2), dict(alpha_dyn=-1.0), dict(alpha_dyn=math.inf)):
+        cp2 = dz.CoarsenParams()
+        cp2.R_lc, cp2.b, cp2.k_min = 10.0, 1.0, 2
+        cp2.criterion, cp2.alpha_dyn = dz.DZS_CRIT_DYNAMICAL, 1.0
+        for k, v in bad.items():
+            setattr(cp2, k, v)
+        with pytest.raises(dz.DZSError):
+            ctx.dzs_coarsen(box, st, cp2)
+    # the geometric criterion still needs theta > 0
+    cp3 = dz.CoarsenParams()
+    cp3.R_lc, cp3.b, cp3.k_min, cp3.theta = 10.0, 1.0, 2, 0.0
+    with pytest.raises(dz.DZSError):
+        ctx.dzs_coarsen(box, st, cp3)
+
+
 def test_coarsen_no_merge_region_is_identity(dz, ctx):
     import torch
     L = 100.0
@@ -395,7 +461,8 @@ def test_coarsen_no_merge_region_is_identity(dz, ctx):
 
 # -------------------------------------------------------------------------------- KDK step
 
-@pytest.mark.parametrize("coarsen,fp32", [(False, False), (True, False), (True, True)])
+@pytest.mark.parametrize("coarsen,fp32", [(False, False), (True, False), (True, True),
+                                           ("dyn", False)])
 def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
     """One step of the 32^3 box: Zel'dovich at z = 49, L = 100, mesh 64.  In the precision form
     the drift, the coarsening and the lightcone test stay FP64 (bit-exact); the force and the
@@ -411,6 +478,9 @@ def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
     fac = oracle.step_factors(a0, a1)
     fac.update(a0=a0, a1=a1)
     cparams = dict(R_lc=20.0, b=5 * L / n_side, theta=1.0, k_min=4) if coarsen else None
+    if coarsen == "dyn":
+        # dynamical criterion on the previous (initial) force; alpha = 0.3 merges ~1000 nodes
+        cparams.update(theta=None, alpha_dyn=0.3)
     _log(f"kdk coarsen={coarsen} fp32={fp32}")
     prec = dz.DZS_FP32 if fp32 else dz.DZS_FP64
     tol = 1e-5 if fp32 else 1e-9
@@ -424,7 +494,12 @@ def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
     sp.do_coarsen = 1 if coarsen else 0
     if coarsen:
         sp.coarsen.R_lc, sp.coarsen.b = cparams["R_lc"], cparams["b"]
-        sp.coarsen.theta, sp.coarsen.k_min = cparams["theta"], cparams["k_min"]
+        sp.coarsen.k_min = cparams["k_min"]
+        if coarsen == "dyn":
+            sp.coarsen.criterion = dz.DZS_CRIT_DYNAMICAL
+            sp.coarsen.alpha_dyn = cparams["alpha_dyn"]
+        else:
+            sp.coarsen.theta = cparams["theta"]
     sp.pm = dz.PMParams(ng, prec, r_s, 0, 0)
     sp.tree = dz.TreeParams(r_s, r_cut, 0.0, 8, 64, prec, 0)
     st = dz.State.from_host(ps, g=g0)
@@ -436,6 +511,8 @@ def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
     assert st.n == ref_state.n
     if coarsen:
         assert rep.n_groups == cres[2] > 0
+    if coarsen == "dyn":
+        assert rep.a_min == cres[0]["a_min"]
     o = np.argsort(out["id"])
     r = np.argsort(ref_state.id)
     # positions after the drift (and the coarsening) are bit-exact
@@ -508,3 +585,25 @@ def test_lightcone_emits_every_particle_once_over_a_run(dz, ctx, coarsen):
     assert np.array_equal(ids, np.sort(ps.id))
     assert np.all(rec["mult"] == 1)
     assert np.all((rec["a_cross"] >= 0.02) & (rec["a_cross"] <= 1.0))
+
+
+def test_fp32_mesh_context_matches_and_rejects_plain_pm(dz):
+    """A context whose meshes are sized for the precision form only (the deposit shares the
+    complex mesh) gives the same FP32 PM force bit for bit, and refuses the plain form."""
+    import torch
+    L, ng = 100.0, 64
+    r_s = 1.25 * L / ng
+    ps = _force_case("clustered", 20000, L, 13)
+    box, _ = _box(dz, L, ps.n, 32)
+    out = []
+    for flag in (False, True):
+        c = dz.Context(max_particles=ps.n, max_mesh_side=ng, fp32_meshes=flag)
+        st = dz.State.from_host(ps)
+        c.pm_force(box, st, dz.PMParams(ng, dz.DZS_FP32, r_s, 0, 0))
+        torch.cuda.synchronize()
+        out.append(np.stack([st.gx[: ps.n].cpu().numpy(), st.gy[: ps.n].cpu().numpy()]))
+        if flag:
+            with pytest.raises(dz.DZSError):
+                c.pm_force(box, st, dz.PMParams(ng, dz.DZS_FP64, r_s, 0, 0))
+        c.close()
+    assert np.array_equal(out[0], out[1])
