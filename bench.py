@@ -314,6 +314,95 @@ def run_lean(args, dz, torch, dzs_ics):
     }
 
 
+def run_full(args, dz, torch, dzs_ics):
+    """One whole run of the 1024^3 configuration, DZS (`--full-run dzs`) or full resolution
+    (`--full-run std`), in the lean memory plan.  Each step's lightcone records are drained
+    into a 128^3 density mesh after the step (outside its timing); the mesh, the per-step
+    times and the particle counts go to `--out` (.npz) for `--compare`."""
+    P = dict(PRESETS["c5"])
+    if args.n_side:
+        f = args.n_side / P["n_side"]
+        P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
+    W = workload(**P)
+    W["prec"] = dz.DZS_FP32
+    n_steps = min(args.steps or W["n_steps"], W["n_steps"])
+    dzs = args.full_run == "dzs"
+    log(f"c5 full run ({args.full_run}): N={W['N']} L={W['L']} ng={W['ng']} steps={n_steps}")
+    t0 = time.perf_counter()
+    ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
+    log(f"initial conditions ready ({time.perf_counter() - t0:.0f} s)")
+    box = dz.make_box(W["L"], W["m0"], W["eps0"])
+    ctx = dz.Context(W["N"], W["ng"], fp32_meshes=True)
+    st = dz.State.from_host(ics)
+    del ics
+    params = make_params(dz, W, dzs)
+    import copy
+    sp0 = copy.deepcopy(params[0])
+    sp0.K1 = sp0.K2 = 0.0
+    sp0.lc.D = 0.0
+    sp0.do_lightcone = sp0.do_coarsen = 0
+    ctx.kdk_step(box, st, sp0, None)
+    ring = dz.LCRing(min(W["N"], max(1 << 24, W["N"] // 5)))
+    ring.reset()
+    M = 128
+    rho = torch.zeros(M ** 3, dtype=torch.float64, device="cuda")
+    free, total = torch.cuda.mem_get_info()
+    log(f"resident: {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f}")
+    torch.cuda.synchronize()
+    ctx.timing(enable=True, reset=True)
+    per_step, counts, merged, records, overflow = [], [], 0, 0, False
+    for s_ in range(n_steps):
+        t1 = time.perf_counter()
+        rep = ctx.kdk_step(box, st, params[s_], ring)
+        torch.cuda.synchronize()
+        per_step.append(time.perf_counter() - t1)
+        merged += int(rep.n_groups)
+        counts.append(st.n)
+        nrec = int(ring.count.item())
+        overflow = overflow or bool(ring.overflow.item())
+        records += min(nrec, ring.capacity)
+        lightcone_density(ring, W["L"], M, rho)
+        ring.reset()
+        torch.cuda.synchronize()   # the drain must not run into the next step's timing
+        log(f"  step {s_ + 1}/{n_steps}: {per_step[-1]:.3f} s, N = {st.n}, lightcone {nrec}")
+    kern = ctx.timing(enable=False, reset=True)
+    peak = torch.cuda.max_memory_allocated()
+    ctx.close()
+    if args.out:
+        np.savez(args.out, rho=rho.view(M, M, M).cpu().numpy(), per_step=np.array(per_step),
+                 counts=np.array(counts), L=W["L"], N=W["N"])
+    return {"full_run": args.full_run, "workload": f"{W['n_side']}^3 particles, L={W['L']:g} "
+            f"Mpc/h, mesh {W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, {n_steps} of "
+            f"{W['n_steps']} log KDK steps, lightcone, tree theta {W['theta_tree']}, precision "
+            f"form" + (", DZS" if dzs else ", full resolution"),
+            "wall_s": sum(per_step), "particles_final": st.n, "merged_nodes": merged,
+            "lightcone_records": records, "ring_overflow": overflow,
+            "torch_peak_GiB": peak / 2 ** 30,
+            "kernels_s": {c: round(ms * calls / 1e3, 3) for c, (ms, calls) in
+                          sorted(kern.items(), key=lambda kv: -kv[1][0] * kv[1][1]) if calls}}
+
+
+def compare_full(paths):
+    """M-W and M-LC from the .npz files of a DZS and a full-resolution run."""
+    import torch
+    a, b = (np.load(p) for p in paths)
+    L = float(a["L"])
+    rho_a, rho_b = torch.from_numpy(a["rho"]), torch.from_numpy(b["rho"])
+    k, pa, _ = power_spectrum(rho_a, L)
+    _, pb, _ = power_spectrum(rho_b, L)
+    ratio = pa / pb - 1.0
+    wa, wb = float(a["per_step"].sum()), float(b["per_step"].sum())
+    return {"dzs_s": wa, "std_s": wb, "M_W_dzs_over_std": wa / wb,
+            "M_LC_max_abs_P_ratio_minus_1": float(np.abs(ratio).max()),
+            "P_ratio_minus_1_by_bin": [round(float(v), 8) for v in ratio],
+            "k_bins_h_per_Mpc": [round(float(v), 5) for v in k],
+            "rms_pixel_density_difference":
+                float(torch.sqrt(torch.mean((rho_a - rho_b) ** 2)) / rho_b.mean()),
+            "lightcone_mass": [float(rho_a.sum()), float(rho_b.sum())],
+            "particles_final": [int(a["counts"][-1]), int(b["counts"][-1])],
+            "N": int(a["N"])}
+
+
 def _smooth(n):
     while n % 2 == 0:
         n //= 2
@@ -446,16 +535,18 @@ def lightcone_records(ring):
     return ints[:, 0], ints[:, 1].to(torch.float64), rec[:, 2:5]
 
 
-def lightcone_density(ring, L, M):
+def lightcone_density(ring, L, M, rho=None):
     """Mass (in particle masses) of the lightcone records deposited by cloud-in-cell onto an
-    M^3 mesh, each record at its crossing position wrapped into the box (observer at 0)."""
+    M^3 mesh, each record at its crossing position wrapped into the box (observer at 0);
+    added to `rho` (flat, M^3) when given."""
     import torch
     _, mult, d = lightcone_records(ring)
     u = torch.remainder(d, L) * (M / L)
     i0 = torch.floor(u)
     f = u - i0
     i0 = i0.to(torch.int64) % M
-    rho = torch.zeros(M ** 3, dtype=torch.float64, device=d.device)
+    if rho is None:
+        rho = torch.zeros(M ** 3, dtype=torch.float64, device=d.device)
     for cx in (0, 1):
         wx = f[:, 0] if cx else 1 - f[:, 0]
         ix = (i0[:, 0] + cx) % M
@@ -548,6 +639,12 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "for scaling HBM byte counters), then exit")
+    ap.add_argument("--full-run", choices=("dzs", "std"), default=None,
+                    help="with --workload c5: one whole run, DZS or full resolution, its "
+                         "lightcone density and timings saved to --out")
+    ap.add_argument("--out", default=None, help="output .npz of --full-run")
+    ap.add_argument("--compare", nargs=2, default=None, metavar=("DZS_NPZ", "STD_NPZ"),
+                    help="M-W and M-LC from two --full-run outputs (no GPU)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default=None,
                     help="fp64: plain form; fp32: FP32 pair, mesh and FFT arithmetic "
                          "(default: the workload's)")
@@ -556,6 +653,9 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.compare:
+        print(json.dumps(compare_full(args.compare)), flush=True)
+        return
     import torch
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -572,6 +672,9 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(run_ensemble(args, dz, torch, dzs_ics)), flush=True)
+        return
+    if args.workload == "c5" and args.full_run:
+        print(json.dumps(run_full(args, dz, torch, dzs_ics)), flush=True)
         return
     if args.workload == "c5":
         print(json.dumps(run_lean(args, dz, torch, dzs_ics)), flush=True)
