@@ -561,10 +561,10 @@ template <typename T> __device__ __forceinline__ T gsoft_inner(T r, T h) {
 }
 
 // One interaction-list entry in LDS: position (shifted to the image nearest the group; in
-// FP32 relative to the group centre), mass, spline support.
+// FP32 relative to the group centre), mass, spline support and its square.
 template <typename T> struct src_entry {
     T x, y, z, m;
-    T h, pad;
+    T h, h2;
 };
 
 template <typename T> struct split_coef;
@@ -576,6 +576,16 @@ template <> struct split_coef<float> {
     static constexpr int N = WALK_QF;
     static __device__ __forceinline__ float at(const walk_args &A, int k) { return A.qf[k]; }
 };
+
+// 1/sqrt: the FP32 form takes the hardware approximation (about 1 ulp; its inputs are far
+// from the denormal range), the plain form the correctly refined FP64 one.
+__device__ __forceinline__ double pair_rsqrt(double a) { return rsqrt(a); }
+__device__ __forceinline__ float pair_rsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
+// The larger of two non-negative squared supports (no NaN canonicalisation needed).
+__device__ __forceinline__ double pair_hmax(double a, double b) { return a > b ? a : b; }
+__device__ __forceinline__ float pair_hmax(float a, float b) {
+    return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
 
 // Separation of a list entry from the target (minimum image for wide groups).
 template <typename T, bool MINIMG>
@@ -589,54 +599,65 @@ __device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T
         dy = wmin_image(dy, L);
         dz = wmin_image(dz, L);
     }
-    return dx * dx + dy * dy + dz * dz;
+    return wfma(dx, dx, wfma(dy, dy, dz * dz));
 }
 
-// The lane's share of the list (entries s, s + P, s + 2P, ...) in two passes per block of 64
-// of its entries: a cheap pass marks the entries inside r_cut in a 64-bit mask, then the lane
-// evaluates only the marked pairs, in ascending order.  A list culled against the group's box
-// holds several times more entries than any one target's cutoff sphere; without the mask the
-// whole wave would step through the force arithmetic for every entry some lane accepts.
+// The lane's share of the list (entries s, s + P, s + 2P, ...) in two passes per block of 32
+// of its entries: a cheap pass shifts one acceptance bit per entry (inside r_cut, not the
+// target itself) into a 32-bit mask, first entry highest, then the lane evaluates only the
+// marked pairs in ascending order.  A list culled against the group's box holds several
+// times more entries than any one target's cutoff sphere; without the mask the whole wave
+// would step through the force arithmetic for every entry some lane accepts.  The caller
+// fills the P entries past the list with far-away sentinels, so the block bound is uniform.
+//
+// Pair force: m r_ij g_soft(r) S(r/r_s) with S = 1 - u^3 q(u^2), u = r/r_s; outside the
+// spline support g_soft = r^-3 and the product is r^-3 - r_s^-3 q, one fused operation.
 template <typename T, bool MINIMG>
 __device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W,
                                           const src_entry<T> *src, uint32_t nlist, uint32_t s,
-                                          uint32_t P, T xi, T yi, T zi, T hi, T &ax, T &ay,
-                                          T &az, uint32_t &n_pairs) {
-    const T rcut2 = T(W.rcut2), rs_inv = T(W.rs_inv), rs_inv2 = T(W.rs_inv2);
+                                          uint32_t P, T xi, T yi, T zi, T hi, T hi2, T &ax,
+                                          T &ay, T &az, uint32_t &n_pairs) {
+    const T rcut2 = T(W.rcut2), rs_inv2 = T(W.rs_inv2);
+    const T rs_inv3 = T(W.rs_inv * W.rs_inv2);
     const T t_scale = T(A.t_scale), L = T(W.L);
     constexpr int QN = split_coef<T>::N;
-    for (uint32_t base = s; base < nlist; base += 64u * P) {
-        uint64_t mask = 0;
-        for (uint32_t k = 0; k < 64u; ++k) {
-            const uint32_t j = base + k * P;
-            if (j >= nlist)
-                break;
+    // entries per lane: uniform, so the block loops run on the scalar unit
+    const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
+    for (uint32_t kb = 0; kb < n_max; kb += 32u) {
+        const src_entry<T> *blk = src + s + kb * P;
+        const uint32_t kmax =
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)(n_max - kb < 32u ? n_max - kb : 32u));
+        uint32_t mask = 0;
+        for (uint32_t k = 0; k < kmax; ++k) {
             T dx, dy, dz;
-            const T r2 = pair_sep<T, MINIMG>(src[j], xi, yi, zi, L, dx, dy, dz);
-            if (r2 < rcut2 && r2 > T(0.0))
-                mask |= 1ull << k;
+            const T r2 = pair_sep<T, MINIMG>(blk[k * P], xi, yi, zi, L, dx, dy, dz);
+            mask = mask + mask + ((r2 < rcut2 && r2 > T(0.0)) ? 1u : 0u);
         }
-        n_pairs += (uint32_t)__popcll(mask);
+        mask <<= 32u - kmax;
+        n_pairs += (uint32_t)__popc(mask);
         while (mask) {
-            const uint32_t k = (uint32_t)__builtin_ctzll(mask);
-            mask &= mask - 1ull;
-            const src_entry<T> &e = src[base + k * P];
+            const uint32_t k = (uint32_t)__builtin_clz(mask);
+            mask ^= 0x80000000u >> k;
+            const src_entry<T> &e = blk[k * P];
             T dx, dy, dz;
             const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
-            const T rinv = wrsqrt(r2);
+            const T rinv = pair_rsqrt(r2);
             const T w = r2 * rs_inv2;
             const T t = wfma(w, t_scale, T(-1.0));
             T q = split_coef<T>::at(A, QN - 1);
 #pragma unroll
             for (int c = QN - 2; c >= 0; --c)
                 q = wfma(q, t, split_coef<T>::at(A, c));
-            const T u = r2 * rinv * rs_inv;
-            const T S = T(1.0) - u * w * q;
-            const T h = wmax(e.h, hi);
-            T ker = rinv * rinv * rinv;
-            if (r2 < h * h)
-                ker = gsoft_inner(r2 * rinv, h);
-            const T f = e.m * ker * S;
+            const T rq = rs_inv3 * q;
+            T g;
+            if (r2 < pair_hmax(e.h2, hi2)) {
+                const T r = r2 * rinv;
+                const T ks = gsoft_inner(r, wmax(e.h, hi));
+                g = ks - ks * (r2 * r) * rq;
+            } else {
+                g = wfma(rinv * rinv, rinv, -rq);
+            }
+            const T f = e.m * g;
             ax = wfma(f, dx, ax);
             ay = wfma(f, dy, ay);
             az = wfma(f, dz, az);
@@ -648,7 +669,7 @@ template <typename T, bool CELLS, bool BATCH>
 __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     static_assert(!(CELLS && BATCH), "a batch walk starts at the box nodes");
     constexpr int KBL = BATCH ? DZS_BATCH_LEVELS : 0;  // tree levels above a box
-    __shared__ src_entry<T> src[WALK_LIST];
+    __shared__ src_entry<T> src[WALK_LIST + 64];
     __shared__ uint32_t q_first[64];
     __shared__ uint32_t q_pref[65];
     __shared__ double q_shift[3][64];
@@ -705,6 +726,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         const bool rel = sizeof(T) == 4;
         const double ox = rel ? gcx : 0.0, oy = rel ? gcy : 0.0, oz = rel ? gcz : 0.0;
         const T txi = T(xi - ox), tyi = T(yi - oy), tzi = T(zi - oz), thi = T(hi);
+        const T thi2 = thi * thi;
 
         T ax = T(0.0), ay = T(0.0), az = T(0.0);
         uint32_t nlist = 0;
@@ -712,11 +734,18 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         bool wide = false;
 
         auto flush = [&]() {
+            if (lane < P) {  // sentinels: far outside every cutoff, in any image
+                src_entry<T> &e = src[nlist + lane];
+                e.x = e.y = e.z = T(1e30);
+                e.m = e.h = e.h2 = T(0.0);
+            }
             __syncthreads();
             if (wide)
-                pair_loop<T, true>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
+                pair_loop<T, true>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
+                                   az, n_pairs);
             else
-                pair_loop<T, false>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, ax, ay, az, n_pairs);
+                pair_loop<T, false>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
+                                    az, n_pairs);
             nlist = 0;
             __syncthreads();
         };
@@ -862,7 +891,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                     src[slot].y = T(comy + shy - oy);
                     src[slot].z = T(comz + shz - oz);
                     src[slot].m = T(A.nd_mass[node]);
-                    src[slot].h = T(A.nd_hmax[node]);
+                    const T hn = T(A.nd_hmax[node]);
+                    src[slot].h = hn;
+                    src[slot].h2 = hn * hn;
                 }
                 nlist += nmono;
             }
@@ -923,7 +954,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                             e.y = T(ey_ - oy);
                             e.z = T(ez_ - oz);
                             e.m = T(W.m0 * md);
-                            e.h = T(W.h0 * cbrt(md));
+                            const T hj = T(W.h0 * cbrt(md));
+                            e.h = hj;
+                            e.h2 = hj * hj;
                         }
                         nlist += nk;
                     }
