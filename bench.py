@@ -382,6 +382,87 @@ def run_full(args, dz, torch, dzs_ics):
                           sorted(kern.items(), key=lambda kv: -kv[1][0] * kv[1][1]) if calls}}
 
 
+SWEEP = {  # parameter -> values; the fiducial setting is theta 0.1, b 5 lambda, l_max 4 lambda
+    "theta": (0.01, 0.03, 0.1, 0.2, 0.5, 1.0),
+    "alpha_dyn": (1e-4, 1e-3, 1e-2, 1e-1),
+    "b_over_lambda": (100.0, 10.0, 5.0, 2.0, 1.0, 0.0),
+    "lmax_over_lambda": (2, 4, 8, 32, 64),
+}
+
+
+def run_sweep(args, dz, torch, dzs_ics):
+    """The de-refinement parameters one at a time around the fiducial setting, on a small
+    box with the lightcone geometry of a large one: 128^3 particles, L = 8192 Mpc/h (64 Mpc/h
+    per particle), mesh 256^3, 100 log steps from z = 49 in the precision form; DZS starts
+    once R_lc + b < sqrt(3)/2 L (step 37).  Each run starts from the same initial state and
+    force; reported: N_fin / N_init, wall time against the full-resolution run, and the
+    lightcone comparison against it (64^3 density mesh of the records, drained every step)."""
+    import copy
+    W = workload(n_side=128, L=8192.0, ng=256, seed=20050540, n_steps=100, lmax_over_lambda=4)
+    W["prec"] = dz.DZS_FP32
+    N, lam = W["N"], W["lam"]
+    ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
+    box = dz.make_box(W["L"], W["m0"], W["eps0"])
+    ctx = dz.Context(N, W["ng"])
+    st0 = dz.State.from_host(ics)
+    base = make_params(dz, W, True)
+    sp0 = copy.deepcopy(base[0])
+    sp0.K1 = sp0.K2 = 0.0
+    sp0.lc.D = 0.0
+    sp0.do_lightcone = sp0.do_coarsen = 0
+    ctx.kdk_step(box, st0, sp0, None)
+    st = dz.State(N)
+    ring = dz.LCRing(N)
+    M = 64
+
+    def one(theta=0.1, alpha=None, b=5.0, lmax=4, dzs=True):
+        params = make_params(dz, W, dzs)
+        for sp in params:
+            sp.coarsen.b = b * lam
+            sp.coarsen.k_min = k_min_for(W["n_side"], lmax)
+            if alpha is None:
+                sp.coarsen.theta = theta
+            else:
+                sp.coarsen.criterion = dz.DZS_CRIT_DYNAMICAL
+                sp.coarsen.alpha_dyn = alpha
+        copy_state(st, st0)
+        rho = torch.zeros(M ** 3, dtype=torch.float64, device="cuda")
+        ring.reset()
+        torch.cuda.synchronize()
+        wall = 0.0
+        for sp in params:
+            t1 = time.perf_counter()
+            ctx.kdk_step(box, st, sp, ring)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t1
+            lightcone_density(ring, W["L"], M, rho)
+            ring.reset()
+            torch.cuda.synchronize()
+        return wall, st.n, rho.view(M, M, M)
+
+    one(dzs=False)   # warm-up of every kernel and allocation
+    t_std, _, rho_std = one(dzs=False)
+    k, p_std, _ = power_spectrum(rho_std, W["L"])
+    rows = []
+    for name, values in SWEEP.items():
+        for v in values:
+            kw = {"theta": dict(theta=v), "alpha_dyn": dict(alpha=v),
+                  "b_over_lambda": dict(b=v), "lmax_over_lambda": dict(lmax=v)}[name]
+            wall, n_fin, rho = one(**kw)
+            _, p, _ = power_spectrum(rho, W["L"])
+            rows.append({"parameter": name, "value": v, "n_fin_over_n_init": n_fin / N,
+                         "t_dzs_over_t_std": wall / t_std,
+                         "M_LC_max_abs_P_ratio_minus_1": float(np.abs(p / p_std - 1.0).max()),
+                         "rms_pixel_density_difference":
+                             float(torch.sqrt(torch.mean((rho - rho_std) ** 2)) / rho_std.mean())})
+            log(f"  {name} = {v}: N_fin/N_init {n_fin / N:.4f}, T/T_std {wall / t_std:.4f}")
+    ctx.close()
+    return {"sweep": "DZS parameters, one at a time around theta 0.1, b 5 lambda, l_max 4 lambda",
+            "workload": f"128^3 particles, L=8192 Mpc/h, mesh 256^3, Zel'dovich z=49 BBKS seed "
+                        f"{W['seed']}, 100 log KDK steps, lightcone, tree theta 0.5, precision form",
+            "std_wall_s": t_std, "rows": rows}
+
+
 def compare_full(paths):
     """M-W and M-LC from the .npz files of a DZS and a full-resolution run."""
     import torch
@@ -627,7 +708,7 @@ def force_error(g, ref):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(PRESETS), default="c2")
+    ap.add_argument("--workload", choices=sorted(PRESETS) + ["sweep"], default="c2")
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the whole run)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n-side", type=int, default=0,
@@ -672,6 +753,9 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(run_ensemble(args, dz, torch, dzs_ics)), flush=True)
+        return
+    if args.workload == "sweep":
+        print(json.dumps(run_sweep(args, dz, torch, dzs_ics)), flush=True)
         return
     if args.workload == "c5" and args.full_run:
         print(json.dumps(run_full(args, dz, torch, dzs_ics)), flush=True)

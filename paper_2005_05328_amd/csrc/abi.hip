@@ -558,16 +558,26 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
     DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &prm->lc, ring, prm->do_lightcone, 1, s));
     const bool can_merge = prm->do_coarsen &&
                            prm->coarsen.R_lc + prm->coarsen.b < 0.5 * sqrt(3.0) * box->L;
+    // the state in key order for the tree: after DZS it already is (the coarsening sorts by
+    // (key, id) and a merged particle stays in its cube's slot); only new keys are needed,
+    // with a full sort if rounding moved a centre of mass out of its cube
+    bool in_order = false;
     if (can_merge && st->n > 0) {
         if (prm->coarsen.criterion == DZS_CRIT_DYNAMICAL)  // g is the previous force here
             DZS_TRY(dzs_coarsen_amin(ctx, box, st, &prm->coarsen, s));
         DZS_TRY(sort_state(ctx, box, st, 1, 0, s));
         DZS_HIP(ctx, hipMemcpyAsync(ctx->dz_perm, ctx->idx, sizeof(uint32_t) * st->n,
                                     hipMemcpyDeviceToDevice, s));
+        const uint64_t n_in = st->n;
         DZS_TRY(dzs_coarsen_sorted(ctx, box, st, &prm->coarsen, nullptr, report, s));
+        if (st->n == n_in)
+            in_order = true;  // nothing merged: the sort's keys still hold
+        else
+            DZS_TRY(dzs_coarsen_rekey(ctx, box, st, &in_order, s));
     }
     if (st->n > 0) {
-        DZS_TRY(sort_state(ctx, box, st, 0, 0, s));
+        if (!in_order)
+            DZS_TRY(sort_state(ctx, box, st, 0, 0, s));
         DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
                                t.group_size, s));
         dzs_pm_params pm = prm->pm;

@@ -54,6 +54,18 @@ struct dz_level_args {
     uint32_t *nmult, *nid;
 };
 
+// Largest minimum-image |x - x_obs| along one axis over the cube [a, a + l), widened by a
+// margin far above the rounding of the keys and of the centre of mass.
+__device__ __forceinline__ double dz_axis_far(double a, double l, double xo, double L) {
+    const double m = 1e-9 * L;
+    const double u = a - m - xo, v = a + l + m - xo;
+    // the farthest offset, L/2 (mod L), lies inside [u, v]
+    if (ceil((u - 0.5 * L) / L) <= floor((v - 0.5 * L) / L))
+        return 0.5 * L;
+    const double wu = u - L * floor(u / L + 0.5), wv = v - L * floor(v / L + 0.5);
+    return fmax(fabs(wu), fabs(wv));
+}
+
 __global__ __launch_bounds__(DZ_THREADS) void k_dz_level(dz_level_args A) {
     const uint64_t i = (uint64_t)blockIdx.x * DZ_THREADS + threadIdx.x;
     if (i >= A.n || A.head[i] != DZ_NONE)
@@ -62,6 +74,27 @@ __global__ __launch_bounds__(DZ_THREADS) void k_dz_level(dz_level_args A) {
     const uint64_t pk = A.key[i] >> sh;
     if (i > 0 && (A.key[i - 1] >> sh) == pk)
         return;  // not the first member of its level-k cube
+    {
+        // A cube whose every point is too close to merge is skipped before its members are
+        // visited: this bound never excludes a cube the criterion would merge.
+        const double l = ldexp(A.L, -A.k);
+        const double fx = dz_axis_far((double)dzs_compact3(pk >> 2) * l, l, A.xo[0], A.L);
+        const double fy = dz_axis_far((double)dzs_compact3(pk >> 1) * l, l, A.xo[1], A.L);
+        const double fz = dz_axis_far((double)dzs_compact3(pk) * l, l, A.xo[2], A.L);
+        const double far2 = fx * fx + fy * fy + fz * fz;
+        if (A.crit == DZS_CRIT_GEOMETRIC) {
+            if (far2 * (1.0 + 1e-12) <= A.T2)
+                return;
+        } else {
+            const double Dmax = sqrt(far2) * (1.0 + 1e-12) - A.Rb;
+            if (!(Dmax > 0.0))
+                return;
+            const double amin = sqrt(__longlong_as_double((long long)*A.amin2));
+            const double D2 = Dmax * Dmax;
+            if ((A.Gm0 * 2.0) * A.lk2 >= (A.alpha * amin) * (D2 * D2) * (1.0 + 1e-9))
+                return;
+        }
+    }
     uint64_t e = i + 1;
     while (e < A.n && (A.key[e] >> sh) == pk)
         ++e;
@@ -172,6 +205,37 @@ dzs_status dzs_coarsen_amin(dzs_ctx *ctx, const dzs_box *box, const dzs_particle
                        box->L, prm->x_obs[0], prm->x_obs[1], prm->x_obs[2], prm->R_lc + prm->b,
                        slot);
     return dzs_check_launch(ctx, "dz_amin");
+}
+
+// After a merge the state stays in key order (a merged particle takes its cube's first slot
+// and its centre of mass lies in that cube), unless rounding put a centre of mass on the
+// cube's far face: flag any descent.
+__global__ __launch_bounds__(1) void k_dz_flag_clear(uint32_t *flag) { *flag = 0u; }
+
+__global__ __launch_bounds__(DZ_THREADS) void k_dz_unsorted(uint64_t n, const uint64_t *key,
+                                                           uint32_t *flag) {
+    const uint64_t i = (uint64_t)blockIdx.x * DZ_THREADS + threadIdx.x;
+    if (i + 1 < n && key[i] > key[i + 1])
+        atomicOr(flag, 1u);
+}
+
+dzs_status dzs_coarsen_rekey(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                             bool *sorted, hipStream_t s) {
+    *sorted = true;
+    if (p->n < 2)
+        return dzs_launch_keys(ctx, p->x, p->y, p->z, p->n, box->L, ctx->key, nullptr, s);
+    DZS_TRY(dzs_launch_keys(ctx, p->x, p->y, p->z, p->n, box->L, ctx->key, nullptr, s));
+    uint32_t *flag = ctx->d_small + DZS_SMALL_UNSORTED;
+    hipLaunchKernelGGL(k_dz_flag_clear, dim3(1), dim3(1), 0, s, flag);
+    DZS_TRY(dzs_check_launch(ctx, "dz_flag_clear"));
+    hipLaunchKernelGGL(k_dz_unsorted, dim3(blocks_for(p->n, DZ_THREADS)), dim3(DZ_THREADS), 0, s,
+                       p->n, (const uint64_t *)ctx->key, flag);
+    DZS_TRY(dzs_check_launch(ctx, "dz_unsorted"));
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + DZS_SMALL_UNSORTED, flag, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+    DZS_HIP(ctx, hipStreamSynchronize(s));
+    *sorted = ctx->h_small[DZS_SMALL_UNSORTED] == 0u;
+    return DZS_OK;
 }
 
 __global__ __launch_bounds__(DZ_THREADS) void k_dz_init(uint64_t n, uint32_t *head) {
@@ -301,6 +365,10 @@ dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p
         hipLaunchKernelGGL(k_dz_init, dim3(blocks), dim3(DZ_THREADS), 0, s, n, ctx->dz_head);
         DZS_TRY(dzs_check_launch(ctx, "dz_init"));
         for (int k = prm->k_min; k <= DZS_KEY_BITS; ++k) {
+            // geometric: no centre of mass lies beyond sqrt(3)/2 L (minimum image), so a level
+            // whose threshold exceeds it cannot merge anything
+            if (!dyn && T2[k] > 0.75 * box->L * box->L * (1.0 + 1e-9))
+                continue;
             A.k = k;
             A.T2 = T2[k];
             const double lk = ldexp(box->L, -k);

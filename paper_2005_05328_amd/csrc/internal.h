@@ -242,6 +242,17 @@ __device__ __forceinline__ uint64_t dzs_spread3(uint64_t v) {
     return v;
 }
 
+// gather every third bit of v (from bit 0) into the low 21 bits: the inverse of dzs_spread3
+__device__ __forceinline__ uint64_t dzs_compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v | (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v | (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v | (v >> 16)) & 0x1f00000000ffffull;
+    v = (v | (v >> 32)) & 0x1fffffull;
+    return v;
+}
+
 __device__ __forceinline__ uint64_t dzs_cell(double v, double s) {
     double t = floor(v * s);
     t = t < 0.0 ? 0.0 : t;
@@ -335,10 +346,16 @@ dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
 // d_small word slots: 8 the coarsening survivor count, 9 its head count, 16..17 the bits of
 // the dynamical criterion's min g.g (8-byte aligned).
 #define DZS_SMALL_AMIN 16
+// d_small word 20: set when the keys of a coarsened state are out of order
+#define DZS_SMALL_UNSORTED 20
 // Reduce the dynamical criterion's a_min^2 over the state (before any reordering that leaves
 // g behind) into d_small[DZS_SMALL_AMIN].
 dzs_status dzs_coarsen_amin(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                             const dzs_coarsen_params *prm, hipStream_t s);
+// Keys of the coarsened state into ctx->key and whether they are still ascending
+// (synchronises the stream).
+dzs_status dzs_coarsen_rekey(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                             bool *sorted, hipStream_t s);
 dzs_status dzs_coarsen_sorted(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p,
                               const dzs_coarsen_params *prm, uint32_t *group_of,
                               dzs_coarsen_report *report, hipStream_t s);
