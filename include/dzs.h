@@ -213,6 +213,44 @@ const char *dzs_last_error(const dzs_ctx *ctx);
  * Chebyshev series, by Gauss-Legendre quadrature.  Leaves every other field untouched. */
 dzs_status dzs_step_factors(double a0, double a1, double omega_m, dzs_step_params *out);
 
+/* ---- run control and forecast (host only, no device work) ----------------------------- */
+
+/* Halt conditions of a DZS run (Sec. 4.1.1): a run stops and writes its state, so that it can
+ * be continued with resources fitted to its shrinking particle count, when
+ *   - the workload balance (largest over mean work per task) exceeds max_balance (> 0), or
+ *   - R(t) = N(t) / N_init falls below min_ratio, or
+ *   - the wall time t has reached runtime_limit_s (> 0) and R, extrapolated linearly from the
+ *     previous sample (t_prev, ratio_prev), would fall below min_ratio within
+ *     restart_window_s of the restart.
+ * Returns the DZS_HALT_* reasons that hold (0: carry on).  Null arguments return 0. */
+#define DZS_HALT_BALANCE 1u
+#define DZS_HALT_RATIO 2u
+#define DZS_HALT_PREDICTED 4u
+typedef struct {
+    double max_balance;       /* <= 0: no balance condition */
+    double min_ratio;         /* R threshold */
+    double runtime_limit_s;   /* <= 0: no run-time limit */
+    double restart_window_s;  /* look-ahead after a restart */
+} dzs_halt_params;
+typedef struct {
+    double balance;           /* current workload balance */
+    double ratio, ratio_prev; /* R now and at the previous sample */
+    double t, t_prev;         /* wall time now and at the previous sample, s */
+} dzs_halt_state;
+uint32_t dzs_halt_check(const dzs_halt_params *prm, const dzs_halt_state *st);
+
+/* Forecast of the DZS speed-up T_STD / T_DZS (Sec. 4.2, eqs. 6-7): a run costs as much as
+ * without DZS until a_DZS, where the lightcone sphere holds half the box (4/3 pi chi^3 =
+ * L^3 / 2), and nothing after; the cost grows as a^r with r interpolated linearly in the
+ * particle mass m between 0.4 (the 8192 Mpc/h, 512^3 run) and 1 (the 512 Mpc/h, 512^3 run),
+ * extrapolated to finer masses and held at 0.4 for coarser ones: speedup = a_DZS^-r.
+ * L in Mpc/h; m in 1e10 Msun/h (flat LCDM, Omega_m = omega_m).  DZS_EINVAL if the sphere
+ * already holds half the box at a = 1e-4 or an argument is out of range. */
+typedef struct {
+    double a_dzs, r, speedup, particle_mass;
+} dzs_forecast;
+dzs_status dzs_forecast_speedup(double L, double n_part, double omega_m, dzs_forecast *out);
+
 /* ---- the gravity step ---------------------------------------------------------------- */
 
 /* DZS coarsening (Sec. 2.2).  Reorders the state in place to ascending (Morton key, id),

@@ -22,7 +22,8 @@ _lib = _abi.load()
 
 __all__ = ["Context", "State", "Box", "CoarsenParams", "PMParams", "TreeParams", "LCParams",
            "StepParams", "LCRing", "DZSError", "step_factors", "DZS_FP64", "DZS_FP32",
-           "DZS_CRIT_GEOMETRIC", "DZS_CRIT_DYNAMICAL", "lib"]
+           "DZS_CRIT_GEOMETRIC", "DZS_CRIT_DYNAMICAL", "halt_check", "forecast_speedup",
+           "lib"]
 
 
 def lib():
@@ -135,6 +136,23 @@ class LCRing:
 
 def make_box(L, m0, eps0, G=43.0091) -> Box:
     return Box(float(L), float(m0), float(eps0), float(G))
+
+
+def halt_check(balance, ratio, ratio_prev, t, t_prev, max_balance=0.0, min_ratio=0.0,
+               runtime_limit_s=0.0, restart_window_s=0.0) -> int:
+    """The DZS_HALT_* reasons to stop a run (0: carry on); see dzs_halt_check."""
+    prm = _abi.HaltParams(max_balance, min_ratio, runtime_limit_s, restart_window_s)
+    st = _abi.HaltState(balance, ratio, ratio_prev, t, t_prev)
+    return int(_lib.dzs_halt_check(C.byref(prm), C.byref(st)))
+
+
+def forecast_speedup(L: float, n_part: float, omega_m: float = 0.3) -> _abi.Forecast:
+    """a_DZS, r and the forecast speed-up T_STD / T_DZS; see dzs_forecast_speedup."""
+    out = _abi.Forecast()
+    rc = _lib.dzs_forecast_speedup(float(L), float(n_part), float(omega_m), C.byref(out))
+    if rc != 0:
+        raise DZSError("dzs_forecast_speedup", rc, "no a_DZS in [1e-4, 1] or bad argument")
+    return out
 
 
 def step_factors(a0: float, a1: float, omega_m: float = 0.3) -> StepParams:

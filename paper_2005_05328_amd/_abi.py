@@ -21,8 +21,25 @@ DZS_CRIT_GEOMETRIC, DZS_CRIT_DYNAMICAL = 0, 1
 EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_factors",
            "dzs_coarsen", "pm_force", "tree_force", "lightcone_emit", "kdk_step",
            "kdk_step_batch", "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
-           "dzs_sort_state", "dzs_counters", "dzs_timing")
+           "dzs_sort_state", "dzs_counters", "dzs_timing", "dzs_halt_check",
+           "dzs_forecast_speedup")
+DZS_HALT_BALANCE, DZS_HALT_RATIO, DZS_HALT_PREDICTED = 1, 2, 4
 DZS_BATCH_MAX = 512
+
+
+class HaltParams(C.Structure):
+    _fields_ = [("max_balance", C.c_double), ("min_ratio", C.c_double),
+                ("runtime_limit_s", C.c_double), ("restart_window_s", C.c_double)]
+
+
+class HaltState(C.Structure):
+    _fields_ = [("balance", C.c_double), ("ratio", C.c_double), ("ratio_prev", C.c_double),
+                ("t", C.c_double), ("t_prev", C.c_double)]
+
+
+class Forecast(C.Structure):
+    _fields_ = [("a_dzs", C.c_double), ("r", C.c_double), ("speedup", C.c_double),
+                ("particle_mass", C.c_double)]
 
 
 class Capacity(C.Structure):
@@ -108,6 +125,9 @@ def load():
     L.dzs_last_error.argtypes = [P]
     L.dzs_last_error.restype = C.c_char_p
     L.dzs_step_factors.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(StepParams)]
+    L.dzs_halt_check.argtypes = [C.POINTER(HaltParams), C.POINTER(HaltState)]
+    L.dzs_halt_check.restype = C.c_uint32
+    L.dzs_forecast_speedup.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(Forecast)]
     L.dzs_coarsen.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(CoarsenParams),
                               P, C.POINTER(CoarsenReport), P]
     L.pm_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(PMParams), P]
@@ -128,6 +148,6 @@ def load():
     for name in ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_step_factors", "dzs_coarsen",
                  "pm_force", "tree_force", "lightcone_emit", "kdk_step", "kdk_step_batch",
                  "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
-                 "dzs_sort_state", "dzs_counters", "dzs_timing"):
+                 "dzs_sort_state", "dzs_counters", "dzs_timing", "dzs_forecast_speedup"):
         getattr(L, name).restype = st
     return L

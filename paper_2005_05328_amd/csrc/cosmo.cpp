@@ -142,3 +142,56 @@ extern "C" dzs_status dzs_step_factors(double a0, double a1, double omega_m,
     cheb_fit([&](double a) { return drift(a0, a, omega_m); }, a0, a1, n, out->lc.cheb_drift);
     return DZS_OK;
 }
+
+// ---------------------------------------------------------------------------------------
+// Run control (Sec. 4.1.1) and the speed-up forecast (Sec. 4.2, eqs. 4-7): host logic only.
+// ---------------------------------------------------------------------------------------
+
+extern "C" uint32_t dzs_halt_check(const dzs_halt_params *prm, const dzs_halt_state *st) {
+    if (!prm || !st)
+        return 0u;
+    uint32_t why = 0u;
+    if (prm->max_balance > 0.0 && st->balance > prm->max_balance)
+        why |= DZS_HALT_BALANCE;
+    if (st->ratio < prm->min_ratio)
+        why |= DZS_HALT_RATIO;
+    if (prm->runtime_limit_s > 0.0 && st->t >= prm->runtime_limit_s && st->t > st->t_prev) {
+        // R(t) extrapolated linearly from the last two samples to the end of the window
+        // that follows the restart
+        const double slope = (st->ratio - st->ratio_prev) / (st->t - st->t_prev);
+        if (st->ratio + slope * prm->restart_window_s < prm->min_ratio)
+            why |= DZS_HALT_PREDICTED;
+    }
+    return why;
+}
+
+extern "C" dzs_status dzs_forecast_speedup(double L, double n_part, double omega_m,
+                                           dzs_forecast *out) {
+    if (!out || !(L > 0.0) || !(n_part >= 1.0) || !(omega_m > 0.0) || !(omega_m <= 1.0))
+        return DZS_EINVAL;
+    // particle mass (1e10 Msun/h) from the critical density 2.775e11 h^2 Msun / Mpc^3
+    const double rho_crit = 27.75366;
+    auto mass = [&](double Lb, double n) { return omega_m * rho_crit * Lb * Lb * Lb / n; };
+    const double m = mass(L, n_part);
+    const double m_small = mass(512.0, 512.0 * 512.0 * 512.0);
+    const double m_large = mass(8192.0, 512.0 * 512.0 * 512.0);
+    const double r_lin = 0.4 + (1.0 - 0.4) / (m_small - m_large) * (m - m_large);
+    const double r = r_lin > 0.4 ? r_lin : 0.4;
+    // a_DZS: the lightcone sphere holds half the box volume, 4/3 pi chi^3 = L^3 / 2
+    const double R = cbrt(3.0 / (8.0 * 3.14159265358979323846)) * L;
+    double lo = 1e-4, hi = 1.0;
+    if (!(chi(lo, omega_m) > R))
+        return DZS_EINVAL;  // the sphere encloses half the box from the start
+    for (int it = 0; it < 200 && hi - lo > 1e-15; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (chi(mid, omega_m) > R)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    out->a_dzs = 0.5 * (lo + hi);
+    out->r = r;
+    out->speedup = pow(out->a_dzs, -r);
+    out->particle_mass = m;
+    return DZS_OK;
+}
