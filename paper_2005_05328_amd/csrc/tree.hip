@@ -1161,7 +1161,7 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.key = (const uint64_t *)ctx->key;
     A.boxes = boxes;
     int K = 0;
-    if (prm->theta <= 1.0 && prm->precision == DZS_FP32 && !boxes)
+    if (prm->theta <= 1.0 && !boxes)
         while (K < DZS_CELL_K_MAX && ldexp(box->L, -(K + 1)) >= prm->r_cut)
             ++K;
     A.cell_K = K;
@@ -1191,8 +1191,6 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     DZS_TRY(dzs_check_launch(ctx, "walk_counter_clear"));
     {
         dzs_timed t(ctx, KC_TREE_WALK, s);
-        // the start-cell variant carries more scalar state; in FP64 its register pressure
-        // costs more than the shorter traversal saves, so the plain form starts at the root
         if (boxes && fp32)
             hipLaunchKernelGGL((k_tree_walk<float, false, true>), dim3(slots), dim3(64), 0, s, A);
         else if (boxes)
@@ -1201,6 +1199,8 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
             hipLaunchKernelGGL((k_tree_walk<float, true, false>), dim3(slots), dim3(64), 0, s, A);
         else if (fp32)
             hipLaunchKernelGGL((k_tree_walk<float, false, false>), dim3(slots), dim3(64), 0, s, A);
+        else if (K > 0)
+            hipLaunchKernelGGL((k_tree_walk<double, true, false>), dim3(slots), dim3(64), 0, s, A);
         else
             hipLaunchKernelGGL((k_tree_walk<double, false, false>), dim3(slots), dim3(64), 0, s, A);
         DZS_TRY(dzs_check_launch(ctx, "tree_walk"));
