@@ -314,6 +314,9 @@ def run_lean(args, dz, torch, dzs_ics):
     }
 
 
+FULL_NSIDE = 64   # sky pixels of ~0.9 deg for the 1024^3 runs
+
+
 def run_full(args, dz, torch, dzs_ics):
     """One whole run of the 1024^3 configuration, DZS (`--full-run dzs`) or full resolution
     (`--full-run std`), in the lean memory plan.  Each step's lightcone records are drained
@@ -346,6 +349,8 @@ def run_full(args, dz, torch, dzs_ics):
     ring.reset()
     M = 128
     rho = torch.zeros(M ** 3, dtype=torch.float64, device="cuda")
+    from paper_2005_05328_amd import skymaps
+    sky = torch.zeros(12 * FULL_NSIDE ** 2, dtype=torch.float64, device="cuda")
     free, total = torch.cuda.mem_get_info()
     log(f"resident: {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f}")
     torch.cuda.synchronize()
@@ -362,20 +367,27 @@ def run_full(args, dz, torch, dzs_ics):
         overflow = overflow or bool(ring.overflow.item())
         records += min(nrec, ring.capacity)
         lightcone_density(ring, W["L"], M, rho)
+        _, mult_r, d_r = lightcone_records(ring)
+        skymaps.sky_map(d_r, mult_r, FULL_NSIDE, sky)
         ring.reset()
         torch.cuda.synchronize()   # the drain must not run into the next step's timing
         log(f"  step {s_ + 1}/{n_steps}: {per_step[-1]:.3f} s, N = {st.n}, lightcone {nrec}")
     kern = ctx.timing(enable=False, reset=True)
     peak = torch.cuda.max_memory_allocated()
+    profile = mean_mass_by_distance(st, W["L"])
     ctx.close()
     if args.out:
         np.savez(args.out, rho=rho.view(M, M, M).cpu().numpy(), per_step=np.array(per_step),
-                 counts=np.array(counts), L=W["L"], N=W["N"])
+                 counts=np.array(counts), L=W["L"], N=W["N"], sky=sky.cpu().numpy(),
+                 mean_mult=np.array([v if v is not None else np.nan
+                                     for v in profile["mean_multiplicity"]]),
+                 shell_r=np.array(profile["shell_outer_radius"]))
     return {"full_run": args.full_run, "workload": f"{W['n_side']}^3 particles, L={W['L']:g} "
             f"Mpc/h, mesh {W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, {n_steps} of "
             f"{W['n_steps']} log KDK steps, lightcone, tree theta {W['theta_tree']}, precision "
             f"form" + (", DZS" if dzs else ", full resolution"),
             "wall_s": sum(per_step), "particles_final": st.n, "merged_nodes": merged,
+            "mean_mass_by_distance": profile,
             "lightcone_records": records, "ring_overflow": overflow,
             "torch_peak_GiB": peak / 2 ** 30,
             "kernels_s": {c: round(ms * calls / 1e3, 3) for c, (ms, calls) in
@@ -473,7 +485,11 @@ def compare_full(paths):
     _, pb, _ = power_spectrum(rho_b, L)
     ratio = pa / pb - 1.0
     wa, wb = float(a["per_step"].sum()), float(b["per_step"].sum())
-    return {"dzs_s": wa, "std_s": wb, "M_W_dzs_over_std": wa / wb,
+    sky = None
+    if "sky" in a.files and "sky" in b.files:
+        from paper_2005_05328_amd import skymaps
+        sky = skymaps.compare_maps(a["sky"], b["sky"], FULL_NSIDE, SKY_LMAX)
+    return {"dzs_s": wa, "std_s": wb, "M_W_dzs_over_std": wa / wb, "sky_map": sky,
             "M_LC_max_abs_P_ratio_minus_1": float(np.abs(ratio).max()),
             "P_ratio_minus_1_by_bin": [round(float(v), 8) for v in ratio],
             "k_bins_h_per_Mpc": [round(float(v), 5) for v in k],
@@ -666,6 +682,30 @@ def power_spectrum(rho, L, n_bins=16):
     return kc[keep].cpu().numpy(), (p[keep] / c[keep]).cpu().numpy(), c[keep].cpu().numpy()
 
 
+SKY_NSIDE, SKY_LMAX = 32, 48   # equal-area sky pixels of ~1.8 deg, C_l to l = 48
+
+
+def mean_mass_by_distance(st, L, x_obs=(0.0, 0.0, 0.0), n_bins=16):
+    """Mean multiplicity of the particles in shells of minimum-image distance from the
+    observer (the paper's mean particle mass against d_obs), out to sqrt(3)/2 L."""
+    import torch
+    n = st.n
+    d2 = torch.zeros(n, dtype=torch.float64, device=st.x.device)
+    for k, xo in zip(("x", "y", "z"), x_obs):
+        dd = getattr(st, k)[:n] - xo
+        dd = dd - L * torch.floor(dd / L + 0.5)
+        d2 += dd * dd
+    edges = np.linspace(0.0, 0.5 * math.sqrt(3.0) * L, n_bins + 1)
+    idx = torch.clamp((torch.sqrt(d2) / edges[1]).to(torch.int64), 0, n_bins - 1)
+    mult = st.mult[:n].to(torch.float64)
+    cnt = torch.zeros(n_bins, dtype=torch.float64, device=d2.device).index_add_(
+        0, idx, torch.ones_like(mult))
+    mass = torch.zeros(n_bins, dtype=torch.float64, device=d2.device).index_add_(0, idx, mult)
+    c, m = cnt.cpu().numpy(), mass.cpu().numpy()
+    return {"shell_outer_radius": [round(float(v), 3) for v in edges[1:]],
+            "mean_multiplicity": [round(float(a / b), 4) if b else None for a, b in zip(m, c)]}
+
+
 def compare_lightcones(ring_a, rho_a, ring_b, rho_b, L, eps0):
     """M-LC (max |P_a/P_b - 1| over the bins), rms pixel density difference, and the
     displacement percentiles of records present in both runs, in units of eps0."""
@@ -685,7 +725,17 @@ def compare_lightcones(ring_a, rho_a, ring_b, rho_b, L, eps0):
     r = (torch.sqrt((dx ** 2).sum(1)) / eps0).cpu().numpy()
     pct = {f"p{q}": float(np.percentile(r, q)) for q in (50, 99, 99.9)} if r.size else {}
     pct["max"] = float(r.max()) if r.size else None
+    # the paper's accuracy statements use the softening length h = 2.8 eps
+    frac_h = ({f"over_{t}h": float((r > 2.8 * t).mean()) for t in (0.01, 0.1, 1, 8)}
+              if r.size else {})
+    from paper_2005_05328_amd import skymaps
+    _, ma, _ = lightcone_records(ring_a)
+    _, mb, _ = lightcone_records(ring_b)
+    sky_a = skymaps.sky_map(da, ma, SKY_NSIDE)
+    sky_b = skymaps.sky_map(db, mb, SKY_NSIDE)
+    sky = skymaps.compare_maps(sky_a.cpu().numpy(), sky_b.cpu().numpy(), SKY_NSIDE, SKY_LMAX)
     return {"M_LC_max_abs_P_ratio_minus_1": float(np.abs(ratio).max()),
+            "sky_map": sky, "displaced_fraction": frac_h,
             "P_ratio_minus_1_by_bin": [round(float(v), 8) for v in ratio],
             "k_bins_h_per_Mpc": [round(float(v), 5) for v in k],
             "rms_pixel_density_difference": rms,
@@ -835,6 +885,7 @@ def main():
     twin = None
     if twin_kind:
         final_main = {k: getattr(st, k)[: st.n].clone() for k in ("x", "y", "z", "px", "py", "pz")}
+        mass_profile = mean_mass_by_distance(st, W["L"])
         rho_main = lightcone_density(ring, W["L"], M)
         log(f"timed twin ({'full resolution' if twin_kind == 'dzs' else 'FP64 plain form'})")
         t_twin, merged_twin = run(params_twin, K, True, g0_twin, ring_twin)
@@ -846,7 +897,7 @@ def main():
             twin = {"kind": "DZS vs full resolution", "std_s": t_twin, "dzs_s": t_main,
                     "dzs_over_std": t_main / t_twin, "twins_bitwise_identical": bool(same),
                     "merged_nodes": merged, "particles_final": [n_final, st.n],
-                    "lightcone": lc}
+                    "mean_mass_by_distance": mass_profile, "lightcone": lc}
         else:
             del final_main
             log("forces on the final plain-form state in both forms")
