@@ -613,12 +613,50 @@ def cpu_baseline(W, ics, box_o, n_steps=8):
                                       [0.0, 0.0, 0.0])
     t = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         None)
+    except OSError:
+        pass
     return {"value": W["N"] * n_steps / t, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": (f"the oracle's FP64 kick-drift-kick step (full PM {W['ng']}^3, direct-sum "
                        f"short range for all {W['N']} particles, lightcone test) over the first "
                        f"{n_steps} of the {W['n_steps']} steps (z = 49 to "
                        f"{1 / a[n_steps] - 1:.1f}), {t:.1f} s; OpenMP short range, "
                        f"single-threaded numpy FFT; the GPU figure averages all timed steps")}
+
+
+def force_rate(ctx, box, st, W, dz, torch, reps=10, warm=3):
+    """M-F: particle force updates per second of one full force evaluation (PM, then the
+    tree: keys, sort, build, walk) on the current state, median of `reps` HIP-event-timed
+    calls after `warm` warm-ups; also the tree-only and PM-only times."""
+    pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, 0)
+    tp = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"], W["group"], W["prec"], 1)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    calls = {"force": lambda: (ctx.pm_force(box, st, pm), ctx.tree_force(box, st, tp)),
+             "pm": lambda: ctx.pm_force(box, st, pm),
+             "tree": lambda: ctx.tree_force(box, st, tp)}
+    med = {}
+    for name, fn in calls.items():
+        for _ in range(warm):
+            fn()
+        med[name] = float(np.median([timed(fn) for _ in range(reps)]))
+    n = st.n
+    return {"M_F_force_updates_per_s": n / (med["force"] * 1e-3), "force_ms": med["force"],
+            "tree_force_updates_per_s": n / (med["tree"] * 1e-3), "tree_force_ms": med["tree"],
+            "pm_force_ms": med["pm"], "particles": n,
+            "method": f"median of {reps} after {warm} warm-ups, HIP events, final state"}
 
 
 # ---- twin-run diagnostics (measurement only: they run after the timed region) -------------
@@ -765,6 +803,8 @@ def main():
                     help="particles per side (box and mesh scaled with it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-twin", action="store_true")
+    ap.add_argument("--no-force-rate", action="store_true",
+                    help="skip the force-only rate (M-F) measured after the run")
     ap.add_argument("--group", type=int, default=0, help="targets per wave group (power of 2)")
     ap.add_argument("--leaf", type=int, default=0, help="particles per tree leaf")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -952,6 +992,7 @@ def main():
         box_o = oracle.Box(L=W["L"], m0=W["m0"], eps0=W["eps0"])
         cpu = cpu_baseline(W, ics, box_o)
 
+    mf = force_rate(ctx, box, st, W, dz, torch) if not args.no_force_rate else None
     ms_per_step = 1e3 * t_main / K
     out = {
         "metric": METRIC, "value": N * K / t_main, "unit": UNIT, "n_gpus": 1, "steps": K,
@@ -968,6 +1009,7 @@ def main():
                    "preset": args.workload, "particles": N, "mesh": W["ng"], "box": W["L"],
                    "parallelism": "1 GPU"},
         "roofline": roofline, "hbm_kernels": hbm, "cpu_baseline": cpu, "twin": twin,
+        "force_rate": mf,
         "pair_interactions_per_step": pairs / K, "lightcone_records": n_records,
         "particles_final": n_final,
         "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
