@@ -132,9 +132,20 @@ typedef struct {
 } dzs_pm_params;
 
 /* Tree (short-range) parameters: g_i = -G sum m_j r_ij g_soft(r_ij, h_ij) S(r_ij/r_s) over
- * sources closer than r_cut, S(u) = erfc(u/2) + u/sqrt(pi) exp(-u^2/4); nodes whose side l
- * satisfies l < theta * d (d = distance from the target group's bounding box to the node
- * centre of mass) act as monopoles.  theta = 0 opens every node (exact direct sum). */
+ * sources closer than r_cut, S(u) = erfc(u/2) + u/sqrt(pi) exp(-u^2/4).  Opening criteria
+ * (Sec. 2.1 and 2.2.1, eqs. 1 and 2), with d the distance from the target group's bounding
+ * box to the node's centre of mass:
+ *  - geometric: a node of side l acts as a monopole when l < theta * d; theta = 0 opens
+ *    every node (exact direct sum);
+ *  - relative: a node of mass M acts as a monopole when G M l^2 < alpha_open a_min d^4,
+ *    a_min the smallest |g| the group's targets held before the call (their previous
+ *    accelerations; a target with g = 0 makes its group open every node).  kdk_step reads
+ *    the accelerations the state holds on entry; a step whose coarsening merged particles
+ *    (no previous acceleration for them) falls back to the geometric criterion.
+ * With either criterion, when theta <= 1 (geometric) or always (relative) the walk starts at
+ * the nodes of the cells at least r_cut wide, so nodes above them are always opened. */
+#define DZS_OPEN_GEOMETRIC 0
+#define DZS_OPEN_RELATIVE 1
 typedef struct {
     double r_s, r_cut;   /* split scale and cutoff (r_cut < L/2, r_cut <= 5 r_s) */
     double theta;        /* opening angle, >= 0 */
@@ -147,6 +158,9 @@ typedef struct {
                             dropped, a jump of G m S(r_cut/r_s)/r_cut^2 in that target's
                             force) */
     int32_t accumulate;  /* 0: g = g_short, 1: g += g_short */
+    int32_t opening;     /* DZS_OPEN_GEOMETRIC or DZS_OPEN_RELATIVE */
+    int32_t reserved;
+    double alpha_open;   /* relative criterion's accuracy parameter (>= 0) */
 } dzs_tree_params;
 
 /* Lightcone crossing over one drift a0 -> a1 (positions at a0, momenta constant).
@@ -201,8 +215,8 @@ typedef struct {
  * 117 bytes per particle (keys and sort indices 24; one arena of 89 shared by the tree, with
  * node capacity max_particles/2 + 4096, and the DZS coarsening buffers; group starts 4) plus
  * the meshes (32 bytes per cell, 12 with DZS_CAP_FP32_MESHES); tree_force adds 52 bytes per
- * particle of sorted copies at its first call.  Returns DZS_ENOMEM if the device memory does
- * not suffice. */
+ * particle of sorted copies at its first call, and the relative opening criterion 4 bytes
+ * per particle at its first use.  Returns DZS_ENOMEM if the device memory does not suffice. */
 dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap);
 dzs_status dzs_ctx_destroy(dzs_ctx *ctx);
 /* Text of the context's last failure ("" if none); valid until the next call. */

@@ -16,6 +16,7 @@ DZS_CHEB_MAX = 24
 DZS_FP64, DZS_FP32 = 0, 1
 DZS_CAP_FP32_MESHES = 1
 DZS_CRIT_GEOMETRIC, DZS_CRIT_DYNAMICAL = 0, 1
+DZS_OPEN_GEOMETRIC, DZS_OPEN_RELATIVE = 0, 1
 
 # every entry point include/dzs.h declares
 EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_factors",
@@ -76,7 +77,8 @@ class PMParams(C.Structure):
 class TreeParams(C.Structure):
     _fields_ = [("r_s", C.c_double), ("r_cut", C.c_double), ("theta", C.c_double),
                 ("leaf_size", C.c_int32), ("group_size", C.c_int32), ("precision", C.c_int32),
-                ("accumulate", C.c_int32)]
+                ("accumulate", C.c_int32), ("opening", C.c_int32), ("reserved", C.c_int32),
+                ("alpha_open", C.c_double)]
 
 
 class LCParams(C.Structure):

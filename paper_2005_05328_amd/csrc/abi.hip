@@ -132,7 +132,7 @@ static dzs_status alloc(dzs_ctx *ctx, T **p, uint64_t count) {
 
 static void release(dzs_ctx *ctx) {
     void *ptrs[] = {ctx->key, ctx->key_alt, ctx->idx, ctx->idx_alt, ctx->hist, ctx->hist_scan,
-                    ctx->scan_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult,
+                    ctx->scan_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult, ctx->aold,
                     ctx->sgx, ctx->sgy, ctx->sgz, ctx->arena, ctx->bstate, ctx->grp_first,
                     ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl,
                     ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members,
@@ -362,6 +362,11 @@ static dzs_status check_tree(dzs_ctx *ctx, const dzs_box *box, const dzs_tree_pa
         return dzs_fail(ctx, DZS_EINVAL, "tree: r_cut must not exceed 5 r_s");
     if (t->precision != DZS_FP64 && t->precision != DZS_FP32)
         return dzs_fail(ctx, DZS_EINVAL, "tree: precision must be DZS_FP64 or DZS_FP32");
+    if (t->opening != DZS_OPEN_GEOMETRIC && t->opening != DZS_OPEN_RELATIVE)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: unknown opening criterion %d", t->opening);
+    if (t->opening == DZS_OPEN_RELATIVE && !(t->alpha_open >= 0.0 && t->alpha_open < HUGE_VAL))
+        return dzs_fail(ctx, DZS_EINVAL, "tree: the relative criterion needs a finite "
+                        "alpha_open >= 0");
     return DZS_OK;
 }
 
@@ -478,6 +483,13 @@ extern "C" dzs_status pm_force(dzs_ctx *ctx, const dzs_box *box, const dzs_parti
     return dzs_pm_run(ctx, box, p, prm, (hipStream_t)stream);
 }
 
+// |g| buffer of the relative opening criterion, allocated at its first use (4 B/particle)
+static dzs_status alloc_aold(dzs_ctx *ctx) {
+    if (!ctx->aold)
+        DZS_TRY(alloc(ctx, &ctx->aold, ctx->cap_n));
+    return DZS_OK;
+}
+
 extern "C" dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                                  const dzs_tree_params *prm, void *stream) {
     DZS_TRY(check_common(ctx, box, p));
@@ -508,12 +520,19 @@ extern "C" dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_par
         DZS_TRY(dzs_gather_f64(ctx, p->z, ctx->idx, ctx->sz, n, s));
         DZS_TRY(dzs_gather_u32(ctx, p->mult, ctx->idx, ctx->smult, n, s));
     }
+    const float *aold = nullptr;
+    if (t.opening == DZS_OPEN_RELATIVE) {
+        // the targets' |g| on entry, in tree order
+        DZS_TRY(alloc_aold(ctx));
+        DZS_TRY(dzs_launch_gnorm(ctx, n, p->gx, p->gy, p->gz, ctx->idx, ctx->aold, s));
+        aold = ctx->aold;
+    }
     DZS_TRY(dzs_tree_build(ctx, box, n, ctx->sx, ctx->sy, ctx->sz, ctx->smult, t.leaf_size,
                            t.group_size, s));
     dzs_tree_params tw = t;
     tw.accumulate = 0;
     DZS_TRY(dzs_tree_walk(ctx, box, n, ctx->sx, ctx->sy, ctx->sz, ctx->smult, ctx->sgx, ctx->sgy,
-                          ctx->sgz, &tw, s));
+                          ctx->sgz, &tw, s, aold));
     {
         dzs_timed tm(ctx, KC_PERMUTE, s);
         DZS_TRY(dzs_scatter_add_f64(ctx, ctx->sgx, ctx->idx, p->gx, n, t.accumulate, s));
@@ -554,6 +573,14 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
     if (report)
         *report = dzs_coarsen_report{st->n, st->n, 0, NAN};
 
+    // relative opening: the accelerations held on entry, carried through every reordering;
+    // lost (geometric fallback) when the coarsening merges particles
+    const bool relative = t.opening == DZS_OPEN_RELATIVE && st->n > 0;
+    bool aold_ok = relative;
+    if (relative) {
+        DZS_TRY(alloc_aold(ctx));
+        DZS_TRY(dzs_launch_gnorm(ctx, st->n, st->gx, st->gy, st->gz, nullptr, ctx->aold, s));
+    }
     DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s));
     DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &prm->lc, ring, prm->do_lightcone, 1, s));
     const bool can_merge = prm->do_coarsen &&
@@ -566,18 +593,25 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
         if (prm->coarsen.criterion == DZS_CRIT_DYNAMICAL)  // g is the previous force here
             DZS_TRY(dzs_coarsen_amin(ctx, box, st, &prm->coarsen, s));
         DZS_TRY(sort_state(ctx, box, st, 1, 0, s));
+        if (aold_ok)
+            DZS_TRY(dzs_permute_f32(ctx, ctx->aold, ctx->idx, st->n, s));
         DZS_HIP(ctx, hipMemcpyAsync(ctx->dz_perm, ctx->idx, sizeof(uint32_t) * st->n,
                                     hipMemcpyDeviceToDevice, s));
         const uint64_t n_in = st->n;
         DZS_TRY(dzs_coarsen_sorted(ctx, box, st, &prm->coarsen, nullptr, report, s));
-        if (st->n == n_in)
+        if (st->n == n_in) {
             in_order = true;  // nothing merged: the sort's keys still hold
-        else
+        } else {
+            aold_ok = false;
             DZS_TRY(dzs_coarsen_rekey(ctx, box, st, &in_order, s));
+        }
     }
     if (st->n > 0) {
-        if (!in_order)
+        if (!in_order) {
             DZS_TRY(sort_state(ctx, box, st, 0, 0, s));
+            if (aold_ok)
+                DZS_TRY(dzs_permute_f32(ctx, ctx->aold, ctx->idx, st->n, s));
+        }
         DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
                                t.group_size, s));
         dzs_pm_params pm = prm->pm;
@@ -585,7 +619,7 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
         DZS_TRY(dzs_pm_run(ctx, box, st, &pm, s));
         t.accumulate = 1;
         DZS_TRY(dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx, st->gy,
-                              st->gz, &t, s));
+                              st->gz, &t, s, aold_ok ? ctx->aold : nullptr));
         DZS_TRY(dzs_launch_kick(ctx, st, prm->K2, s));
     }
     return DZS_OK;
@@ -617,6 +651,8 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     if (prm->do_coarsen)
         return dzs_fail(ctx, DZS_EINVAL, "batch: coarsening runs per box (dzs_coarsen), not in "
                         "the batched step");
+    if (prm->tree.opening != DZS_OPEN_GEOMETRIC)
+        return dzs_fail(ctx, DZS_EINVAL, "batch: only the geometric opening criterion");
     dzs_tree_params t, t_in = prm->tree;
     t_in.r_s = batch->r_s[0];
     t_in.r_cut = batch->r_cut[0];

@@ -104,6 +104,7 @@ struct dzs_ctx {
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
     uint32_t *smult = nullptr;
     double *sgx = nullptr, *sgy = nullptr, *sgz = nullptr;
+    float *aold = nullptr;  // |g| on entry, for the relative opening criterion (lazy)
 
     // ---- octree (structure of arrays)
     uint64_t cap_nodes = 0;
@@ -310,6 +311,10 @@ dzs_status dzs_permute_state(dzs_ctx *ctx, dzs_particles *p, const uint32_t *per
                              int with_g, hipStream_t s);
 dzs_status dzs_gather_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm, double *dst,
                           uint64_t n, hipStream_t s);
+dzs_status dzs_launch_gnorm(dzs_ctx *ctx, uint64_t n, const double *gx, const double *gy,
+                            const double *gz, const uint32_t *perm, float *out, hipStream_t s);
+dzs_status dzs_permute_f32(dzs_ctx *ctx, float *arr, const uint32_t *perm, uint64_t n,
+                           hipStream_t s);
 dzs_status dzs_gather_u32(dzs_ctx *ctx, const uint32_t *src, const uint32_t *perm,
                           uint32_t *dst, uint64_t n, hipStream_t s);
 dzs_status dzs_scatter_add_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm,
@@ -323,16 +328,19 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const
                              const double *y, const double *z, const uint32_t *mult,
                              int leaf_size, int group_size, int KB, const dzs_bbox *boxes,
                              hipStream_t s);
+// aold (device, n floats, tree order): the targets' previous |g| for the relative opening
+// criterion; nullptr makes a relative-criterion call use the geometric one.
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
-                         double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s);
+                         double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s,
+                         const float *aold = nullptr);
 
 dzs_status dzs_batch_roots(dzs_ctx *ctx, dzs_bbox *boxes, hipStream_t s);
 dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s);
 dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                             const double *y, const double *z, const uint32_t *mult, double *gx,
                             double *gy, double *gz, const dzs_tree_params *prm,
-                            const dzs_bbox *boxes, hipStream_t s);
+                            const dzs_bbox *boxes, hipStream_t s, const float *aold = nullptr);
 
 // pm.hip
 bool dzs_pm_mesh_ok(int ng);

@@ -308,6 +308,36 @@ dzs_status dzs_permute_state(dzs_ctx *ctx, dzs_particles *p, const uint32_t *per
     return DZS_OK;
 }
 
+// |g| of each particle (slot i takes particle perm[i] when perm is given), in FP32: the
+// relative opening criterion's previous accelerations.
+__global__ __launch_bounds__(PT_THREADS) void k_gnorm(uint64_t n, const double *__restrict__ gx,
+                                                      const double *__restrict__ gy,
+                                                      const double *__restrict__ gz,
+                                                      const uint32_t *__restrict__ perm,
+                                                      float *__restrict__ out) {
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint64_t j = perm ? perm[i] : i;
+    out[i] = (float)sqrt(gx[j] * gx[j] + gy[j] * gy[j] + gz[j] * gz[j]);
+}
+
+dzs_status dzs_launch_gnorm(dzs_ctx *ctx, uint64_t n, const double *gx, const double *gy,
+                            const double *gz, const uint32_t *perm, float *out, hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_gnorm, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n, gx,
+                       gy, gz, perm, out);
+    return dzs_check_launch(ctx, "gnorm");
+}
+
+dzs_status dzs_permute_f32(dzs_ctx *ctx, float *arr, const uint32_t *perm, uint64_t n,
+                           hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    return permute_one<float>(ctx, arr, perm, n, s);
+}
+
 dzs_status dzs_gather_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm, double *dst,
                           uint64_t n, hipStream_t s) {
     if (n == 0)

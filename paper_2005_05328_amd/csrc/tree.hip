@@ -470,6 +470,10 @@ struct walk_args {
     // a batch: the box of a group is its first particle's key prefix
     const uint64_t *key;
     const dzs_bbox *boxes;
+    // relative opening criterion: previous |g| per target (nullptr: geometric) and
+    // alpha_open / G (the walk's masses and distances carry no G)
+    const float *aold;
+    double alpha_g;
 };
 
 // Geometry and constants of the box a group lives in.
@@ -722,6 +726,14 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         const double gcx = 0.5 * (mnx + mxx), gcy = 0.5 * (mny + mxy), gcz = 0.5 * (mnz + mxz);
         const double ghx = 0.5 * (mxx - mnx), ghy = 0.5 * (mxy - mny), ghz = 0.5 * (mxz - mnz);
         const double ghmax = fmax(ghx, fmax(ghy, ghz));
+        // relative criterion: alpha / G times the smallest previous |g| of the group
+        double alpha_a = 0.0;
+        if (A.aold) {
+            double a = valid ? (double)A.aold[i] : __builtin_inf();
+            for (int o = 32; o >= 1; o >>= 1)
+                a = fmin(a, __shfl_xor(a, o, 64));
+            alpha_a = A.alpha_g * a;
+        }
         // list coordinates: absolute in FP64, relative to the group centre in FP32
         const bool rel = sizeof(T) == 4;
         const double ox = rel ? gcx : 0.0, oy = rel ? gcy : 0.0, oz = rel ? gcz : 0.0;
@@ -850,7 +862,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                     act = 1;
                 } else {
                     act = 3;
-                    if (A.theta2 > 0.0) {
+                    if (A.theta2 > 0.0 || A.aold) {
                         const double cx = comx + shx - gcx;
                         const double cy = comy + shy - gcy;
                         const double cz = comz + shz - gcz;
@@ -859,8 +871,13 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                         const double ez = fmax(0.0, fabs(cz) - ghz);
                         const double d2 = ex * ex + ey * ey + ez * ez;
                         const double side = ldexp(W.L, -(nlev - KBL));
-                        if (side * side < A.theta2 * d2)
+                        if (A.aold) {
+                            // G M l^2 < alpha a_min d^4
+                            if (A.nd_mass[node] * (side * side) < alpha_a * (d2 * d2))
+                                act = 2;
+                        } else if (side * side < A.theta2 * d2) {
                             act = 2;
+                        }
                     }
                 }
             }
@@ -1102,8 +1119,9 @@ static double split_poly_f32(double wmax, float *qf) {
 
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
-                         double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s) {
-    return dzs_tree_walk_ex(ctx, box, n, x, y, z, mult, gx, gy, gz, prm, nullptr, s);
+                         double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s,
+                         const float *aold) {
+    return dzs_tree_walk_ex(ctx, box, n, x, y, z, mult, gx, gy, gz, prm, nullptr, s, aold);
 }
 
 // boxes != nullptr: a batch (device table of the boxes; the keys in ctx->key carry the box);
@@ -1111,9 +1129,10 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
 dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                             const double *y, const double *z, const uint32_t *mult, double *gx,
                             double *gy, double *gz, const dzs_tree_params *prm,
-                            const dzs_bbox *boxes, hipStream_t s) {
+                            const dzs_bbox *boxes, hipStream_t s, const float *aold) {
     if (n == 0 || !ctx->tree_built)
         return DZS_OK;
+    const bool relative = prm->opening == DZS_OPEN_RELATIVE && aold && !boxes;
     walk_args A;
     memset(&A, 0, sizeof(A));
     A.grp_first = ctx->grp_first;
@@ -1137,6 +1156,8 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.gx = gx; A.gy = gy; A.gz = gz;
     A.accumulate = prm->accumulate;
     A.G_lanes = prm->group_size;
+    A.aold = relative ? aold : nullptr;
+    A.alpha_g = relative ? prm->alpha_open / box->G : 0.0;
     const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
     if (ctx->q_wmax != wmax) {
         ctx->q_err = split_poly(wmax, ctx->q_coef);
@@ -1161,7 +1182,7 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.key = (const uint64_t *)ctx->key;
     A.boxes = boxes;
     int K = 0;
-    if (prm->theta <= 1.0 && !boxes)
+    if ((prm->theta <= 1.0 || relative) && !boxes)
         while (K < DZS_CELL_K_MAX && ldexp(box->L, -(K + 1)) >= prm->r_cut)
             ++K;
     A.cell_K = K;

@@ -265,6 +265,68 @@ def test_tree_force_matches_direct_sum(dz, ctx, kind, n, theta, tol, gsize):
     assert np.array_equal(st.gx[: ps.n].cpu().numpy(), g[0])
 
 
+@pytest.mark.parametrize("kind,n,gsize", [("clustered", 20000, 32), ("merged", 30001, 16)])
+def test_tree_force_relative_opening(dz, ctx, kind, n, gsize):
+    """Relative opening criterion (G M l^2 < alpha a_min d^4, a_min from the accelerations
+    held on entry): alpha = 0 accepts no monopole and reproduces the opening-angle-0 walk bit
+    for bit; a small alpha stays close to the oracle's direct sum, and the error and the
+    interaction count move the right way with alpha.  The accelerations on entry are the
+    oracle's PM + short-range force (the previous force of a run)."""
+    import torch
+    L, ng = 100.0, 64
+    r_s = 1.25 * L / ng
+    r_cut = 4.5 * r_s
+    ps = _force_case(kind, n, L, 23)
+    _log(f"tree relative kind={kind} n={ps.n} group={gsize}")
+    box, obox = _box(dz, L, ps.n, 32)
+    ref = oracle.short_range(ps.x, ps.y, ps.z, ps.mult, obox, r_s, r_cut)
+    g_old = ref + oracle.pm_force(ps.x, ps.y, ps.z, ps.mult, obox, ng, r_s)
+    st = dz.State.from_host(ps)
+
+    def run(alpha=None):
+        for a, k in enumerate(("gx", "gy", "gz")):
+            getattr(st, k)[: ps.n] = torch.from_numpy(np.ascontiguousarray(g_old[a]))
+        tp = dz.TreeParams(r_s, r_cut, 0.0, 8, gsize, dz.DZS_FP64, 0)
+        if alpha is not None:
+            tp.opening, tp.alpha_open = dz.DZS_OPEN_RELATIVE, alpha
+        ctx.pair_interactions(reset=True)
+        ctx.tree_force(box, st, tp)
+        torch.cuda.synchronize()
+        g = np.stack([st.gx[: ps.n].cpu().numpy(), st.gy[: ps.n].cpu().numpy(),
+                      st.gz[: ps.n].cpu().numpy()])
+        return g, ctx.pair_interactions(reset=True)
+
+    g_exact, p_exact = run()
+    g0, p0 = run(0.0)
+    assert np.array_equal(g0, g_exact) and p0 == p_exact
+    scale = math.sqrt(np.mean(np.sum(g_old ** 2, axis=0)))
+    errs, pairs = [], []
+    for alpha in (0.05, 0.005, 0.0005):
+        g, pr = run(alpha)
+        e = math.sqrt(np.mean(np.sum((g - ref) ** 2, axis=0))) / scale
+        _log(f"  alpha {alpha}: rms error / rms|g_old| {e:.3e}, interactions {pr} of {p_exact}")
+        errs.append(e)
+        pairs.append(pr)
+    assert errs[0] <= 2e-2 and errs[2] <= 1e-3
+    assert errs[0] >= errs[1] >= errs[2]
+    assert pairs[0] <= pairs[1] <= pairs[2] <= p_exact and pairs[0] < p_exact
+
+
+def test_tree_relative_opening_rejects(dz, ctx):
+    import torch
+    L = 100.0
+    ps = dzs_ics.clustered_random(2000, L, seed=3)
+    box, _ = _box(dz, L, ps.n, 12)
+    st = dz.State.from_host(ps)
+    for opening, alpha in ((2, 0.01), (dz.DZS_OPEN_RELATIVE, -1.0),
+                           (dz.DZS_OPEN_RELATIVE, math.inf)):
+        tp = dz.TreeParams(1.95, 8.8, 0.5, 8, 32, dz.DZS_FP64, 0)
+        tp.opening, tp.alpha_open = opening, alpha
+        with pytest.raises(dz.DZSError):
+            ctx.tree_force(box, st, tp)
+    torch.cuda.synchronize()
+
+
 # Precision form: pair, mesh and FFT arithmetic in FP32 (unit roundoff 6e-8), positions and
 # the accumulated force in FP64.  Bar: rms relative error <= 1e-5 against the FP64 oracle
 # (the opening-angle-0 force bar; FP32 rounding of relative coordinates, ~1e-7 of r_cut,
@@ -462,7 +524,7 @@ def test_coarsen_no_merge_region_is_identity(dz, ctx):
 # -------------------------------------------------------------------------------- KDK step
 
 @pytest.mark.parametrize("coarsen,fp32", [(False, False), (True, False), (True, True),
-                                           ("dyn", False)])
+                                           ("dyn", False), ("relative-opening", False)])
 def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
     """One step of the 32^3 box: Zel'dovich at z = 49, L = 100, mesh 64.  In the precision form
     the drift, the coarsening and the lightcone test stay FP64 (bit-exact); the force and the
@@ -477,6 +539,9 @@ def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
     a0, a1 = 0.02, 0.02 * math.exp(0.07824)
     fac = oracle.step_factors(a0, a1)
     fac.update(a0=a0, a1=a1)
+    rel_open = coarsen == "relative-opening"
+    if rel_open:
+        coarsen = False
     cparams = dict(R_lc=20.0, b=5 * L / n_side, theta=1.0, k_min=4) if coarsen else None
     if coarsen == "dyn":
         # dynamical criterion on the previous (initial) force; alpha = 0.3 merges ~1000 nodes
@@ -502,6 +567,10 @@ def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
             sp.coarsen.theta = cparams["theta"]
     sp.pm = dz.PMParams(ng, prec, r_s, 0, 0)
     sp.tree = dz.TreeParams(r_s, r_cut, 0.0, 8, 64, prec, 0)
+    if rel_open:
+        # monopoles accepted by G M l^2 < alpha |g_0|_min d^4 on the entry force g0
+        sp.tree.opening, sp.tree.alpha_open = dz.DZS_OPEN_RELATIVE, 1e-3
+        tol = 2e-3
     st = dz.State.from_host(ps, g=g0)
     ring = dz.LCRing(1000)
     ring.reset()
@@ -538,9 +607,9 @@ def test_kdk_step_matches_oracle(dz, ctx, coarsen, fp32):
     for a, k in enumerate(("px", "py", "pz")):
         scale = np.abs(getattr(ref_state, k)).max()
         dp = out[k][o] - getattr(ref_state, k)[r]
-        if fp32:
+        if fp32 or rel_open:
             # the closing kick is FP64: the momentum differs by exactly K2 times the force
-            # difference checked above (which may hold a cutoff flip)
+            # difference checked above (which may hold a cutoff flip or monopoles)
             dp = dp - fac["K2"] * (gg[a] - ref_g[a, r])
         assert np.abs(dp).max() <= 1e-9 * scale
     assert ring.records()["count"] == 0   # chi(z=49) >> L: no particle on the lightcone
