@@ -375,6 +375,7 @@ def run_full(args, dz, torch, dzs_ics):
     kern = ctx.timing(enable=False, reset=True)
     peak = torch.cuda.max_memory_allocated()
     profile = mean_mass_by_distance(st, W["L"])
+    mass_total = int(st.mult[: st.n].to(torch.int64).sum().item())
     ctx.close()
     if args.out:
         np.savez(args.out, rho=rho.view(M, M, M).cpu().numpy(), per_step=np.array(per_step),
@@ -387,6 +388,8 @@ def run_full(args, dz, torch, dzs_ics):
             f"{W['n_steps']} log KDK steps, lightcone, tree theta {W['theta_tree']}, precision "
             f"form" + (", DZS" if dzs else ", full resolution"),
             "wall_s": sum(per_step), "particles_final": st.n, "merged_nodes": merged,
+            "summed_multiplicity": mass_total, "mass_conserved": mass_total == W["N"],
+            "every_particle_emitted_once": records == W["N"] and not overflow,
             "mean_mass_by_distance": profile,
             "lightcone_records": records, "ring_overflow": overflow,
             "torch_peak_GiB": peak / 2 ** 30,
