@@ -389,7 +389,7 @@ def run_full(args, dz, torch, dzs_ics):
             f"form" + (", DZS" if dzs else ", full resolution"),
             "wall_s": sum(per_step), "particles_final": st.n, "merged_nodes": merged,
             "summed_multiplicity": mass_total, "mass_conserved": mass_total == W["N"],
-            "every_particle_emitted_once": records == W["N"] and not overflow,
+            "lightcone_records_equal_N": records == W["N"] and not overflow,
             "mean_mass_by_distance": profile,
             "lightcone_records": records, "ring_overflow": overflow,
             "torch_peak_GiB": peak / 2 ** 30,
