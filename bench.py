@@ -185,6 +185,57 @@ def run_ensemble(args, dz, torch, dzs_ics):
     del graph
     ctx.close()
 
+    # Run control: the lightcone keeps shrinking, so every box is coarsened again (R_lc = L/8);
+    # the halt predicate compares the particle count with the last packing's and, once it has
+    # fallen below 90%, the batch is packed again (new offsets, tables and context) and the
+    # same steps are timed on the smaller batch.
+    log("run control: second coarsening and re-packing")
+    h_all = st.to_host()
+    rctx = dz.Context(max(first[b + 1] - first[b] for b in range(64)) + 64, max(ngs))
+    parts2, first2 = [], [0]
+    for b in range(64):
+        lo, hi = first[b], first[b + 1]
+        sub = _P()
+        for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+            setattr(sub, k, h_all[k][lo:hi])
+        sst = dz.State.from_host(sub)
+        cp = dz.CoarsenParams()
+        cp.R_lc, cp.b, cp.theta = 0.125 * specs[b]["L"], 0.0, 1.0
+        cp.k_min = k_min_for(specs[b]["n_side"], 2 ** specs[b]["level"])
+        rctx.dzs_coarsen(boxes[b], sst, cp)
+        torch.cuda.synchronize()
+        hb = sst.to_host()
+        parts2.append(hb)
+        first2.append(first2[-1] + hb["x"].shape[0])
+    rctx.close()
+    N2 = first2[-1]
+    ratio = N2 / N
+    reasons = dz.halt_check(balance=1.0, ratio=ratio, ratio_prev=1.0, t=1.0, t_prev=0.0,
+                            min_ratio=0.9)
+    repack = {"particles_before": N, "particles_after": N2, "ratio": ratio,
+              "halt_reasons": reasons, "repacked": False}
+    if reasons & dz._abi.DZS_HALT_RATIO:
+        allp2 = _P()
+        for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+            setattr(allp2, k, np.concatenate([hb[k] for hb in parts2]))
+        pctx = dz.Context(N2 + 64, side)
+        pst = dz.State.from_host(allp2, capacity=N2 + 64)
+        pst0 = dz.State(N2 + 64)
+        copy_state(pst0, pst)
+        for s_ in range(args.warmup):
+            pctx.kdk_step_batch(boxes, first2, ngs, rss, rcs, pst, params(s_, group, leaf), ring)
+        copy_state(pst, pst0)
+        ring.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(K):
+            pctx.kdk_step_batch(boxes, first2, ngs, rss, rcs, pst, params(s_, group, leaf), ring)
+        torch.cuda.synchronize()
+        t_packed = time.perf_counter() - t0
+        pctx.close()
+        repack.update(repacked=True, ms_per_step_before=1e3 * t_batch / K,
+                      ms_per_step_after=1e3 * t_packed / K)
+
     # the same steps box by box with the single-box call
     log("box-by-box comparison")
     bctx = dz.Context(max(first[b + 1] - first[b] for b in range(64)) + 64, max(ngs))
@@ -230,7 +281,8 @@ def run_ensemble(args, dz, torch, dzs_ics):
                      "graph_matches_eager_bitwise": bool(graph_same), "box_by_box_s": t_loop,
                      "batched_speedup": t_loop / t_batch, "graph_speedup": t_loop / t_graph,
                      "autotuned": {"group": group, "leaf": leaf},
-                     "autotune_s_per_step": {k: v[0] for k, v in tune.items()}},
+                     "autotune_s_per_step": {k: v[0] for k, v in tune.items()},
+                     "run_control": repack},
         "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
                                                                     key=lambda kv: -kv[1])},
     }

@@ -541,8 +541,6 @@ __global__ __launch_bounds__(TB_THREADS) void k_cell_fill(
 // (precision form; coordinates relative to the group centre, so FP32 keeps ~1e-7 of r_cut).
 __device__ __forceinline__ double wfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float wfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double wrsqrt(double a) { return rsqrt(a); }
-__device__ __forceinline__ float wrsqrt(float a) { return rsqrtf(a); }
 __device__ __forceinline__ double wmax(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ float wmax(float a, float b) { return fmaxf(a, b); }
 template <typename T> __device__ __forceinline__ T wmin_image(T d, T L) {
@@ -903,7 +901,6 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                     flush();
                 if (act == 2) {
                     const uint32_t slot = nlist + (uint32_t)__popcll(mono & lt_mask);
-                    const uint64_t c = A.cap;
                     src[slot].x = T(comx + shx - ox);
                     src[slot].y = T(comy + shy - oy);
                     src[slot].z = T(comz + shz - oz);
