@@ -464,3 +464,112 @@ def kdk_step(ps, g, box: Box, fac, ng, r_s, r_cut, x_obs, coarsen_params=None, s
     s.py = kick(s.py, gn[1], fac["K2"])
     s.pz = kick(s.pz, gn[2], fac["K2"])
     return s, gn, rec, cres
+
+
+# ======================================================================================
+# Individual power-of-two time steps (Sec. 2.1) with DZS only at global steps and the
+# out-of-lightcone limiter (Sec. 2.2): a block-step kick-drift-kick inside one global step.
+#
+# Readings: the global step [a0, a1] is cut into S = 2^B sub-steps of equal length in ln a;
+# a particle in bin b steps over 2^(B-b) sub-steps, its kicks reaching the midpoint of its own
+# step in ln a (so B = 0 is the plain step).  Bins are set at the start of the global step
+# from the accelerations held then: the step allowed is delta = sqrt(C eps / |g|), with
+# C = 2 eta a0^3 H(a0)^2 (a constant acceleration moves a particle by eta eps over delta) and
+# eps = eps0 mult^(1/3); the bin is the smallest b <= B with ln(a1/a0) 2^-b <= delta.
+# Limiter: a particle outside the lightcone sphere (|x - x_obs| >= R_lim, minimum image)
+# takes at most the largest bin held inside (no limit when nothing is inside).  Every
+# particle that ends a step at a sub-step boundary gets its new force there (the full PM +
+# short-range force).  DZS acts once every particle is synchronised at a1 (after the closing
+# kicks, so the merged momenta are all taken at a1), and the merged particles' force is then
+# computed anew (a state that merged nothing keeps its forces).
+# ======================================================================================
+
+def hier_bins(ps, g, box: Box, a0, a1, max_bin, eta, x_obs=None, R_lim=None, om=OMEGA_M):
+    """Power-of-two bins of the particles for the global step a0 -> a1 (see above)."""
+    H = H0 * math.sqrt(om / (a0 * a0 * a0) + (1.0 - om))
+    C = 2.0 * eta * (a0 * a0 * a0) * (H * H)
+    Dl = math.log(a1 / a0)
+    g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2]
+    gn = np.sqrt(g2)
+    eps = box.eps0 * np.cbrt(np.asarray(ps.mult, np.float64))
+    with np.errstate(divide="ignore"):
+        delta = np.where(gn > 0, np.sqrt(C * eps / np.where(gn > 0, gn, 1.0)), np.inf)
+    bins = np.zeros(ps.n, np.int64)
+    for b in range(max_bin):
+        bins[(bins == b) & (math.ldexp(Dl, -b) > delta)] += 1
+    if R_lim is not None and x_obs is not None and ps.n:
+        d = [min_image(getattr(ps, k) - x_obs[i], ps.L) for i, k in enumerate(("x", "y", "z"))]
+        inside = np.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) < R_lim
+        if inside.any():
+            cap = int(bins[inside].max())
+            bins[~inside] = np.minimum(bins[~inside], cap)
+    return bins
+
+
+def hier_grid(a0, a1, max_bin):
+    """Half-sub-step grid u_k, k = 0 .. 2 S, uniform in ln a from a0 to a1 (ends exact)."""
+    S = 1 << max_bin
+    la0, Dl = math.log(a0), math.log(a1 / a0)
+    u = [math.exp(la0 + Dl * k / (2 * S)) for k in range(2 * S + 1)]
+    u[0], u[-1] = a0, a1
+    return u
+
+
+def kdk_step_hier(ps, g, box: Box, a0, a1, max_bin, eta, ng, r_s, r_cut, x_obs, R_lim=None,
+                  coarsen_params=None, solve=False, bins=None):
+    """One global step a0 -> a1 with individual power-of-two steps.  Returns (new state, g
+    (3, n) at a1, lightcone records of every sub-drift, coarsening result or None, bins)."""
+    s = ps.copy()
+    g = np.array(g, np.float64, copy=True)
+    if bins is None:
+        bins = hier_bins(s, g, box, a0, a1, max_bin, eta, x_obs, R_lim)
+    S = 1 << max_bin
+    u = hier_grid(a0, a1, max_bin)
+    chi2 = [0.0 if uk >= 1.0 else chi(uk) ** 2 for uk in u]
+    records, cres = [], None
+    for j in range(S):
+        for b in range(max_bin + 1):
+            L = 1 << (max_bin - b)
+            if j % L == 0:
+                sel = bins == b
+                if sel.any():
+                    K = kick_factor(u[2 * j], u[2 * j + L])
+                    s.px[sel] = kick(s.px[sel], g[0, sel], K)
+                    s.py[sel] = kick(s.py[sel], g[1, sel], K)
+                    s.pz[sel] = kick(s.pz[sel], g[2, sel], K)
+        D = drift_factor(u[2 * j], u[2 * j + 2])
+        records.append(lightcone_records(s, x_obs, u[2 * j], u[2 * j + 2], D, chi2[2 * j],
+                                         chi2[2 * j + 2], solve=solve))
+        s.x = drift(s.x, s.px, D, s.L)
+        s.y = drift(s.y, s.py, D, s.L)
+        s.z = drift(s.z, s.pz, D, s.L)
+        jn = j + 1
+        active = np.array([(jn % (1 << (max_bin - int(b)))) == 0 for b in bins], bool)
+        if not active.any():
+            continue
+        gn = total_force(s.x, s.y, s.z, s.mult, box, ng, r_s, r_cut)
+        g[:, active] = gn[:, active]
+        for b in range(max_bin + 1):
+            L = 1 << (max_bin - b)
+            if jn % L == 0:
+                sel = (bins == b) & active
+                if sel.any():
+                    K = kick_factor(u[2 * jn - L], u[2 * jn])
+                    s.px[sel] = kick(s.px[sel], g[0, sel], K)
+                    s.py[sel] = kick(s.py[sel], g[1, sel], K)
+                    s.pz[sel] = kick(s.pz[sel], g[2, sel], K)
+    if coarsen_params is not None:
+        extra = {}
+        if coarsen_params.get("alpha_dyn") is not None:
+            extra = {"g": g, "Gm0": box.G * box.m0}
+        out, group_of, nm = coarsen(s, x_obs, **coarsen_params, **extra)
+        cres = (out, group_of, nm)
+        for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+            setattr(s, k, out[k])
+        if nm > 0:
+            g = total_force(s.x, s.y, s.z, s.mult, box, ng, r_s, r_cut)
+        else:
+            g2 = np.empty_like(g)
+            g2[:, group_of] = g
+            g = g2
+    return s, g, records, cres, bins
