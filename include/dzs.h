@@ -209,6 +209,28 @@ typedef struct {
     dzs_tree_params tree;
 } dzs_step_params;
 
+/* Individual power-of-two time steps (Sec. 2.1) inside one global step a0 -> a1: 2^max_bin
+ * sub-steps of equal length in ln a; a particle in bin b steps over 2^(max_bin - b) of them,
+ * each of its steps a kick-drift-kick whose kicks reach the step's midpoint in ln a.  Bins
+ * are set at a0 from the accelerations the state holds: the step allowed is
+ * delta = sqrt(C eps / |g|), C = 2 eta a0^3 H(a0)^2, eps = eps0 mult^(1/3), and the bin is the
+ * smallest b <= max_bin with ln(a1/a0) 2^-b <= delta (|g| = 0: bin 0).  With the limiter
+ * (Sec. 2.2) particles outside the sphere |x - x_obs| < R_lim (x_obs: the coarsening
+ * parameters' observer) take at most the largest bin inside it (no limit when nobody is
+ * inside).  Every particle ending a step at a sub-step boundary gets its new force there
+ * (PM + tree; the walk serves only those targets).  DZS runs once all particles are
+ * synchronised at a1 (after the closing kicks), and a coarsening that merged particles is
+ * followed by a new force for the whole state. */
+#define DZS_HIER_MAX_BIN 6
+typedef struct {
+    int32_t max_bin;   /* 0..DZS_HIER_MAX_BIN (0: the plain step) */
+    int32_t limiter;   /* 1: cap the bins outside the sphere of radius R_lim */
+    double eta;        /* accuracy parameter of the bin rule (> 0) */
+    double R_lim;      /* limiter radius (the lightcone radius at a0 plus the buffer) */
+    double a0, a1;     /* the global step */
+    double omega_m;    /* flat LCDM */
+} dzs_hier_params;
+
 /* ---- context ------------------------------------------------------------------------ */
 
 /* Create a context on HIP device `device` and allocate its scratch for `cap`: about
@@ -221,6 +243,18 @@ dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap
 dzs_status dzs_ctx_destroy(dzs_ctx *ctx);
 /* Text of the context's last failure ("" if none); valid until the next call. */
 const char *dzs_last_error(const dzs_ctx *ctx);
+
+/* One global step with individual time steps (dzs_hier_params).  prm supplies pm, tree,
+ * coarsen, do_lightcone and do_coarsen (its K1, K2 and lc are not read: the sub-step factors
+ * come from hp).  bins_out (optional, device, >= n bytes) receives each particle's bin, in
+ * the order of the state on entry.  The state is left in key order (or (key, id) order
+ * after a coarsening that merged nothing), synchronised at a1 with g = the force at a1.
+ * The relative opening criterion is not supported here (DZS_EINVAL).  Synchronises the
+ * stream (the limiter, the capacity checks, the coarsening count). */
+dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_particles *state,
+                         const dzs_step_params *prm, const dzs_hier_params *hp,
+                         dzs_lc_ring *ring, dzs_coarsen_report *report, uint8_t *bins_out,
+                         void *stream);
 
 /* Host helper: flat LCDM (Omega_m = omega_m, no radiation) kick, drift and lightcone
  * factors for the step a0 -> a1: K1, K2, lc.D, lc.chi2_0, lc.chi2_1, lc.a0, lc.a1 and the

@@ -231,6 +231,24 @@ class Context:
         st.n = int(v.n)
         return rep
 
+    def kdk_step_hier(self, box: Box, st: State, prm: StepParams, max_bin: int, eta: float,
+                      a0: float, a1: float, omega_m: float = 0.3, limiter: bool = False,
+                      R_lim: float = 0.0, ring: LCRing | None = None, bins_out=None,
+                      stream=None):
+        """One global step a0 -> a1 with individual power-of-two time steps (bins 0..max_bin);
+        bins_out (optional uint8 tensor) receives the bins in the entry order."""
+        v = st.view()
+        rep = CoarsenReport()
+        hp = _abi.HierParams(int(max_bin), int(bool(limiter)), float(eta), float(R_lim),
+                             float(a0), float(a1), float(omega_m))
+        rv = C.byref(ring.view()) if ring is not None else None
+        self._check("kdk_step_hier", _lib.kdk_step_hier(self._h, C.byref(box), C.byref(v),
+                                                        C.byref(prm), C.byref(hp), rv,
+                                                        C.byref(rep), _ptr(bins_out),
+                                                        _stream_handle(stream)))
+        st.n = int(v.n)
+        return rep
+
     def kdk_step_batch(self, boxes, first, ng, r_s, r_cut, st: State, prm: StepParams,
                        ring: LCRing | None = None, stream=None):
         """One step of every box of a batch; box b owns st's particles first[b]:first[b+1]."""

@@ -23,9 +23,16 @@ EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_fact
            "dzs_coarsen", "pm_force", "tree_force", "lightcone_emit", "kdk_step",
            "kdk_step_batch", "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
            "dzs_sort_state", "dzs_counters", "dzs_timing", "dzs_halt_check",
-           "dzs_forecast_speedup")
+           "dzs_forecast_speedup", "kdk_step_hier")
+DZS_HIER_MAX_BIN = 6
 DZS_HALT_BALANCE, DZS_HALT_RATIO, DZS_HALT_PREDICTED = 1, 2, 4
 DZS_BATCH_MAX = 512
+
+
+class HierParams(C.Structure):
+    _fields_ = [("max_bin", C.c_int32), ("limiter", C.c_int32), ("eta", C.c_double),
+                ("R_lim", C.c_double), ("a0", C.c_double), ("a1", C.c_double),
+                ("omega_m", C.c_double)]
 
 
 class HaltParams(C.Structure):
@@ -127,6 +134,9 @@ def load():
     L.dzs_last_error.argtypes = [P]
     L.dzs_last_error.restype = C.c_char_p
     L.dzs_step_factors.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(StepParams)]
+    L.kdk_step_hier.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(StepParams),
+                                C.POINTER(HierParams), C.POINTER(LCRing),
+                                C.POINTER(CoarsenReport), P, P]
     L.dzs_halt_check.argtypes = [C.POINTER(HaltParams), C.POINTER(HaltState)]
     L.dzs_halt_check.restype = C.c_uint32
     L.dzs_forecast_speedup.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(Forecast)]
@@ -150,6 +160,7 @@ def load():
     for name in ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_step_factors", "dzs_coarsen",
                  "pm_force", "tree_force", "lightcone_emit", "kdk_step", "kdk_step_batch",
                  "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
-                 "dzs_sort_state", "dzs_counters", "dzs_timing", "dzs_forecast_speedup"):
+                 "dzs_sort_state", "dzs_counters", "dzs_timing", "dzs_forecast_speedup",
+                 "kdk_step_hier"):
         getattr(L, name).restype = st
     return L

@@ -4,6 +4,8 @@
 #include <stdarg.h>
 #include <stdlib.h>
 
+#include <vector>
+
 #include "internal.h"
 
 const char *const dzs_kclass_names[KC_COUNT] = {
@@ -621,6 +623,127 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
         DZS_TRY(dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx, st->gy,
                               st->gz, &t, s, aold_ok ? ctx->aold : nullptr));
         DZS_TRY(dzs_launch_kick(ctx, st, prm->K2, s));
+    }
+    return DZS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// individual time steps
+// ---------------------------------------------------------------------------------------
+// The force of the targets that end a step at sub-step boundary jn (all when bins is null):
+// key order, tree, PM for everyone, the walk for the active targets only.
+static dzs_status hier_force(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st,
+                             const dzs_step_params *prm, const dzs_tree_params &t0,
+                             const uint8_t *bins, uint32_t jn, uint32_t B, bool in_order,
+                             hipStream_t s) {
+    if (st->n == 0)
+        return DZS_OK;
+    if (!in_order) {
+        DZS_TRY(sort_state(ctx, box, st, 0, 0, s));
+        if (bins)
+            DZS_TRY(dzs_permute_u8(ctx, ctx->hbins, ctx->idx, st->n, s));
+    }
+    dzs_tree_params t = t0;
+    DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
+                           t.group_size, s));
+    dzs_pm_params pm = prm->pm;
+    pm.accumulate = 0;
+    DZS_TRY(dzs_pm_run(ctx, box, st, &pm, s));
+    t.accumulate = 1;
+    struct walk_set {
+        dzs_ctx *c;
+        ~walk_set() { c->walk_bins = nullptr; }
+    } guard{ctx};
+    ctx->walk_bins = bins;
+    ctx->walk_jn = jn;
+    ctx->walk_B = B;
+    return dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx, st->gy, st->gz,
+                         &t, s);
+}
+
+extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st,
+                                    const dzs_step_params *prm, const dzs_hier_params *hp,
+                                    dzs_lc_ring *ring, dzs_coarsen_report *report,
+                                    uint8_t *bins_out, void *stream) {
+    DZS_TRY(check_common(ctx, box, st));
+    if (!prm || !hp)
+        return dzs_fail(ctx, DZS_EINVAL, "hier: null parameters");
+    if (st->n > 0 && (!st->px || !st->py || !st->pz || !st->gx || !st->gy || !st->gz || !st->id ||
+                      !st->type))
+        return dzs_fail(ctx, DZS_EINVAL, "null state array");
+    dzs_tree_params t;
+    DZS_TRY(check_tree(ctx, box, &prm->tree, &t));
+    if (t.opening != DZS_OPEN_GEOMETRIC)
+        return dzs_fail(ctx, DZS_EINVAL, "hier: only the geometric opening criterion");
+    DZS_TRY(check_pm(ctx, &prm->pm));
+    if (prm->do_lightcone && (!ring || !ring->records || !ring->count || !ring->overflow))
+        return dzs_fail(ctx, DZS_EINVAL, "hier: null lightcone ring");
+    if (prm->do_coarsen)
+        DZS_TRY(check_coarsen(ctx, &prm->coarsen));
+    const int B = hp->max_bin;
+    if (B < 0 || B > DZS_HIER_MAX_BIN || !(hp->eta > 0.0) || !(hp->a0 > 0.0) ||
+        !(hp->a1 > hp->a0) || !(hp->a1 <= 1.0) || !(hp->omega_m > 0.0) ||
+        !(hp->omega_m <= 1.0) || (hp->limiter && !(hp->R_lim >= 0.0)))
+        return dzs_fail(ctx, DZS_EINVAL, "hier: need 0 <= max_bin <= %d, eta > 0, "
+                        "0 < a0 < a1 <= 1, 0 < omega_m <= 1, R_lim >= 0", DZS_HIER_MAX_BIN);
+    hipStream_t s = (hipStream_t)stream;
+    if (report)
+        *report = dzs_coarsen_report{st->n, st->n, 0, NAN};
+    const int S = 1 << B;
+    const double om = hp->omega_m, a0 = hp->a0, a1 = hp->a1;
+    const double Dl = log(a1 / a0);
+    // half-sub-step grid, uniform in ln a, ends exact
+    std::vector<double> u(2 * S + 1);
+    for (int k = 0; k <= 2 * S; ++k)
+        u[k] = exp(log(a0) + Dl * k / (2 * S));
+    u[0] = a0;
+    u[2 * S] = a1;
+    if (st->n > 0) {
+        if (!ctx->hbins)
+            DZS_TRY(alloc(ctx, &ctx->hbins, ctx->cap_n));
+        const double H = 100.0 * sqrt(om / (a0 * a0 * a0) + (1.0 - om));
+        const double C = 2.0 * hp->eta * (a0 * a0 * a0) * (H * H);
+        DZS_TRY(dzs_launch_hier_bins(ctx, box, st, C, Dl, B, prm->coarsen.x_obs, hp->R_lim,
+                                     hp->limiter, ctx->hbins, s));
+        if (bins_out)
+            DZS_HIP(ctx, hipMemcpyAsync(bins_out, ctx->hbins, st->n, hipMemcpyDeviceToDevice, s));
+    }
+    for (int j = 0; j < S && st->n > 0; ++j) {
+        double K[DZS_HIER_MAX_BIN + 1] = {0.0};
+        for (int b = 0; b <= B; ++b) {
+            const int L = 1 << (B - b);
+            if (j % L == 0)
+                K[b] = dzs_kick_factor(u[2 * j], u[2 * j + L], om);
+        }
+        DZS_TRY(dzs_launch_kick_bins(ctx, st, ctx->hbins, K, s));
+        dzs_step_params sub = *prm;
+        DZS_TRY(dzs_step_factors(u[2 * j], u[2 * j + 2], om, &sub));
+        DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &sub.lc, ring, prm->do_lightcone, 1, s));
+        const int jn = j + 1;
+        DZS_TRY(hier_force(ctx, box, st, prm, t, ctx->hbins, (uint32_t)jn, (uint32_t)B, false,
+                           s));
+        for (int b = 0; b <= B; ++b) {
+            const int L = 1 << (B - b);
+            K[b] = jn % L == 0 ? dzs_kick_factor(u[2 * jn - L], u[2 * jn], om) : 0.0;
+        }
+        DZS_TRY(dzs_launch_kick_bins(ctx, st, ctx->hbins, K, s));
+    }
+    // every particle is synchronised at a1: DZS, then a new force if anything merged
+    const bool can_merge = prm->do_coarsen &&
+                           prm->coarsen.R_lc + prm->coarsen.b < 0.5 * sqrt(3.0) * box->L;
+    if (can_merge && st->n > 0) {
+        if (prm->coarsen.criterion == DZS_CRIT_DYNAMICAL)
+            DZS_TRY(dzs_coarsen_amin(ctx, box, st, &prm->coarsen, s));
+        DZS_TRY(sort_state(ctx, box, st, 1, 1, s));
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->dz_perm, ctx->idx, sizeof(uint32_t) * st->n,
+                                    hipMemcpyDeviceToDevice, s));
+        const uint64_t n_in = st->n;
+        DZS_TRY(dzs_coarsen_sorted(ctx, box, st, &prm->coarsen, nullptr, report, s));
+        if (st->n != n_in && st->n > 0) {
+            bool in_order = false;
+            DZS_TRY(dzs_coarsen_rekey(ctx, box, st, &in_order, s));
+            DZS_TRY(hier_force(ctx, box, st, prm, t, nullptr, 0u, 0u, in_order, s));
+        }
     }
     return DZS_OK;
 }

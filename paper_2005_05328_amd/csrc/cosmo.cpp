@@ -112,6 +112,8 @@ void cheb_fit(F f, double a0, double a1, int n, double *c) {
 
 }  // namespace
 
+double dzs_kick_factor(double a0, double a1, double omega_m) { return kick(a0, a1, omega_m); }
+
 void dzs_merge_thresholds(double L, double R_lc, double b, double theta, double *T2) {
     for (int k = 0; k <= 21; ++k) {
         double lk = ldexp(L, -k);

@@ -105,6 +105,11 @@ struct dzs_ctx {
     uint32_t *smult = nullptr;
     double *sgx = nullptr, *sgy = nullptr, *sgz = nullptr;
     float *aold = nullptr;  // |g| on entry, for the relative opening criterion (lazy)
+    uint8_t *hbins = nullptr;  // bins of the individual time steps (lazy)
+    // the walk's active set during an individual-step force: target i is active when
+    // (walk_jn mod 2^(walk_B - bin_i)) == 0; walk_bins == nullptr: every target
+    const uint8_t *walk_bins = nullptr;
+    uint32_t walk_jn = 0, walk_B = 0;
 
     // ---- octree (structure of arrays)
     uint64_t cap_nodes = 0;
@@ -315,6 +320,17 @@ dzs_status dzs_launch_gnorm(dzs_ctx *ctx, uint64_t n, const double *gx, const do
                             const double *gz, const uint32_t *perm, float *out, hipStream_t s);
 dzs_status dzs_permute_f32(dzs_ctx *ctx, float *arr, const uint32_t *perm, uint64_t n,
                            hipStream_t s);
+dzs_status dzs_permute_u8(dzs_ctx *ctx, uint8_t *arr, const uint32_t *perm, uint64_t n,
+                          hipStream_t s);
+// individual time steps: bins of the global step (C = 2 eta a0^3 H(a0)^2, Dl = ln(a1/a0)),
+// the limiter when asked, and kicks by bin
+dzs_status dzs_launch_hier_bins(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                                double C, double Dl, int B, const double *x_obs, double R_lim,
+                                int limiter, uint8_t *bins, hipStream_t s);
+dzs_status dzs_launch_kick_bins(dzs_ctx *ctx, const dzs_particles *p, const uint8_t *bins,
+                                const double *K, hipStream_t s);
+// host cosmology (cosmo.cpp): K(a0, a1) = int da / (a^2 H)
+double dzs_kick_factor(double a0, double a1, double omega_m);
 dzs_status dzs_gather_u32(dzs_ctx *ctx, const uint32_t *src, const uint32_t *perm,
                           uint32_t *dst, uint64_t n, hipStream_t s);
 dzs_status dzs_scatter_add_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm,
@@ -356,6 +372,8 @@ dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
 #define DZS_SMALL_AMIN 16
 // d_small word 20: set when the keys of a coarsened state are out of order
 #define DZS_SMALL_UNSORTED 20
+// d_small word 24: largest bin + 1 inside the limiter sphere (0: nobody inside)
+#define DZS_SMALL_HIER_CAP 24
 // Reduce the dynamical criterion's a_min^2 over the state (before any reordering that leaves
 // g behind) into d_small[DZS_SMALL_AMIN].
 dzs_status dzs_coarsen_amin(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,

@@ -308,6 +308,132 @@ dzs_status dzs_permute_state(dzs_ctx *ctx, dzs_particles *p, const uint32_t *per
     return DZS_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// individual power-of-two time steps
+// ---------------------------------------------------------------------------------------
+// Bin of each particle for a global step of length Dl in ln a: the smallest b <= B with
+// Dl 2^-b <= delta = sqrt(C eps / |g|), eps = eps0 mult^(1/3) (|g| = 0: bin 0).  With a
+// limiter radius, the largest bin among particles inside the sphere is reduced (as bin + 1,
+// 0 = nobody inside) into *cap.
+__global__ __launch_bounds__(PT_THREADS) void k_hier_bins(
+    uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ gx, const double *__restrict__ gy,
+    const double *__restrict__ gz, const uint32_t *__restrict__ mult, double eps0, double C,
+    double Dl, int B, double L, double xo0, double xo1, double xo2, double R_lim,
+    uint8_t *__restrict__ bins, uint32_t *cap) {
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    uint32_t inside_bin = 0;
+    if (i < n) {
+        const double g2 = gx[i] * gx[i] + gy[i] * gy[i] + gz[i] * gz[i];
+        const double gn = sqrt(g2);
+        const double eps = eps0 * cbrt((double)mult[i]);
+        const double delta = gn > 0.0 ? sqrt(C * eps / gn) : __builtin_inf();
+        int b = 0;
+        while (b < B && ldexp(Dl, -b) > delta)
+            ++b;
+        bins[i] = (uint8_t)b;
+        if (cap) {
+            const double dx = dzs_min_image(x[i] - xo0, L);
+            const double dy = dzs_min_image(y[i] - xo1, L);
+            const double dz = dzs_min_image(z[i] - xo2, L);
+            if (sqrt(dx * dx + dy * dy + dz * dz) < R_lim)
+                inside_bin = (uint32_t)b + 1u;
+        }
+    }
+    if (cap) {
+        for (int o = 32; o >= 1; o >>= 1)
+            inside_bin = max(inside_bin, (uint32_t)__shfl_xor((int)inside_bin, o, 64));
+        if ((threadIdx.x & 63u) == 0u && inside_bin > 0u)
+            atomicMax(cap, inside_bin);
+    }
+}
+
+__global__ __launch_bounds__(PT_THREADS) void k_hier_limit(
+    uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, double L, double xo0, double xo1, double xo2, double R_lim,
+    const uint32_t *__restrict__ cap, uint8_t *__restrict__ bins) {
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n || *cap == 0u)
+        return;
+    const double dx = dzs_min_image(x[i] - xo0, L);
+    const double dy = dzs_min_image(y[i] - xo1, L);
+    const double dz = dzs_min_image(z[i] - xo2, L);
+    if (!(sqrt(dx * dx + dy * dy + dz * dz) < R_lim)) {
+        const uint8_t c = (uint8_t)(*cap - 1u);
+        if (bins[i] > c)
+            bins[i] = c;
+    }
+}
+
+__global__ __launch_bounds__(1) void k_hier_cap_clear(uint32_t *cap) { *cap = 0u; }
+
+struct bin_factors {
+    double K[DZS_HIER_MAX_BIN + 1];  // kick factor of each bin at this boundary (0: none)
+};
+
+// p += g K[bin] for the bins that kick at this boundary
+__global__ __launch_bounds__(PT_THREADS) void k_kick_bins(
+    uint64_t n, double *__restrict__ px, double *__restrict__ py, double *__restrict__ pz,
+    const double *__restrict__ gx, const double *__restrict__ gy,
+    const double *__restrict__ gz, const uint8_t *__restrict__ bins, bin_factors F) {
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n)
+        return;
+    const double K = F.K[bins[i]];
+    if (K == 0.0)
+        return;
+    px[i] = px[i] + gx[i] * K;
+    py[i] = py[i] + gy[i] * K;
+    pz[i] = pz[i] + gz[i] * K;
+}
+
+dzs_status dzs_launch_hier_bins(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                                double C, double Dl, int B, const double *x_obs, double R_lim,
+                                int limiter, uint8_t *bins, hipStream_t s) {
+    if (p->n == 0)
+        return DZS_OK;
+    uint32_t *cap = limiter ? ctx->d_small + DZS_SMALL_HIER_CAP : nullptr;
+    if (cap) {
+        hipLaunchKernelGGL(k_hier_cap_clear, dim3(1), dim3(1), 0, s, cap);
+        DZS_TRY(dzs_check_launch(ctx, "hier_cap_clear"));
+    }
+    const uint32_t b = blocks_for(p->n, PT_THREADS);
+    hipLaunchKernelGGL(k_hier_bins, dim3(b), dim3(PT_THREADS), 0, s, p->n, (const double *)p->x,
+                       (const double *)p->y, (const double *)p->z, (const double *)p->gx,
+                       (const double *)p->gy, (const double *)p->gz, (const uint32_t *)p->mult,
+                       box->eps0, C, Dl, B, box->L, x_obs[0], x_obs[1], x_obs[2], R_lim, bins,
+                       cap);
+    DZS_TRY(dzs_check_launch(ctx, "hier_bins"));
+    if (cap) {
+        hipLaunchKernelGGL(k_hier_limit, dim3(b), dim3(PT_THREADS), 0, s, p->n,
+                           (const double *)p->x, (const double *)p->y, (const double *)p->z,
+                           box->L, x_obs[0], x_obs[1], x_obs[2], R_lim, (const uint32_t *)cap,
+                           bins);
+        DZS_TRY(dzs_check_launch(ctx, "hier_limit"));
+    }
+    return DZS_OK;
+}
+
+dzs_status dzs_launch_kick_bins(dzs_ctx *ctx, const dzs_particles *p, const uint8_t *bins,
+                                const double *K, hipStream_t s) {
+    if (p->n == 0)
+        return DZS_OK;
+    bin_factors F;
+    for (int b = 0; b <= DZS_HIER_MAX_BIN; ++b)
+        F.K[b] = K[b];
+    hipLaunchKernelGGL(k_kick_bins, dim3(blocks_for(p->n, PT_THREADS)), dim3(PT_THREADS), 0, s,
+                       p->n, p->px, p->py, p->pz, (const double *)p->gx, (const double *)p->gy,
+                       (const double *)p->gz, bins, F);
+    return dzs_check_launch(ctx, "kick_bins");
+}
+
+dzs_status dzs_permute_u8(dzs_ctx *ctx, uint8_t *arr, const uint32_t *perm, uint64_t n,
+                          hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    return permute_one<uint8_t>(ctx, arr, perm, n, s);
+}
+
 // |g| of each particle (slot i takes particle perm[i] when perm is given), in FP32: the
 // relative opening criterion's previous accelerations.
 __global__ __launch_bounds__(PT_THREADS) void k_gnorm(uint64_t n, const double *__restrict__ gx,

@@ -474,6 +474,10 @@ struct walk_args {
     // alpha_open / G (the walk's masses and distances carry no G)
     const float *aold;
     double alpha_g;
+    // individual time steps: only targets with (hier_jn mod 2^(hier_B - bin)) == 0 get a
+    // force (bins == nullptr: every target)
+    const uint8_t *bins;
+    uint32_t hier_jn, hier_B;
 };
 
 // Geometry and constants of the box a group lives in.
@@ -709,6 +713,10 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         }
         const bool valid = tl < cnt;
         const uint32_t i = valid ? first + tl : first;
+        const bool active =
+            valid && (!A.bins || (A.hier_jn & ((1u << (A.hier_B - A.bins[i])) - 1u)) == 0u);
+        if (A.bins && __ballot(active) == 0ull)
+            continue;  // no target of this group ends a step at this boundary
         const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
         const double hi = W.h0 * cbrt((double)A.mult[i]);
         // group bounding box
@@ -990,13 +998,13 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             az += __shfl_xor(az, o, 64);
         }
         {
-            uint64_t cnt_pairs = valid ? n_pairs : 0u;
+            uint64_t cnt_pairs = active ? n_pairs : 0u;
             for (int o = 32; o >= 1; o >>= 1)
                 cnt_pairs += __shfl_xor(cnt_pairs, o, 64);
             if (lane == 0)
                 atomicAdd(A.pair_count, (unsigned long long)cnt_pairs);
         }
-        if (valid && ph == 0) {
+        if (active && ph == 0) {
             const double gxv = W.Gc * (double)ax, gyv = W.Gc * (double)ay, gzv = W.Gc * (double)az;
             if (A.accumulate) {
                 A.gx[i] += gxv;
@@ -1154,6 +1162,9 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.accumulate = prm->accumulate;
     A.G_lanes = prm->group_size;
     A.aold = relative ? aold : nullptr;
+    A.bins = boxes ? nullptr : ctx->walk_bins;
+    A.hier_jn = ctx->walk_jn;
+    A.hier_B = ctx->walk_B;
     A.alpha_g = relative ? prm->alpha_open / box->G : 0.0;
     const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
     if (ctx->q_wmax != wmax) {

@@ -1,0 +1,149 @@
+"""Individual power-of-two time steps on the GPU (kdk_step_hier) against the oracle's block
+step (paper Sec. 2.1; DZS at the synchronised end of the global step and the
+out-of-lightcone limiter of Sec. 2.2).
+
+A clustered set of 4000 particles (L = 50, mesh 32^3) whose accelerations spread it over four
+bins (eta 0.1, max_bin 3): the bins are integer decisions taken in FP64 from the same inputs
+on both sides and must agree exactly; the state after the global step carries the force
+bar of the opening-angle-0 walk (1e-9) through four sub-steps.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import dzs_ics
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+L, NG = 50.0, 32
+R_S = 1.25 * L / NG
+R_CUT = 4.5 * R_S
+A0, A1, B, ETA = 0.3, 0.32, 3, 0.1
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dz():
+    import torch  # noqa: F401
+    import paper_2005_05328_amd as dz
+    return dz
+
+
+def _case():
+    ps = dzs_ics.clustered_random(4000, L, seed=91, r_clump=L / 25, vel=30.0)
+    m0 = dzs_ics.particle_mass(L, 16 ** 3)
+    obox = oracle.Box(L=L, m0=m0, eps0=L / 16 / 40)
+    g0 = oracle.total_force(ps.x, ps.y, ps.z, ps.mult, obox, NG, R_S, R_CUT)
+    return ps, obox, g0
+
+
+def _params(dz, coarsen=None):
+    sp = dz.step_factors(A0, A1, 0.3)
+    sp.do_lightcone = 1
+    sp.pm = dz.PMParams(NG, dz.DZS_FP64, R_S, 0, 0)
+    sp.tree = dz.TreeParams(R_S, R_CUT, 0.0, 8, 32, dz.DZS_FP64, 0)
+    sp.do_coarsen = 0
+    if coarsen is not None:
+        sp.do_coarsen = 1
+        for d in range(3):
+            sp.coarsen.x_obs[d] = coarsen["x_obs"][d]
+        sp.coarsen.R_lc, sp.coarsen.b = coarsen["R_lc"], coarsen["b"]
+        sp.coarsen.theta, sp.coarsen.k_min = coarsen["theta"], coarsen["k_min"]
+    return sp
+
+
+@pytest.mark.parametrize("limiter", [False, True])
+def test_hier_step_matches_oracle(dz, limiter):
+    import torch
+    ps, obox, g0 = _case()
+    xo = [float(ps.x[427]), float(ps.y[427]), float(ps.z[427])] if limiter else [0.0, 0.0, 0.0]
+    R_lim = 2.0 if limiter else None
+    _log(f"hier limiter={limiter}")
+    ref_bins = oracle.hier_bins(ps, g0, obox, A0, A1, B, ETA, x_obs=xo, R_lim=R_lim)
+    if limiter:
+        assert (ref_bins != oracle.hier_bins(ps, g0, obox, A0, A1, B, ETA)).sum() > 100
+    ref, ref_g, _, _, _ = oracle.kdk_step_hier(ps, g0, obox, A0, A1, B, ETA, NG, R_S, R_CUT, xo,
+                                               R_lim=R_lim)
+    box = dz.make_box(L, obox.m0, obox.eps0)
+    ctx = dz.Context(ps.n, NG)
+    st = dz.State.from_host(ps, g=g0)
+    sp = _params(dz)
+    for d in range(3):
+        sp.coarsen.x_obs[d] = xo[d]
+    ring = dz.LCRing(4096)
+    ring.reset()
+    bins = torch.zeros(ps.n, dtype=torch.uint8, device="cuda")
+    ctx.kdk_step_hier(box, st, sp, B, ETA, A0, A1, limiter=limiter, R_lim=R_lim or 0.0,
+                      ring=ring, bins_out=bins)
+    torch.cuda.synchronize()
+    got_bins = bins.cpu().numpy().astype(np.int64)
+    _log(f"  bins {np.bincount(got_bins, minlength=B + 1)}")
+    assert np.array_equal(got_bins, ref_bins)
+    out = st.to_host()
+    o, r = np.argsort(out["id"]), np.argsort(ref.id)
+    for k in ("x", "y", "z"):
+        d = oracle.min_image(out[k][o] - getattr(ref, k)[r], L)
+        assert np.abs(d).max() <= 1e-9 * L, k
+    for k in ("px", "py", "pz"):
+        scale = np.abs(getattr(ref, k)).max()
+        assert np.abs(out[k][o] - getattr(ref, k)[r]).max() <= 1e-9 * scale, k
+    gg = np.stack([out["gx"][o], out["gy"][o], out["gz"][o]])
+    err = math.sqrt(np.mean(np.sum((gg - ref_g[:, r]) ** 2, 0)) / np.mean(np.sum(ref_g ** 2, 0)))
+    _log(f"  g rms rel err {err:.3e}")
+    assert err <= 1e-9
+    ctx.close()
+
+
+def test_hier_step_with_dzs_at_the_end(dz):
+    import torch
+    ps, obox, g0 = _case()
+    cpar = dict(x_obs=[0.0, 0.0, 0.0], R_lc=10.0, b=1.0, theta=1.0, k_min=3)
+    ocp = {k: v for k, v in cpar.items() if k != "x_obs"}
+    ref, ref_g, _, cres, _ = oracle.kdk_step_hier(ps, g0, obox, A0, A1, B, ETA, NG, R_S, R_CUT,
+                                                  cpar["x_obs"], coarsen_params=ocp)
+    assert cres[2] > 0
+    box = dz.make_box(L, obox.m0, obox.eps0)
+    ctx = dz.Context(ps.n, NG)
+    st = dz.State.from_host(ps, g=g0)
+    ring = dz.LCRing(4096)
+    ring.reset()
+    rep = ctx.kdk_step_hier(box, st, _params(dz, cpar), B, ETA, A0, A1, ring=ring)
+    torch.cuda.synchronize()
+    assert rep.n_groups == cres[2] and st.n == ref.n
+    out = st.to_host()
+    o, r = np.argsort(out["id"]), np.argsort(ref.id)
+    for k in ("mult", "id", "type"):
+        assert np.array_equal(out[k][o], getattr(ref, k)[r]), k
+    for k in ("x", "y", "z"):
+        d = oracle.min_image(out[k][o] - getattr(ref, k)[r], L)
+        assert np.abs(d).max() <= 1e-9 * L, k
+    gg = np.stack([out["gx"][o], out["gy"][o], out["gz"][o]])
+    err = math.sqrt(np.mean(np.sum((gg - ref_g[:, r]) ** 2, 0)) / np.mean(np.sum(ref_g ** 2, 0)))
+    _log(f"  hier + DZS: {cres[2]} merged nodes, g rms rel err {err:.3e}")
+    assert err <= 1e-9
+    ctx.close()
+
+
+def test_hier_rejects(dz):
+    ps, obox, g0 = _case()
+    box = dz.make_box(L, obox.m0, obox.eps0)
+    ctx = dz.Context(ps.n, NG)
+    st = dz.State.from_host(ps, g=g0)
+    sp = _params(dz)
+    sp.do_lightcone = 0
+    for kw in (dict(max_bin=7), dict(max_bin=-1), dict(eta=0.0), dict(a1=A0)):
+        args = dict(max_bin=B, eta=ETA, a0=A0, a1=A1)
+        args.update(kw)
+        with pytest.raises(dz.DZSError):
+            ctx.kdk_step_hier(box, st, sp, args["max_bin"], args["eta"], args["a0"], args["a1"])
+    sp.tree.opening, sp.tree.alpha_open = dz.DZS_OPEN_RELATIVE, 0.01
+    with pytest.raises(dz.DZSError):
+        ctx.kdk_step_hier(box, st, sp, B, ETA, A0, A1)
+    ctx.close()
