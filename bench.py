@@ -865,6 +865,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "for scaling HBM byte counters), then exit")
+    ap.add_argument("--hier", type=int, default=0, metavar="B",
+                    help="individual power-of-two time steps: 2^B sub-steps per global step")
+    ap.add_argument("--eta", type=float, default=0.025,
+                    help="accuracy parameter of the individual time-step bins")
     ap.add_argument("--full-run", choices=("dzs", "std"), default=None,
                     help="with --workload c5: one whole run, DZS or full resolution, its "
                          "lightcone density and timings saved to --out")
@@ -959,7 +963,14 @@ def main():
         t0 = time.perf_counter()
         merged = 0
         for s_ in range(steps):
-            rep = ctx.kdk_step(box, st, params[s_], rg)
+            if args.hier:
+                # individual power-of-two steps inside the global step, limiter at R_lc + b
+                sp_ = params[s_]
+                rep = ctx.kdk_step_hier(box, st, sp_, args.hier, args.eta, sp_.lc.a0, sp_.lc.a1,
+                                        limiter=True,
+                                        R_lim=math.sqrt(sp_.lc.chi2_0) + sp_.coarsen.b, ring=rg)
+            else:
+                rep = ctx.kdk_step(box, st, params[s_], rg)
             merged += int(rep.n_groups)
             if timed and (s_ + 1) % 10 == 0:
                 log(f"  step {s_ + 1}/{steps}")
@@ -1060,7 +1071,10 @@ def main():
                                 f"(l_max {W['lmax_over_lambda']} lambda) + lightcone, "
                                 f"tree theta {W['theta_tree']}, "
                                 + ("precision form (FP32 pair/mesh/FFT, FP64 state)" if fp32
-                                   else "FP64 plain form")),
+                                   else "FP64 plain form")
+                                + (f", individual power-of-two steps (2^{args.hier} sub-steps, "
+                                   f"eta {args.eta}, out-of-lightcone limiter)"
+                                   if args.hier else "")),
                    "preset": args.workload, "particles": N, "mesh": W["ng"], "box": W["L"],
                    "parallelism": "1 GPU"},
         "roofline": roofline, "hbm_kernels": hbm, "cpu_baseline": cpu, "twin": twin,
