@@ -131,20 +131,21 @@ def run_ensemble(args, dz, torch, dzs_ics):
     st = dz.State(N + 64)
     ring = dz.LCRing(1024)
 
-    def params(s_, group, leaf):
+    def params(s_, group, leaf, chunk=0):
         sp_ = dz.step_factors(float(a[s_]), float(a[s_ + 1]), 0.3)
         sp_.do_lightcone, sp_.do_coarsen = 1, 0
-        sp_.pm = dz.PMParams(0, prec, 0.0, 0, 0)
+        sp_.pm = dz.PMParams(0, prec, 0.0, 0, chunk)
         sp_.tree = dz.TreeParams(0.0, 0.0, 0.5, leaf, group, prec, 0)
         return sp_
 
-    def batch_run(steps, group, leaf):
+    def batch_run(steps, group, leaf, chunk=0):
         copy_state(st, st0)
         ring.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s_ in range(steps):
-            ctx.kdk_step_batch(boxes, first, ngs, rss, rcs, st, params(s_, group, leaf), ring)
+            ctx.kdk_step_batch(boxes, first, ngs, rss, rcs, st, params(s_, group, leaf, chunk),
+                               ring)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -156,11 +157,19 @@ def run_ensemble(args, dz, torch, dzs_ics):
             tune[f"group {group} leaf {leaf}"] = (batch_run(1, group, leaf), group, leaf)
     best = min(tune.values())
     group, leaf = best[1], best[2]
-    log(f"autotune: group {group}, leaf {leaf}")
-    batch_run(args.warmup, group, leaf)
+    # deposit tiles: the deposit's own kernel time over two steps per candidate chunk
+    # (-1: direct atomics)
+    dep_tune = {}
+    for chunk in (-1, 256, 1024, 4096):
+        ctx.timing(enable=True, reset=True)
+        batch_run(2, group, leaf, chunk)
+        dep_tune[chunk] = ctx.timing(enable=False, reset=True)["pm_deposit"][0] / 2
+    chunk = min(dep_tune, key=dep_tune.get)
+    log(f"autotune: group {group}, leaf {leaf}, deposit chunk {chunk}")
+    batch_run(args.warmup, group, leaf, chunk)
     ctx.timing(enable=True, reset=True)
     ctx.pair_interactions(reset=True)
-    t_batch = batch_run(K, group, leaf)
+    t_batch = batch_run(K, group, leaf, chunk)
     kern = ctx.timing(enable=False, reset=True)
     pairs = ctx.pair_interactions(reset=True)
     final_eager = {k: getattr(st, k)[: st.n].clone() for k in ("x", "px", "gx")}
@@ -172,11 +181,11 @@ def run_ensemble(args, dz, torch, dzs_ics):
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        ctx.kdk_step_batch(boxes, first, ngs, rss, rcs, st, params(0, group, leaf), ring)
+        ctx.kdk_step_batch(boxes, first, ngs, rss, rcs, st, params(0, group, leaf, chunk), ring)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s_ in range(K):
-        ctx.kdk_step_batch_stage(params(s_, group, leaf))
+        ctx.kdk_step_batch_stage(params(s_, group, leaf, chunk))
         graph.replay()
         torch.cuda.synchronize()
     t_graph = time.perf_counter() - t0
@@ -223,13 +232,13 @@ def run_ensemble(args, dz, torch, dzs_ics):
         pst0 = dz.State(N2 + 64)
         copy_state(pst0, pst)
         for s_ in range(args.warmup):
-            pctx.kdk_step_batch(boxes, first2, ngs, rss, rcs, pst, params(s_, group, leaf), ring)
+            pctx.kdk_step_batch(boxes, first2, ngs, rss, rcs, pst, params(s_, group, leaf, chunk), ring)
         copy_state(pst, pst0)
         ring.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s_ in range(K):
-            pctx.kdk_step_batch(boxes, first2, ngs, rss, rcs, pst, params(s_, group, leaf), ring)
+            pctx.kdk_step_batch(boxes, first2, ngs, rss, rcs, pst, params(s_, group, leaf, chunk), ring)
         torch.cuda.synchronize()
         t_packed = time.perf_counter() - t0
         pctx.close()
@@ -250,7 +259,7 @@ def run_ensemble(args, dz, torch, dzs_ics):
     t0 = time.perf_counter()
     for s_ in range(K):
         for b in range(64):
-            sp_ = params(s_, group, leaf)
+            sp_ = params(s_, group, leaf, chunk)
             sp_.pm = dz.PMParams(ngs[b], prec, rss[b], 0, 0)
             sp_.tree = dz.TreeParams(rss[b], rcs[b], 0.5, leaf, group, prec, 0)
             bctx.kdk_step(boxes[b], states[b], sp_, ring)
@@ -280,8 +289,9 @@ def run_ensemble(args, dz, torch, dzs_ics):
         "ensemble": {"batched_s": t_batch, "graph_replays_s": t_graph,
                      "graph_matches_eager_bitwise": bool(graph_same), "box_by_box_s": t_loop,
                      "batched_speedup": t_loop / t_batch, "graph_speedup": t_loop / t_graph,
-                     "autotuned": {"group": group, "leaf": leaf},
+                     "autotuned": {"group": group, "leaf": leaf, "deposit_chunk": chunk},
                      "autotune_s_per_step": {k: v[0] for k, v in tune.items()},
+                     "autotune_deposit_ms": {str(k): v for k, v in dep_tune.items()},
                      "run_control": repack},
         "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
                                                                     key=lambda kv: -kv[1])},
@@ -297,6 +307,7 @@ def run_lean(args, dz, torch, dzs_ics):
         f = args.n_side / P["n_side"]
         P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
     W = workload(**P)
+    W["deposit_chunk"] = args.deposit_chunk
     W["prec"] = dz.DZS_FP32
     K = max(1, min(args.steps or 3, W["n_steps"] - args.warmup))
     log(f"c5: N={W['N']} L={W['L']} ng={W['ng']} warmup={args.warmup} timed={K}")
@@ -379,6 +390,7 @@ def run_full(args, dz, torch, dzs_ics):
         f = args.n_side / P["n_side"]
         P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
     W = workload(**P)
+    W["deposit_chunk"] = args.deposit_chunk
     W["prec"] = dz.DZS_FP32
     n_steps = min(args.steps or W["n_steps"], W["n_steps"])
     dzs = args.full_run == "dzs"
@@ -592,7 +604,7 @@ def make_params(dz, W, do_coarsen):
         sp.coarsen.b = W["b"]
         sp.coarsen.theta = W["theta_dzs"]
         sp.coarsen.k_min = k_min_for(W["n_side"], W["lmax_over_lambda"])
-        sp.pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, 0)
+        sp.pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, W.get("deposit_chunk", 0))
         sp.tree = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"], W["group"],
                                 W["prec"], 0)
         out.append(sp)
@@ -688,7 +700,7 @@ def force_rate(ctx, box, st, W, dz, torch, reps=10, warm=3):
     """M-F: particle force updates per second of one full force evaluation (PM, then the
     tree: keys, sort, build, walk) on the current state, median of `reps` HIP-event-timed
     calls after `warm` warm-ups; also the tree-only and PM-only times."""
-    pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, 0)
+    pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, W.get("deposit_chunk", 0))
     tp = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"], W["group"], W["prec"], 1)
 
     def timed(fn):
@@ -862,6 +874,8 @@ def main():
                     help="skip the force-only rate (M-F) measured after the run")
     ap.add_argument("--group", type=int, default=0, help="targets per wave group (power of 2)")
     ap.add_argument("--leaf", type=int, default=0, help="particles per tree leaf")
+    ap.add_argument("--deposit-chunk", type=int, default=0,
+                    help="particles per LDS deposit tile (0: library default, -1: direct)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "for scaling HBM byte counters), then exit")
@@ -921,6 +935,7 @@ def main():
         W["group"] = args.group
     if args.leaf:
         W["leaf"] = args.leaf
+    W["deposit_chunk"] = args.deposit_chunk
     prec_name = args.precision or P["precision"]
     W["prec"] = dz.DZS_FP32 if prec_name == "fp32" else dz.DZS_FP64
     fp32 = W["prec"] == dz.DZS_FP32
@@ -935,7 +950,8 @@ def main():
     st0 = dz.State.from_host(ics)
 
     def force(state, prec):
-        ctx.pm_force(box, state, dz.PMParams(W["ng"], prec, W["r_s"], 0, 0))
+        ctx.pm_force(box, state,
+                     dz.PMParams(W["ng"], prec, W["r_s"], 0, W.get("deposit_chunk", 0)))
         ctx.tree_force(box, state, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"],
                                                  W["leaf"], W["group"], prec, 1))
         torch.cuda.synchronize()

@@ -14,6 +14,7 @@
 //   interp      particle, weighted with the same cloud-in-cell weights (one kernel)
 //
 // Mesh layout: index (ix * N_g + iy) * N_g + iz.  Mesh points at j * Delta, Delta = L / N_g.
+#include <limits.h>
 #include <math.h>
 #include <vector>
 
@@ -25,6 +26,7 @@
 #define FFT_MAX_STAGES 12
 #define FFT_MAX_SLOTS 4
 #define DEP_FRAC 4294967296.0  // 2^32: fixed-point scale of the deposit
+#define DEP_TILE 4096          // mesh points of the LDS deposit tile (32 KB of 64-bit sums)
 
 static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
 
@@ -165,18 +167,55 @@ __device__ __forceinline__ void load_twiddles(C *s_tw, const double2 *tw, int n)
 // ---------------------------------------------------------------------------------------
 // deposit
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void cic_axis(double x, double delta, int ng, int &i0, int &i1,
-                                         double &w0, double &w1) {
+// Unwrapped cloud-in-cell base index floor(x / Delta) of one axis and the weights of the
+// base point and the next one.
+__device__ __forceinline__ int cic_base(double x, double delta, double &w0, double &w1) {
     const double u = x / delta;
     const double f = floor(u);
-    int i = (int)f;
     w1 = u - f;
     w0 = 1.0 - w1;
+    return (int)f;
+}
+
+__device__ __forceinline__ int wrap_index(int i, int ng) {
     i %= ng;
-    if (i < 0)
-        i += ng;
+    return i < 0 ? i + ng : i;
+}
+
+__device__ __forceinline__ void cic_axis(double x, double delta, int ng, int &i0, int &i1,
+                                         double &w0, double &w1) {
+    const int i = wrap_index(cic_base(x, delta, w0, w1), ng);
     i0 = i;
     i1 = i + 1 == ng ? 0 : i + 1;
+}
+
+// One corner's contribution in 32.32 fixed point (the same expression on every path, so the
+// integer sums, and with them the mesh, do not depend on which path adds them).
+__device__ __forceinline__ unsigned long long dep_fixed(double m, double wx, double wy, double wz) {
+    return (unsigned long long)llrint(m * wx * wy * wz);
+}
+
+// Direct deposit: eight 64-bit atomic adds per particle into the mesh.
+__device__ __forceinline__ void dep_direct(const double *__restrict__ x, const double *__restrict__ y,
+                                           const double *__restrict__ z,
+                                           const uint32_t *__restrict__ mult, uint64_t p,
+                                           double delta, int ng, unsigned long long *q) {
+    int ix[2], iy[2], iz[2];
+    double wx[2], wy[2], wz[2];
+    cic_axis(x[p], delta, ng, ix[0], ix[1], wx[0], wx[1]);
+    cic_axis(y[p], delta, ng, iy[0], iy[1], wy[0], wy[1]);
+    cic_axis(z[p], delta, ng, iz[0], iz[1], wz[0], wz[1]);
+    const double m = (double)mult[p] * DEP_FRAC;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const unsigned long long iv = dep_fixed(m, wx[a], wy[b], wz[c]);
+                if (iv)
+                    atomicAdd(&q[((uint64_t)ix[a] * ng + iy[b]) * ng + iz[c]], iv);
+            }
 }
 
 __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit(uint64_t n, const double *__restrict__ x,
@@ -195,23 +234,123 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit(uint64_t n, const dou
         ng = bx.ng;
         q += bx.mesh_off;
     }
-    int ix[2], iy[2], iz[2];
-    double wx[2], wy[2], wz[2];
-    cic_axis(x[p], delta, ng, ix[0], ix[1], wx[0], wx[1]);
-    cic_axis(y[p], delta, ng, iy[0], iy[1], wy[0], wy[1]);
-    cic_axis(z[p], delta, ng, iz[0], iz[1], wz[0], wz[1]);
-    const double m = (double)mult[p] * DEP_FRAC;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const double v = m * wx[a] * wy[b] * wz[c];
-                const unsigned long long iv = (unsigned long long)llrint(v);
-                if (iv)
-                    atomicAdd(&q[((uint64_t)ix[a] * ng + iy[b]) * ng + iz[c]], iv);
+    dep_direct(x, y, z, mult, p, delta, ng, q);
+}
+
+// LDS-binned deposit.  A workgroup takes `chunk` consecutive particles (in key order they
+// fill a compact region), finds the box of mesh points their clouds touch (unwrapped
+// indices, so a region across the periodic boundary stays compact) and, when it holds at most
+// DEP_TILE points and the particles share one box of a batch, sums their contributions into
+// an LDS tile with 64-bit LDS atomics and then adds each non-zero tile point to the mesh
+// (wrapped) with one global atomic.  Otherwise the chunk adds directly.  The mesh is the same
+// integer sum either way.
+__global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
+    uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const uint32_t *__restrict__ mult, double delta, int ng,
+    unsigned long long *__restrict__ q, pm_batch B, uint32_t chunk) {
+    __shared__ unsigned long long s_tile[DEP_TILE];
+    __shared__ int s_red[PM_THREADS / 64][8];
+    const uint64_t p0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+    const uint32_t tid = threadIdx.x;
+    // ---- bounding box of the chunk's base indices, and the range of its boxes
+    int lo0 = INT_MAX, lo1 = INT_MAX, lo2 = INT_MAX, hi0 = INT_MIN, hi1 = INT_MIN, hi2 = INT_MIN;
+    int blo = INT_MAX, bhi = INT_MIN;
+    for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+        double d = delta;
+        if (B.boxes) {
+            const int b = (int)(B.key[p] >> DZS_BATCH_SHIFT);
+            d = B.boxes[b].delta;
+            blo = min(blo, b);
+            bhi = max(bhi, b);
+        }
+        double w0, w1;
+        const int i = cic_base(x[p], d, w0, w1), j = cic_base(y[p], d, w0, w1),
+                  k = cic_base(z[p], d, w0, w1);
+        lo0 = min(lo0, i); hi0 = max(hi0, i);
+        lo1 = min(lo1, j); hi1 = max(hi1, j);
+        lo2 = min(lo2, k); hi2 = max(hi2, k);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo0 = min(lo0, __shfl_xor(lo0, o, 64)); hi0 = max(hi0, __shfl_xor(hi0, o, 64));
+        lo1 = min(lo1, __shfl_xor(lo1, o, 64)); hi1 = max(hi1, __shfl_xor(hi1, o, 64));
+        lo2 = min(lo2, __shfl_xor(lo2, o, 64)); hi2 = max(hi2, __shfl_xor(hi2, o, 64));
+        blo = min(blo, __shfl_xor(blo, o, 64)); bhi = max(bhi, __shfl_xor(bhi, o, 64));
+    }
+    if ((tid & 63u) == 0u) {
+        int *r = s_red[tid >> 6];
+        r[0] = lo0; r[1] = lo1; r[2] = lo2; r[3] = hi0; r[4] = hi1; r[5] = hi2;
+        r[6] = blo; r[7] = bhi;
+    }
+    __syncthreads();
+    for (int w = 0; w < PM_THREADS / 64; ++w) {
+        const int *r = s_red[w];
+        lo0 = min(lo0, r[0]); lo1 = min(lo1, r[1]); lo2 = min(lo2, r[2]);
+        hi0 = max(hi0, r[3]); hi1 = max(hi1, r[4]); hi2 = max(hi2, r[5]);
+        blo = min(blo, r[6]); bhi = max(bhi, r[7]);
+    }
+    // points spanned per axis (base .. base + 1); every thread holds the same values, so the
+    // choice below is uniform over the workgroup
+    const int64_t ex = (int64_t)hi0 - lo0 + 2, ey = (int64_t)hi1 - lo1 + 2,
+                  ez = (int64_t)hi2 - lo2 + 2;
+    const bool fits = (!B.boxes || blo == bhi) && ex <= DEP_TILE && ey <= DEP_TILE && ez <= DEP_TILE &&
+                      ex * ey * ez <= DEP_TILE;
+    unsigned long long *qb = q;
+    if (B.boxes && blo == bhi) {
+        const dzs_bbox &bx = B.boxes[blo];
+        delta = bx.delta;
+        ng = bx.ng;
+        qb = q + bx.mesh_off;
+    }
+    if (!fits) {
+        for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+            double d = delta;
+            int g = ng;
+            unsigned long long *qq = q;
+            if (B.boxes) {
+                const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
+                d = bx.delta;
+                g = bx.ng;
+                qq = q + bx.mesh_off;
             }
+            dep_direct(x, y, z, mult, p, d, g, qq);
+        }
+        return;
+    }
+    const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez;
+    const uint32_t cells = (uint32_t)(ex * ey * ez);
+    for (uint32_t c = tid; c < cells; c += PM_THREADS)
+        s_tile[c] = 0ull;
+    __syncthreads();
+    for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+        double wx[2], wy[2], wz[2];
+        const uint32_t i = (uint32_t)(cic_base(x[p], delta, wx[0], wx[1]) - lo0);
+        const uint32_t j = (uint32_t)(cic_base(y[p], delta, wy[0], wy[1]) - lo1);
+        const uint32_t k = (uint32_t)(cic_base(z[p], delta, wz[0], wz[1]) - lo2);
+        const double m = (double)mult[p] * DEP_FRAC;
+#pragma unroll
+        for (uint32_t a = 0; a < 2; ++a)
+#pragma unroll
+            for (uint32_t b = 0; b < 2; ++b)
+#pragma unroll
+                for (uint32_t c = 0; c < 2; ++c) {
+                    const unsigned long long iv = dep_fixed(m, wx[a], wy[b], wz[c]);
+                    if (iv)
+                        atomicAdd(&s_tile[((i + a) * tey + (j + b)) * tez + (k + c)], iv);
+                }
+    }
+    __syncthreads();
+    const uint32_t pyz = tey * tez;
+    for (uint32_t c = tid; c < cells; c += PM_THREADS) {
+        const unsigned long long v = s_tile[c];
+        if (!v)
+            continue;
+        const uint32_t a = c / pyz, r = c - a * pyz;
+        const uint32_t b = r / tez, e = r - b * tez;
+        const int ix = wrap_index(lo0 + (int)a, ng), iy = wrap_index(lo1 + (int)b, ng),
+                  iz = wrap_index(lo2 + (int)e, ng);
+        atomicAdd(&qb[((uint64_t)ix * ng + iy) * ng + iz], v);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -507,21 +646,31 @@ __global__ __launch_bounds__(PM_THREADS) void k_zero_u64(uint64_t n, unsigned lo
         a[i] = 0ull;
 }
 
+// chunk: particles per LDS tile (a power of two in [DZS_DEPOSIT_CHUNK_MIN, _MAX]), 0 for the
+// default, -1 for the direct deposit.
 static dzs_status pm_deposit(dzs_ctx *ctx, const dzs_particles *p, uint64_t cells, double delta,
-                             int ng, pm_batch B, hipStream_t s) {
+                             int ng, pm_batch B, int32_t chunk, hipStream_t s) {
     dzs_timed t(ctx, KC_PM_DEPOSIT, s);
     const uint64_t zb = (cells + PM_THREADS - 1) / PM_THREADS;
     hipLaunchKernelGGL(k_zero_u64, dim3((uint32_t)(zb < 65536 ? zb : 65536)), dim3(PM_THREADS), 0,
                        s, cells, (unsigned long long *)ctx->mesh_q);
     DZS_TRY(dzs_check_launch(ctx, "mesh_clear"));
-    if (p->n > 0) {
+    if (p->n == 0)
+        return DZS_OK;
+    if (chunk == 0)
+        chunk = DZS_DEPOSIT_CHUNK_DEFAULT;
+    if (chunk < 0) {
         hipLaunchKernelGGL(k_pm_deposit, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0, s,
                            p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,
                            (const uint32_t *)p->mult, delta, ng, (unsigned long long *)ctx->mesh_q,
                            B);
-        DZS_TRY(dzs_check_launch(ctx, "pm_deposit"));
+    } else {
+        hipLaunchKernelGGL(k_pm_deposit_tiled, dim3(blocks_for(p->n, (uint32_t)chunk)),
+                           dim3(PM_THREADS), 0, s, p->n, (const double *)p->x,
+                           (const double *)p->y, (const double *)p->z, (const uint32_t *)p->mult,
+                           delta, ng, (unsigned long long *)ctx->mesh_q, B, (uint32_t)chunk);
     }
-    return DZS_OK;
+    return dzs_check_launch(ctx, "pm_deposit");
 }
 
 dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
@@ -542,7 +691,7 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
     const double *gt = ctx->pm_tables + 2 * ng;
     const double *k2t = ctx->pm_tables + 3 * ng;
     const pm_batch none{nullptr, nullptr, 0, nullptr};
-    DZS_TRY(pm_deposit(ctx, p, ng3, delta, ng, none, s));
+    DZS_TRY(pm_deposit(ctx, p, ng3, delta, ng, none, prm->deposit_chunk, s));
     const int TZ = tile_lines(ng, 16);
     const int TL = tile_lines(ng, FFT_ELEMS);
     const double q_scale = box->m0 / (DEP_FRAC * delta * delta * delta);
@@ -637,10 +786,10 @@ dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStre
 
 // The long-range force of every box of a prepared batch into g (g = g_long); db is the device
 // box table and ctx->key the sorted keys (box in the top digits) of the particles.
-dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision, const dzs_bbox *db,
-                            double G, hipStream_t s) {
+dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
+                            int32_t deposit_chunk, const dzs_bbox *db, double G, hipStream_t s) {
     const pm_batch all{db, nullptr, 0, (const uint64_t *)ctx->key};
-    DZS_TRY(pm_deposit(ctx, p, ctx->batch_cells, 0.0, 0, all, s));
+    DZS_TRY(pm_deposit(ctx, p, ctx->batch_cells, 0.0, 0, all, deposit_chunk, s));
     for (size_t c = 0; c < ctx->batch_sides.size(); ++c) {
         const int ng = ctx->batch_sides[c];
         fft_plan P;

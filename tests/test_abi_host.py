@@ -89,3 +89,15 @@ def test_null_context_is_an_error_not_a_crash():
     assert L.dzs_ctx_destroy(None) == _abi.DZS_EINVAL
     h = C.c_void_p()
     assert L.dzs_ctx_create(C.byref(h), 0, None) == _abi.DZS_EINVAL
+
+
+def test_header_constants_match_the_binding():
+    """Every #define of include/dzs.h that the ctypes mirror repeats has the same value."""
+    from paper_2005_05328_amd import _abi
+    txt = open(os.path.join(ROOT, "include", "dzs.h")).read()
+    defs = dict(re.findall(r"^#define\s+(DZS_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", txt, flags=re.M))
+    shared = [k for k in defs if hasattr(_abi, k)]
+    assert {"DZS_DEPOSIT_CHUNK_MIN", "DZS_DEPOSIT_CHUNK_MAX", "DZS_DEPOSIT_CHUNK_DEFAULT",
+            "DZS_FP32", "DZS_BATCH_MAX"} <= set(shared)
+    for k in shared:
+        assert getattr(_abi, k) == int(defs[k]), k

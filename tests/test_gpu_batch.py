@@ -230,3 +230,31 @@ def test_batched_steps_back_to_back_are_deterministic(dz):
     ctx.close()
     for k in ("x", "y", "z", "px", "py", "pz", "gx", "gy", "gz", "id"):
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_batched_deposit_chunks_give_identical_steps(dz):
+    """The LDS-binned deposit in a batch (a chunk spanning two boxes adds directly): one
+    batched step with the direct deposit and with tiles of 256 and the default gives
+    bit-identical states (the mesh is the same integer sum)."""
+    import torch
+    sets, boxes, _, first, ng, r_s, r_cut = _setup(dz)
+    allp = _concat(sets)
+    ctx = dz.Context(max_particles=first[-1] + 64, max_mesh_side=81)
+    ring = dz.LCRing(1024)
+    outs = []
+    for chunk in (-1, 256, 0):
+        st = dz.State.from_host(allp)
+        ring.reset()
+        sp = dz.step_factors(0.1, 0.11, 0.3)
+        sp.do_lightcone, sp.do_coarsen = 1, 0
+        sp.pm = dz.PMParams(0, dz.DZS_FP64, 0.0, 0, chunk)
+        sp.tree = dz.TreeParams(0.0, 0.0, 0.5, 16, 32, dz.DZS_FP64, 0)
+        _log(f"batched step, deposit chunk {chunk}")
+        ctx.kdk_step_batch(boxes, first, ng, r_s, r_cut, st, sp, ring)
+        torch.cuda.synchronize()
+        outs.append(st.to_host())
+    ctx.check()
+    ctx.close()
+    for o in outs[1:]:
+        for k in ("x", "y", "z", "px", "py", "pz", "gx", "gy", "gz", "id"):
+            assert np.array_equal(outs[0][k], o[k]), k
