@@ -52,12 +52,14 @@ def log(msg):
 PRESETS = {
     "c2": dict(n_side=128, L=256.0, ng=256, seed=20050529, n_steps=50, lmax_over_lambda=2,
                precision="fp64", twin="dzs"),
+    # leaves of 8 for the large clustered runs (the 512^3 run's walk: 310 ms per launch
+    # against 330 with leaves of 16); 16 at 128^3
     "c3": dict(n_side=512, L=1000.0, ng=512, seed=20050530, n_steps=50, lmax_over_lambda=4,
-               precision="fp32", twin="precision"),
+               precision="fp32", twin="precision", leaf=8),
     "c5s": dict(n_side=256, L=2000.0, ng=256, seed=20050532, n_steps=100, lmax_over_lambda=4,
-                precision="fp32", twin="dzs"),
+                precision="fp32", twin="dzs", leaf=8),
     "c5": dict(n_side=1024, L=2000.0, ng=1024, seed=20050532, n_steps=100, lmax_over_lambda=4,
-               precision="fp32", twin="dzs"),
+               precision="fp32", twin="dzs", leaf=8),
     # the 64-box ensemble: run by run_ensemble(), not by the single-box path
     "c4": dict(n_side=0, L=0.0, ng=0, seed=20051000, n_steps=10, lmax_over_lambda=0,
                precision="fp32", twin=None),
@@ -157,15 +159,16 @@ def run_ensemble(args, dz, torch, dzs_ics):
             tune[f"group {group} leaf {leaf}"] = (batch_run(1, group, leaf), group, leaf)
     best = min(tune.values())
     group, leaf = best[1], best[2]
-    # deposit tiles: the deposit's own kernel time over two steps per candidate chunk
-    # (-1: direct atomics)
+    # PM tiles: deposit + interpolation kernel time over two steps per candidate chunk
+    # (-1: no tiles)
     dep_tune = {}
     for chunk in (-1, 256, 1024, 4096):
         ctx.timing(enable=True, reset=True)
         batch_run(2, group, leaf, chunk)
-        dep_tune[chunk] = ctx.timing(enable=False, reset=True)["pm_deposit"][0] / 2
+        tk = ctx.timing(enable=False, reset=True)
+        dep_tune[chunk] = (tk["pm_deposit"][0] + tk["pm_interp"][0]) / 2
     chunk = min(dep_tune, key=dep_tune.get)
-    log(f"autotune: group {group}, leaf {leaf}, deposit chunk {chunk}")
+    log(f"autotune: group {group}, leaf {leaf}, PM tile chunk {chunk}")
     batch_run(args.warmup, group, leaf, chunk)
     ctx.timing(enable=True, reset=True)
     ctx.pair_interactions(reset=True)
@@ -289,9 +292,9 @@ def run_ensemble(args, dz, torch, dzs_ics):
         "ensemble": {"batched_s": t_batch, "graph_replays_s": t_graph,
                      "graph_matches_eager_bitwise": bool(graph_same), "box_by_box_s": t_loop,
                      "batched_speedup": t_loop / t_batch, "graph_speedup": t_loop / t_graph,
-                     "autotuned": {"group": group, "leaf": leaf, "deposit_chunk": chunk},
+                     "autotuned": {"group": group, "leaf": leaf, "tile_chunk": chunk},
                      "autotune_s_per_step": {k: v[0] for k, v in tune.items()},
-                     "autotune_deposit_ms": {str(k): v for k, v in dep_tune.items()},
+                     "autotune_pm_tiles_ms": {str(k): v for k, v in dep_tune.items()},
                      "run_control": repack},
         "kernels_ms_per_step": {c: round(v / K, 4) for c, v in sorted(totals.items(),
                                                                     key=lambda kv: -kv[1])},
@@ -307,7 +310,9 @@ def run_lean(args, dz, torch, dzs_ics):
         f = args.n_side / P["n_side"]
         P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
     W = workload(**P)
-    W["deposit_chunk"] = args.deposit_chunk
+    W["tile_chunk"] = args.pm_chunk
+    W["group"] = args.group or W["group"]
+    W["leaf"] = args.leaf or W["leaf"]
     W["prec"] = dz.DZS_FP32
     K = max(1, min(args.steps or 3, W["n_steps"] - args.warmup))
     log(f"c5: N={W['N']} L={W['L']} ng={W['ng']} warmup={args.warmup} timed={K}")
@@ -390,7 +395,9 @@ def run_full(args, dz, torch, dzs_ics):
         f = args.n_side / P["n_side"]
         P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
     W = workload(**P)
-    W["deposit_chunk"] = args.deposit_chunk
+    W["tile_chunk"] = args.pm_chunk
+    W["group"] = args.group or W["group"]
+    W["leaf"] = args.leaf or W["leaf"]
     W["prec"] = dz.DZS_FP32
     n_steps = min(args.steps or W["n_steps"], W["n_steps"])
     dzs = args.full_run == "dzs"
@@ -576,13 +583,13 @@ def _smooth(n):
 
 
 def workload(n_side=128, L=256.0, ng=256, seed=20050529, n_steps=50, lmax_over_lambda=2,
-             **_):
+             leaf=16, **_):
     import dzs_ics
     lam = L / n_side
     return dict(n_side=n_side, N=n_side ** 3, L=L, ng=ng, r_s=1.25 * L / ng,
                 r_cut=4.5 * 1.25 * L / ng, eps0=lam / 40, m0=dzs_ics.particle_mass(L, n_side ** 3),
                 lam=lam, a_init=1.0 / 50.0, n_steps=n_steps, theta_tree=0.5, theta_dzs=0.1,
-                b=5 * lam, lmax_over_lambda=lmax_over_lambda, seed=seed, leaf=16, group=32)
+                b=5 * lam, lmax_over_lambda=lmax_over_lambda, seed=seed, leaf=leaf, group=32)
 
 
 def k_min_for(n_side, j):
@@ -604,7 +611,7 @@ def make_params(dz, W, do_coarsen):
         sp.coarsen.b = W["b"]
         sp.coarsen.theta = W["theta_dzs"]
         sp.coarsen.k_min = k_min_for(W["n_side"], W["lmax_over_lambda"])
-        sp.pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, W.get("deposit_chunk", 0))
+        sp.pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, W.get("tile_chunk", 0))
         sp.tree = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"], W["group"],
                                 W["prec"], 0)
         out.append(sp)
@@ -700,7 +707,7 @@ def force_rate(ctx, box, st, W, dz, torch, reps=10, warm=3):
     """M-F: particle force updates per second of one full force evaluation (PM, then the
     tree: keys, sort, build, walk) on the current state, median of `reps` HIP-event-timed
     calls after `warm` warm-ups; also the tree-only and PM-only times."""
-    pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, W.get("deposit_chunk", 0))
+    pm = dz.PMParams(W["ng"], W["prec"], W["r_s"], 0, W.get("tile_chunk", 0))
     tp = dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"], W["leaf"], W["group"], W["prec"], 1)
 
     def timed(fn):
@@ -874,8 +881,8 @@ def main():
                     help="skip the force-only rate (M-F) measured after the run")
     ap.add_argument("--group", type=int, default=0, help="targets per wave group (power of 2)")
     ap.add_argument("--leaf", type=int, default=0, help="particles per tree leaf")
-    ap.add_argument("--deposit-chunk", type=int, default=0,
-                    help="particles per LDS deposit tile (0: library default, -1: direct)")
+    ap.add_argument("--pm-chunk", type=int, default=0,
+                    help="particles per LDS tile of deposit and interpolation (0: default, -1: none)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the reference "
                          "for scaling HBM byte counters), then exit")
@@ -935,7 +942,7 @@ def main():
         W["group"] = args.group
     if args.leaf:
         W["leaf"] = args.leaf
-    W["deposit_chunk"] = args.deposit_chunk
+    W["tile_chunk"] = args.pm_chunk
     prec_name = args.precision or P["precision"]
     W["prec"] = dz.DZS_FP32 if prec_name == "fp32" else dz.DZS_FP64
     fp32 = W["prec"] == dz.DZS_FP32
@@ -951,7 +958,7 @@ def main():
 
     def force(state, prec):
         ctx.pm_force(box, state,
-                     dz.PMParams(W["ng"], prec, W["r_s"], 0, W.get("deposit_chunk", 0)))
+                     dz.PMParams(W["ng"], prec, W["r_s"], 0, W.get("tile_chunk", 0)))
         ctx.tree_force(box, state, dz.TreeParams(W["r_s"], W["r_cut"], W["theta_tree"],
                                                  W["leaf"], W["group"], prec, 1))
         torch.cuda.synchronize()

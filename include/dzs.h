@@ -128,20 +128,24 @@ typedef struct {
                             and interpolation in FP32 (rms error ~1e-6 of the force) */
     double r_s;          /* split scale */
     int32_t accumulate;  /* 0: g = g_long, 1: g += g_long */
-    int32_t deposit_chunk; /* LDS-binned deposit: particles per workgroup tile, a power of two
-                            in [DZS_DEPOSIT_CHUNK_MIN, DZS_DEPOSIT_CHUNK_MAX]; 0 = the library's
-                            default (DZS_DEPOSIT_CHUNK_DEFAULT); -1 = direct global atomics.
-                            A workgroup sums its chunk of consecutive particles (compact in key
-                            order) into an LDS tile spanning their cloud-in-cell points, up to
-                            4096 of them, and adds each non-zero point to the mesh once; a
-                            chunk whose points do not fit (or, in a batch, that spans two
-                            boxes) adds directly.  The mesh is the same integer sum for every
-                            value: the choice changes speed only. */
+    int32_t tile_chunk;  /* particles per workgroup tile of the deposit and of the
+                            interpolation: a power of two in [DZS_PM_CHUNK_MIN,
+                            DZS_PM_CHUNK_MAX]; 0 = the library's default
+                            (DZS_PM_CHUNK_DEFAULT); -1 = no tiles.  A workgroup takes a chunk of
+                            consecutive particles (compact in key order).  Deposit: it sums
+                            their cloud-in-cell contributions into an LDS tile spanning their
+                            points, up to 4096 of them, and adds each non-zero point to the mesh
+                            once.  Interpolation (only when the particles are at least half as
+                            many as the mesh points): it loads the potential their 4-point
+                            stencils read, up to 4096 values, into LDS once.  A chunk whose points do
+                            not fit (or, in a batch, that spans two boxes) reads and adds
+                            directly.  Mesh and forces are the same bits for every value: the
+                            choice changes speed only. */
 } dzs_pm_params;
 
-#define DZS_DEPOSIT_CHUNK_MIN 256
-#define DZS_DEPOSIT_CHUNK_MAX 16384
-#define DZS_DEPOSIT_CHUNK_DEFAULT 256
+#define DZS_PM_CHUNK_MIN 256
+#define DZS_PM_CHUNK_MAX 16384
+#define DZS_PM_CHUNK_DEFAULT 256
 
 /* Tree (short-range) parameters: g_i = -G sum m_j r_ij g_soft(r_ij, h_ij) S(r_ij/r_s) over
  * sources closer than r_cut, S(u) = erfc(u/2) + u/sqrt(pi) exp(-u^2/4).  Opening criteria

@@ -14,8 +14,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (DZS_CRIT_DYNAMICAL, DZS_CRIT_GEOMETRIC, DZS_DEPOSIT_CHUNK_DEFAULT,
-                   DZS_DEPOSIT_CHUNK_MAX, DZS_DEPOSIT_CHUNK_MIN, DZS_FP32, DZS_FP64,
+from ._abi import (DZS_CRIT_DYNAMICAL, DZS_CRIT_GEOMETRIC, DZS_PM_CHUNK_DEFAULT,
+                   DZS_PM_CHUNK_MAX, DZS_PM_CHUNK_MIN, DZS_FP32, DZS_FP64,
                    DZS_OPEN_GEOMETRIC, DZS_OPEN_RELATIVE, Box,
                    CoarsenParams, CoarsenReport, LCParams, LCRecord, PMParams, StepParams,
                    TreeParams)
@@ -25,8 +25,8 @@ _lib = _abi.load()
 __all__ = ["Context", "State", "Box", "CoarsenParams", "PMParams", "TreeParams", "LCParams",
            "StepParams", "LCRing", "DZSError", "step_factors", "DZS_FP64", "DZS_FP32",
            "DZS_CRIT_GEOMETRIC", "DZS_CRIT_DYNAMICAL", "DZS_OPEN_GEOMETRIC",
-           "DZS_OPEN_RELATIVE", "DZS_DEPOSIT_CHUNK_MIN", "DZS_DEPOSIT_CHUNK_MAX",
-           "DZS_DEPOSIT_CHUNK_DEFAULT", "halt_check", "forecast_speedup",
+           "DZS_OPEN_RELATIVE", "DZS_PM_CHUNK_MIN", "DZS_PM_CHUNK_MAX",
+           "DZS_PM_CHUNK_DEFAULT", "halt_check", "forecast_speedup",
            "lib"]
 
 

@@ -27,7 +27,7 @@ EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_fact
 DZS_HIER_MAX_BIN = 6
 DZS_HALT_BALANCE, DZS_HALT_RATIO, DZS_HALT_PREDICTED = 1, 2, 4
 DZS_BATCH_MAX = 512
-DZS_DEPOSIT_CHUNK_MIN, DZS_DEPOSIT_CHUNK_MAX, DZS_DEPOSIT_CHUNK_DEFAULT = 256, 16384, 256
+DZS_PM_CHUNK_MIN, DZS_PM_CHUNK_MAX, DZS_PM_CHUNK_DEFAULT = 256, 16384, 256
 
 
 class HierParams(C.Structure):
@@ -79,7 +79,7 @@ class CoarsenReport(C.Structure):
 
 class PMParams(C.Structure):
     _fields_ = [("ng", C.c_int32), ("precision", C.c_int32), ("r_s", C.c_double),
-                ("accumulate", C.c_int32), ("deposit_chunk", C.c_int32)]
+                ("accumulate", C.c_int32), ("tile_chunk", C.c_int32)]
 
 
 class TreeParams(C.Structure):

@@ -384,11 +384,11 @@ static dzs_status check_pm(dzs_ctx *ctx, const dzs_pm_params *m) {
         return dzs_fail(ctx, DZS_EINVAL, "pm: r_s must be positive");
     if (m->precision != DZS_FP64 && m->precision != DZS_FP32)
         return dzs_fail(ctx, DZS_EINVAL, "pm: precision must be DZS_FP64 or DZS_FP32");
-    const int32_t dc = m->deposit_chunk;
+    const int32_t dc = m->tile_chunk;
     if (dc != 0 && dc != -1 &&
-        (dc < DZS_DEPOSIT_CHUNK_MIN || dc > DZS_DEPOSIT_CHUNK_MAX || (dc & (dc - 1)) != 0))
-        return dzs_fail(ctx, DZS_EINVAL, "pm: deposit_chunk %d must be 0, -1 or a power of two "
-                        "in [%d, %d]", dc, DZS_DEPOSIT_CHUNK_MIN, DZS_DEPOSIT_CHUNK_MAX);
+        (dc < DZS_PM_CHUNK_MIN || dc > DZS_PM_CHUNK_MAX || (dc & (dc - 1)) != 0))
+        return dzs_fail(ctx, DZS_EINVAL, "pm: tile_chunk %d must be 0, -1 or a power of two "
+                        "in [%d, %d]", dc, DZS_PM_CHUNK_MIN, DZS_PM_CHUNK_MAX);
     if (m->precision == DZS_FP64 && ctx->fp32_meshes)
         return dzs_fail(ctx, DZS_EINVAL, "pm: the context holds meshes for the precision form "
                         "only (DZS_CAP_FP32_MESHES)");
@@ -885,7 +885,7 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     DZS_TRY(dzs_tree_build_ex(ctx, &batch->boxes[0], st->n, st->x, st->y, st->z, st->mult,
                               t.leaf_size, t.group_size, DZS_BATCH_LEVELS, ctx->batch_box, s));
     DZS_TRY(dzs_batch_roots(ctx, ctx->batch_box, s));
-    DZS_TRY(dzs_pm_run_batch(ctx, st, prm->pm.precision, prm->pm.deposit_chunk, ctx->batch_box,
+    DZS_TRY(dzs_pm_run_batch(ctx, st, prm->pm.precision, prm->pm.tile_chunk, ctx->batch_box,
                              batch->boxes[0].G, s));
     t.r_s = batch->r_s[0];
     t.r_cut = batch->r_cut[0];

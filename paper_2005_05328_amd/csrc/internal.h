@@ -364,7 +364,7 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                       const dzs_pm_params *prm, hipStream_t s);
 dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStream_t s);
 dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
-                            int32_t deposit_chunk, const dzs_bbox *db, double G, hipStream_t s);
+                            int32_t tile_chunk, const dzs_bbox *db, double G, hipStream_t s);
 
 // coarsen.hip
 // d_small word slots: 8 the coarsening survivor count, 9 its head count, 16..17 the bits of

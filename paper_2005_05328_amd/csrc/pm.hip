@@ -27,6 +27,7 @@
 #define FFT_MAX_SLOTS 4
 #define DEP_FRAC 4294967296.0  // 2^32: fixed-point scale of the deposit
 #define DEP_TILE 4096          // mesh points of the LDS deposit tile (32 KB of 64-bit sums)
+#define INTERP_TILE 4096       // potential values of the LDS interpolation tile
 
 static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
 
@@ -237,25 +238,18 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit(uint64_t n, const dou
     dep_direct(x, y, z, mult, p, delta, ng, q);
 }
 
-// LDS-binned deposit.  A workgroup takes `chunk` consecutive particles (in key order they
-// fill a compact region), finds the box of mesh points their clouds touch (unwrapped
-// indices, so a region across the periodic boundary stays compact) and, when it holds at most
-// DEP_TILE points and the particles share one box of a batch, sums their contributions into
-// an LDS tile with 64-bit LDS atomics and then adds each non-zero tile point to the mesh
-// (wrapped) with one global atomic.  Otherwise the chunk adds directly.  The mesh is the same
-// integer sum either way.
-__global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
-    uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const uint32_t *__restrict__ mult, double delta, int ng,
-    unsigned long long *__restrict__ q, pm_batch B, uint32_t chunk) {
-    __shared__ unsigned long long s_tile[DEP_TILE];
-    __shared__ int s_red[PM_THREADS / 64][8];
-    const uint64_t p0 = (uint64_t)blockIdx.x * chunk;
-    const uint64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+// Bounding box of the cloud-in-cell base indices of particles [p0, p1) (unwrapped) and the
+// range of their boxes (batch), reduced over the workgroup: every thread returns the same
+// values.  s_red: PM_THREADS / 64 rows of 8 ints of LDS.
+__device__ __forceinline__ void chunk_bounds(uint64_t p0, uint64_t p1, const double *__restrict__ x,
+                                             const double *__restrict__ y,
+                                             const double *__restrict__ z, double delta,
+                                             const pm_batch &B, int (*s_red)[8], int &lo0,
+                                             int &lo1, int &lo2, int &hi0, int &hi1, int &hi2,
+                                             int &blo, int &bhi) {
     const uint32_t tid = threadIdx.x;
-    // ---- bounding box of the chunk's base indices, and the range of its boxes
-    int lo0 = INT_MAX, lo1 = INT_MAX, lo2 = INT_MAX, hi0 = INT_MIN, hi1 = INT_MIN, hi2 = INT_MIN;
-    int blo = INT_MAX, bhi = INT_MIN;
+    lo0 = lo1 = lo2 = blo = INT_MAX;
+    hi0 = hi1 = hi2 = bhi = INT_MIN;
     for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
         double d = delta;
         if (B.boxes) {
@@ -289,12 +283,32 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
         hi0 = max(hi0, r[3]); hi1 = max(hi1, r[4]); hi2 = max(hi2, r[5]);
         blo = min(blo, r[6]); bhi = max(bhi, r[7]);
     }
+}
+
+// LDS-binned deposit.  A workgroup takes `chunk` consecutive particles (in key order they
+// fill a compact region), finds the box of mesh points their clouds touch (unwrapped
+// indices, so a region across the periodic boundary stays compact) and, when it holds at most
+// DEP_TILE points and the particles share one box of a batch, sums their contributions into
+// an LDS tile with 64-bit LDS atomics and then adds each non-zero tile point to the mesh
+// (wrapped) with one global atomic.  Otherwise the chunk adds directly.  The mesh is the same
+// integer sum either way.
+__global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
+    uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const uint32_t *__restrict__ mult, double delta, int ng,
+    unsigned long long *__restrict__ q, pm_batch B, uint32_t chunk) {
+    __shared__ unsigned long long s_tile[DEP_TILE];
+    __shared__ int s_red[PM_THREADS / 64][8];
+    const uint64_t p0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+    const uint32_t tid = threadIdx.x;
+    int lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi;
+    chunk_bounds(p0, p1, x, y, z, delta, B, s_red, lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi);
     // points spanned per axis (base .. base + 1); every thread holds the same values, so the
     // choice below is uniform over the workgroup
     const int64_t ex = (int64_t)hi0 - lo0 + 2, ey = (int64_t)hi1 - lo1 + 2,
                   ez = (int64_t)hi2 - lo2 + 2;
-    const bool fits = (!B.boxes || blo == bhi) && ex <= DEP_TILE && ey <= DEP_TILE && ez <= DEP_TILE &&
-                      ex * ey * ez <= DEP_TILE;
+    const bool fits = (!B.boxes || blo == bhi) && ex <= DEP_TILE && ey <= DEP_TILE &&
+                      ez <= DEP_TILE && ex * ey * ez <= DEP_TILE;
     unsigned long long *qb = q;
     if (B.boxes && blo == bhi) {
         const dzs_bbox &bx = B.boxes[blo];
@@ -461,6 +475,75 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(C *__restrict__ c,
 // ---------------------------------------------------------------------------------------
 // gradient + interpolation
 // ---------------------------------------------------------------------------------------
+// The 4-point difference of the potential at the 8 cloud-in-cell points of one particle,
+// weighted with the cloud-in-cell weights.  at(a, b, c) returns the potential at index offsets
+// from the particle's base point (a, b, c in [-2, 3]); both paths below run this same
+// arithmetic, so they give the same bits.
+template <typename Rt, typename At>
+__device__ __forceinline__ void cic_gradient(const At &at, const double *wx, const double *wy,
+                                             const double *wz, Rt &sx, Rt &sy, Rt &sz) {
+    const Rt c1 = Rt(2.0 / 3.0), c2 = Rt(1.0 / 12.0);
+    sx = sy = sz = Rt(0.0);
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const Rt w = Rt(wx[a] * wy[b] * wz[c]);
+                const Rt dxp = c1 * (at(a + 1, b, c) - at(a - 1, b, c)) -
+                               c2 * (at(a + 2, b, c) - at(a - 2, b, c));
+                const Rt dyp = c1 * (at(a, b + 1, c) - at(a, b - 1, c)) -
+                               c2 * (at(a, b + 2, c) - at(a, b - 2, c));
+                const Rt dzp = c1 * (at(a, b, c + 1) - at(a, b, c - 1)) -
+                               c2 * (at(a, b, c + 2) - at(a, b, c - 2));
+                sx += w * dxp;
+                sy += w * dyp;
+                sz += w * dzp;
+            }
+}
+
+// index i0 + d wrapped to [0, ng) for |d| <= 3 < ng
+__device__ __forceinline__ int wrap_near(int i, int ng) {
+    return i < 0 ? i + ng : (i >= ng ? i - ng : i);
+}
+
+template <typename Rt>
+__device__ __forceinline__ void interp_store(uint64_t p, double delta, Rt sx, Rt sy, Rt sz,
+                                             double *__restrict__ gx, double *__restrict__ gy,
+                                             double *__restrict__ gz, int accumulate) {
+    const double s = -1.0 / delta;
+    if (accumulate) {
+        gx[p] += s * (double)sx;
+        gy[p] += s * (double)sy;
+        gz[p] += s * (double)sz;
+    } else {
+        gx[p] = s * (double)sx;
+        gy[p] = s * (double)sy;
+        gz[p] = s * (double)sz;
+    }
+}
+
+// Direct: the potential read from the mesh (wrapped indices).
+template <typename Rt>
+__device__ __forceinline__ void interp_direct(const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z,
+                                              const Rt *__restrict__ phi, uint64_t p, double delta,
+                                              int ng, double *__restrict__ gx,
+                                              double *__restrict__ gy, double *__restrict__ gz,
+                                              int accumulate) {
+    double wx[2], wy[2], wz[2];
+    const int i = wrap_index(cic_base(x[p], delta, wx[0], wx[1]), ng);
+    const int j = wrap_index(cic_base(y[p], delta, wy[0], wy[1]), ng);
+    const int k = wrap_index(cic_base(z[p], delta, wz[0], wz[1]), ng);
+    const uint64_t N = (uint64_t)ng;
+    auto at = [&](int a, int b, int c) -> Rt {
+        return phi[((uint64_t)wrap_near(i + a, ng) * N + wrap_near(j + b, ng)) * N +
+                   wrap_near(k + c, ng)];
+    };
+    Rt sx, sy, sz;
+    cic_gradient<Rt>(at, wx, wy, wz, sx, sy, sz);
+    interp_store<Rt>(p, delta, sx, sy, sz, gx, gy, gz, accumulate);
+}
+
 template <typename Rt>
 __global__ __launch_bounds__(PM_THREADS) void k_pm_interp(
     uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
@@ -476,44 +559,74 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_interp(
         ng = bx.ng;
         phi += bx.mesh_off;
     }
-    int ix[2], iy[2], iz[2];
-    double wx[2], wy[2], wz[2];
-    cic_axis(x[p], delta, ng, ix[0], ix[1], wx[0], wx[1]);
-    cic_axis(y[p], delta, ng, iy[0], iy[1], wy[0], wy[1]);
-    cic_axis(z[p], delta, ng, iz[0], iz[1], wz[0], wz[1]);
-    const uint64_t N = (uint64_t)ng;
-    auto at = [&](int a, int b, int c) -> Rt {
-        a = (a % ng + ng) % ng;
-        b = (b % ng + ng) % ng;
-        c = (c % ng + ng) % ng;
-        return phi[((uint64_t)a * N + b) * N + c];
-    };
-    const Rt c1 = Rt(2.0 / 3.0), c2 = Rt(1.0 / 12.0);
-    Rt sx = Rt(0.0), sy = Rt(0.0), sz = Rt(0.0);
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int c = 0; c < 2; ++c) {
-                const Rt w = Rt(wx[a] * wy[b] * wz[c]);
-                const int i = ix[a], j = iy[b], k = iz[c];
-                const Rt dxp = c1 * (at(i + 1, j, k) - at(i - 1, j, k)) -
-                               c2 * (at(i + 2, j, k) - at(i - 2, j, k));
-                const Rt dyp = c1 * (at(i, j + 1, k) - at(i, j - 1, k)) -
-                               c2 * (at(i, j + 2, k) - at(i, j - 2, k));
-                const Rt dzp = c1 * (at(i, j, k + 1) - at(i, j, k - 1)) -
-                               c2 * (at(i, j, k + 2) - at(i, j, k - 2));
-                sx += w * dxp;
-                sy += w * dyp;
-                sz += w * dzp;
+    interp_direct<Rt>(x, y, z, phi, p, delta, ng, gx, gy, gz, accumulate);
+}
+
+// LDS-staged: a workgroup takes `chunk` consecutive particles, loads once the block of
+// potential values their stencils read (base - 2 .. base + 3 on each axis, wrapped) into LDS
+// when it holds at most INTERP_TILE values and the chunk lies in one box of a batch, and
+// evaluates every particle from LDS; otherwise each particle reads the mesh directly.
+template <typename Rt>
+__global__ __launch_bounds__(PM_THREADS) void k_pm_interp_tiled(
+    uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const Rt *__restrict__ phi, double delta, int ng,
+    double *__restrict__ gx, double *__restrict__ gy, double *__restrict__ gz, int accumulate,
+    pm_batch B, uint32_t chunk) {
+    __shared__ Rt s_phi[INTERP_TILE];
+    __shared__ int s_red[PM_THREADS / 64][8];
+    const uint64_t p0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+    const uint32_t tid = threadIdx.x;
+    int lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi;
+    chunk_bounds(p0, p1, x, y, z, delta, B, s_red, lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi);
+    const int64_t ex = (int64_t)hi0 - lo0 + 6, ey = (int64_t)hi1 - lo1 + 6,
+                  ez = (int64_t)hi2 - lo2 + 6;
+    const bool fits = (!B.boxes || blo == bhi) && ex <= INTERP_TILE && ey <= INTERP_TILE &&
+                      ez <= INTERP_TILE && ex * ey * ez <= INTERP_TILE;
+    if (!fits) {
+        for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+            double d = delta;
+            int g = ng;
+            const Rt *ph = phi;
+            if (B.boxes) {
+                const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
+                d = bx.delta;
+                g = bx.ng;
+                ph = phi + bx.mesh_off;
             }
-    const double s = -1.0 / delta;
-    if (accumulate) {
-        gx[p] += s * (double)sx;
-        gy[p] += s * (double)sy;
-        gz[p] += s * (double)sz;
-    } else {
-        gx[p] = s * (double)sx;
-        gy[p] = s * (double)sy;
-        gz[p] = s * (double)sz;
+            interp_direct<Rt>(x, y, z, ph, p, d, g, gx, gy, gz, accumulate);
+        }
+        return;
+    }
+    if (B.boxes) {
+        const dzs_bbox &bx = B.boxes[blo];
+        delta = bx.delta;
+        ng = bx.ng;
+        phi += bx.mesh_off;
+    }
+    const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez, pyz = tey * tez;
+    const uint32_t cells = (uint32_t)(ex * ey * ez);
+    const uint64_t N = (uint64_t)ng;
+    for (uint32_t c = tid; c < cells; c += PM_THREADS) {
+        const uint32_t a = c / pyz, r = c - a * pyz;
+        const uint32_t b = r / tez, e = r - b * tez;
+        const int ix = wrap_index(lo0 - 2 + (int)a, ng), iy = wrap_index(lo1 - 2 + (int)b, ng),
+                  iz = wrap_index(lo2 - 2 + (int)e, ng);
+        s_phi[c] = phi[((uint64_t)ix * N + iy) * N + iz];
+    }
+    __syncthreads();
+    for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+        double wx[2], wy[2], wz[2];
+        // tile coordinates of the base point (the tile starts at lo - 2)
+        const int i = cic_base(x[p], delta, wx[0], wx[1]) - lo0 + 2;
+        const int j = cic_base(y[p], delta, wy[0], wy[1]) - lo1 + 2;
+        const int k = cic_base(z[p], delta, wz[0], wz[1]) - lo2 + 2;
+        auto at = [&](int a, int b, int c) -> Rt {
+            return s_phi[((uint32_t)(i + a) * tey + (uint32_t)(j + b)) * tez + (uint32_t)(k + c)];
+        };
+        Rt sx, sy, sz;
+        cic_gradient<Rt>(at, wx, wy, wz, sx, sy, sz);
+        interp_store<Rt>(p, delta, sx, sy, sz, gx, gy, gz, accumulate);
     }
 }
 
@@ -627,15 +740,29 @@ static dzs_status pm_solve(dzs_ctx *ctx, const fft_plan &P, const double2 *tw, c
     return DZS_OK;
 }
 
+// Tiles only when the particles are at least half as many as the mesh points: on a finer
+// mesh a chunk's stencils rarely fit the tile and the direct reads are faster.
 template <typename Rt>
 static dzs_status pm_interp(dzs_ctx *ctx, const dzs_particles *p, int accumulate, double delta,
-                            int ng, pm_batch B, hipStream_t s) {
+                            int ng, pm_batch B, int32_t chunk, uint64_t cells, hipStream_t s) {
     if (p->n == 0)
         return DZS_OK;
     dzs_timed t(ctx, KC_PM_INTERP, s);
-    hipLaunchKernelGGL(k_pm_interp<Rt>, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0,
-                       s, p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,
-                       (const Rt *)ctx->mesh_phi, delta, ng, p->gx, p->gy, p->gz, accumulate, B);
+    if (chunk == 0)
+        chunk = DZS_PM_CHUNK_DEFAULT;
+    if (2 * p->n < cells)
+        chunk = -1;
+    if (chunk < 0) {
+        hipLaunchKernelGGL(k_pm_interp<Rt>, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS),
+                           0, s, p->n, (const double *)p->x, (const double *)p->y,
+                           (const double *)p->z, (const Rt *)ctx->mesh_phi, delta, ng, p->gx,
+                           p->gy, p->gz, accumulate, B);
+    } else {
+        hipLaunchKernelGGL(k_pm_interp_tiled<Rt>, dim3(blocks_for(p->n, (uint32_t)chunk)),
+                           dim3(PM_THREADS), 0, s, p->n, (const double *)p->x,
+                           (const double *)p->y, (const double *)p->z, (const Rt *)ctx->mesh_phi,
+                           delta, ng, p->gx, p->gy, p->gz, accumulate, B, (uint32_t)chunk);
+    }
     return dzs_check_launch(ctx, "pm_interp");
 }
 
@@ -646,7 +773,7 @@ __global__ __launch_bounds__(PM_THREADS) void k_zero_u64(uint64_t n, unsigned lo
         a[i] = 0ull;
 }
 
-// chunk: particles per LDS tile (a power of two in [DZS_DEPOSIT_CHUNK_MIN, _MAX]), 0 for the
+// chunk: particles per LDS tile (a power of two in [DZS_PM_CHUNK_MIN, _MAX]), 0 for the
 // default, -1 for the direct deposit.
 static dzs_status pm_deposit(dzs_ctx *ctx, const dzs_particles *p, uint64_t cells, double delta,
                              int ng, pm_batch B, int32_t chunk, hipStream_t s) {
@@ -658,7 +785,7 @@ static dzs_status pm_deposit(dzs_ctx *ctx, const dzs_particles *p, uint64_t cell
     if (p->n == 0)
         return DZS_OK;
     if (chunk == 0)
-        chunk = DZS_DEPOSIT_CHUNK_DEFAULT;
+        chunk = DZS_PM_CHUNK_DEFAULT;
     if (chunk < 0) {
         hipLaunchKernelGGL(k_pm_deposit, dim3(blocks_for(p->n, PM_THREADS)), dim3(PM_THREADS), 0, s,
                            p->n, (const double *)p->x, (const double *)p->y, (const double *)p->z,
@@ -691,17 +818,18 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
     const double *gt = ctx->pm_tables + 2 * ng;
     const double *k2t = ctx->pm_tables + 3 * ng;
     const pm_batch none{nullptr, nullptr, 0, nullptr};
-    DZS_TRY(pm_deposit(ctx, p, ng3, delta, ng, none, prm->deposit_chunk, s));
+    DZS_TRY(pm_deposit(ctx, p, ng3, delta, ng, none, prm->tile_chunk, s));
     const int TZ = tile_lines(ng, 16);
     const int TL = tile_lines(ng, FFT_ELEMS);
     const double q_scale = box->m0 / (DEP_FRAC * delta * delta * delta);
     const double gconst = -4.0 * 3.14159265358979323846 * box->G / (double)ng3;
     if (prm->precision == DZS_FP32) {
         DZS_TRY(pm_solve<float2>(ctx, P, tw, gt, k2t, TZ, TL, q_scale, gconst, 1, none, s));
-        return pm_interp<float>(ctx, p, prm->accumulate, delta, ng, none, s);
+        return pm_interp<float>(ctx, p, prm->accumulate, delta, ng, none, prm->tile_chunk, ng3,
+                                s);
     }
     DZS_TRY(pm_solve<double2>(ctx, P, tw, gt, k2t, TZ, TL, q_scale, gconst, 1, none, s));
-    return pm_interp<double>(ctx, p, prm->accumulate, delta, ng, none, s);
+    return pm_interp<double>(ctx, p, prm->accumulate, delta, ng, none, prm->tile_chunk, ng3, s);
 }
 
 // A batch: every box's mesh at its offset of the mesh arrays.  dzs_pm_batch_prepare fills
@@ -787,9 +915,9 @@ dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStre
 // The long-range force of every box of a prepared batch into g (g = g_long); db is the device
 // box table and ctx->key the sorted keys (box in the top digits) of the particles.
 dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
-                            int32_t deposit_chunk, const dzs_bbox *db, double G, hipStream_t s) {
+                            int32_t tile_chunk, const dzs_bbox *db, double G, hipStream_t s) {
     const pm_batch all{db, nullptr, 0, (const uint64_t *)ctx->key};
-    DZS_TRY(pm_deposit(ctx, p, ctx->batch_cells, 0.0, 0, all, deposit_chunk, s));
+    DZS_TRY(pm_deposit(ctx, p, ctx->batch_cells, 0.0, 0, all, tile_chunk, s));
     for (size_t c = 0; c < ctx->batch_sides.size(); ++c) {
         const int ng = ctx->batch_sides[c];
         fft_plan P;
@@ -808,6 +936,6 @@ dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
                                       gconst, nm, B, s));
     }
     if (precision == DZS_FP32)
-        return pm_interp<float>(ctx, p, 0, 0.0, 0, all, s);
-    return pm_interp<double>(ctx, p, 0, 0.0, 0, all, s);
+        return pm_interp<float>(ctx, p, 0, 0.0, 0, all, tile_chunk, ctx->batch_cells, s);
+    return pm_interp<double>(ctx, p, 0, 0.0, 0, all, tile_chunk, ctx->batch_cells, s);
 }

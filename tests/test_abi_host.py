@@ -97,7 +97,7 @@ def test_header_constants_match_the_binding():
     txt = open(os.path.join(ROOT, "include", "dzs.h")).read()
     defs = dict(re.findall(r"^#define\s+(DZS_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", txt, flags=re.M))
     shared = [k for k in defs if hasattr(_abi, k)]
-    assert {"DZS_DEPOSIT_CHUNK_MIN", "DZS_DEPOSIT_CHUNK_MAX", "DZS_DEPOSIT_CHUNK_DEFAULT",
+    assert {"DZS_PM_CHUNK_MIN", "DZS_PM_CHUNK_MAX", "DZS_PM_CHUNK_DEFAULT",
             "DZS_FP32", "DZS_BATCH_MAX"} <= set(shared)
     for k in shared:
         assert getattr(_abi, k) == int(defs[k]), k

@@ -232,12 +232,19 @@ def test_batched_steps_back_to_back_are_deterministic(dz):
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
-def test_batched_deposit_chunks_give_identical_steps(dz):
-    """The LDS-binned deposit in a batch (a chunk spanning two boxes adds directly): one
-    batched step with the direct deposit and with tiles of 256 and the default gives
-    bit-identical states (the mesh is the same integer sum)."""
+@pytest.mark.parametrize("coarse_meshes", [False, True])
+def test_batched_pm_tiles_give_identical_steps(dz, coarse_meshes):
+    """The LDS tiles of deposit and interpolation in a batch (a chunk spanning two boxes reads
+    and adds directly): one batched step without tiles, with tiles of 256 and with the default
+    gives bit-identical states.  With meshes of about one point per particle the
+    interpolation uses its tiles too."""
     import torch
     sets, boxes, _, first, ng, r_s, r_cut = _setup(dz)
+    if coarse_meshes:
+        ng = [16, 24, 32, 12, 18]
+        r_s = [1.25 * b.L / g for b, g in zip(boxes, ng)]
+        r_cut = [4.5 * r for r in r_s]
+        assert 2 * first[-1] >= sum(g ** 3 for g in ng)
     allp = _concat(sets)
     ctx = dz.Context(max_particles=first[-1] + 64, max_mesh_side=81)
     ring = dz.LCRing(1024)
@@ -249,7 +256,7 @@ def test_batched_deposit_chunks_give_identical_steps(dz):
         sp.do_lightcone, sp.do_coarsen = 1, 0
         sp.pm = dz.PMParams(0, dz.DZS_FP64, 0.0, 0, chunk)
         sp.tree = dz.TreeParams(0.0, 0.0, 0.5, 16, 32, dz.DZS_FP64, 0)
-        _log(f"batched step, deposit chunk {chunk}")
+        _log(f"batched step, PM tile chunk {chunk}")
         ctx.kdk_step_batch(boxes, first, ng, r_s, r_cut, st, sp, ring)
         torch.cuda.synchronize()
         outs.append(st.to_host())

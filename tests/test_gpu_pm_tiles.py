@@ -1,13 +1,14 @@
-"""The LDS-binned cloud-in-cell deposit against the direct one (paper Sec. 2.1, the PM density
-assignment).
+"""The LDS tiles of the PM deposit and interpolation against the direct kernels (paper Sec.
+2.1: cloud-in-cell assignment and interpolation of the mesh force).
 
-Both paths add the same 32.32 fixed-point contributions with integer atomics, so the mesh, and
-every force computed from it, must be bit-identical for every deposit_chunk: the direct
-deposit (-1), the tiled one at each chunk size, and the default (0).  The PM force of the
-tiled path is also checked against the FP64 oracle at the PM bar (1e-8).  Inputs are put in
-key order first, as the step does before its force, so that chunks are compact and the tile
-path runs; a host mirror of the kernel's fit rule asserts that both the tile path and the
-fallback are exercised.
+Deposit: both paths add the same 32.32 fixed-point contributions with integer atomics, so the
+mesh is the same integer sum.  Interpolation: both paths evaluate the same 4-point differences
+and weights in the same order, from the same potential values (read from LDS or from the
+mesh).  So every force must be bit-identical for every tile_chunk: no tiles (-1), each chunk
+size, and the default (0).  The PM force of the tiled path is also checked against the FP64
+oracle at the PM bar (1e-8).  Inputs are put in key order first, as the step does before its
+force, so that chunks are compact and the tiles are used; a host mirror of the kernels' fit
+rules asserts that both the tiles and the direct fallback are exercised.
 """
 import math
 import sys
@@ -21,7 +22,6 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 L, NG = 100.0, 64
-R_S = 1.25 * L / NG
 TILE = 4096
 CHUNKS = [256, 1024, 4096, 16384]
 
@@ -65,22 +65,28 @@ def _case(kind):
     return ps
 
 
-def _fits(x, y, z, n, chunk):
-    """Which chunks the kernel bins in LDS: the unwrapped base indices floor(x / Delta) of a
-    chunk span at most TILE points, counting base + 1 on every axis."""
-    delta = L / NG
+def _fits(x, y, z, n, chunk, pad, ng):
+    """Which chunks a kernel tiles in LDS: the unwrapped base indices floor(x / Delta) of a
+    chunk, widened by `pad` points per axis (deposit: base + 1, pad 2; interpolation: base - 2
+    .. base + 3, pad 6), span at most TILE points.  The interpolation uses tiles only when the
+    particles are at least half as many as the mesh points."""
+    if pad == 6 and 2 * n < ng ** 3:
+        return np.zeros(0, bool)
+    delta = L / ng
     out = []
     for p0 in range(0, n, chunk):
         sl = slice(p0, min(n, p0 + chunk))
-        ext = [int(np.floor(v[sl] / delta).max() - np.floor(v[sl] / delta).min()) + 2
+        ext = [int(np.floor(v[sl] / delta).max() - np.floor(v[sl] / delta).min()) + pad
                for v in (x, y, z)]
         out.append(ext[0] * ext[1] * ext[2] <= TILE)
     return np.array(out)
 
 
-@pytest.mark.parametrize("kind", ["clustered", "zeldovich", "corner"])
-def test_deposit_chunks_give_identical_forces(dz, ctx, kind):
+@pytest.mark.parametrize("kind,ng", [("clustered", 64), ("clustered", 32), ("zeldovich", 64),
+                                     ("zeldovich", 32), ("corner", 64), ("corner", 32)])
+def test_tile_chunks_give_identical_forces(dz, ctx, kind, ng):
     import torch
+    r_s = 1.25 * L / ng
     ps = _case(kind)
     n = ps.n
     m0 = dzs_ics.particle_mass(L, 32 ** 3)
@@ -90,31 +96,34 @@ def test_deposit_chunks_give_identical_forces(dz, ctx, kind):
     ctx.sort_state(box, st, ties_by_id=True)
     torch.cuda.synchronize()
     h = st.to_host()
-    _log(f"deposit kind={kind} n={n}")
+    _log(f"PM tiles kind={kind} n={n} mesh {ng}")
 
     def force(chunk):
-        ctx.pm_force(box, st, dz.PMParams(NG, dz.DZS_FP64, R_S, 0, chunk))
+        ctx.pm_force(box, st, dz.PMParams(ng, dz.DZS_FP64, r_s, 0, chunk))
         torch.cuda.synchronize()
         return np.stack([st.gx[:n].cpu().numpy(), st.gy[:n].cpu().numpy(),
                          st.gz[:n].cpu().numpy()])
 
     g_direct = force(-1)
-    n_fit = 0
+    n_fit = {2: 0, 6: 0}
     for chunk in CHUNKS + [0]:
         g = force(chunk)
         assert np.array_equal(g, g_direct), chunk
         if chunk:
-            fit = _fits(h["x"], h["y"], h["z"], n, chunk)
-            n_fit += int(fit.sum())
-            _log(f"  chunk {chunk}: {int(fit.sum())} of {fit.size} chunks binned in LDS")
-    assert n_fit > 0
-    ref = oracle.pm_force(h["x"], h["y"], h["z"], h["mult"], obox, NG, R_S)
+            for pad in (2, 6):
+                fit = _fits(h["x"], h["y"], h["z"], n, chunk, pad, ng)
+                n_fit[pad] += int(fit.sum())
+                _log(f"  chunk {chunk}, pad {pad}: {int(fit.sum())} of {fit.size} chunks in LDS")
+    # on the 64^3 mesh (more points than twice the particles) the interpolation reads the
+    # mesh directly; on the 32^3 mesh it uses tiles
+    assert n_fit[2] > 0 and (n_fit[6] > 0 or ng == 64)
+    ref = oracle.pm_force(h["x"], h["y"], h["z"], h["mult"], obox, ng, r_s)
     err = math.sqrt(np.mean(np.sum((g_direct - ref) ** 2, 0)) / np.mean(np.sum(ref ** 2, 0)))
     _log(f"  pm rms rel err {err:.3e}")
     assert err <= 1e-8
 
 
-def test_deposit_of_an_unsorted_state_matches(dz, ctx):
+def test_tiles_of_an_unsorted_state_match(dz, ctx):
     """Out of key order the chunks are scattered and mostly add directly: same forces."""
     import torch
     ps = _case("clustered")
@@ -123,17 +132,17 @@ def test_deposit_of_an_unsorted_state_matches(dz, ctx):
     st = dz.State.from_host(ps)
     out = []
     for chunk in (-1, 256, 0):
-        ctx.pm_force(box, st, dz.PMParams(NG, dz.DZS_FP64, R_S, 0, chunk))
+        ctx.pm_force(box, st, dz.PMParams(32, dz.DZS_FP64, 1.25 * L / 32, 0, chunk))
         torch.cuda.synchronize()
         out.append(np.stack([st.gx[:n].cpu().numpy(), st.gy[:n].cpu().numpy(),
                              st.gz[:n].cpu().numpy()]))
-    fit = _fits(ps.x, ps.y, ps.z, n, 256)
+    fit = _fits(ps.x, ps.y, ps.z, n, 256, 2, 32)
     _log(f"unsorted: {int(fit.sum())} of {fit.size} chunks of 256 binned in LDS")
     assert np.array_equal(out[1], out[0]) and np.array_equal(out[2], out[0])
 
 
-def test_deposit_chunk_fp32_mesh(dz, ctx):
-    """The precision form reads the same fixed-point mesh: identical forces too."""
+def test_tile_chunk_fp32_mesh(dz, ctx):
+    """The precision form (FP32 potential in the tiles): identical forces too."""
     import torch
     ps = _case("clustered")
     n = ps.n
@@ -141,17 +150,18 @@ def test_deposit_chunk_fp32_mesh(dz, ctx):
     st = dz.State.from_host(ps)
     ctx.sort_state(box, st)
     out = []
-    for chunk in (-1, 1024):
-        ctx.pm_force(box, st, dz.PMParams(NG, dz.DZS_FP32, R_S, 0, chunk))
+    for chunk in (-1, 256, 1024):
+        ctx.pm_force(box, st, dz.PMParams(32, dz.DZS_FP32, 1.25 * L / 32, 0, chunk))
         torch.cuda.synchronize()
-        out.append(st.gx[:n].cpu().numpy().copy())
-    assert np.array_equal(out[0], out[1])
+        out.append(np.stack([st.gx[:n].cpu().numpy(), st.gy[:n].cpu().numpy(),
+                             st.gz[:n].cpu().numpy()]))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
-def test_deposit_chunk_rejects(dz, ctx):
+def test_tile_chunk_rejects(dz, ctx):
     ps = _case("zeldovich")
     box = dz.make_box(L, dzs_ics.particle_mass(L, ps.n), L / 32 / 40)
     st = dz.State.from_host(ps)
     for bad in (-2, 1, 128, 300, 768, 32768):
         with pytest.raises(dz.DZSError):
-            ctx.pm_force(box, st, dz.PMParams(NG, dz.DZS_FP64, R_S, 0, bad))
+            ctx.pm_force(box, st, dz.PMParams(NG, dz.DZS_FP64, 1.25 * L / NG, 0, bad))
