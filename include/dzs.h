@@ -54,7 +54,9 @@ typedef struct dzs_ctx dzs_ctx;
 /* Capacities fixed at context creation; the context allocates all its scratch then. */
 typedef struct {
     uint64_t max_particles;  /* largest particle count any call will see */
-    uint32_t max_mesh_side;  /* largest PM mesh side N_g (N_g = 2^a 3^b, 8 <= N_g <= 1024) */
+    uint32_t max_mesh_side;  /* 0 (no PM) or 8..1024: room for meshes of up to
+                                max_mesh_side^3 points (a mesh side itself must be an
+                                even 2^a 3^b) */
     uint32_t flags;          /* DZS_CAP_* bits */
 } dzs_capacity;
 
@@ -123,7 +125,7 @@ typedef struct {
  * assignment; Green's function -4 pi G exp(-k^2 r_s^2) / (k^2 W(k)^2) with the CIC window
  * W deconvolved twice; 4-point finite-difference gradient; CIC interpolation. */
 typedef struct {
-    int32_t ng;          /* mesh side */
+    int32_t ng;          /* mesh side: 2^a 3^b with a >= 1, 8 <= ng <= max_mesh_side */
     int32_t precision;   /* DZS_FP64, or DZS_FP32: FFT, Green's function product, gradient
                             and interpolation in FP32 (rms error ~1e-6 of the force) */
     double r_s;          /* split scale */
@@ -365,7 +367,7 @@ typedef struct {
     const dzs_box *boxes;   /* [n_boxes]: L, m0, eps0 of each box; G equal for all */
     const uint64_t *first;  /* [n_boxes + 1]: first[0] = 0, non-decreasing, first[n_boxes] =
                                state->n */
-    const int32_t *ng;      /* [n_boxes]: PM mesh side of each box (2^a 3^b, 8 .. 1024); the
+    const int32_t *ng;      /* [n_boxes]: PM mesh side of each box (2^a 3^b, a >= 1, 8 .. 1024); the
                                meshes together need sum ng^3 <= max_mesh_side^3 of the context */
     const double *r_s;      /* [n_boxes]: split scale of each box */
     const double *r_cut;    /* [n_boxes]: cutoff, r_cut < L/2, r_cut <= 5 r_s, the same

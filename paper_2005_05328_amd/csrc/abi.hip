@@ -288,7 +288,7 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
 extern "C" dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap) {
     if (!out || !cap || cap->max_particles == 0 || cap->max_particles > 0xfffff000ull)
         return DZS_EINVAL;
-    if (cap->max_mesh_side != 0 && !dzs_pm_mesh_ok((int)cap->max_mesh_side))
+    if (cap->max_mesh_side != 0 && (cap->max_mesh_side < 8 || cap->max_mesh_side > 1024))
         return DZS_EINVAL;
     *out = nullptr;
     int ndev = 0;
@@ -376,7 +376,7 @@ static dzs_status check_pm(dzs_ctx *ctx, const dzs_pm_params *m) {
     if (!m)
         return dzs_fail(ctx, DZS_EINVAL, "null PM parameters");
     if (!dzs_pm_mesh_ok(m->ng))
-        return dzs_fail(ctx, DZS_EINVAL, "pm: mesh side %d must be 2^a 3^b in [8, 1024]", m->ng);
+        return dzs_fail(ctx, DZS_EINVAL, "pm: mesh side %d must be an even 2^a 3^b in [8, 1024]", m->ng);
     if ((uint32_t)m->ng > ctx->cap_ng)
         return dzs_fail(ctx, DZS_ECAPACITY, "pm: mesh side %d exceeds the context's %u", m->ng,
                         ctx->cap_ng);

@@ -368,17 +368,117 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
 }
 
 // ---------------------------------------------------------------------------------------
-// strided passes (x or y): a tile is TZ consecutive iz values x all n positions along the
-// axis, for a fixed other index.  stride_axis = N_g^2 (x) or N_g (y).
+// x passes, real <-> half spectrum.  The density and the potential are real, so only the
+// planes k_x = 0 .. N_g/2 of the transform are kept (the others are their conjugates): the
+// y and z passes run on N_g/2 + 1 planes.  A tile is 2 CL consecutive iz values for a fixed
+// iy; lines iz0 + t and iz0 + t + CL travel as the real and imaginary parts of one complex
+// line of length N_g, and their spectra are separated (forward) or combined (inverse) with
+// the conjugate symmetry of a real line's transform.  The complex mesh keeps the layout
+// (k_x N_g + iy) N_g + iz.
 // ---------------------------------------------------------------------------------------
-template <int MODE, typename C>  // 0: x forward from fixed point, 1: y forward, 2: y inverse,
-                                 // 3: x inverse to phi
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
-    const unsigned long long *q, C *c, decltype(C::x) *__restrict__ phi,
-    const double2 *__restrict__ tw, fft_plan P, int TZ, double q_scale, pm_batch B) {
-    // q and c may be the same memory (meshes for the precision form only): every element of
-    // the tile is loaded before the first store
+template <typename C>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_x_r2c(const unsigned long long *q, C *c,
+                                                           const double2 *__restrict__ tw,
+                                                           fft_plan P, int CL, double q_scale,
+                                                           pm_batch B) {
+    // q and c may be the same memory (meshes for the precision form only): the tile writes
+    // only cells it has read, after all of its loads
     typedef decltype(C::x) Rt;
+    __shared__ C s_buf[FFT_ELEMS];
+    __shared__ C s_tw[1024];
+    const int n = P.n;
+    const int TZ = 2 * CL;
+    const int tiles_z = n / TZ;
+    uint32_t blk = blockIdx.x;
+    if (B.boxes) {
+        const dzs_bbox &bx = B.boxes[B.members[blk / (uint32_t)B.blocks_per_mesh]];
+        blk %= (uint32_t)B.blocks_per_mesh;
+        q += bx.mesh_off;
+        c += bx.mesh_off;
+        q_scale = bx.q_scale;
+    }
+    const int iy = blk / tiles_z;
+    const int iz0 = (blk % tiles_z) * TZ;
+    const uint64_t sx = (uint64_t)n * n;
+    const uint64_t base = (uint64_t)iy * n + iz0;
+    load_twiddles(s_tw, tw, n);
+    for (int e = threadIdx.x; e < n * CL; e += FFT_THREADS) {
+        const int t = e % CL, a = e / CL;
+        const uint64_t gi = base + (uint64_t)a * sx + t;
+        s_buf[a * CL + t] = C{Rt((double)(long long)q[gi] * q_scale),
+                              Rt((double)(long long)q[gi + CL] * q_scale)};
+    }
+    __syncthreads();
+    fft_lines<false>(s_buf, s_tw, P, CL, CL, 1);
+    // Z = A + i B with A, B the spectra of the two real lines: A[k] = (Z[k] + conj Z[n-k]) / 2,
+    // B[k] = (Z[k] - conj Z[n-k]) / 2i
+    const int nh = n / 2 + 1;
+    for (int e = threadIdx.x; e < nh * CL; e += FFT_THREADS) {
+        const int t = e % CL, k = e / CL;
+        const C z = s_buf[k * CL + t];
+        const C w = s_buf[(k == 0 ? 0 : n - k) * CL + t];
+        const uint64_t gi = base + (uint64_t)k * sx + t;
+        c[gi] = C{Rt(0.5) * (z.x + w.x), Rt(0.5) * (z.y - w.y)};
+        c[gi + CL] = C{Rt(0.5) * (z.y + w.y), Rt(-0.5) * (z.x - w.x)};
+    }
+}
+
+template <typename C>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_x_c2r(const C *__restrict__ c,
+                                                           decltype(C::x) *__restrict__ phi,
+                                                           const double2 *__restrict__ tw,
+                                                           fft_plan P, int CL, pm_batch B) {
+    typedef decltype(C::x) Rt;
+    __shared__ C s_buf[FFT_ELEMS];
+    __shared__ C s_tw[1024];
+    const int n = P.n;
+    const int TZ = 2 * CL;
+    const int tiles_z = n / TZ;
+    uint32_t blk = blockIdx.x;
+    if (B.boxes) {
+        const dzs_bbox &bx = B.boxes[B.members[blk / (uint32_t)B.blocks_per_mesh]];
+        blk %= (uint32_t)B.blocks_per_mesh;
+        c += bx.mesh_off;
+        phi += bx.mesh_off;
+    }
+    const int iy = blk / tiles_z;
+    const int iz0 = (blk % tiles_z) * TZ;
+    const uint64_t sx = (uint64_t)n * n;
+    const uint64_t base = (uint64_t)iy * n + iz0;
+    load_twiddles(s_tw, tw, n);
+    // Z[k] = A[k] + i B[k], Z[n-k] = conj A[k] + i conj B[k]; the k_x = 0 and N_g/2 values of
+    // a real line's spectrum are real (their imaginary rounding is dropped, as the real part
+    // of a full inverse transform drops it)
+    const int nh = n / 2 + 1;
+    for (int e = threadIdx.x; e < nh * CL; e += FFT_THREADS) {
+        const int t = e % CL, k = e / CL;
+        const uint64_t gi = base + (uint64_t)k * sx + t;
+        C a = c[gi], b = c[gi + CL];
+        const bool edge = k == 0 || 2 * k == n;
+        if (edge)
+            a.y = b.y = Rt(0.0);
+        s_buf[k * CL + t] = C{a.x - b.y, a.y + b.x};
+        if (!edge)
+            s_buf[(n - k) * CL + t] = C{a.x + b.y, b.x - a.y};
+    }
+    __syncthreads();
+    fft_lines<true>(s_buf, s_tw, P, CL, CL, 1);
+    for (int e = threadIdx.x; e < n * CL; e += FFT_THREADS) {
+        const int t = e % CL, a = e / CL;
+        const uint64_t gi = base + (uint64_t)a * sx + t;
+        const C z = s_buf[a * CL + t];
+        phi[gi] = z.x;
+        phi[gi + CL] = z.y;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// y passes: a tile is TZ consecutive iz values x all N_g values of iy, for a fixed k_x plane.
+// ---------------------------------------------------------------------------------------
+template <bool INV, typename C>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_y(C *__restrict__ c,
+                                                       const double2 *__restrict__ tw,
+                                                       fft_plan P, int TZ, pm_batch B) {
     __shared__ C s_buf[FFT_ELEMS];
     __shared__ C s_tw[1024];
     const int n = P.n;
@@ -387,44 +487,26 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_strided(
     if (B.boxes) {
         const dzs_bbox &bx = B.boxes[B.members[blk / (uint32_t)B.blocks_per_mesh]];
         blk %= (uint32_t)B.blocks_per_mesh;
-        q += bx.mesh_off;
         c += bx.mesh_off;
-        phi += bx.mesh_off;
-        q_scale = bx.q_scale;
     }
-    const int other = blk / tiles_z;  // iy for the x pass, ix for the y pass
+    const int ix = blk / tiles_z;
     const int iz0 = (blk % tiles_z) * TZ;
-    const bool xpass = (MODE == 0 || MODE == 3);
-    const uint64_t stride_axis = xpass ? (uint64_t)n * n : (uint64_t)n;
-    const uint64_t base = xpass ? (uint64_t)other * n + iz0 : (uint64_t)other * n * n + iz0;
+    const uint64_t base = (uint64_t)ix * n * n + iz0;
     load_twiddles(s_tw, tw, n);
     const int total = n * TZ;
     for (int e = threadIdx.x; e < total; e += FFT_THREADS) {
         const int t = e % TZ, a = e / TZ;
-        const uint64_t gi = base + (uint64_t)a * stride_axis + t;
-        C v;
-        if (MODE == 0)
-            v = C{Rt((double)(long long)q[gi] * q_scale), Rt(0.0)};
-        else
-            v = c[gi];
-        s_buf[a * TZ + t] = v;
+        s_buf[a * TZ + t] = c[base + (uint64_t)a * n + t];
     }
     __syncthreads();
-    if (MODE == 0 || MODE == 1)
-        fft_lines<false>(s_buf, s_tw, P, TZ, TZ, 1);
-    else
-        fft_lines<true>(s_buf, s_tw, P, TZ, TZ, 1);
+    fft_lines<INV>(s_buf, s_tw, P, TZ, TZ, 1);
     for (int e = threadIdx.x; e < total; e += FFT_THREADS) {
         const int t = e % TZ, a = e / TZ;
-        const uint64_t gi = base + (uint64_t)a * stride_axis + t;
-        if (MODE == 3)
-            phi[gi] = s_buf[a * TZ + t].x;
-        else
-            c[gi] = s_buf[a * TZ + t];
+        c[base + (uint64_t)a * n + t] = s_buf[a * TZ + t];
     }
 }
 
-// z pass: TL whole contiguous lines (fixed ix, consecutive iy): forward FFT, Green's
+// z pass: TL whole contiguous lines (fixed k_x plane, consecutive iy): forward FFT, Green's
 // function, inverse FFT.
 template <typename C>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_z_green(C *__restrict__ c,
@@ -660,9 +742,18 @@ static int tile_lines(int ng, int cap) {
     return t;
 }
 
+// complex lines per x tile: each carries two real lines, so 2 CL must divide N_g
+static int pair_lines(int ng) {
+    int t = 1;
+    while (2 * t <= 16 && 2 * t * ng <= FFT_ELEMS && ng % (4 * t) == 0)
+        t *= 2;
+    return t;
+}
+
+// even 2^a 3^b sides (the x passes pair real lines and keep N_g/2 + 1 planes)
 bool dzs_pm_mesh_ok(int ng) {
     fft_plan P;
-    return ng >= 8 && ng <= 1024 && make_plan(ng, &P);
+    return ng >= 8 && ng <= 1024 && ng % 2 == 0 && make_plan(ng, &P);
 }
 
 // tables at ctx->pm_tables: [0, 2n) twiddles (double2), [2n, 3n) gt, [3n, 4n) k^2
@@ -694,29 +785,34 @@ static dzs_status upload_tables(dzs_ctx *ctx, int ng, double L, double r_s, hipS
 // inverse) over n_meshes meshes of side P.n, in the complex type C of the form.
 template <typename C>
 static dzs_status pm_solve(dzs_ctx *ctx, const fft_plan &P, const double2 *tw, const double *gt,
-                           const double *k2t, int TZ, int TL, double q_scale, double gconst,
-                           uint32_t n_meshes, pm_batch B, hipStream_t s) {
+                           const double *k2t, double q_scale, double gconst, uint32_t n_meshes,
+                           pm_batch B, hipStream_t s) {
     typedef decltype(C::x) Rt;
     const int ng = P.n;
-    const uint32_t strided_per = (uint32_t)((uint64_t)ng * (ng / TZ));
-    const uint32_t z_per = (uint32_t)((uint64_t)ng * (ng / TL));
+    const int nkx = ng / 2 + 1;                  // k_x planes kept
+    const int CL = pair_lines(ng);               // complex lines per x tile (2 CL real lines)
+    const int TZ = tile_lines(ng, 16);           // lines per y tile
+    const int TL = tile_lines(ng, FFT_ELEMS);    // lines per z tile
+    const uint32_t x_per = (uint32_t)((uint64_t)ng * (ng / (2 * CL)));
+    const uint32_t y_per = (uint32_t)((uint64_t)nkx * (ng / TZ));
+    const uint32_t z_per = (uint32_t)((uint64_t)nkx * (ng / TL));
     const unsigned long long *mq = (const unsigned long long *)ctx->mesh_q;
     C *mc = (C *)ctx->mesh_c;
     Rt *phi = (Rt *)ctx->mesh_phi;
-    pm_batch Bs = B, Bz = B;
-    Bs.blocks_per_mesh = (int)strided_per;
+    pm_batch Bx = B, By = B, Bz = B;
+    Bx.blocks_per_mesh = (int)x_per;
+    By.blocks_per_mesh = (int)y_per;
     Bz.blocks_per_mesh = (int)z_per;
-    const dim3 gs(strided_per * n_meshes), gz(z_per * n_meshes);
+    const dim3 gx(x_per * n_meshes), gy(y_per * n_meshes), gz(z_per * n_meshes);
     {
         dzs_timed t(ctx, KC_PM_FFT_X, s);
-        hipLaunchKernelGGL((k_fft_strided<0, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
-                           TZ, q_scale, Bs);
+        hipLaunchKernelGGL(k_fft_x_r2c<C>, gx, dim3(FFT_THREADS), 0, s, mq, mc, tw, P, CL,
+                           q_scale, Bx);
         DZS_TRY(dzs_check_launch(ctx, "fft_x_fwd"));
     }
     {
         dzs_timed t(ctx, KC_PM_FFT_Y, s);
-        hipLaunchKernelGGL((k_fft_strided<1, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
-                           TZ, q_scale, Bs);
+        hipLaunchKernelGGL((k_fft_y<false, C>), gy, dim3(FFT_THREADS), 0, s, mc, tw, P, TZ, By);
         DZS_TRY(dzs_check_launch(ctx, "fft_y_fwd"));
     }
     {
@@ -727,14 +823,12 @@ static dzs_status pm_solve(dzs_ctx *ctx, const fft_plan &P, const double2 *tw, c
     }
     {
         dzs_timed t(ctx, KC_PM_FFT_Y, s);
-        hipLaunchKernelGGL((k_fft_strided<2, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
-                           TZ, q_scale, Bs);
+        hipLaunchKernelGGL((k_fft_y<true, C>), gy, dim3(FFT_THREADS), 0, s, mc, tw, P, TZ, By);
         DZS_TRY(dzs_check_launch(ctx, "fft_y_inv"));
     }
     {
         dzs_timed t(ctx, KC_PM_FFT_X, s);
-        hipLaunchKernelGGL((k_fft_strided<3, C>), gs, dim3(FFT_THREADS), 0, s, mq, mc, phi, tw, P,
-                           TZ, q_scale, Bs);
+        hipLaunchKernelGGL(k_fft_x_c2r<C>, gx, dim3(FFT_THREADS), 0, s, mc, phi, tw, P, CL, Bx);
         DZS_TRY(dzs_check_launch(ctx, "fft_x_inv"));
     }
     return DZS_OK;
@@ -804,8 +898,8 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                       const dzs_pm_params *prm, hipStream_t s) {
     const int ng = prm->ng;
     fft_plan P;
-    if (!make_plan(ng, &P))
-        return dzs_fail(ctx, DZS_EINVAL, "pm_force: mesh side %d is not 2^a 3^b", ng);
+    if (!dzs_pm_mesh_ok(ng) || !make_plan(ng, &P))
+        return dzs_fail(ctx, DZS_EINVAL, "pm_force: mesh side %d is not an even 2^a 3^b", ng);
     const uint64_t ng3 = (uint64_t)ng * ng * ng;
     const double delta = box->L / ng;
     if (ctx->pm_tab_ng != ng || ctx->pm_tab_L != box->L || ctx->pm_tab_rs != prm->r_s) {
@@ -819,16 +913,14 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
     const double *k2t = ctx->pm_tables + 3 * ng;
     const pm_batch none{nullptr, nullptr, 0, nullptr};
     DZS_TRY(pm_deposit(ctx, p, ng3, delta, ng, none, prm->tile_chunk, s));
-    const int TZ = tile_lines(ng, 16);
-    const int TL = tile_lines(ng, FFT_ELEMS);
     const double q_scale = box->m0 / (DEP_FRAC * delta * delta * delta);
     const double gconst = -4.0 * 3.14159265358979323846 * box->G / (double)ng3;
     if (prm->precision == DZS_FP32) {
-        DZS_TRY(pm_solve<float2>(ctx, P, tw, gt, k2t, TZ, TL, q_scale, gconst, 1, none, s));
+        DZS_TRY(pm_solve<float2>(ctx, P, tw, gt, k2t, q_scale, gconst, 1, none, s));
         return pm_interp<float>(ctx, p, prm->accumulate, delta, ng, none, prm->tile_chunk, ng3,
                                 s);
     }
-    DZS_TRY(pm_solve<double2>(ctx, P, tw, gt, k2t, TZ, TL, q_scale, gconst, 1, none, s));
+    DZS_TRY(pm_solve<double2>(ctx, P, tw, gt, k2t, q_scale, gconst, 1, none, s));
     return pm_interp<double>(ctx, p, prm->accumulate, delta, ng, none, prm->tile_chunk, ng3, s);
 }
 
@@ -840,10 +932,9 @@ dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStre
     ctx->batch_sides.clear();
     uint64_t cells = 0;
     for (uint32_t b = 0; b < nb; ++b) {
-        fft_plan P;
-        if (!make_plan(hb[b].ng, &P) || hb[b].ng > 1024 || hb[b].ng < 8)
-            return dzs_fail(ctx, DZS_EINVAL, "batch: box %u mesh side %d is not 2^a 3^b in "
-                            "[8, 1024]", b, hb[b].ng);
+        if (!dzs_pm_mesh_ok(hb[b].ng))
+            return dzs_fail(ctx, DZS_EINVAL, "batch: box %u mesh side %d is not an even 2^a 3^b "
+                            "in [8, 1024]", b, hb[b].ng);
         hb[b].mesh_off = cells;
         cells += (uint64_t)hb[b].ng * hb[b].ng * hb[b].ng;
         bool seen = false;
@@ -927,13 +1018,12 @@ dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
                          (const uint64_t *)ctx->key};
         const double2 *tw = (const double2 *)(ctx->batch_tab + ctx->batch_tw_off[c]);
         const double gconst = -4.0 * 3.14159265358979323846 * G / ((double)ng * ng * ng);
-        const int TZ = tile_lines(ng, 16), TL = tile_lines(ng, FFT_ELEMS);
         if (precision == DZS_FP32)
-            DZS_TRY(pm_solve<float2>(ctx, P, tw, ctx->batch_tab, ctx->batch_tab, TZ, TL, 0.0,
-                                     gconst, nm, B, s));
+            DZS_TRY(pm_solve<float2>(ctx, P, tw, ctx->batch_tab, ctx->batch_tab, 0.0, gconst, nm,
+                                     B, s));
         else
-            DZS_TRY(pm_solve<double2>(ctx, P, tw, ctx->batch_tab, ctx->batch_tab, TZ, TL, 0.0,
-                                      gconst, nm, B, s));
+            DZS_TRY(pm_solve<double2>(ctx, P, tw, ctx->batch_tab, ctx->batch_tab, 0.0, gconst, nm,
+                                      B, s));
     }
     if (precision == DZS_FP32)
         return pm_interp<float>(ctx, p, 0, 0.0, 0, all, tile_chunk, ctx->batch_cells, s);
