@@ -422,10 +422,12 @@ static dzs_status check_lc(dzs_ctx *ctx, const dzs_lc_params *lc, const dzs_lc_r
 // ---------------------------------------------------------------------------------------
 // sorting the state
 // ---------------------------------------------------------------------------------------
+// tree_only: the order a tree build needs (keys ordered to level DZS_TREE_LEVELS, stable), not
+// the full key order
 static dzs_status sort_state(dzs_ctx *ctx, const dzs_box *box, dzs_particles *p, int ties_by_id,
-                             int with_g, hipStream_t s) {
+                             int with_g, hipStream_t s, bool tree_only = false) {
     DZS_TRY(dzs_launch_keys(ctx, p->x, p->y, p->z, p->n, box->L, ctx->key, ctx->idx, s));
-    DZS_TRY(dzs_radix_sort(ctx, p->n, s));
+    DZS_TRY(dzs_radix_sort(ctx, p->n, s, tree_only ? DZS_TREE_FIRST_PASS : 0));
     if (ties_by_id)
         DZS_TRY(dzs_fix_ties(ctx, p->n, p->id, s));
     return dzs_permute_state(ctx, p, ctx->idx, with_g, s);
@@ -519,7 +521,7 @@ extern "C" dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_par
         DZS_TRY(alloc(ctx, &ctx->sgz, ctx->cap_n));
     }
     DZS_TRY(dzs_launch_keys(ctx, p->x, p->y, p->z, n, box->L, ctx->key, ctx->idx, s));
-    DZS_TRY(dzs_radix_sort(ctx, n, s));
+    DZS_TRY(dzs_radix_sort(ctx, n, s, DZS_TREE_FIRST_PASS));
     {
         dzs_timed tm(ctx, KC_PERMUTE, s);
         DZS_TRY(dzs_gather_f64(ctx, p->x, ctx->idx, ctx->sx, n, s));
@@ -615,7 +617,7 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
     }
     if (st->n > 0) {
         if (!in_order) {
-            DZS_TRY(sort_state(ctx, box, st, 0, 0, s));
+            DZS_TRY(sort_state(ctx, box, st, 0, 0, s, true));
             if (aold_ok)
                 DZS_TRY(dzs_permute_f32(ctx, ctx->aold, ctx->idx, st->n, s));
         }
@@ -644,7 +646,7 @@ static dzs_status hier_force(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st
     if (st->n == 0)
         return DZS_OK;
     if (!in_order) {
-        DZS_TRY(sort_state(ctx, box, st, 0, 0, s));
+        DZS_TRY(sort_state(ctx, box, st, 0, 0, s, true));
         if (bins)
             DZS_TRY(dzs_permute_u8(ctx, ctx->hbins, ctx->idx, st->n, s));
     }
@@ -880,7 +882,7 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     // keys with the box on top, one sort for every box: each box stays in its range
     DZS_TRY(dzs_launch_keys(ctx, st->x, st->y, st->z, st->n, 1.0, ctx->key, ctx->idx, s, true,
                             nb));
-    DZS_TRY(dzs_radix_sort(ctx, st->n, s));
+    DZS_TRY(dzs_radix_sort(ctx, st->n, s, DZS_TREE_FIRST_PASS));
     DZS_TRY(dzs_permute_state(ctx, st, ctx->idx, 0, s));
     DZS_TRY(dzs_tree_build_ex(ctx, &batch->boxes[0], st->n, st->x, st->y, st->z, st->mult,
                               t.leaf_size, t.group_size, DZS_BATCH_LEVELS, ctx->batch_box, s));

@@ -12,6 +12,11 @@
 #include "../../include/dzs.h"
 
 #define DZS_KEY_BITS 21
+// deepest level of the force tree: the sort before a tree build orders the keys to this level
+// only (bits 16..62), the build stops there (a level-15 node of more than leaf_size
+// particles stays a leaf)
+#define DZS_TREE_LEVELS 15
+#define DZS_TREE_FIRST_PASS 2  // radix passes of 8 bits skipped by that sort
 #define DZS_CELL_K_MAX 7  // deepest level of the walk start cells (8^7 cells, 10 MB)
 #define DZS_KEY_SIDE 2097152.0
 
@@ -297,7 +302,8 @@ dzs_status dzs_scan_u32(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_
 dzs_status dzs_scan_u32_dev(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n_max,
                             const uint32_t *n_dev, uint32_t *total_dev, hipStream_t s);
 uint64_t dzs_sort_hist_words(uint64_t n);
-dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s);  // ctx->key/idx in+out
+dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s,
+                          int first_pass = 0);  // ctx->key/idx in+out; an even first_pass
 dzs_status dzs_fix_ties(dzs_ctx *ctx, uint64_t n, const uint32_t *id, hipStream_t s);
 
 // particles.hip

@@ -1,7 +1,8 @@
 // Exclusive prefix scan (u32) and stable LSD radix sort of (u64 Morton key, u32 index)
 // pairs for gfx950.
 //
-// Sort: 8 passes of 8-bit digits.  Per pass: (1) each 256-thread block counts the digits of
+// Sort: 8 passes of 8-bit digits (the sort before a tree build skips the lowest two: the tree
+// reads the keys' order to level 15 only).  Per pass: (1) each 256-thread block counts the digits of
 // its 4096-key tile in LDS; (2) one exclusive scan over the digit-major table gives every
 // (digit, tile) its global start; (3) each block ranks its tile stably — wave-level digit
 // matching through eight ballots, per-wave counts combined in LDS — stages the tile in LDS in
@@ -242,11 +243,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
 }
 
-dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s) {
+dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s, int first_pass) {
     if (n <= 1)
         return DZS_OK;
     if (n > 0xffffffffull)
         return dzs_fail(ctx, DZS_EINVAL, "radix sort: n exceeds 2^32-1");
+    if (first_pass < 0 || first_pass > 6 || (first_pass & 1))
+        return dzs_fail(ctx, DZS_EINVAL, "radix sort: first pass %d", first_pass);
     const uint32_t tiles = (uint32_t)((n + SORT_TILE - 1) / SORT_TILE);
     const uint64_t words = 256ull * tiles;
     if (words > ctx->hist_cap)
@@ -254,7 +257,7 @@ dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s) {
     dzs_timed t(ctx, KC_SORT, s);
     uint64_t *kin = ctx->key, *kout = ctx->key_alt;
     uint32_t *iin = ctx->idx, *iout = ctx->idx_alt;
-    for (int pass = 0; pass < 8; ++pass) {
+    for (int pass = first_pass; pass < 8; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(SORT_THREADS), 0, s, kin, n, shift,
                            ctx->hist, tiles);
@@ -266,7 +269,7 @@ dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s) {
         uint64_t *tk = kin; kin = kout; kout = tk;
         uint32_t *ti = iin; iin = iout; iout = ti;
     }
-    // eight passes: the result is back in ctx->key / ctx->idx
+    // an even number of passes: the result is back in ctx->key / ctx->idx
     return DZS_OK;
 }
 

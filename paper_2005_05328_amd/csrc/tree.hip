@@ -72,46 +72,82 @@ __global__ void k_tree_level(uint32_t *bs, int k, uint64_t cap) {
         bs[BS_LEVEL + j] = bs[BS_NODES];
 }
 
-// For each frontier node at level k: the 9 bounds of its 8 octant sub-ranges.
+// For each frontier node at level k: the 9 bounds of its 8 octant sub-ranges.  One wave per
+// node (grid-stride over the frontier).  A node of at most 64 particles is read in one round;
+// a larger one is searched for the 7 inner bounds at once: lanes 9 (d - 1) .. 9 (d - 1) + 8
+// sample the bracket of "first index whose digit is >= d" at 9 points, which shrinks it about
+// 9-fold per round (dependent loads: log_9 of the node size, not 7 log_2 of it).
 __global__ __launch_bounds__(TB_THREADS) void k_tree_split(
     const uint32_t *__restrict__ frontier, const uint32_t *__restrict__ bs, int k,
     const uint64_t *__restrict__ key,
     const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     uint32_t *__restrict__ bounds, uint32_t *__restrict__ nchild, uint32_t *__restrict__ ninternal,
     uint32_t leaf, int KB) {
-    uint32_t f = blockIdx.x * TB_THREADS + threadIdx.x;
-    if (f >= bs[BS_NF])
-        return;
-    const uint32_t node = frontier[f];
-    const uint32_t s = nd_first[node], e = s + nd_count[node];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t waves = gridDim.x * (TB_THREADS / 64);
+    const uint32_t nf = bs[BS_NF];
     const int shift = 3 * (DZS_KEY_BITS - (k + 1));
-    uint32_t b[9];
-    b[0] = s;
-    b[8] = e;
-    for (uint32_t d = 1; d < 8; ++d) {
-        // first index in [b[d-1], e) whose digit is >= d
-        uint32_t lo = b[d - 1], hi = e;
-        while (lo < hi) {
-            uint32_t mid = lo + ((hi - lo) >> 1);
-            uint32_t dig = (uint32_t)(key[mid] >> shift) & 7u;
-            if (dig < d)
-                lo = mid + 1;
-            else
-                hi = mid;
+    const uint32_t g = lane / 9u, j = lane - 9u * g;  // search group (digit g + 1), sample
+    for (uint32_t f = blockIdx.x * (TB_THREADS / 64) + (threadIdx.x >> 6); f < nf; f += waves) {
+        const uint32_t node = frontier[f];
+        const uint32_t s = nd_first[node], e = s + nd_count[node];
+        uint32_t b = s;  // lane d in 1..7: first index in [s, e) whose digit is >= d
+        if (e - s <= 64u) {
+            const uint32_t i = s + lane;
+            const uint32_t dig = i < e ? (uint32_t)(key[i] >> shift) & 7u : 8u;
+            for (uint32_t d = 1; d < 8; ++d) {
+                const uint64_t m = __ballot(dig < d);
+                if (lane == d)
+                    b = s + (uint32_t)__popcll(m);
+            }
+        } else {
+            uint32_t lo = s, hi = e;  // the bound lies in [lo, hi]
+            const uint32_t d = g + 1u;
+            while (__ballot(g < 7u && lo < hi) != 0ull) {
+                const uint32_t len = hi - lo;
+                const uint32_t step = (len + 8u) / 9u;
+                const uint32_t p = lo + j * step;
+                // positions at or past hi count as "digit >= d" (the bracket's invariant)
+                bool ge = true;
+                if (g < 7u && lo < hi && p < hi)
+                    ge = ((uint32_t)(key[p] >> shift) & 7u) >= d;
+                const uint64_t m = __ballot(ge);
+                if (g < 7u && lo < hi) {
+                    const uint32_t gm = (uint32_t)(m >> (9u * g)) & 0x1ffu;
+                    if (gm & 1u) {
+                        hi = lo;  // the digit at lo is already >= d
+                    } else if (gm == 0u) {
+                        lo += 8u * step + 1u;  // every sample (all below hi) has digit < d
+                    } else {
+                        // between the last sample below d and the first at or above it
+                        const uint32_t jj = (uint32_t)__builtin_ctz(gm);
+                        const uint32_t nhi = lo + jj * step;
+                        lo += (jj - 1u) * step + 1u;
+                        hi = nhi < hi ? nhi : hi;
+                    }
+                }
+            }
+            const uint32_t src = (lane >= 1u && lane <= 7u) ? 9u * (lane - 1u) : 0u;
+            const uint32_t got = __shfl(lo, (int)src, 64);
+            if (lane >= 1u && lane <= 7u)
+                b = got;
         }
-        b[d] = lo;
-    }
-    uint32_t nc = 0, ni = 0;
-    for (int d = 0; d < 8; ++d) {
-        uint32_t c = b[d + 1] - b[d];
-        bounds[(uint64_t)f * 9 + d] = b[d];
-        nc += c > 0;
+        if (lane == 8u)
+            b = e;
+        // counts of the 8 children (lane d: bound d + 1 - bound d)
+        const uint32_t bn = __shfl_down(b, 1, 64);
+        const uint32_t c = lane < 8u ? bn - b : 0u;
+        const bool child = lane < 8u && c > 0u;
         // nodes above level KB (the box digits of a batch) always split
-        ni += c > 0 && (c > leaf || k + 1 < KB) && k + 1 < DZS_KEY_BITS;
+        const bool internal = child && (c > leaf || k + 1 < KB) && k + 1 < DZS_TREE_LEVELS;
+        const uint64_t mc = __ballot(child), mi = __ballot(internal);
+        if (lane <= 8u)
+            bounds[(uint64_t)f * 9 + lane] = b;
+        if (lane == 0u) {
+            nchild[f] = (uint32_t)__popcll(mc);
+            ninternal[f] = (uint32_t)__popcll(mi);
+        }
     }
-    bounds[(uint64_t)f * 9 + 8] = e;
-    nchild[f] = nc;
-    ninternal[f] = ni;
 }
 
 __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
@@ -141,7 +177,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
         nd_child[c] = 0;
         nd_nchild[c] = 0;
         nd_level[c] = (uint8_t)(k + 1);
-        if ((e - s > leaf || k + 1 < KB) && k + 1 < DZS_KEY_BITS)
+        if ((e - s > leaf || k + 1 < KB) && k + 1 < DZS_TREE_LEVELS)
             frontier_next[q++] = c;
         ++c;
         ++nc;
@@ -328,12 +364,15 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
                            KB);
         DZS_TRY(dzs_check_launch(ctx, "tree_root"));
         uint32_t *fr = ctx->frontier, *fr_next = ctx->frontier_next;
-        for (int k = 0; k < DZS_KEY_BITS; ++k) {
+        for (int k = 0; k < DZS_TREE_LEVELS; ++k) {
             deepest = k + 1;
             uint64_t ub = k <= KB ? n : n / (leaf + 1) + 1;
             if (k < 8 && (1ull << (3 * k)) < ub)
                 ub = 1ull << (3 * k);
-            hipLaunchKernelGGL(k_tree_split, dim3(blocks_for(ub, TB_THREADS)), dim3(TB_THREADS), 0,
+            // one wave per frontier node, grid-stride
+            const uint64_t sb = (ub + TB_THREADS / 64 - 1) / (TB_THREADS / 64);
+            hipLaunchKernelGGL(k_tree_split, dim3((uint32_t)(sb < 2048 ? sb : 2048)),
+                               dim3(TB_THREADS), 0,
                                s, fr, (const uint32_t *)bs, k, ctx->key, ctx->nd_first,
                                ctx->nd_count, ctx->child_bounds, ctx->fr_nchild,
                                ctx->fr_ninternal, leaf, KB);
