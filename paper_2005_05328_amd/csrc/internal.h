@@ -301,6 +301,10 @@ dzs_status dzs_scan_u32(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_
 // the same over min(n_max, *n_dev) elements, the count read on the device
 dzs_status dzs_scan_u32_dev(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n_max,
                             const uint32_t *n_dev, uint32_t *total_dev, hipStream_t s);
+dzs_status dzs_scan2_u32_dev(dzs_ctx *ctx, const uint32_t *in0, uint32_t *out0,
+                             const uint32_t *in1, uint32_t *out1, uint64_t n_max,
+                             const uint32_t *n_dev, uint32_t *total0, uint32_t *total1,
+                             hipStream_t s);
 uint64_t dzs_sort_hist_words(uint64_t n);
 dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s,
                           int first_pass = 0);  // ctx->key/idx in+out; an even first_pass

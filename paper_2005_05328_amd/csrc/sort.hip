@@ -60,11 +60,25 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *__
         part[blockIdx.x] = tot;
 }
 
-// scan one tile (blocked: thread t owns items t*16 .. t*16+15), adding the tile offset
+// Offset of tile b from the unscanned tile sums part[0..b) (b <= SCAN_TILE), summed by the
+// block; every thread returns it.
+__device__ __forceinline__ uint32_t tile_offset(const uint32_t *__restrict__ part, uint32_t b,
+                                                uint32_t *s_wave) {
+    uint32_t sum = 0;
+    for (uint32_t i = threadIdx.x; i < b; i += SCAN_THREADS)
+        sum += part[i];
+    uint32_t tot;
+    block_excl_scan_256(sum, s_wave, &tot);
+    return tot;
+}
+
+// scan one tile (blocked: thread t owns items t*16 .. t*16+15), adding the tile offset: the
+// scanned tile sums offs[b], or the unscanned tile sums part[0..b) (two-launch scan), or 0
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out,
                                                             uint64_t n,
                                                             const uint32_t *__restrict__ offs,
+                                                            const uint32_t *__restrict__ part,
                                                             uint32_t *__restrict__ total,
                                                             const uint32_t *__restrict__ n_dev) {
     __shared__ uint32_t s_wave[4];
@@ -83,6 +97,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile(const uint32_t *__re
     uint32_t run = block_excl_scan_256(sum, s_wave, &tot);
     if (offs)
         run += offs[blockIdx.x];
+    else if (part)
+        run += tile_offset(part, blockIdx.x, s_wave);
 #pragma unroll
     for (int r = 0; r < SCAN_ITEMS; ++r) {
         uint64_t e = base + r;
@@ -92,6 +108,76 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile(const uint32_t *__re
     }
     if (total && threadIdx.x == SCAN_THREADS - 1 && blockIdx.x == gridDim.x - 1)
         *total = run;
+}
+
+// Two independent scans of the same length in one pass (the tree build's child and
+// internal-node counts): tile sums of in0 to part[b], of in1 to part[nb + b].
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan2_reduce(const uint32_t *__restrict__ in0,
+                                                               const uint32_t *__restrict__ in1,
+                                                               uint64_t n,
+                                                               uint32_t *__restrict__ part,
+                                                               const uint32_t *__restrict__ n_dev) {
+    __shared__ uint32_t s_wave[4];
+    if (n_dev && *n_dev < n)
+        n = *n_dev;
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s0 = 0, s1 = 0;
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t e = base + (uint64_t)r * SCAN_THREADS + threadIdx.x;
+        if (e < n) {
+            s0 += in0[e];
+            s1 += in1[e];
+        }
+    }
+    uint32_t t0, t1;
+    block_excl_scan_256(s0, s_wave, &t0);
+    block_excl_scan_256(s1, s_wave, &t1);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t0;
+        part[gridDim.x + blockIdx.x] = t1;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan2_tile(
+    const uint32_t *__restrict__ in0, uint32_t *__restrict__ out0,
+    const uint32_t *__restrict__ in1, uint32_t *__restrict__ out1, uint64_t n,
+    const uint32_t *__restrict__ part, uint32_t *__restrict__ total0,
+    uint32_t *__restrict__ total1, const uint32_t *__restrict__ n_dev) {
+    __shared__ uint32_t s_wave[4];
+    if (n_dev && *n_dev < n)
+        n = *n_dev;
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v0[SCAN_ITEMS], v1[SCAN_ITEMS];
+    uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t e = base + r;
+        v0[r] = e < n ? in0[e] : 0u;
+        v1[r] = e < n ? in1[e] : 0u;
+        s0 += v0[r];
+        s1 += v1[r];
+    }
+    uint32_t t;
+    uint32_t run0 = block_excl_scan_256(s0, s_wave, &t);
+    uint32_t run1 = block_excl_scan_256(s1, s_wave, &t);
+    if (part) {
+        run0 += tile_offset(part, blockIdx.x, s_wave);
+        run1 += tile_offset(part + gridDim.x, blockIdx.x, s_wave);
+    }
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t e = base + r;
+        if (e < n) {
+            out0[e] = run0;
+            out1[e] = run1;
+        }
+        run0 += v0[r];
+        run1 += v1[r];
+    }
+    if (threadIdx.x == SCAN_THREADS - 1 && blockIdx.x == gridDim.x - 1) {
+        *total0 = run0;
+        *total1 = run1;
+    }
 }
 
 uint64_t dzs_scan_tmp_words(uint64_t n) {
@@ -104,13 +190,15 @@ uint64_t dzs_scan_tmp_words(uint64_t n) {
     return words + 64;
 }
 
+// One tile: one launch.  Up to SCAN_TILE tiles: tile sums, then the tiles, each adding the
+// sum of the tile sums before it (two launches).  More: the tile sums are scanned recursively.
 static dzs_status scan_rec(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint64_t n,
                            uint32_t *total_dev, uint32_t *tmp, const uint32_t *n_dev,
                            hipStream_t s) {
     uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb <= 1) {
         hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SCAN_THREADS), 0, s, in, out, n,
-                           (const uint32_t *)nullptr, total_dev, n_dev);
+                           (const uint32_t *)nullptr, (const uint32_t *)nullptr, total_dev, n_dev);
         return dzs_check_launch(ctx, "scan_tile");
     }
     // tiles past the device count sum to zero, so the partial sums need no count of their own
@@ -118,9 +206,14 @@ static dzs_status scan_rec(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uint
     hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, n, part,
                        n_dev);
     DZS_TRY(dzs_check_launch(ctx, "scan_reduce"));
+    if (nb <= SCAN_TILE) {
+        hipLaunchKernelGGL(k_scan_tile, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, out, n,
+                           (const uint32_t *)nullptr, (const uint32_t *)part, total_dev, n_dev);
+        return dzs_check_launch(ctx, "scan_tile");
+    }
     DZS_TRY(scan_rec(ctx, part, part_scan, nb, nullptr, tmp + 2 * nb, nullptr, s));
     hipLaunchKernelGGL(k_scan_tile, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in, out, n,
-                       (const uint32_t *)part_scan, total_dev, n_dev);
+                       (const uint32_t *)part_scan, (const uint32_t *)nullptr, total_dev, n_dev);
     return dzs_check_launch(ctx, "scan_tile");
 }
 
@@ -145,6 +238,34 @@ dzs_status dzs_scan_u32_dev(dzs_ctx *ctx, const uint32_t *in, uint32_t *out, uin
         return dzs_fail(ctx, DZS_ECAPACITY, "scan of %llu elements exceeds scratch",
                         (unsigned long long)n_max);
     return scan_rec(ctx, in, out, n_max, total_dev, ctx->scan_tmp, n_dev, s);
+}
+
+// Two exclusive scans of n_max (count on the device) elements with one pair of launches when
+// they span at most SCAN_TILE tiles; otherwise one scan after the other.
+dzs_status dzs_scan2_u32_dev(dzs_ctx *ctx, const uint32_t *in0, uint32_t *out0,
+                             const uint32_t *in1, uint32_t *out1, uint64_t n_max,
+                             const uint32_t *n_dev, uint32_t *total0, uint32_t *total1,
+                             hipStream_t s) {
+    if (n_max == 0)
+        n_max = 1;
+    const uint64_t nb = (n_max + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb > SCAN_TILE) {
+        DZS_TRY(dzs_scan_u32_dev(ctx, in0, out0, n_max, n_dev, total0, s));
+        return dzs_scan_u32_dev(ctx, in1, out1, n_max, n_dev, total1, s);
+    }
+    if (dzs_scan_tmp_words(n_max) > ctx->scan_tmp_cap)
+        return dzs_fail(ctx, DZS_ECAPACITY, "scan of %llu elements exceeds scratch",
+                        (unsigned long long)n_max);
+    uint32_t *part = nullptr;
+    if (nb > 1) {
+        part = ctx->scan_tmp;  // 2 nb words
+        hipLaunchKernelGGL(k_scan2_reduce, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in0, in1,
+                           n_max, part, n_dev);
+        DZS_TRY(dzs_check_launch(ctx, "scan2_reduce"));
+    }
+    hipLaunchKernelGGL(k_scan2_tile, dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, s, in0, out0, in1,
+                       out1, n_max, (const uint32_t *)part, total0, total1, n_dev);
+    return dzs_check_launch(ctx, "scan2_tile");
 }
 
 // ---------------------------------------------------------------------------------------

@@ -377,10 +377,9 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
                                ctx->nd_count, ctx->child_bounds, ctx->fr_nchild,
                                ctx->fr_ninternal, leaf, KB);
             DZS_TRY(dzs_check_launch(ctx, "tree_split"));
-            DZS_TRY(dzs_scan_u32_dev(ctx, ctx->fr_nchild, ctx->fr_child_off, ub, bs + BS_NF,
-                                     bs + BS_CHILDREN, s));
-            DZS_TRY(dzs_scan_u32_dev(ctx, ctx->fr_ninternal, ctx->fr_int_off, ub, bs + BS_NF,
-                                     bs + BS_INTERNAL, s));
+            DZS_TRY(dzs_scan2_u32_dev(ctx, ctx->fr_nchild, ctx->fr_child_off, ctx->fr_ninternal,
+                                      ctx->fr_int_off, ub, bs + BS_NF, bs + BS_CHILDREN,
+                                      bs + BS_INTERNAL, s));
             hipLaunchKernelGGL(k_tree_emit, dim3(blocks_for(ub, TB_THREADS)), dim3(TB_THREADS), 0,
                                s, fr, (const uint32_t *)bs, k, ctx->child_bounds,
                                ctx->fr_child_off, ctx->fr_int_off, cap, ctx->nd_first,
