@@ -628,13 +628,15 @@ def copy_state(dst, src):
 # precision form mesh values are 4-byte reals / 8-byte complex instead of 8 / 16
 def algorithmic_bytes(cls, N, C, fp32=False):
     r, c = (4, 8) if fp32 else (8, 16)
+    n = round(C ** (1.0 / 3.0))
+    H = (n // 2 + 1) * n * n  # complex cells of the half spectrum (k_x = 0 .. n/2)
     return {
         "kick": 72 * N, "drift_lightcone": 72 * N, "morton_keys": 36 * N,
         "pm_deposit": 28 * N + 8 * C,
-        # x pass: forward reads the 8-byte fixed-point mesh and writes complex; inverse reads
-        # complex and writes the real potential (the class averages both launches)
-        "pm_fft_x": ((8 + c) + (c + r)) * C // 2,
-        "pm_fft_y": 2 * c * C, "pm_fft_z_green": 2 * c * C,
+        # x pass: forward reads the 8-byte fixed-point mesh and writes the half spectrum;
+        # inverse reads it and writes the real potential (the class averages both launches)
+        "pm_fft_x": ((8 * C + c * H) + (c * H + r * C)) // 2,
+        "pm_fft_y": 2 * c * H, "pm_fft_z_green": 2 * c * H,
         "pm_interp": 48 * N + r * C,
     }.get(cls)
 

@@ -478,7 +478,8 @@ dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s) {
 // passes the monomial coefficients in t = 2 w / w_max - 1; the kernel evaluates it by Horner.
 // The fit is checked on the host to 1e-12 relative error in S.
 // ---------------------------------------------------------------------------------------
-#define WALK_QN 20  // split-factor polynomial coefficients (Horner, fully unrolled)
+#define WALK_QN 18  // split-factor polynomial coefficients (Horner, fully unrolled): worst
+                    // relative error in S 1.3e-13 at r_cut = 4.5 r_s, 7e-12 at 5 r_s
 #define WALK_QF 12  // the same for FP32 evaluation
 
 struct walk_args {
