@@ -185,6 +185,12 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_emit(
     nd_nchild[node] = (uint8_t)nc;
 }
 
+// mult^(1/3), the softening factor of a particle of multiplicity mult (1 for an original
+// particle without the library call: most particles)
+__device__ __forceinline__ double mult_cbrt(uint32_t mult) {
+    return mult == 1u ? 1.0 : cbrt((double)mult);
+}
+
 // Moments of node v (mass, centre of mass, particle bounding box, largest softening): of its
 // particles for a leaf, of its children (already complete) otherwise.
 __device__ __forceinline__ void node_moments(
@@ -207,7 +213,7 @@ __device__ __forceinline__ void node_moments(
         const uint32_t s = nd_first[v], e = s + nd_count[v];
         for (uint32_t j = s; j < e; ++j) {
             const double mj = m0 * (double)mult[j];
-            const double hj = h0 * cbrt((double)mult[j]);
+            const double hj = h0 * mult_cbrt(mult[j]);
             const double xj = x[j], yj = y[j], zj = z[j];
             m += mj;
             sx += mj * xj;
@@ -764,7 +770,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         if (A.bins && __ballot(active) == 0ull)
             continue;  // no target of this group ends a step at this boundary
         const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
-        const double hi = W.h0 * cbrt((double)A.mult[i]);
+        const double hi = W.h0 * mult_cbrt(A.mult[i]);
         // group bounding box
         double mnx = xi, mny = yi, mnz = zi, mxx = xi, mxy = yi, mxz = zi;
         for (int o = 32; o >= 1; o >>= 1) {
@@ -1022,7 +1028,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                             e.y = T(ey_ - oy);
                             e.z = T(ez_ - oz);
                             e.m = T(W.m0 * md);
-                            const T hj = T(W.h0 * cbrt(md));
+                            const T hj = T(W.h0 * mult_cbrt(mj));
                             e.h = hj;
                             e.h2 = hj * hj;
                         }

@@ -1,5 +1,6 @@
 """Parity at the full sizes of the benchmark workloads, in the launch configuration bench.py
-times (tree opening angle 0.5, 32 targets per group, leaf size 16), on sampled outputs.
+times (tree opening angle 0.5, 32 targets per group, leaves of 16 at 128^3 and 8 at 512^3,
+the default PM tiles), on sampled outputs.
 
 The GPU computes the force of every particle; the oracle computes it for a seeded sample of
 targets: the PM part on the full mesh (deposit of every particle, Poisson solve, 4-point
@@ -22,8 +23,10 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    "128cube_fp64": dict(n_side=128, L=256.0, ng=256, seed=20050529, fp32=False, n_t=1500),
-    "512cube_fp32": dict(n_side=512, L=1000.0, ng=512, seed=20050530, fp32=True, n_t=600),
+    "128cube_fp64": dict(n_side=128, L=256.0, ng=256, seed=20050529, fp32=False, n_t=1500,
+                         leaf=16),
+    "512cube_fp32": dict(n_side=512, L=1000.0, ng=512, seed=20050530, fp32=True, n_t=600,
+                         leaf=8),
 }
 
 
@@ -86,10 +89,10 @@ def test_full_size_force_on_sampled_targets(name):
     ctx.pm_force(box, st, dz.PMParams(ng, prec, r_s, 0, 0))
     torch.cuda.synchronize()
     g_pm = np.stack([st.gx[:n].cpu().numpy(), st.gy[:n].cpu().numpy(), st.gz[:n].cpu().numpy()])
-    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, 0.5, 16, 32, prec, 1))
+    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, 0.5, c["leaf"], 32, prec, 1))
     torch.cuda.synchronize()
     g_all = np.stack([st.gx[:n].cpu().numpy(), st.gy[:n].cpu().numpy(), st.gz[:n].cpu().numpy()])
-    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, 0.0, 16, 32, prec, 0))
+    ctx.tree_force(box, st, dz.TreeParams(r_s, r_cut, 0.0, c["leaf"], 32, prec, 0))
     torch.cuda.synchronize()
     g_sr0 = np.stack([st.gx[:n].cpu().numpy(), st.gy[:n].cpu().numpy(), st.gz[:n].cpu().numpy()])
     ctx.close()
