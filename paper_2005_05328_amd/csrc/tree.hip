@@ -487,6 +487,16 @@ dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s) {
 #define WALK_QN 18  // split-factor polynomial coefficients (Horner, fully unrolled): worst
                     // relative error in S 1.3e-13 at r_cut = 4.5 r_s, 7e-12 at 5 r_s
 #define WALK_QF 12  // the same for FP32 evaluation
+// list region / cutoff sphere below which a group evaluates densely: in FP32 the one-pass loop
+// wins even for wide groups (512^3 walk: 300 ms masked, 285 ms at 2.5, 282 ms at 3-4, 281 ms
+// dense everywhere), in FP64 the masked loop wins everywhere (128^3 walk: 2.38 ms masked,
+// 2.40 at 2.0, 2.81 dense everywhere)
+#ifndef WALK_DENSE_E_F32
+#define WALK_DENSE_E_F32 6.0
+#endif
+#ifndef WALK_DENSE_E_F64
+#define WALK_DENSE_E_F64 0.0
+#endif
 
 struct walk_args {
     const uint32_t *grp_first;
@@ -660,6 +670,32 @@ __device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T
     return wfma(dx, dx, wfma(dy, dy, dz * dz));
 }
 
+// Pair force factor g (the force on the target is m r_ij g): g_soft(r) S(r/r_s) with
+// S = 1 - u^3 q(u^2), u = r/r_s; outside the spline support g_soft = r^-3 and the product is
+// r^-3 - r_s^-3 q, one fused operation.
+template <typename T>
+__device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T eh2, T hi, T hi2,
+                                         T rs_inv2, T rs_inv3, T t_scale) {
+    constexpr int QN = split_coef<T>::N;
+    const T rinv = pair_rsqrt(r2);
+    const T w = r2 * rs_inv2;
+    const T t = wfma(w, t_scale, T(-1.0));
+    T q = split_coef<T>::at(A, QN - 1);
+#pragma unroll
+    for (int c = QN - 2; c >= 0; --c)
+        q = wfma(q, t, split_coef<T>::at(A, c));
+    const T rq = rs_inv3 * q;
+    T g;
+    if (r2 < pair_hmax(eh2, hi2)) {
+        const T r = r2 * rinv;
+        const T ks = gsoft_inner(r, wmax(eh, hi));
+        g = ks - ks * (r2 * r) * rq;
+    } else {
+        g = wfma(rinv * rinv, rinv, -rq);
+    }
+    return g;
+}
+
 // The lane's share of the list (entries s, s + P, s + 2P, ...) in two passes per block of 32
 // of its entries: a cheap pass shifts one acceptance bit per entry (inside r_cut, not the
 // target itself) into a 32-bit mask, first entry highest, then the lane evaluates only the
@@ -667,9 +703,6 @@ __device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T
 // times more entries than any one target's cutoff sphere; without the mask the whole wave
 // would step through the force arithmetic for every entry some lane accepts.  The caller
 // fills the P entries past the list with far-away sentinels, so the block bound is uniform.
-//
-// Pair force: m r_ij g_soft(r) S(r/r_s) with S = 1 - u^3 q(u^2), u = r/r_s; outside the
-// spline support g_soft = r^-3 and the product is r^-3 - r_s^-3 q, one fused operation.
 template <typename T, bool MINIMG>
 __device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W,
                                           const src_entry<T> *src, uint32_t nlist, uint32_t s,
@@ -678,7 +711,6 @@ __device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W
     const T rcut2 = T(W.rcut2), rs_inv2 = T(W.rs_inv2);
     const T rs_inv3 = T(W.rs_inv * W.rs_inv2);
     const T t_scale = T(A.t_scale), L = T(W.L);
-    constexpr int QN = split_coef<T>::N;
     // entries per lane: uniform, so the block loops run on the scalar unit
     const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
     for (uint32_t kb = 0; kb < n_max; kb += 32u) {
@@ -699,27 +731,39 @@ __device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W
             const src_entry<T> &e = blk[k * P];
             T dx, dy, dz;
             const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
-            const T rinv = pair_rsqrt(r2);
-            const T w = r2 * rs_inv2;
-            const T t = wfma(w, t_scale, T(-1.0));
-            T q = split_coef<T>::at(A, QN - 1);
-#pragma unroll
-            for (int c = QN - 2; c >= 0; --c)
-                q = wfma(q, t, split_coef<T>::at(A, c));
-            const T rq = rs_inv3 * q;
-            T g;
-            if (r2 < pair_hmax(e.h2, hi2)) {
-                const T r = r2 * rinv;
-                const T ks = gsoft_inner(r, wmax(e.h, hi));
-                g = ks - ks * (r2 * r) * rq;
-            } else {
-                g = wfma(rinv * rinv, rinv, -rq);
-            }
-            const T f = e.m * g;
+            const T f = e.m * pair_factor<T>(A, r2, e.h, e.h2, hi, hi2, rs_inv2, rs_inv3, t_scale);
             ax = wfma(f, dx, ax);
             ay = wfma(f, dy, ay);
             az = wfma(f, dz, az);
         }
+    }
+}
+
+// The lane's share of the list in one pass: every entry is evaluated and the pairs outside
+// r_cut (and the target itself) are multiplied by zero.  All lanes of a phase read the same
+// entry and every lane works on every iteration, so when most of the list lies inside most
+// targets' cutoff spheres (a compact group) this costs less than the masked two-pass loop.
+template <typename T, bool MINIMG>
+__device__ __forceinline__ void pair_dense(const walk_args &A, const walk_geom &W,
+                                           const src_entry<T> *src, uint32_t nlist, uint32_t s,
+                                           uint32_t P, T xi, T yi, T zi, T hi, T hi2, T &ax,
+                                           T &ay, T &az, uint32_t &n_pairs) {
+    const T rcut2 = T(W.rcut2), rs_inv2 = T(W.rs_inv2);
+    const T rs_inv3 = T(W.rs_inv * W.rs_inv2);
+    const T t_scale = T(A.t_scale), L = T(W.L);
+    const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
+    for (uint32_t k = 0; k < n_max; ++k) {
+        const src_entry<T> &e = src[s + k * P];
+        T dx, dy, dz;
+        const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
+        const bool in = r2 < rcut2 && r2 > T(0.0);
+        const T g = pair_factor<T>(A, r2, e.h, e.h2, hi, hi2, rs_inv2, rs_inv3, t_scale);
+        // the factor of a pair outside (or of the target itself: r = 0) is not used
+        const T f = in ? e.m * g : T(0.0);
+        ax = wfma(f, dx, ax);
+        ay = wfma(f, dy, ay);
+        az = wfma(f, dz, az);
+        n_pairs += in ? 1u : 0u;
     }
 }
 
@@ -784,6 +828,15 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         const double gcx = 0.5 * (mnx + mxx), gcy = 0.5 * (mny + mxy), gcz = 0.5 * (mnz + mxz);
         const double ghx = 0.5 * (mxx - mnx), ghy = 0.5 * (mxy - mny), ghz = 0.5 * (mxz - mnz);
         const double ghmax = fmax(ghx, fmax(ghy, ghz));
+        // the list is culled to the group's box grown by r_cut (Steiner: volume, surface,
+        // edge and ball terms); when that region is at most WALK_DENSE_E_* times one cutoff
+        // sphere, enough entries are inside enough targets' spheres to evaluate densely
+        const double rc = W.rcut, pi = 3.14159265358979323846;
+        const double v_ball = (4.0 / 3.0) * pi * rc * rc * rc;
+        const double v_list = 8.0 * ghx * ghy * ghz + 8.0 * rc * (ghx * ghy + ghy * ghz + ghz * ghx) +
+                              2.0 * pi * rc * rc * (ghx + ghy + ghz) + v_ball;
+        const double dense_e = sizeof(T) == 4 ? WALK_DENSE_E_F32 : WALK_DENSE_E_F64;
+        const bool dense = v_list <= dense_e * v_ball;
         // relative criterion: alpha / G times the smallest previous |g| of the group
         double alpha_a = 0.0;
         if (A.aold) {
@@ -810,12 +863,20 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 e.m = e.h = e.h2 = T(0.0);
             }
             __syncthreads();
-            if (wide)
+            if (dense) {
+                if (wide)
+                    pair_dense<T, true>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
+                                        ay, az, n_pairs);
+                else
+                    pair_dense<T, false>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
+                                         ay, az, n_pairs);
+            } else if (wide) {
                 pair_loop<T, true>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
                                    az, n_pairs);
-            else
+            } else {
                 pair_loop<T, false>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
                                     az, n_pairs);
+            }
             nlist = 0;
             __syncthreads();
         };
