@@ -211,9 +211,10 @@ __device__ __forceinline__ void node_moments(
     const uint32_t nc = nd_nchild[v];
     if (nc == 0) {
         const uint32_t s = nd_first[v], e = s + nd_count[v];
+        uint32_t mmax = 0;
         for (uint32_t j = s; j < e; ++j) {
-            const double mj = m0 * (double)mult[j];
-            const double hj = h0 * mult_cbrt(mult[j]);
+            const uint32_t mu = mult[j];
+            const double mj = m0 * (double)mu;
             const double xj = x[j], yj = y[j], zj = z[j];
             m += mj;
             sx += mj * xj;
@@ -221,8 +222,9 @@ __device__ __forceinline__ void node_moments(
             sz += mj * zj;
             mnx = fmin(mnx, xj); mny = fmin(mny, yj); mnz = fmin(mnz, zj);
             mxx = fmax(mxx, xj); mxy = fmax(mxy, yj); mxz = fmax(mxz, zj);
-            hmax = fmax(hmax, hj);
+            mmax = mu > mmax ? mu : mmax;
         }
+        hmax = h0 * mult_cbrt(mmax);  // the softening grows with the multiplicity
     } else {
         const uint32_t c0 = nd_child[v];
         for (uint32_t c = c0; c < c0 + nc; ++c) {
