@@ -181,6 +181,10 @@ struct dzs_ctx {
     // ---- timing
     bool timing = false;
     dzs_timer_pool *timers = nullptr;
+    // second stream (default priority) for the mesh solve that overlaps the tree build and
+    // walk of kdk_step, and its fork / join events; created at first use
+    hipStream_t pm_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_pm = nullptr;
     double t_ms[KC_COUNT] = {0};
     uint64_t t_calls[KC_COUNT] = {0};
 };
@@ -370,6 +374,10 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
 
 // pm.hip
 bool dzs_pm_mesh_ok(int ng);
+dzs_status dzs_pm_solve(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                        const dzs_pm_params *prm, hipStream_t s);
+dzs_status dzs_pm_apply(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                        const dzs_pm_params *prm, hipStream_t s);
 dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                       const dzs_pm_params *prm, hipStream_t s);
 dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStream_t s);

@@ -894,8 +894,9 @@ static dzs_status pm_deposit(dzs_ctx *ctx, const dzs_particles *p, uint64_t cell
     return dzs_check_launch(ctx, "pm_deposit");
 }
 
-dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
-                      const dzs_pm_params *prm, hipStream_t s) {
+// The potential on the mesh (deposit, forward FFT, Green's function, inverse FFT).
+dzs_status dzs_pm_solve(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                        const dzs_pm_params *prm, hipStream_t s) {
     const int ng = prm->ng;
     fft_plan P;
     if (!dzs_pm_mesh_ok(ng) || !make_plan(ng, &P))
@@ -915,13 +916,29 @@ dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
     DZS_TRY(pm_deposit(ctx, p, ng3, delta, ng, none, prm->tile_chunk, s));
     const double q_scale = box->m0 / (DEP_FRAC * delta * delta * delta);
     const double gconst = -4.0 * 3.14159265358979323846 * box->G / (double)ng3;
-    if (prm->precision == DZS_FP32) {
-        DZS_TRY(pm_solve<float2>(ctx, P, tw, gt, k2t, q_scale, gconst, 1, none, s));
+    if (prm->precision == DZS_FP32)
+        return pm_solve<float2>(ctx, P, tw, gt, k2t, q_scale, gconst, 1, none, s);
+    return pm_solve<double2>(ctx, P, tw, gt, k2t, q_scale, gconst, 1, none, s);
+}
+
+// The long-range force at the particles from the potential dzs_pm_solve left on the mesh
+// (same box, particles and parameters).
+dzs_status dzs_pm_apply(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                        const dzs_pm_params *prm, hipStream_t s) {
+    const int ng = prm->ng;
+    const uint64_t ng3 = (uint64_t)ng * ng * ng;
+    const double delta = box->L / ng;
+    const pm_batch none{nullptr, nullptr, 0, nullptr};
+    if (prm->precision == DZS_FP32)
         return pm_interp<float>(ctx, p, prm->accumulate, delta, ng, none, prm->tile_chunk, ng3,
                                 s);
-    }
-    DZS_TRY(pm_solve<double2>(ctx, P, tw, gt, k2t, q_scale, gconst, 1, none, s));
     return pm_interp<double>(ctx, p, prm->accumulate, delta, ng, none, prm->tile_chunk, ng3, s);
+}
+
+dzs_status dzs_pm_run(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
+                      const dzs_pm_params *prm, hipStream_t s) {
+    DZS_TRY(dzs_pm_solve(ctx, box, p, prm, s));
+    return dzs_pm_apply(ctx, box, p, prm, s);
 }
 
 // A batch: every box's mesh at its offset of the mesh arrays.  dzs_pm_batch_prepare fills
