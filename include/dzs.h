@@ -349,7 +349,10 @@ dzs_status lightcone_emit(dzs_ctx *ctx, const dzs_box *box, const dzs_particles 
  *   DZS coarsening at a1 (optional; skipped when R_lc + b >= sqrt(3)/2 L, where no node can
  *   qualify); reorder the state by Morton key; g = PM + tree; p += g K2.
  * The state is left sorted by Morton key.  report (optional) receives the coarsening
- * counts.  Synchronises the stream (coarsening counts; the capacity check after the walk). */
+ * counts.  Synchronises the stream (coarsening counts; the capacity check after the walk).
+ * The mesh solve runs on a stream the context owns (default priority), forked from and
+ * joined back to `stream` with events inside the call, so all of the step's work is ordered
+ * before whatever the caller enqueues on `stream` next. */
 dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *state,
                     const dzs_step_params *prm, dzs_lc_ring *ring, dzs_coarsen_report *report,
                     void *stream);
