@@ -677,11 +677,18 @@ static dzs_status hier_force(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st
             DZS_TRY(dzs_permute_u8(ctx, ctx->hbins, ctx->idx, st->n, s));
     }
     dzs_tree_params t = t0;
-    DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
-                           t.group_size, s));
+    // the mesh solve overlaps the tree build, as in kdk_step
+    DZS_TRY(ensure_pm_stream(ctx));
+    DZS_HIP(ctx, hipEventRecord(ctx->ev_fork, s));
+    DZS_HIP(ctx, hipStreamWaitEvent(ctx->pm_stream, ctx->ev_fork, 0));
     dzs_pm_params pm = prm->pm;
     pm.accumulate = 0;
-    DZS_TRY(dzs_pm_run(ctx, box, st, &pm, s));
+    DZS_TRY(dzs_pm_solve(ctx, box, st, &pm, ctx->pm_stream));
+    DZS_HIP(ctx, hipEventRecord(ctx->ev_pm, ctx->pm_stream));
+    DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
+                           t.group_size, s));
+    DZS_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_pm, 0));
+    DZS_TRY(dzs_pm_apply(ctx, box, st, &pm, s));
     t.accumulate = 1;
     struct walk_set {
         dzs_ctx *c;
