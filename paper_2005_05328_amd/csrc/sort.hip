@@ -4,10 +4,10 @@
 // Sort: 8 passes of 8-bit digits (the sort before a tree build skips the lowest two: the tree
 // reads the keys' order to level 15 only).  Per pass: (1) each 256-thread block counts the digits of
 // its 4096-key tile in LDS; (2) one exclusive scan over the digit-major table gives every
-// (digit, tile) its global start; (3) each block ranks its tile stably — wave-level digit
-// matching through eight ballots, per-wave counts combined in LDS — stages the tile in LDS in
-// local digit order, and writes it out so that consecutive lanes write consecutive addresses
-// of the same digit run.
+// (digit, tile) its global start; (3) each block ranks its tile stably — each wave ranks its
+// own quarter of the tile by wave-level digit matching through eight ballots, then the waves'
+// digit counts become offsets — stages the tile in LDS in local digit order, and writes it out
+// so that consecutive lanes write consecutive addresses of the same digit run.
 #include "internal.h"
 
 #define SCAN_THREADS 256
@@ -295,14 +295,22 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__r
     hist[(uint64_t)threadIdx.x * tiles + blockIdx.x] = s_h[threadIdx.x];
 }
 
+// Each wave ranks its own contiguous quarter of the tile (16 rounds of 64 keys, in input
+// order) against running per-wave digit counts in LDS, with no block barrier between rounds:
+// lanes holding the same digit are found with eight ballots, the lowest of them advances the
+// wave's count.  Then the waves' counts become offsets (wave 0's keys of a digit first), the
+// tile is staged in LDS in local digit order, and written out so that consecutive lanes write
+// consecutive addresses of the same digit run.  Equal digits keep their input order.
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
     uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out, uint64_t n, int shift,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hist_scan, uint32_t tiles) {
+    constexpr int WAVES = SORT_THREADS / 64;
+    constexpr int ROUNDS = SORT_ITEMS;  // rounds of 64 keys per wave: 4 waves x 16 x 64 = tile
     __shared__ uint64_t s_key[SORT_TILE];
     __shared__ uint32_t s_idx[SORT_TILE];
-    __shared__ uint32_t s_lstart[256], s_run[256], s_gstart[256];
-    __shared__ uint32_t s_wcnt[4][256];
+    __shared__ uint32_t s_lstart[256], s_gstart[256];
+    __shared__ uint32_t s_wcnt[WAVES][256];
     __shared__ uint32_t s_wave[4];
 
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -310,56 +318,64 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t cnt = (uint32_t)((n - base) < SORT_TILE ? (n - base) : SORT_TILE);
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
-    uint32_t c = hist[(uint64_t)tid * tiles + blockIdx.x];
+    const uint32_t c = hist[(uint64_t)tid * tiles + blockIdx.x];
     s_gstart[tid] = hist_scan[(uint64_t)tid * tiles + blockIdx.x];
-    uint32_t ls = block_excl_scan_256(c, s_wave, nullptr);
-    s_lstart[tid] = ls;
-    s_run[tid] = 0;
-    for (int w = 0; w < 4; ++w)
+    s_lstart[tid] = block_excl_scan_256(c, s_wave, nullptr);
+    for (int w = 0; w < WAVES; ++w)
         s_wcnt[w][tid] = 0;
     __syncthreads();
 
-    for (uint32_t r = 0; r < SORT_ITEMS; ++r) {
-        const uint32_t local = r * SORT_THREADS + tid;
+    uint64_t k[ROUNDS];
+    uint32_t id[ROUNDS], pos[ROUNDS];
+    const uint32_t q0 = wave * (ROUNDS * 64);
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t local = q0 + (uint32_t)r * 64u + lane;
         const bool valid = local < cnt;
-        uint64_t k = valid ? key_in[base + local] : 0ull;
-        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        k[r] = valid ? key_in[base + local] : 0ull;
+        id[r] = valid ? idx_in[base + local] : 0u;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            uint64_t bal = __ballot(((d >> bit) & 1u) != 0u);
+            const uint64_t bal = __ballot(((d >> bit) & 1u) != 0u);
             m &= ((d >> bit) & 1u) ? bal : ~bal;
         }
         const uint32_t rank = (uint32_t)__popcll(m & lt_mask);
-        const uint32_t wcount = (uint32_t)__popcll(m);
-        const uint32_t tag = r + 1;
+        // every lane reads the wave's count before the lowest lane of the digit advances it
+        // (LDS operations of one wave complete in order)
+        const uint32_t prev = s_wcnt[wave][d];
+        pos[r] = prev + rank;
         if (valid && rank == 0)
-            s_wcnt[wave][d] = (tag << 16) | wcount;
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = 0;
-            for (uint32_t w = 0; w < wave; ++w) {
-                uint32_t v = s_wcnt[w][d];
-                pre += ((v >> 16) == tag) ? (v & 0xffffu) : 0u;
-            }
-            uint32_t lp = s_lstart[d] + s_run[d] + pre + rank;
-            s_key[lp] = k;
-            s_idx[lp] = idx_in[base + local];
-        }
-        __syncthreads();
-        uint32_t tot = 0;
-        for (int w = 0; w < 4; ++w) {
-            uint32_t v = s_wcnt[w][tid];
-            tot += ((v >> 16) == tag) ? (v & 0xffffu) : 0u;
-        }
-        s_run[tid] += tot;
-        __syncthreads();
+            s_wcnt[wave][d] = prev + (uint32_t)__popcll(m);
     }
+    __syncthreads();
+    {
+        // offsets of each wave's run of digit tid inside the tile
+        uint32_t run = s_lstart[tid];
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t t = s_wcnt[w][tid];
+            s_wcnt[w][tid] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const uint32_t local = q0 + (uint32_t)r * 64u + lane;
+        if (local < cnt) {
+            const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+            const uint32_t lp = s_wcnt[wave][d] + pos[r];
+            s_key[lp] = k[r];
+            s_idx[lp] = id[r];
+        }
+    }
+    __syncthreads();
     for (uint32_t i = tid; i < cnt; i += SORT_THREADS) {
-        uint64_t k = s_key[i];
-        uint32_t d = (uint32_t)(k >> shift) & 255u;
-        uint64_t gp = (uint64_t)s_gstart[d] + (i - s_lstart[d]);
-        key_out[gp] = k;
+        const uint64_t kk = s_key[i];
+        const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+        const uint64_t gp = (uint64_t)s_gstart[d] + (i - s_lstart[d]);
+        key_out[gp] = kk;
         idx_out[gp] = s_idx[i];
     }
 }
