@@ -167,7 +167,9 @@ typedef struct {
 typedef struct {
     double r_s, r_cut;   /* split scale and cutoff (r_cut < L/2, r_cut <= 5 r_s) */
     double theta;        /* opening angle, >= 0 */
-    int32_t leaf_size;   /* particles per tree leaf, 1..64 (0 = default 8) */
+    int32_t leaf_size;   /* particles per tree leaf, 1..64 (0 = default 8); the context
+                            holds n/2 + 4096 nodes, which leaves of fewer than 8 particles
+                            can exceed in clustered states (DZS_ECAPACITY) */
     int32_t group_size;  /* targets per wave64 group, a power of two <= 64 (0 = default
                             16); each target is served by 64/group_size lanes */
     int32_t precision;   /* DZS_FP64, or DZS_FP32: interaction list and pair arithmetic in
