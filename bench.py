@@ -301,95 +301,180 @@ def run_ensemble(args, dz, torch, dzs_ics):
     }
 
 
-def run_lean(args, dz, torch, dzs_ics):
-    """The 1024^3 configuration on one GPU: a single state (no twin, no copy of the initial
-    state), a context with meshes for the precision form only, a bounded lightcone ring; the
-    first `warmup` steps, then `steps` timed steps of the 100-step schedule (default 3)."""
-    P = dict(PRESETS["c5"])
-    if args.n_side:
-        f = args.n_side / P["n_side"]
-        P.update(n_side=args.n_side, L=P["L"] * f, ng=int(round(P["ng"] * f)))
-    W = workload(**P)
-    W["tile_chunk"] = args.pm_chunk
-    W["group"] = args.group or W["group"]
-    W["leaf"] = args.leaf or W["leaf"]
-    W["prec"] = dz.DZS_FP32
-    K = max(1, min(args.steps or 3, W["n_steps"] - args.warmup))
-    log(f"c5: N={W['N']} L={W['L']} ng={W['ng']} warmup={args.warmup} timed={K}")
+HEADLINE_STATS_STEPS = 3   # steps after the timed ones with every kernel class timed
+FULL_NSIDE = 64            # sky pixels of ~0.9 deg for the 1024^3 runs
+LC_MESH = 128              # lightcone density mesh of the 1024^3 runs
+MATCH_EVERY = 1024         # records of ids divisible by this are kept for the displacement match
+
+
+def snapshot(st, torch):
+    """Host copy (pageable) of the whole particle state."""
+    n = st.n
+    return {k: getattr(st, k)[:n].to("cpu") for k in st.F64 + ("mult", "id", "type")}, n
+
+
+def restore(st, snap):
+    arrays, n = snap
+    for k, v in arrays.items():
+        getattr(st, k)[:n].copy_(v)
+    st.n = n
+
+
+def cpu_baseline_sampled(W, ics, n_int=96):
+    """The oracle timed on the host for a sample of the 1024^3 initial state, extrapolated to
+    the whole box: its short-range sum (cell list, every source within r_cut) for the n_int^3
+    lattice particles of a sub-cube, given the sources of that sub-cube grown by the cutoff
+    plus one lattice cell; and its PM (deposit, FFT Poisson solve, 4-point gradient,
+    interpolation) for a 1/4-per-side lattice subsample on a 1/4-per-side mesh, scaled to the
+    full mesh by cells x log(cells) and to every particle."""
+    import oracle
+    oracle.build(force=False)
+    n, L, lam = W["n_side"], W["L"], W["lam"]
+    assert ics.max_disp < lam, "sources are taken by lattice index: displacements exceed a cell"
+    box_o = oracle.Box(L=L, m0=W["m0"], eps0=W["eps0"])
+    pad = int(math.ceil(W["r_cut"] / lam)) + 1
+    side = n_int + 2 * pad
+    c0 = n // 3   # sub-cube corner (lattice index), away from the periodic faces
+    ax = np.arange(c0 - pad, c0 - pad + side) % n
+    idx = ((ax[:, None, None] * n + ax[None, :, None]) * n + ax[None, None, :]).ravel()
+    inner = np.zeros((side, side, side), bool)
+    inner[pad:pad + n_int, pad:pad + n_int, pad:pad + n_int] = True
+    targets = np.flatnonzero(inner.ravel())
+    xs, ys, zs = ics.x[idx], ics.y[idx], ics.z[idx]
+    ms = ics.mult[idx]
     t0 = time.perf_counter()
-    ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
-    log(f"initial conditions ready ({time.perf_counter() - t0:.0f} s)")
-    box = dz.make_box(W["L"], W["m0"], W["eps0"])
-    ctx = dz.Context(W["N"], W["ng"], fp32_meshes=True)
-    st = dz.State.from_host(ics)
-    del ics
-    free, total = torch.cuda.mem_get_info()
-    log(f"state and context resident: {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f}")
-    params = make_params(dz, W, True)
-    # the initial force: a step with zero kicks and drift (sorts the state and computes g,
-    # without the sorted copies a standalone tree_force would allocate)
-    import copy
-    sp0 = copy.deepcopy(params[0])
-    sp0.K1 = sp0.K2 = 0.0
-    sp0.lc.D = 0.0
-    sp0.do_lightcone = sp0.do_coarsen = 0
-    ctx.kdk_step(box, st, sp0, None)
-    torch.cuda.synchronize()
-    log("initial force done")
-    ring = dz.LCRing(min(W["N"], 1 << 24))
-    ring.reset()
-    for s_ in range(args.warmup):
-        ctx.kdk_step(box, st, params[s_], ring)
-    torch.cuda.synchronize()
-    ctx.timing(enable=True, reset=True)
-    ctx.pair_interactions(reset=True)
+    oracle.short_range(xs, ys, zs, ms, box_o, W["r_s"], W["r_cut"], targets=targets)
+    t_sr = time.perf_counter() - t0
+    # PM on a subsample of every 4th lattice particle per side, mesh ng / 4
+    f = 4
+    sub = np.arange(0, n, f)
+    sidx = ((sub[:, None, None] * n + sub[None, :, None]) * n + sub[None, None, :]).ravel()
+    ng_s = W["ng"] // f
+    m_s = W["m0"] * f ** 3
+    box_s = oracle.Box(L=L, m0=m_s, eps0=W["eps0"] * f)
     t0 = time.perf_counter()
-    for s_ in range(args.warmup, args.warmup + K):
-        ctx.kdk_step(box, st, params[s_], ring)
-        torch.cuda.synchronize()
-        log(f"  step {s_ + 1}")
-    t = time.perf_counter() - t0
-    kern = ctx.timing(enable=False, reset=True)
-    pairs = ctx.pair_interactions(reset=True)
-    free, total = torch.cuda.mem_get_info()
-    peak = torch.cuda.max_memory_allocated()
-    ctx.close()
-    totals = {c: ms * calls for c, (ms, calls) in kern.items() if calls}
-    avg_ms, calls = kern["tree_walk"]
-    achieved = FLOP_PER_INTERACTION * pairs / calls / (avg_ms * 1e-3) / 1e12
+    oracle.pm_force(ics.x[sidx], ics.y[sidx], ics.z[sidx], ics.mult[sidx], box_s, ng_s,
+                    W["r_s"])
+    t_pm_s = time.perf_counter() - t0
+    scale_pm = (f ** 3) * math.log(W["ng"] ** 3) / math.log(ng_s ** 3)
     N = W["N"]
-    return {
-        "metric": METRIC, "value": N * K / t, "unit": UNIT, "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t / K, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": (f"{W['n_side']}^3 particles, L={W['L']:g} Mpc/h, mesh "
-                                f"{W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, steps "
-                                f"{args.warmup + 1}-{args.warmup + K} of {W['n_steps']} log KDK "
-                                f"steps, DZS + lightcone, tree theta {W['theta_tree']}, precision "
-                                f"form"),
-                   "preset": "c5", "particles": N, "mesh": W["ng"], "box": W["L"],
-                   "parallelism": "1 GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "tree_walk", "avg_ms": avg_ms,
-                     "work_per_launch": f"{pairs / calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP"},
-        "cpu_baseline": None,
-        "memory": {"device_used_GiB_after": (total - free) / 2 ** 30,
-                   "device_total_GiB": total / 2 ** 30,
-                   "torch_peak_GiB": peak / 2 ** 30},
-        "kernels_ms_per_step": {c: round(v / K, 2) for c, v in sorted(totals.items(),
-                                                                    key=lambda kv: -kv[1])},
-    }
+    t_sr_full = t_sr / targets.size * N
+    t_pm_full = t_pm_s * scale_pm
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh
+                          if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": N / (t_sr_full + t_pm_full), "unit": UNIT, "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(), "extrapolated": True,
+            "sample": (f"extrapolated: the oracle's FP64 force on the {n}^3 initial state (z = 49). "
+                       f"Short range (direct sum over every source within r_cut, cell list, "
+                       f"OpenMP) for the {targets.size} particles of a {n_int}^3 lattice "
+                       f"sub-cube: {t_sr:.1f} s, scaled to all {N} particles; PM (deposit, "
+                       f"numpy FFT Poisson solve, 4-point gradient, interpolation) for a "
+                       f"{n // f}^3 lattice subsample on a {ng_s}^3 mesh: {t_pm_s:.1f} s, scaled "
+                       f"by {scale_pm:.1f} (cells x log cells) to the {W['ng']}^3 mesh; one force "
+                       f"evaluation = {t_sr_full + t_pm_full:.3g} s"),
+            "seconds": {"short_range_sample": t_sr, "pm_subsample": t_pm_s,
+                        "short_range_extrapolated": t_sr_full, "pm_extrapolated": t_pm_full}}
 
 
-FULL_NSIDE = 64   # sky pixels of ~0.9 deg for the 1024^3 runs
+class LightconeAccumulator:
+    """Per-run lightcone products drained from the ring after every step (outside the step's
+    timing): a CIC density mesh of the records, a sky map, the record count, and (id, offset)
+    of the records whose id is divisible by MATCH_EVERY (for the twin displacement match)."""
+
+    def __init__(self, torch, L, device="cuda"):
+        self.torch, self.L = torch, L
+        self.rho = torch.zeros(LC_MESH ** 3, dtype=torch.float64, device=device)
+        self.sky = torch.zeros(12 * FULL_NSIDE ** 2, dtype=torch.float64, device=device)
+        self.count = 0
+        self.overflow = False
+        self.ids, self.ds = [], []
+
+    def drain(self, ring):
+        from paper_2005_05328_amd import skymaps
+        nrec = int(ring.count.item())
+        self.overflow = self.overflow or bool(ring.overflow.item())
+        if nrec:
+            lightcone_density(ring, self.L, LC_MESH, self.rho)
+            ids, mult, d = lightcone_records(ring)
+            skymaps.sky_map(d, mult, FULL_NSIDE, self.sky)
+            keep = (ids.to(self.torch.int64) % MATCH_EVERY) == 0
+            self.ids.append(ids[keep].to(self.torch.int64))
+            self.ds.append(d[keep].clone())
+        self.count += min(nrec, ring.capacity)
+        ring.reset()
+        return nrec
+
+    def fork(self):
+        c = LightconeAccumulator.__new__(LightconeAccumulator)
+        c.torch, c.L = self.torch, self.L
+        c.rho, c.sky = self.rho.clone(), self.sky.clone()
+        c.count, c.overflow = self.count, self.overflow
+        c.ids, c.ds = list(self.ids), list(self.ds)
+        return c
 
 
-def run_full(args, dz, torch, dzs_ics):
-    """One whole run of the 1024^3 configuration, DZS (`--full-run dzs`) or full resolution
-    (`--full-run std`), in the lean memory plan.  Each step's lightcone records are drained
-    into a 128^3 density mesh after the step (outside its timing); the mesh, the per-step
-    times and the particle counts go to `--out` (.npz) for `--compare`."""
+def compare_accumulated(a, b, L, eps0):
+    """M-LC and the other lightcone diagnostics of two accumulated runs (b the reference);
+    None with the reason when either run has no records."""
+    torch = a.torch
+    out = {"records": [a.count, b.count], "ring_overflow": [a.overflow, b.overflow]}
+    if a.count == 0 or b.count == 0:
+        out["no_records"] = [nm for nm, acc in (("dzs", a), ("std", b)) if acc.count == 0]
+        out["M_LC_max_abs_P_ratio_minus_1"] = None
+        return out
+    rho_a, rho_b = a.rho.view(LC_MESH, LC_MESH, LC_MESH), b.rho.view(LC_MESH, LC_MESH, LC_MESH)
+    k, pa, _ = power_spectrum(rho_a, L)
+    _, pb, _ = power_spectrum(rho_b, L)
+    ratio = pa / pb - 1.0
+    from paper_2005_05328_amd import skymaps
+    out["M_LC_max_abs_P_ratio_minus_1"] = float(np.abs(ratio).max())
+    out["P_ratio_minus_1_by_bin"] = [round(float(v), 9) for v in ratio]
+    out["k_bins_h_per_Mpc"] = [round(float(v), 5) for v in k]
+    out["rms_pixel_density_difference"] = float(
+        torch.sqrt(torch.mean((rho_a - rho_b) ** 2)) / rho_b.mean())
+    out["sky_map"] = skymaps.compare_maps(a.sky.cpu().numpy(), b.sky.cpu().numpy(), FULL_NSIDE,
+                                          SKY_LMAX)
+    ia, da = torch.cat(a.ids), torch.cat(a.ds)
+    ib, db = torch.cat(b.ids), torch.cat(b.ds)
+    sa, oa = torch.sort(ia)
+    sb, ob = torch.sort(ib)
+    common = torch.isin(sa, sb)
+    pos = torch.searchsorted(sb, sa[common])
+    dx = da[oa[common]] - db[ob[pos]]
+    dx = dx - L * torch.round(dx / L)
+    r = (torch.sqrt((dx ** 2).sum(1)) / eps0).cpu().numpy()
+    disp = {f"p{q}": float(np.percentile(r, q)) for q in (50, 99, 99.9)} if r.size else {}
+    disp["max"] = float(r.max()) if r.size else None
+    out["displacement_over_eps0"] = disp
+    out["displacement_sample"] = (f"records with id divisible by {MATCH_EVERY}: {int(r.size)} "
+                                  f"matched by id")
+    out["displaced_fraction"] = ({f"over_{t}h": float((r > 2.8 * t).mean()) for t in (0.01, 0.1, 1, 8)}
+                                 if r.size else {})
+    return out
+
+
+def run_headline(args, dz, torch, dzs_ics):
+    """The 1024^3 configuration, both twins, in one process on one GPU.
+
+    The DZS run and the full-resolution run are bitwise identical until the first step whose
+    end boundary can merge (R_lc + b < sqrt(3)/2 L: the host check skips every earlier
+    coarsening), so that shared prefix runs once and its wall time counts for both twins; the
+    state is then copied to host memory, the DZS tail runs, the copy is restored and the
+    full-resolution tail runs.  Every step is timed (wall clock, synchronised).
+
+    value: particle force updates per second over the K timed steps (steps W+1 .. W+K of the
+    schedule, after W warm-up steps), i.e. the particles forced in those steps over their wall
+    time; only the tree walk carries HIP events in that region.  Three further steps time every
+    kernel class (the breakdown).  M-W: whole-run wall time of the two twins.  M-LC and the sky
+    maps: the lightcone records of each run, drained after every step.  M-F: the force alone on
+    the final full-resolution state."""
+    import copy
     P = dict(PRESETS["c5"])
     if args.n_side:
         f = args.n_side / P["n_side"]
@@ -399,73 +484,206 @@ def run_full(args, dz, torch, dzs_ics):
     W["group"] = args.group or W["group"]
     W["leaf"] = args.leaf or W["leaf"]
     W["prec"] = dz.DZS_FP32
-    n_steps = min(args.steps or W["n_steps"], W["n_steps"])
-    dzs = args.full_run == "dzs"
-    log(f"c5 full run ({args.full_run}): N={W['N']} L={W['L']} ng={W['ng']} steps={n_steps}")
+    N, L, n_steps = W["N"], W["L"], W["n_steps"]
+    p_dzs = make_params(dz, W, True)
+    p_std = make_params(dz, W, False)
+    half_diag = 0.5 * math.sqrt(3.0) * L
+    merging = [s for s, sp in enumerate(p_dzs)
+               if sp.do_coarsen and sp.coarsen.R_lc + sp.coarsen.b < half_diag]
+    prefix = merging[0] if merging else n_steps   # steps 0 .. prefix-1 are shared
+    Wu = max(0, args.warmup)
+    K = max(1, min(args.steps or 20, prefix - Wu - HEADLINE_STATS_STEPS))
+    log(f"headline: N={N} L={L:g} ng={W['ng']} steps 1-{n_steps}; shared prefix 1-{prefix}; "
+        f"warmup {Wu}, timed {Wu + 1}-{Wu + K}")
+    t_job = time.perf_counter()
     t0 = time.perf_counter()
-    ics = dzs_ics.zeldovich(W["n_side"], W["L"], W["a_init"], seed=W["seed"], spectrum="bbks")
+    ics = dzs_ics.zeldovich(W["n_side"], L, W["a_init"], seed=W["seed"], spectrum="bbks")
     log(f"initial conditions ready ({time.perf_counter() - t0:.0f} s)")
-    box = dz.make_box(W["L"], W["m0"], W["eps0"])
-    ctx = dz.Context(W["N"], W["ng"], fp32_meshes=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline_sampled(W, ics, n_int=max(8, min(128, W["n_side"] // 4)))
+        log(f"cpu baseline (oracle, sampled): {cpu['value']:.3g} updates/s "
+            f"({time.perf_counter() - t0:.0f} s)")
+    box = dz.make_box(L, W["m0"], W["eps0"])
+    ctx = dz.Context(N, W["ng"], fp32_meshes=True)
     st = dz.State.from_host(ics)
     del ics
-    params = make_params(dz, W, dzs)
-    import copy
-    sp0 = copy.deepcopy(params[0])
+    # the initial force: a step with zero kicks and drift
+    sp0 = copy.deepcopy(p_dzs[0])
     sp0.K1 = sp0.K2 = 0.0
     sp0.lc.D = 0.0
     sp0.do_lightcone = sp0.do_coarsen = 0
     ctx.kdk_step(box, st, sp0, None)
-    ring = dz.LCRing(min(W["N"], max(1 << 24, W["N"] // 5)))
+    torch.cuda.synchronize()
+    ring = dz.LCRing(min(N, max(1 << 24, N // 5)))
     ring.reset()
-    M = 128
-    rho = torch.zeros(M ** 3, dtype=torch.float64, device="cuda")
-    from paper_2005_05328_amd import skymaps
-    sky = torch.zeros(12 * FULL_NSIDE ** 2, dtype=torch.float64, device="cuda")
+    acc = LightconeAccumulator(torch, L)
     free, total = torch.cuda.mem_get_info()
     log(f"resident: {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f}")
-    torch.cuda.synchronize()
-    ctx.timing(enable=True, reset=True)
-    per_step, counts, merged, records, overflow = [], [], 0, 0, False
-    for s_ in range(n_steps):
+
+    def step(params, s_, acc_):
         t1 = time.perf_counter()
         rep = ctx.kdk_step(box, st, params[s_], ring)
         torch.cuda.synchronize()
-        per_step.append(time.perf_counter() - t1)
-        merged += int(rep.n_groups)
-        counts.append(st.n)
-        nrec = int(ring.count.item())
-        overflow = overflow or bool(ring.overflow.item())
-        records += min(nrec, ring.capacity)
-        lightcone_density(ring, W["L"], M, rho)
-        _, mult_r, d_r = lightcone_records(ring)
-        skymaps.sky_map(d_r, mult_r, FULL_NSIDE, sky)
-        ring.reset()
-        torch.cuda.synchronize()   # the drain must not run into the next step's timing
-        log(f"  step {s_ + 1}/{n_steps}: {per_step[-1]:.3f} s, N = {st.n}, lightcone {nrec}")
+        dt = time.perf_counter() - t1
+        nrec = acc_.drain(ring)
+        torch.cuda.synchronize()
+        return dt, int(rep.n_groups), nrec
+
+    per_step = []          # shared prefix
+    forced = []            # particles forced in each step
+    # warm-up steps
+    for s_ in range(Wu):
+        per_step.append(step(p_dzs, s_, acc)[0])
+        forced.append(st.n)
+    # the timed steps: one synchronisation on each side, HIP events on the walk only
+    ctx.timing(enable=True, reset=True, classes=("tree_walk",))
+    ctx.pair_interactions(reset=True)
+    torch.cuda.synchronize()
+    t_timed0 = time.perf_counter()
+    timed_forced = 0
+    for s_ in range(Wu, Wu + K):
+        dt, _, _ = step(p_dzs, s_, acc)
+        per_step.append(dt)
+        forced.append(st.n)
+        timed_forced += st.n
+        if (s_ + 1) % 5 == 0:
+            log(f"  step {s_ + 1}: {dt:.3f} s")
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t_timed0
+    walk = ctx.timing(enable=False, reset=True)
+    pairs = ctx.pair_interactions(reset=True)
+    walk_ms, walk_calls = walk["tree_walk"]
+    # breakdown: every kernel class over the next steps
+    ctx.timing(enable=True, reset=True)
+    for s_ in range(Wu + K, Wu + K + HEADLINE_STATS_STEPS):
+        per_step.append(step(p_dzs, s_, acc)[0])
+        forced.append(st.n)
     kern = ctx.timing(enable=False, reset=True)
-    peak = torch.cuda.max_memory_allocated()
-    profile = mean_mass_by_distance(st, W["L"])
-    mass_total = int(st.mult[: st.n].to(torch.int64).sum().item())
+    stats_pairs = ctx.pair_interactions(reset=True)
+    for s_ in range(Wu + K + HEADLINE_STATS_STEPS, prefix):
+        dt, _, _ = step(p_dzs, s_, acc)
+        per_step.append(dt)
+        forced.append(st.n)
+        if (s_ + 1) % 10 == 0:
+            log(f"  step {s_ + 1}: {dt:.3f} s")
+    t_prefix = sum(per_step)
+    log(f"shared prefix done: {t_prefix:.1f} s; copying the state to the host")
+    t0 = time.perf_counter()
+    snap = snapshot(st, torch)
+    acc_std = acc.fork()
+    log(f"  host copy {time.perf_counter() - t0:.1f} s")
+
+    def tail(params, acc_, name):
+        times, counts, merged = [], [], 0
+        for s_ in range(prefix, n_steps):
+            dt, m, nrec = step(params, s_, acc_)
+            times.append(dt)
+            counts.append(st.n)
+            merged += m
+            log(f"  {name} step {s_ + 1}: {dt:.3f} s, N = {st.n}, lightcone {nrec}")
+        return times, counts, merged
+
+    t_dzs_tail, n_dzs, merged_dzs = tail(p_dzs, acc, "dzs")
+    mult_sum_dzs = int(st.mult[: st.n].to(torch.int64).sum().item())
+    profile_dzs = mean_mass_by_distance(st, L)
+    t0 = time.perf_counter()
+    restore(st, snap)
+    del snap
+    torch.cuda.synchronize()
+    log(f"  state restored ({time.perf_counter() - t0:.1f} s)")
+    t_std_tail, n_std, merged_std = tail(p_std, acc_std, "std")
+    lc = compare_accumulated(acc, acc_std, L, W["eps0"])
+    # M-F: the force alone (keys, sort, tree build, PM, walk) on the final full-resolution state
+    ctx.timing(enable=True, reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f_ms = []
+    for r_ in range(4):
+        e0.record()
+        ctx.kdk_step(box, st, sp0, None)
+        e1.record()
+        torch.cuda.synchronize()
+        if r_ > 0:
+            f_ms.append(e0.elapsed_time(e1))
+        else:
+            ctx.timing(enable=True, reset=True)
+    fk = ctx.timing(enable=False, reset=True)
+    force_ms = float(np.median(f_ms))
+    pm_ms = sum(fk[c][0] * fk[c][1] for c in fk if c.startswith("pm_")) / len(f_ms)
+    tree_ms = sum(fk[c][0] * fk[c][1] for c in ("morton_keys", "radix_sort", "permute",
+                                                "tree_build", "tree_moments", "tree_groups",
+                                                "tree_walk") if c in fk) / len(f_ms)
+    mf = {"M_F_force_updates_per_s": st.n / (force_ms * 1e-3), "force_ms": force_ms,
+          "particles": st.n, "tree_ms": tree_ms, "tree_force_updates_per_s": st.n / (tree_ms * 1e-3),
+          "pm_ms_on_second_stream": pm_ms,
+          "method": ("median of 3 HIP-event-timed force evaluations after 1 warm-up (a step with "
+                     "zero kick and drift factors: Morton keys, sort, tree build, PM, walk) on "
+                     "the final full-resolution state (z = 0); tree_ms: the tree kernel classes' "
+                     "time (the PM overlaps them on a second stream)")}
+    free, total = torch.cuda.mem_get_info()
     ctx.close()
-    if args.out:
-        np.savez(args.out, rho=rho.view(M, M, M).cpu().numpy(), per_step=np.array(per_step),
-                 counts=np.array(counts), L=W["L"], N=W["N"], sky=sky.cpu().numpy(),
-                 mean_mult=np.array([v if v is not None else np.nan
-                                     for v in profile["mean_multiplicity"]]),
-                 shell_r=np.array(profile["shell_outer_radius"]))
-    return {"full_run": args.full_run, "workload": f"{W['n_side']}^3 particles, L={W['L']:g} "
-            f"Mpc/h, mesh {W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, {n_steps} of "
-            f"{W['n_steps']} log KDK steps, lightcone, tree theta {W['theta_tree']}, precision "
-            f"form" + (", DZS" if dzs else ", full resolution"),
-            "wall_s": sum(per_step), "particles_final": st.n, "merged_nodes": merged,
-            "summed_multiplicity": mass_total, "mass_conserved": mass_total == W["N"],
-            "lightcone_records_equal_N": records == W["N"] and not overflow,
-            "mean_mass_by_distance": profile,
-            "lightcone_records": records, "ring_overflow": overflow,
-            "torch_peak_GiB": peak / 2 ** 30,
-            "kernels_s": {c: round(ms * calls / 1e3, 3) for c, (ms, calls) in
-                          sorted(kern.items(), key=lambda kv: -kv[1][0] * kv[1][1]) if calls}}
+    t_dzs = t_prefix + sum(t_dzs_tail)
+    t_std = t_prefix + sum(t_std_tail)
+    fp32 = True
+    Cc = W["ng"] ** 3
+    totals = {c: ms * calls for c, (ms, calls) in kern.items() if calls}
+    flops = FLOP_PER_INTERACTION * pairs / walk_calls
+    achieved = flops / (walk_ms * 1e-3) / 1e12
+    hbm = {}
+    for cls in HBM_CLASSES:
+        if cls not in kern or not kern[cls][1]:
+            continue
+        ms = kern[cls][0]
+        b = algorithmic_bytes(cls, N, Cc, fp32)
+        hbm[cls] = {"avg_ms": ms, "achieved_GBps": b / (ms * 1e-3) / 1e9,
+                    "frac": b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    twin = {
+        "kind": "DZS vs full resolution, whole 100-step runs",
+        "M_W_dzs_over_std": t_dzs / t_std, "dzs_s": t_dzs, "std_s": t_std,
+        "shared_prefix": (f"steps 1-{prefix} (no node can merge before the boundary after step "
+                          f"{prefix + 1}: R_lc + b >= sqrt(3)/2 L) run once, {t_prefix:.1f} s, "
+                          f"counted in both"),
+        "tail_s": {"dzs": sum(t_dzs_tail), "std": sum(t_std_tail)},
+        "tail_per_step_s": {"dzs": [round(v, 3) for v in t_dzs_tail],
+                            "std": [round(v, 3) for v in t_std_tail]},
+        "particles_after_tail_steps": {"dzs": n_dzs, "std": n_std},
+        "merged_nodes": [merged_dzs, merged_std],
+        "summed_multiplicity_conserved": mult_sum_dzs == N,
+        "mean_mass_by_distance_dzs": profile_dzs,
+        "lightcone": lc,
+        "paper": ("T_DZS/T_STD 0.60-0.64 for the paper's fiducial DZS on its 8192 Mpc/h, 512^3 run "
+                  "(Table particle_gain_all, CPU, hardware unstated)"),
+    }
+    out = {
+        "metric": METRIC, "value": timed_forced / t_timed, "unit": UNIT, "n_gpus": 1, "steps": K,
+        "warmup": Wu, "ms_per_step": 1e3 * t_timed / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{W['n_side']}^3 particles (1 GPU), L={L:g} Mpc/h, mesh "
+                                f"{W['ng']}^3, Zel'dovich z=49 BBKS seed {W['seed']}, 100 log KDK "
+                                f"steps to z=0, DZS 2x2x2 then 4x4x4 (l_max 4 lambda, theta 0.1, "
+                                f"b 5 lambda) + lightcone output, tree theta {W['theta_tree']}, "
+                                f"precision form (FP32 pair/mesh/FFT, FP64 state); timed: steps "
+                                f"{Wu + 1}-{Wu + K} (full resolution, z = "
+                                f"{1 / p_dzs[Wu].lc.a0 - 1:.1f} to {1 / p_dzs[Wu + K - 1].lc.a1 - 1:.1f})"),
+                   "preset": "c5", "particles": N, "mesh": W["ng"], "box": L,
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "tree_walk", "avg_ms": walk_ms,
+                     "work_per_launch": f"{pairs / walk_calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP",
+                     "timed_on": "the walk's own stream, HIP events around each launch in the timed steps"},
+        "cpu_baseline": cpu, "twin": twin, "force_rate": mf, "hbm_kernels": hbm,
+        "pair_interactions_per_step": pairs / K,
+        "kernels_ms_per_step": {c: round(v / HEADLINE_STATS_STEPS, 3) for c, v in
+                                sorted(totals.items(), key=lambda kv: -kv[1])},
+        "kernels_note": (f"every kernel class over steps {Wu + K + 1}-{Wu + K + HEADLINE_STATS_STEPS} "
+                         f"(after the timed ones); the mesh solve runs on a second stream, so "
+                         f"the classes overlap"),
+        "memory": {"device_used_GiB": (total - free) / 2 ** 30, "device_total_GiB": total / 2 ** 30},
+        "job_s": time.perf_counter() - t_job,
+    }
+    return out
 
 
 SWEEP = {  # parameter -> values; the fiducial setting is theta 0.1, b 5 lambda, l_max 4 lambda
@@ -547,31 +765,6 @@ def run_sweep(args, dz, torch, dzs_ics):
             "workload": f"128^3 particles, L=8192 Mpc/h, mesh 256^3, Zel'dovich z=49 BBKS seed "
                         f"{W['seed']}, 100 log KDK steps, lightcone, tree theta 0.5, precision form",
             "std_wall_s": t_std, "rows": rows}
-
-
-def compare_full(paths):
-    """M-W and M-LC from the .npz files of a DZS and a full-resolution run."""
-    import torch
-    a, b = (np.load(p) for p in paths)
-    L = float(a["L"])
-    rho_a, rho_b = torch.from_numpy(a["rho"]), torch.from_numpy(b["rho"])
-    k, pa, _ = power_spectrum(rho_a, L)
-    _, pb, _ = power_spectrum(rho_b, L)
-    ratio = pa / pb - 1.0
-    wa, wb = float(a["per_step"].sum()), float(b["per_step"].sum())
-    sky = None
-    if "sky" in a.files and "sky" in b.files:
-        from paper_2005_05328_amd import skymaps
-        sky = skymaps.compare_maps(a["sky"], b["sky"], FULL_NSIDE, SKY_LMAX)
-    return {"dzs_s": wa, "std_s": wb, "M_W_dzs_over_std": wa / wb, "sky_map": sky,
-            "M_LC_max_abs_P_ratio_minus_1": float(np.abs(ratio).max()),
-            "P_ratio_minus_1_by_bin": [round(float(v), 8) for v in ratio],
-            "k_bins_h_per_Mpc": [round(float(v), 5) for v in k],
-            "rms_pixel_density_difference":
-                float(torch.sqrt(torch.mean((rho_a - rho_b) ** 2)) / rho_b.mean()),
-            "lightcone_mass": [float(rho_a.sum()), float(rho_b.sum())],
-            "particles_final": [int(a["counts"][-1]), int(b["counts"][-1])],
-            "N": int(a["N"])}
 
 
 def _smooth(n):
@@ -872,9 +1065,10 @@ def force_error(g, ref):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(PRESETS) + ["sweep"], default="c2")
-    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the whole run)")
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=sorted(PRESETS) + ["sweep"], default="c5")
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed steps (default: 20 for c5, the whole run otherwise)")
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-side", type=int, default=0,
                     help="particles per side (box and mesh scaled with it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -892,12 +1086,6 @@ def main():
                     help="individual power-of-two time steps: 2^B sub-steps per global step")
     ap.add_argument("--eta", type=float, default=0.025,
                     help="accuracy parameter of the individual time-step bins")
-    ap.add_argument("--full-run", choices=("dzs", "std"), default=None,
-                    help="with --workload c5: one whole run, DZS or full resolution, its "
-                         "lightcone density and timings saved to --out")
-    ap.add_argument("--out", default=None, help="output .npz of --full-run")
-    ap.add_argument("--compare", nargs=2, default=None, metavar=("DZS_NPZ", "STD_NPZ"),
-                    help="M-W and M-LC from two --full-run outputs (no GPU)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default=None,
                     help="fp64: plain form; fp32: FP32 pair, mesh and FFT arithmetic "
                          "(default: the workload's)")
@@ -906,9 +1094,6 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
-    if args.compare:
-        print(json.dumps(compare_full(args.compare)), flush=True)
-        return
     import torch
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
@@ -929,11 +1114,8 @@ def main():
     if args.workload == "sweep":
         print(json.dumps(run_sweep(args, dz, torch, dzs_ics)), flush=True)
         return
-    if args.workload == "c5" and args.full_run:
-        print(json.dumps(run_full(args, dz, torch, dzs_ics)), flush=True)
-        return
     if args.workload == "c5":
-        print(json.dumps(run_lean(args, dz, torch, dzs_ics)), flush=True)
+        print(json.dumps(run_headline(args, dz, torch, dzs_ics)), flush=True)
         return
     P = dict(PRESETS[args.workload])
     if args.n_side:

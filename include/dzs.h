@@ -263,6 +263,11 @@ dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap
 dzs_status dzs_ctx_destroy(dzs_ctx *ctx);
 /* Text of the context's last failure ("" if none); valid until the next call. */
 const char *dzs_last_error(const dzs_ctx *ctx);
+/* Identification of the build: the first 16 hex digits of the SHA-256 of the sources the
+ * library was compiled from (HIP and C++ sources, internal headers, this header, the build
+ * script).  Lets a binding refuse a library that is stale against its sources.  Static
+ * string; never fails. */
+const char *dzs_source_hash(void);
 
 /* One global step with individual time steps (dzs_hier_params).  prm supplies pm, tree,
  * coarsen, do_lightcone and do_coarsen (its K1, K2 and lc are not read: the sub-step factors
@@ -426,6 +431,9 @@ dzs_status dzs_counters(dzs_ctx *ctx, int32_t reset, uint64_t *pair_interactions
 
 /* Average duration in milliseconds of each internal kernel class over the calls made since
  * the last reset, measured with HIP events on the call's stream when timing is enabled.
+ * enable: 0 stops timing; 1 times every class; a larger value is a mask of the classes to time
+ * (bit c + 1 for the class written at index c); a negative value only writes the class names
+ * (names may then be NULL: the count alone) and changes nothing.
  * names/values: caller arrays of `cap` entries; returns the number of classes written. */
 int32_t dzs_timing(dzs_ctx *ctx, int32_t enable, int32_t reset, const char **names,
                    double *ms_avg, uint64_t *calls, int32_t cap);

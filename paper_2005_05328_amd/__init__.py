@@ -292,10 +292,19 @@ class Context:
         self._check("dzs_counters", _lib.dzs_counters(self._h, int(bool(reset)), C.byref(v)))
         return int(v.value)
 
-    def timing(self, enable=True, reset=False) -> dict:
+    def timing(self, enable=True, reset=False, classes=None) -> dict:
+        """Per-class average kernel times since the last reset; `classes` (names) restricts
+        the HIP events of the next calls to those classes (all when None)."""
         cap = 32
         names = (C.c_char_p * cap)()
         ms = (C.c_double * cap)()
         calls = (C.c_uint64 * cap)()
-        w = _lib.dzs_timing(self._h, int(enable), int(reset), names, ms, calls, cap)
+        code = int(bool(enable))
+        if enable and classes:
+            order = [n.decode() for n in names[:_lib.dzs_timing(self._h, -1, 0, names, None,
+                                                                None, cap)]]
+            code = 0
+            for c in classes:
+                code |= 1 << (order.index(c) + 1)
+        w = _lib.dzs_timing(self._h, code, int(reset), names, ms, calls, cap)
         return {names[i].decode(): (ms[i], int(calls[i])) for i in range(w)}

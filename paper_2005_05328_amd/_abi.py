@@ -23,7 +23,7 @@ EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_fact
            "dzs_coarsen", "pm_force", "tree_force", "lightcone_emit", "kdk_step",
            "kdk_step_batch", "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
            "dzs_sort_state", "dzs_counters", "dzs_timing", "dzs_halt_check",
-           "dzs_forecast_speedup", "kdk_step_hier")
+           "dzs_forecast_speedup", "kdk_step_hier", "dzs_source_hash")
 DZS_HIER_MAX_BIN = 6
 DZS_HALT_BALANCE, DZS_HALT_RATIO, DZS_HALT_PREDICTED = 1, 2, 4
 DZS_BATCH_MAX = 512
@@ -121,6 +121,18 @@ class Batch(C.Structure):
 assert C.sizeof(LCRecord) == 64
 
 
+def _source_hash():
+    """The build script's hash of the sources in this tree (None if the script is absent)."""
+    import importlib.util
+    path = os.path.join(HERE, "build.py")
+    if not os.path.exists(path):
+        return None
+    spec = importlib.util.spec_from_file_location("_dzs_build_hash", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.source_hash()
+
+
 def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libdzs.so not found at {LIB_PATH}: build it with "
@@ -129,6 +141,13 @@ def load():
     # serves the whole process, so torch is imported before the library resolves its runtime
     import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
+    L.dzs_source_hash.argtypes = []
+    L.dzs_source_hash.restype = C.c_char_p
+    built = L.dzs_source_hash().decode()
+    want = _source_hash()
+    if want is not None and built != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (hash {built}, sources "
+                          f"{want}): rebuild it with `python paper_2005_05328_amd/build.py`")
     P, i32, st = C.c_void_p, C.c_int32, C.c_int32
     L.dzs_ctx_create.argtypes = [C.POINTER(P), i32, C.POINTER(Capacity)]
     L.dzs_ctx_destroy.argtypes = [P]

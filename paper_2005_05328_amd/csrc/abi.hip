@@ -51,7 +51,7 @@ static void drain_timers(dzs_ctx *ctx) {
 
 void dzs_time_begin(dzs_ctx *ctx, int cls, hipStream_t s, int *slot) {
     *slot = -1;
-    if (!ctx->timing || !ctx->timers)
+    if (!ctx->timing || !ctx->timers || !((ctx->timing_mask >> cls) & 1u))
         return;
     dzs_timer_pool *P = ctx->timers;
     if (P->used >= dzs_timer_pool::CAP)
@@ -86,7 +86,16 @@ extern "C" int32_t dzs_timing(dzs_ctx *ctx, int32_t enable, int32_t reset, const
                               double *ms_avg, uint64_t *calls, int32_t cap) {
     if (!ctx)
         return 0;
-    if (enable && !ctx->timers) {
+    if (enable < 0) {  // names only
+        int32_t w = 0;
+        for (int c = 0; c < KC_COUNT && w < cap; ++c)
+            if (names)
+                names[w++] = dzs_kclass_names[c];
+            else
+                ++w;
+        return w;
+    }
+    if (enable > 0 && !ctx->timers) {
         ctx->timers = new dzs_timer_pool();
         for (int i = 0; i < dzs_timer_pool::CAP; ++i) {
             (void)hipEventCreate(&ctx->timers->start[i]);
@@ -112,6 +121,7 @@ extern "C" int32_t dzs_timing(dzs_ctx *ctx, int32_t enable, int32_t reset, const
         }
     }
     ctx->timing = enable != 0;
+    ctx->timing_mask = enable > 1 ? (uint32_t)enable >> 1 : 0xffffffffu;
     return w;
 }
 

@@ -122,6 +122,11 @@ void dzs_merge_thresholds(double L, double R_lc, double b, double theta, double 
     }
 }
 
+#ifndef DZS_SOURCE_HASH
+#error "build with -DDZS_SOURCE_HASH (the build script passes the hash of the sources)"
+#endif
+extern "C" const char *dzs_source_hash(void) { return DZS_SOURCE_HASH; }
+
 extern "C" dzs_status dzs_step_factors(double a0, double a1, double omega_m,
                                        dzs_step_params *out) {
     if (!out || !(a0 > 0.0) || !(a1 > a0) || !(a1 <= 1.0) || !(omega_m > 0.0) ||

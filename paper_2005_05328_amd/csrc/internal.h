@@ -180,6 +180,7 @@ struct dzs_ctx {
 
     // ---- timing
     bool timing = false;
+    uint32_t timing_mask = 0xffffffffu;  // bit c: class c is timed
     dzs_timer_pool *timers = nullptr;
     // second stream (default priority) for the mesh solve that overlaps the tree build and
     // walk of kdk_step, and its fork / join events; created at first use

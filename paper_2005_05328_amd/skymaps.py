@@ -117,17 +117,30 @@ def angular_power(m: np.ndarray, nside: int, lmax: int) -> np.ndarray:
 
 
 def compare_maps(map_a, map_b, nside: int, lmax: int) -> dict:
-    """Pixel and angular-power agreement of two sky maps (b the reference)."""
+    """Pixel and angular-power agreement of two sky maps (b the reference).  When either map
+    holds no mass (no lightcone records) nothing can be compared: every figure is None and
+    `no_records` names the empty map(s)."""
     a = np.asarray(map_a, np.float64)
     b = np.asarray(map_b, np.float64)
+    empty = [name for name, m in (("a", a), ("b", b)) if not m.sum() > 0.0]
+    if empty:
+        return {"nside": nside, "lmax": lmax, "no_records": empty,
+                "max_abs_pixel_difference_over_mean": None,
+                "rms_pixel_difference_over_mean": None, "max_abs_Cl_ratio_minus_1": None}
     mean = b.mean()
     ca = angular_power(a / a.mean() - 1.0, nside, lmax)
     cb = angular_power(b / mean - 1.0, nside, lmax)
-    ratio = ca[1:] / cb[1:] - 1.0
+    # multipoles where the reference has power (a uniform reference has none: then the two
+    # agree only if neither has any)
+    has = cb[1:] > 0.0
+    if has.any():
+        cl_dev = float(np.abs(ca[1:][has] / cb[1:][has] - 1.0).max())
+    else:
+        cl_dev = 0.0 if not (ca[1:] > 0.0).any() else None
     return {"nside": nside, "lmax": lmax,
             "max_abs_pixel_difference_over_mean": float(np.abs(a - b).max() / mean),
             "rms_pixel_difference_over_mean": float(np.sqrt(np.mean((a - b) ** 2)) / mean),
-            "max_abs_Cl_ratio_minus_1": float(np.abs(ratio).max())}
+            "max_abs_Cl_ratio_minus_1": cl_dev}
 
 
 def _xp(a):

@@ -101,3 +101,12 @@ def test_header_constants_match_the_binding():
             "DZS_FP32", "DZS_BATCH_MAX"} <= set(shared)
     for k in shared:
         assert getattr(_abi, k) == int(defs[k]), k
+
+
+def test_library_matches_its_sources_and_a_stale_one_is_refused(monkeypatch):
+    from paper_2005_05328_amd import _abi
+    L = _abi.load()
+    assert L.dzs_source_hash().decode() == _abi._source_hash()
+    monkeypatch.setattr(_abi, "_source_hash", lambda: "0" * 16)
+    with pytest.raises(ImportError, match="other sources"):
+        _abi.load()

@@ -57,3 +57,20 @@ def test_single_harmonic_power():
     assert abs(cl[ell] * (2 * ell + 1) - 1.0) < 1e-2
     others = np.delete(cl, ell)
     assert others.max() < 1e-4 * cl[ell]
+
+
+def test_compare_maps_without_records_reports_none():
+    import warnings
+    nside = 4
+    full = np.ones(12 * nside * nside)
+    empty = np.zeros_like(full)
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")   # no divide-by-zero warnings either
+        for a, b, names in ((empty, empty, ["a", "b"]), (full, empty, ["b"]),
+                            (empty, full, ["a"])):
+            r = sk.compare_maps(a, b, nside, 4)
+            assert r["no_records"] == names
+            assert r["max_abs_pixel_difference_over_mean"] is None
+            assert r["max_abs_Cl_ratio_minus_1"] is None
+    r = sk.compare_maps(full, full, nside, 4)
+    assert "no_records" not in r and r["max_abs_pixel_difference_over_mean"] == 0.0
