@@ -506,7 +506,7 @@ def run_headline(args, dz, torch, dzs_ics):
         log(f"cpu baseline (oracle, sampled): {cpu['value']:.3g} updates/s "
             f"({time.perf_counter() - t0:.0f} s)")
     box = dz.make_box(L, W["m0"], W["eps0"])
-    ctx = dz.Context(N, W["ng"], fp32_meshes=True)
+    ctx = dz.Context(N, W["ng"], fp32_meshes=True, no_copies=True)
     st = dz.State.from_host(ics)
     del ics
     # the initial force: a step with zero kicks and drift

@@ -51,19 +51,29 @@ typedef int32_t dzs_status;
 
 typedef struct dzs_ctx dzs_ctx;
 
-/* Capacities fixed at context creation; the context allocates all its scratch then. */
+/* Capacities fixed at context creation; the context allocates all its scratch then and no
+ * call allocates device memory afterwards.  The lightcone ring is caller-owned and carries
+ * its own capacity (dzs_lc_ring), so the context needs no per-record scratch and takes no
+ * record capacity. */
 typedef struct {
     uint64_t max_particles;  /* largest particle count any call will see */
     uint32_t max_mesh_side;  /* 0 (no PM) or 8..1024: room for meshes of up to
                                 max_mesh_side^3 points (a mesh side itself must be an
                                 even 2^a 3^b) */
     uint32_t flags;          /* DZS_CAP_* bits */
+    uint32_t max_boxes;      /* largest batch kdk_step_batch will see, 1..DZS_BATCH_MAX
+                                (0 = DZS_BATCH_MAX): sizes the batch's box, offset and mesh
+                                tables */
+    uint32_t reserved;       /* 0 */
 } dzs_capacity;
 
 /* Capacity flag: size the meshes for the precision form only (8-byte complex cells that
  * also hold the fixed-point deposit, 4-byte potential: 12 instead of 32 bytes per cell);
  * plain-form PM calls on such a context fail with DZS_EINVAL. */
 #define DZS_CAP_FP32_MESHES 1u
+/* Capacity flag: no sorted copies for tree_force (28 bytes per particle fewer); tree_force on
+ * such a context needs particles already in key order (dzs_tree_params.presorted = 1). */
+#define DZS_CAP_NO_COPIES 2u
 
 /* Periodic box. */
 typedef struct {
@@ -179,7 +189,12 @@ typedef struct {
                             force) */
     int32_t accumulate;  /* 0: g = g_short, 1: g += g_short */
     int32_t opening;     /* DZS_OPEN_GEOMETRIC or DZS_OPEN_RELATIVE */
-    int32_t reserved;
+    int32_t presorted;   /* tree_force only: 1 = the particles are already in the order a
+                            tree build needs (ascending Morton key to level 15, as kdk_step
+                            and dzs_sort_state leave them): the tree is built on them in place,
+                            without sorted copies.  The order is checked on the device; an
+                            input out of order computes nothing and is reported by dzs_check
+                            (DZS_EINVAL).  kdk_step ignores it. */
     double alpha_open;   /* relative criterion's accuracy parameter (>= 0) */
 } dzs_tree_params;
 
@@ -253,12 +268,13 @@ typedef struct {
 
 /* ---- context ------------------------------------------------------------------------ */
 
-/* Create a context on HIP device `device` and allocate its scratch for `cap`: about
- * 117 bytes per particle (keys and sort indices 24; one arena of 89 shared by the tree, with
- * node capacity max_particles/2 + 4096, and the DZS coarsening buffers; group starts 4) plus
- * the meshes (32 bytes per cell, 12 with DZS_CAP_FP32_MESHES); tree_force adds 52 bytes per
- * particle of sorted copies at its first call, and the relative opening criterion 4 bytes
- * per particle at its first use.  Returns DZS_ENOMEM if the device memory does not suffice. */
+/* Create a context on HIP device `device` and allocate all its scratch for `cap`: about
+ * 123 bytes per particle (keys and sort indices 24; one arena of 89 shared by the tree, with
+ * node capacity max_particles/2 + 4096, and the DZS coarsening buffers; group starts 4; the
+ * relative criterion's |g| 4; time-step bins and the walk's target flags 2), plus 28 bytes per
+ * particle of sorted copies for tree_force unless DZS_CAP_NO_COPIES, plus the meshes (32 bytes
+ * per cell, 12 with DZS_CAP_FP32_MESHES).  No call allocates device memory afterwards.
+ * Returns DZS_ENOMEM if the device memory does not suffice. */
 dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap);
 dzs_status dzs_ctx_destroy(dzs_ctx *ctx);
 /* Text of the context's last failure ("" if none); valid until the next call. */
@@ -340,11 +356,17 @@ dzs_status dzs_coarsen(dzs_ctx *ctx, const dzs_box *box, dzs_particles *inout,
 dzs_status pm_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                     const dzs_pm_params *prm, void *stream);
 
-/* Tree short-range acceleration into g (or added to g).  Particle order is left unchanged
- * (the tree is built on a sorted copy).  Synchronises the stream at the end to check the
- * tree's node capacity and the walk's stack depth (DZS_ECAPACITY). */
+/* Tree short-range acceleration into g (or added to g) of the targets: targets (device,
+ * n_targets indices into the particle arrays, each below n and listed once) or every particle
+ * when targets is NULL; the other entries of g are not touched.  Every particle is a source.
+ * Particle order is left unchanged: the tree is built on sorted copies of the positions and
+ * multiplicities (or, with prm->presorted, on the particles themselves) and the force is
+ * written through the permutation.  Only enqueues work: the tree's node capacity, the walk's
+ * stack depth, the presorted order and the target indices are checked on the device and
+ * reported by the next dzs_check (DZS_ECAPACITY, DZS_EINVAL). */
 dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
-                      const dzs_tree_params *prm, void *stream);
+                      const dzs_tree_params *prm, const uint32_t *targets, uint64_t n_targets,
+                      void *stream);
 
 /* Lightcone crossing test and solve for the drift described by prm (does not move the
  * particles). */
@@ -356,7 +378,11 @@ dzs_status lightcone_emit(dzs_ctx *ctx, const dzs_box *box, const dzs_particles 
  *   DZS coarsening at a1 (optional; skipped when R_lc + b >= sqrt(3)/2 L, where no node can
  *   qualify); reorder the state by Morton key; g = PM + tree; p += g K2.
  * The state is left sorted by Morton key.  report (optional) receives the coarsening
- * counts.  Synchronises the stream (coarsening counts; the capacity check after the walk).
+ * counts.  A step whose coarsening can merge synchronises the stream (the new count is read
+ * back); any other step only enqueues work, so it can be captured into a HIP graph (after one
+ * eager call with the same mesh parameters, which uploads the mesh tables) and replayed: the
+ * factors in prm are then those of the capturing call.  The tree's node capacity and the
+ * walk's stack depth are checked on the device and reported by the next dzs_check.
  * The mesh solve runs on a stream the context owns (default priority), forked from and
  * joined back to `stream` with events inside the call, so all of the step's work is ordered
  * before whatever the caller enqueues on `stream` next. */
@@ -408,8 +434,9 @@ dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_particles *s
  * kdk_step_batch (host memory only; call after the previous replay has finished). */
 dzs_status kdk_step_batch_stage(dzs_ctx *ctx, const dzs_step_params *prm);
 
-/* Synchronise the stream and report (and clear) a tree node-capacity or walk stack-depth
- * overflow left by calls that do not check it themselves (kdk_step_batch): DZS_ECAPACITY. */
+/* Synchronise the stream and report (and clear) what the device recorded since the last
+ * check: a tree node-capacity or walk stack-depth overflow (DZS_ECAPACITY), or a tree_force
+ * input out of key order under presorted or a target index out of range (DZS_EINVAL). */
 dzs_status dzs_check(dzs_ctx *ctx, void *stream);
 
 /* ---- parts of the path, exposed for testing and measurement --------------------------- */

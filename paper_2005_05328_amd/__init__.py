@@ -172,9 +172,10 @@ class Context:
     mesh on one device."""
 
     def __init__(self, max_particles: int, max_mesh_side: int, device: int = 0,
-                 fp32_meshes: bool = False):
-        cap = _abi.Capacity(int(max_particles), int(max_mesh_side),
-                            _abi.DZS_CAP_FP32_MESHES if fp32_meshes else 0)
+                 fp32_meshes: bool = False, no_copies: bool = False, max_boxes: int = 0):
+        flags = (_abi.DZS_CAP_FP32_MESHES if fp32_meshes else 0) | \
+            (_abi.DZS_CAP_NO_COPIES if no_copies else 0)
+        cap = _abi.Capacity(int(max_particles), int(max_mesh_side), flags, int(max_boxes), 0)
         h = C.c_void_p()
         rc = _lib.dzs_ctx_create(C.byref(h), int(device), C.byref(cap))
         if rc != 0:
@@ -211,10 +212,13 @@ class Context:
         self._check("pm_force", _lib.pm_force(self._h, C.byref(box), C.byref(v), C.byref(prm),
                                               _stream_handle(stream)))
 
-    def tree_force(self, box: Box, st: State, prm: TreeParams, stream=None):
+    def tree_force(self, box: Box, st: State, prm: TreeParams, targets=None, stream=None):
+        """Short-range force of `targets` (an int32/uint32 device tensor of indices; every
+        particle when None).  Capacity and order errors surface at the next check()."""
         v = st.view()
+        nt = 0 if targets is None else int(targets.numel())
         self._check("tree_force", _lib.tree_force(self._h, C.byref(box), C.byref(v), C.byref(prm),
-                                                  _stream_handle(stream)))
+                                                  _ptr(targets), nt, _stream_handle(stream)))
 
     def lightcone_emit(self, box: Box, st: State, prm: LCParams, ring: LCRing, stream=None):
         v = st.view()
@@ -272,7 +276,8 @@ class Context:
         self._check("kdk_step_batch_stage", _lib.kdk_step_batch_stage(self._h, C.byref(prm)))
 
     def check(self, stream=None):
-        """Report a deferred tree-capacity or walk-stack overflow (synchronises)."""
+        """Report what the device recorded since the last check: a tree-capacity or
+        walk-stack overflow, or a rejected tree_force input (synchronises)."""
         self._check("dzs_check", _lib.dzs_check(self._h, _stream_handle(stream)))
 
     # ---- parts of the path

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libdzs.so")
 DZS_OK, DZS_EINVAL, DZS_ENOMEM, DZS_ECAPACITY, DZS_EHIP = 0, -1, -2, -3, -4
 DZS_CHEB_MAX = 24
 DZS_FP64, DZS_FP32 = 0, 1
-DZS_CAP_FP32_MESHES = 1
+DZS_CAP_FP32_MESHES, DZS_CAP_NO_COPIES = 1, 2
 DZS_CRIT_GEOMETRIC, DZS_CRIT_DYNAMICAL = 0, 1
 DZS_OPEN_GEOMETRIC, DZS_OPEN_RELATIVE = 0, 1
 
@@ -53,7 +53,7 @@ class Forecast(C.Structure):
 
 class Capacity(C.Structure):
     _fields_ = [("max_particles", C.c_uint64), ("max_mesh_side", C.c_uint32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("max_boxes", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Box(C.Structure):
@@ -85,7 +85,7 @@ class PMParams(C.Structure):
 class TreeParams(C.Structure):
     _fields_ = [("r_s", C.c_double), ("r_cut", C.c_double), ("theta", C.c_double),
                 ("leaf_size", C.c_int32), ("group_size", C.c_int32), ("precision", C.c_int32),
-                ("accumulate", C.c_int32), ("opening", C.c_int32), ("reserved", C.c_int32),
+                ("accumulate", C.c_int32), ("opening", C.c_int32), ("presorted", C.c_int32),
                 ("alpha_open", C.c_double)]
 
 
@@ -163,7 +163,8 @@ def load():
     L.dzs_coarsen.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(CoarsenParams),
                               P, C.POINTER(CoarsenReport), P]
     L.pm_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(PMParams), P]
-    L.tree_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(TreeParams), P]
+    L.tree_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(TreeParams), P,
+                             C.c_uint64, P]
     L.lightcone_emit.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(LCParams),
                                  C.POINTER(LCRing), P]
     L.kdk_step.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(StepParams),

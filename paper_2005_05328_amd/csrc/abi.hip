@@ -145,7 +145,7 @@ static dzs_status alloc(dzs_ctx *ctx, T **p, uint64_t count) {
 static void release(dzs_ctx *ctx) {
     void *ptrs[] = {ctx->key, ctx->key_alt, ctx->idx, ctx->idx_alt, ctx->hist, ctx->hist_scan,
                     ctx->scan_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult, ctx->aold,
-                    ctx->sgx, ctx->sgy, ctx->sgz, ctx->arena, ctx->bstate, ctx->grp_first,
+                    ctx->hbins, ctx->active, ctx->arena, ctx->bstate, ctx->grp_first,
                     ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl,
                     ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members,
                     ctx->step_dev, ctx->fp32_meshes ? nullptr : (void *)ctx->mesh_q, ctx->mesh_c,
@@ -259,16 +259,33 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->walk_counter, 64));
     DZS_HIP(c, hipMemset(c->walk_counter, 0, 64 * sizeof(uint32_t)));
     DZS_TRY(alloc(c, &c->cell_node, 1ull << (3 * DZS_CELL_K_MAX)));
-    DZS_TRY(alloc(c, &c->batch_box, DZS_BATCH_MAX));
-    DZS_TRY(alloc(c, &c->batch_first, DZS_BATCH_MAX + 1));
-    DZS_TRY(alloc(c, &c->batch_members, DZS_BATCH_MAX));
+    // the relative criterion's |g|, the time-step bins and the walk's target flags
+    DZS_TRY(alloc(c, &c->aold, n));
+    DZS_TRY(alloc(c, &c->hbins, n));
+    DZS_TRY(alloc(c, &c->active, n));
+    if (!(cap->flags & DZS_CAP_NO_COPIES)) {
+        // tree_force's sorted copies of an input in any order
+        DZS_TRY(alloc(c, &c->sx, n));
+        DZS_TRY(alloc(c, &c->sy, n));
+        DZS_TRY(alloc(c, &c->sz, n));
+        DZS_TRY(alloc(c, &c->smult, n));
+    }
+    const uint32_t nbox = cap->max_boxes ? cap->max_boxes : DZS_BATCH_MAX;
+    c->cap_boxes = nbox;
+    DZS_TRY(alloc(c, &c->batch_box, nbox));
+    DZS_TRY(alloc(c, &c->batch_first, nbox + 1));
+    DZS_TRY(alloc(c, &c->batch_members, nbox));
+    if (ng > 0) {
+        // per box 2 ng (Green factors, k^2) and per distinct mesh side 2 ng (twiddles)
+        c->batch_tab_cap = 4ull * nbox * ng;
+        DZS_TRY(alloc(c, &c->batch_tab, c->batch_tab_cap));
+    }
     DZS_TRY(alloc(c, &c->step_dev, 1));
     {
         void *hb = nullptr, *hf = nullptr, *hs = nullptr;
-        DZS_HIP(c, hipHostMalloc(&hb, sizeof(dzs_bbox) * DZS_BATCH_MAX, hipHostMallocDefault));
+        DZS_HIP(c, hipHostMalloc(&hb, sizeof(dzs_bbox) * nbox, hipHostMallocDefault));
         c->batch_box_h = (dzs_bbox *)hb;
-        DZS_HIP(c, hipHostMalloc(&hf, sizeof(uint64_t) * (DZS_BATCH_MAX + 1),
-                                 hipHostMallocDefault));
+        DZS_HIP(c, hipHostMalloc(&hf, sizeof(uint64_t) * (nbox + 1), hipHostMallocDefault));
         c->batch_first_h = (uint64_t *)hf;
         DZS_HIP(c, hipHostMalloc(&hs, sizeof(dzs_step_block), hipHostMallocDefault));
         c->step_h = (dzs_step_block *)hs;
@@ -302,7 +319,9 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
 }
 
 extern "C" dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap) {
-    if (!out || !cap || cap->max_particles == 0 || cap->max_particles > 0xfffff000ull)
+    if (!out || !cap || cap->max_particles == 0 || cap->max_particles > 0xfffff000ull ||
+        cap->max_boxes > DZS_BATCH_MAX || cap->reserved != 0 ||
+        (cap->flags & ~(DZS_CAP_FP32_MESHES | DZS_CAP_NO_COPIES)) != 0)
         return DZS_EINVAL;
     if (cap->max_mesh_side != 0 && (cap->max_mesh_side < 8 || cap->max_mesh_side > 1024))
         return DZS_EINVAL;
@@ -518,63 +537,69 @@ extern "C" dzs_status pm_force(dzs_ctx *ctx, const dzs_box *box, const dzs_parti
     return dzs_pm_run(ctx, box, p, prm, (hipStream_t)stream);
 }
 
-// |g| buffer of the relative opening criterion, allocated at its first use (4 B/particle)
-static dzs_status alloc_aold(dzs_ctx *ctx) {
-    if (!ctx->aold)
-        DZS_TRY(alloc(ctx, &ctx->aold, ctx->cap_n));
-    return DZS_OK;
-}
-
 extern "C" dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
-                                 const dzs_tree_params *prm, void *stream) {
+                                 const dzs_tree_params *prm, const uint32_t *targets,
+                                 uint64_t n_targets, void *stream) {
     DZS_TRY(check_common(ctx, box, p));
     dzs_tree_params t;
     DZS_TRY(check_tree(ctx, box, prm, &t));
     if (p->n > 0 && (!p->gx || !p->gy || !p->gz))
         return dzs_fail(ctx, DZS_EINVAL, "null acceleration array");
+    if (t.presorted != 0 && t.presorted != 1)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: presorted must be 0 or 1");
+    if (!t.presorted && !ctx->sx)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: the context has no sorted copies "
+                        "(DZS_CAP_NO_COPIES): pass particles in key order with presorted = 1");
+    if (targets && n_targets > p->n)
+        return dzs_fail(ctx, DZS_EINVAL, "tree: %llu targets for %llu particles",
+                        (unsigned long long)n_targets, (unsigned long long)p->n);
     const uint64_t n = p->n;
-    if (n == 0)
+    if (n == 0 || (targets && n_targets == 0))
         return DZS_OK;
     hipStream_t s = (hipStream_t)stream;
-    if (!ctx->sx) {
-        // the sorted copies of a standalone force call, allocated at its first use
-        DZS_TRY(alloc(ctx, &ctx->sx, ctx->cap_n));
-        DZS_TRY(alloc(ctx, &ctx->sy, ctx->cap_n));
-        DZS_TRY(alloc(ctx, &ctx->sz, ctx->cap_n));
-        DZS_TRY(alloc(ctx, &ctx->smult, ctx->cap_n));
-        DZS_TRY(alloc(ctx, &ctx->sgx, ctx->cap_n));
-        DZS_TRY(alloc(ctx, &ctx->sgy, ctx->cap_n));
-        DZS_TRY(alloc(ctx, &ctx->sgz, ctx->cap_n));
-    }
+    const bool sorted_in = t.presorted != 0;
+    const double *tx = p->x, *ty = p->y, *tz = p->z;
+    const uint32_t *tm = p->mult;
+    const uint32_t *perm = nullptr;  // tree slot -> entry index (none: the same)
     DZS_TRY(dzs_launch_keys(ctx, p->x, p->y, p->z, n, box->L, ctx->key, ctx->idx, s));
-    DZS_TRY(dzs_radix_sort(ctx, n, s, DZS_TREE_FIRST_PASS));
-    {
-        dzs_timed tm(ctx, KC_PERMUTE, s);
+    if (sorted_in) {
+        DZS_TRY(dzs_check_order(ctx, n, s));
+    } else {
+        DZS_TRY(dzs_radix_sort(ctx, n, s, DZS_TREE_FIRST_PASS));
+        dzs_timed tm_(ctx, KC_PERMUTE, s);
         DZS_TRY(dzs_gather_f64(ctx, p->x, ctx->idx, ctx->sx, n, s));
         DZS_TRY(dzs_gather_f64(ctx, p->y, ctx->idx, ctx->sy, n, s));
         DZS_TRY(dzs_gather_f64(ctx, p->z, ctx->idx, ctx->sz, n, s));
         DZS_TRY(dzs_gather_u32(ctx, p->mult, ctx->idx, ctx->smult, n, s));
+        tx = ctx->sx;
+        ty = ctx->sy;
+        tz = ctx->sz;
+        tm = ctx->smult;
+        perm = ctx->idx;
+    }
+    const uint8_t *active = nullptr;
+    if (targets) {
+        // the targets' flags in tree order (entry-order flags staged in the sort's free
+        // ping-pong keys when the tree order differs)
+        uint8_t *flags = sorted_in ? ctx->active : (uint8_t *)ctx->key_alt;
+        DZS_TRY(dzs_mark_targets(ctx, targets, n_targets, n, flags, s));
+        if (!sorted_in)
+            DZS_TRY(dzs_gather_u8(ctx, flags, perm, ctx->active, n, s));
+        active = ctx->active;
     }
     const float *aold = nullptr;
     if (t.opening == DZS_OPEN_RELATIVE) {
         // the targets' |g| on entry, in tree order
-        DZS_TRY(alloc_aold(ctx));
-        DZS_TRY(dzs_launch_gnorm(ctx, n, p->gx, p->gy, p->gz, ctx->idx, ctx->aold, s));
+        DZS_TRY(dzs_launch_gnorm(ctx, n, p->gx, p->gy, p->gz, perm, ctx->aold, s));
         aold = ctx->aold;
     }
-    DZS_TRY(dzs_tree_build(ctx, box, n, ctx->sx, ctx->sy, ctx->sz, ctx->smult, t.leaf_size,
-                           t.group_size, s));
-    dzs_tree_params tw = t;
-    tw.accumulate = 0;
-    DZS_TRY(dzs_tree_walk(ctx, box, n, ctx->sx, ctx->sy, ctx->sz, ctx->smult, ctx->sgx, ctx->sgy,
-                          ctx->sgz, &tw, s, aold));
-    {
-        dzs_timed tm(ctx, KC_PERMUTE, s);
-        DZS_TRY(dzs_scatter_add_f64(ctx, ctx->sgx, ctx->idx, p->gx, n, t.accumulate, s));
-        DZS_TRY(dzs_scatter_add_f64(ctx, ctx->sgy, ctx->idx, p->gy, n, t.accumulate, s));
-        DZS_TRY(dzs_scatter_add_f64(ctx, ctx->sgz, ctx->idx, p->gz, n, t.accumulate, s));
-    }
-    return DZS_OK;
+    DZS_TRY(dzs_tree_build(ctx, box, n, tx, ty, tz, tm, t.leaf_size, t.group_size, s));
+    dzs_walk_io io;
+    io.aold = aold;
+    io.active = active;
+    io.out_perm = perm;
+    DZS_TRY(dzs_tree_walk(ctx, box, n, tx, ty, tz, tm, p->gx, p->gy, p->gz, &t, s, io));
+    return dzs_latch_bad_input(ctx, s);
 }
 
 extern "C" dzs_status lightcone_emit(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
@@ -612,10 +637,8 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
     // lost (geometric fallback) when the coarsening merges particles
     const bool relative = t.opening == DZS_OPEN_RELATIVE && st->n > 0;
     bool aold_ok = relative;
-    if (relative) {
-        DZS_TRY(alloc_aold(ctx));
+    if (relative)
         DZS_TRY(dzs_launch_gnorm(ctx, st->n, st->gx, st->gy, st->gz, nullptr, ctx->aold, s));
-    }
     DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s));
     DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &prm->lc, ring, prm->do_lightcone, 1, s));
     const bool can_merge = prm->do_coarsen &&
@@ -663,8 +686,10 @@ extern "C" dzs_status kdk_step(dzs_ctx *ctx, const dzs_box *box, dzs_particles *
         DZS_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_pm, 0));
         DZS_TRY(dzs_pm_apply(ctx, box, st, &pm, s));
         t.accumulate = 1;
+        dzs_walk_io io;
+        io.aold = aold_ok ? ctx->aold : nullptr;
         DZS_TRY(dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx, st->gy,
-                              st->gz, &t, s, aold_ok ? ctx->aold : nullptr));
+                              st->gz, &t, s, io));
         DZS_TRY(dzs_launch_kick(ctx, st, prm->K2, s));
     }
     return DZS_OK;
@@ -700,15 +725,14 @@ static dzs_status hier_force(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st
     DZS_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_pm, 0));
     DZS_TRY(dzs_pm_apply(ctx, box, st, &pm, s));
     t.accumulate = 1;
-    struct walk_set {
-        dzs_ctx *c;
-        ~walk_set() { c->walk_bins = nullptr; }
-    } guard{ctx};
-    ctx->walk_bins = bins;
-    ctx->walk_jn = jn;
-    ctx->walk_B = B;
+    // the targets that end a step at this boundary (all when bins is null)
+    dzs_walk_io io;
+    if (bins) {
+        DZS_TRY(dzs_launch_hier_active(ctx, st->n, bins, jn, B, ctx->active, s));
+        io.active = ctx->active;
+    }
     return dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx, st->gy, st->gz,
-                         &t, s);
+                         &t, s, io);
 }
 
 extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st,
@@ -749,8 +773,6 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
     u[0] = a0;
     u[2 * S] = a1;
     if (st->n > 0) {
-        if (!ctx->hbins)
-            DZS_TRY(alloc(ctx, &ctx->hbins, ctx->cap_n));
         const double H = 100.0 * sqrt(om / (a0 * a0 * a0) + (1.0 - om));
         const double C = 2.0 * hp->eta * (a0 * a0 * a0) * (H * H);
         DZS_TRY(dzs_launch_hier_bins(ctx, box, st, C, Dl, B, prm->coarsen.x_obs, hp->R_lim,
@@ -795,7 +817,8 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
             DZS_TRY(hier_force(ctx, box, st, prm, t, nullptr, 0u, 0u, in_order, s));
         }
     }
-    return DZS_OK;
+    // the sub-steps' tree capacities and stack depths
+    return dzs_tree_check(ctx, s);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -813,6 +836,9 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     const uint32_t nb = batch->n_boxes;
     if (nb < 1 || nb > DZS_BATCH_MAX)
         return dzs_fail(ctx, DZS_EINVAL, "batch: need 1 <= n_boxes <= %d", DZS_BATCH_MAX);
+    if (nb > ctx->cap_boxes)
+        return dzs_fail(ctx, DZS_ECAPACITY, "batch: %u boxes exceed the context's %u", nb,
+                        ctx->cap_boxes);
     if (batch->first[0] != 0 || batch->first[nb] != st->n)
         return dzs_fail(ctx, DZS_EINVAL, "batch: first[0] must be 0 and first[n_boxes] = n");
     if (st->n > st->capacity || st->n > ctx->cap_n || st->n >= (1ull << 32))
@@ -913,11 +939,6 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
     const lc_args *lc_dev = captured ? &ctx->step_dev->lc : nullptr;
     if (st->n == 0)
         return DZS_OK;
-    struct defer_guard {
-        dzs_ctx *c;
-        ~defer_guard() { c->defer_checks = false; }
-    } guard{ctx};
-    ctx->defer_checks = true;
 
     DZS_TRY(dzs_launch_kick(ctx, st, prm->K1, s, K1_dev));
     DZS_TRY(dzs_launch_drift_lc(ctx, &batch->boxes[0], st, &prm->lc, ring, prm->do_lightcone, 1,

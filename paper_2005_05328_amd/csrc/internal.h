@@ -105,16 +105,14 @@ struct dzs_ctx {
     uint64_t scan_tmp_cap = 0;
     void *gather_tmp = nullptr;  // one array of max_particles doubles for in-place permutes
 
-    // ---- sorted copies used by tree_force on an unsorted input
+    // ---- sorted copies used by tree_force on an input in any order (none with
+    //      DZS_CAP_NO_COPIES)
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
     uint32_t *smult = nullptr;
-    double *sgx = nullptr, *sgy = nullptr, *sgz = nullptr;
-    float *aold = nullptr;  // |g| on entry, for the relative opening criterion (lazy)
-    uint8_t *hbins = nullptr;  // bins of the individual time steps (lazy)
-    // the walk's active set during an individual-step force: target i is active when
-    // (walk_jn mod 2^(walk_B - bin_i)) == 0; walk_bins == nullptr: every target
-    const uint8_t *walk_bins = nullptr;
-    uint32_t walk_jn = 0, walk_B = 0;
+    float *aold = nullptr;     // |g| on entry, for the relative opening criterion
+    uint8_t *hbins = nullptr;  // bins of the individual time steps
+    uint8_t *active = nullptr; // the walk's target flags (tree order)
+    uint32_t cap_boxes = 0;    // batch tables sized for this many boxes
 
     // ---- octree (structure of arrays)
     uint64_t cap_nodes = 0;
@@ -151,10 +149,10 @@ struct dzs_ctx {
     uint32_t *cell_node = nullptr;     // walk start cells: [8^DZS_CELL_K_MAX] node ids
     uint8_t *cell_dl = nullptr;        // and the level offset of each
     double qf_err = 1.0;
-    uint32_t *bstate = nullptr;        // tree build state on the device (counts, level starts)
+    uint32_t *bstate = nullptr;        // tree build state on the device (counts, level starts,
+                                       // the sticky error flags dzs_check reports)
     bool tree_built = false;           // a tree for tree_n particles is in the node arrays
     uint32_t tree_n = 0;
-    bool defer_checks = false;         // skip the synchronising overflow checks (batched step)
     char *arena = nullptr;             // tree and coarsening buffers (shared, see create())
     uint64_t arena_bytes = 0;
     bool fp32_meshes = false;          // meshes sized for the precision form only
@@ -344,14 +342,38 @@ dzs_status dzs_launch_hier_bins(dzs_ctx *ctx, const dzs_box *box, const dzs_part
                                 int limiter, uint8_t *bins, hipStream_t s);
 dzs_status dzs_launch_kick_bins(dzs_ctx *ctx, const dzs_particles *p, const uint8_t *bins,
                                 const double *K, hipStream_t s);
+// the targets that end a step at sub-step boundary jn: active[i] = (jn mod 2^(B - bin_i)) == 0
+dzs_status dzs_launch_hier_active(dzs_ctx *ctx, uint64_t n, const uint8_t *bins, uint32_t jn,
+                                  uint32_t B, uint8_t *active, hipStream_t s);
+// flags[i] = 1 for the listed targets, 0 elsewhere (n entries); an index >= n sets
+// DZS_BS_BADINPUT
+dzs_status dzs_mark_targets(dzs_ctx *ctx, const uint32_t *targets, uint64_t n_targets,
+                            uint64_t n, uint8_t *flags, hipStream_t s);
+dzs_status dzs_gather_u8(dzs_ctx *ctx, const uint8_t *src, const uint32_t *perm, uint8_t *dst,
+                         uint64_t n, hipStream_t s);
 // host cosmology (cosmo.cpp): K(a0, a1) = int da / (a^2 H)
 double dzs_kick_factor(double a0, double a1, double omega_m);
 dzs_status dzs_gather_u32(dzs_ctx *ctx, const uint32_t *src, const uint32_t *perm,
                           uint32_t *dst, uint64_t n, hipStream_t s);
-dzs_status dzs_scatter_add_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm,
-                               double *dst, uint64_t n, int accumulate, hipStream_t s);
 
 // tree.hip
+// Tree build state words (ctx->bstate) that dzs_check reads: sticky error flags.
+#define DZS_BS_OVERFLOW 3   // the tree needed more than the node capacity
+#define DZS_BS_BADINPUT 40  // tree_force: an input out of key order under presorted, or a
+                            // target index out of range (the build and walk of that call
+                            // then do nothing); cleared at the end of the call into
+#define DZS_BS_BADREPORT 41 // the sticky copy dzs_check reports
+// end of a tree_force call: DZS_BS_BADREPORT |= DZS_BS_BADINPUT, DZS_BS_BADINPUT = 0
+dzs_status dzs_latch_bad_input(dzs_ctx *ctx, hipStream_t s);
+// What a walk reads and writes besides the tree and the positions: aold (the relative
+// criterion's |g| on entry, tree order; null = geometric), active (per tree slot, nonzero =
+// a target; null = every particle) and out_perm (tree slot -> index of g written; null = the
+// slot itself).
+struct dzs_walk_io {
+    const float *aold = nullptr;
+    const uint8_t *active = nullptr;
+    const uint32_t *out_perm = nullptr;
+};
 dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                           const double *y, const double *z, const uint32_t *mult,
                           int leaf_size, int group_size, hipStream_t s);
@@ -359,19 +381,22 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const
                              const double *y, const double *z, const uint32_t *mult,
                              int leaf_size, int group_size, int KB, const dzs_bbox *boxes,
                              hipStream_t s);
-// aold (device, n floats, tree order): the targets' previous |g| for the relative opening
-// criterion; nullptr makes a relative-criterion call use the geometric one.
+// io.aold null makes a relative-criterion call use the geometric one.
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
                          double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s,
-                         const float *aold = nullptr);
+                         const dzs_walk_io &io = dzs_walk_io());
+// tree_force, presorted: flag (DZS_BS_BADINPUT) keys in ctx->key out of order to the tree's
+// depth
+dzs_status dzs_check_order(dzs_ctx *ctx, uint64_t n, hipStream_t s);
 
 dzs_status dzs_batch_roots(dzs_ctx *ctx, dzs_bbox *boxes, hipStream_t s);
 dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s);
 dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                             const double *y, const double *z, const uint32_t *mult, double *gx,
                             double *gy, double *gz, const dzs_tree_params *prm,
-                            const dzs_bbox *boxes, hipStream_t s, const float *aold = nullptr);
+                            const dzs_bbox *boxes, hipStream_t s,
+                            const dzs_walk_io &io = dzs_walk_io());
 
 // pm.hip
 bool dzs_pm_mesh_ok(int ng);

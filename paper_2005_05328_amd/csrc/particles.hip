@@ -271,16 +271,6 @@ __global__ __launch_bounds__(PT_THREADS) void k_copy(uint64_t n, const T *__rest
         dst[i] = src[i];
 }
 
-__global__ __launch_bounds__(PT_THREADS) void k_scatter(uint64_t n, const double *__restrict__ src,
-                                                        const uint32_t *__restrict__ perm,
-                                                        double *__restrict__ dst, int accumulate) {
-    uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
-    if (i >= n)
-        return;
-    uint32_t j = perm[i];
-    dst[j] = accumulate ? dst[j] + src[i] : src[i];
-}
-
 template <typename T>
 static dzs_status permute_one(dzs_ctx *ctx, T *arr, const uint32_t *perm, uint64_t n,
                               hipStream_t s) {
@@ -482,11 +472,65 @@ dzs_status dzs_gather_u32(dzs_ctx *ctx, const uint32_t *src, const uint32_t *per
     return dzs_check_launch(ctx, "gather_u32");
 }
 
-dzs_status dzs_scatter_add_f64(dzs_ctx *ctx, const double *src, const uint32_t *perm,
-                               double *dst, uint64_t n, int accumulate, hipStream_t s) {
+dzs_status dzs_gather_u8(dzs_ctx *ctx, const uint8_t *src, const uint32_t *perm, uint8_t *dst,
+                         uint64_t n, hipStream_t s) {
     if (n == 0)
         return DZS_OK;
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n, src,
-                       perm, dst, accumulate);
-    return dzs_check_launch(ctx, "scatter_f64");
+    hipLaunchKernelGGL(k_gather<uint8_t>, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0,
+                       s, n, src, perm, dst);
+    return dzs_check_launch(ctx, "gather_u8");
+}
+
+// ---------------------------------------------------------------------------------------
+// target flags of the walk
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(PT_THREADS) void k_fill_u8(uint64_t n, uint8_t *__restrict__ a,
+                                                        uint8_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i < n)
+        a[i] = v;
+}
+
+__global__ __launch_bounds__(PT_THREADS) void k_mark_targets(uint64_t nt,
+                                                             const uint32_t *__restrict__ t,
+                                                             uint64_t n, uint8_t *__restrict__ flags,
+                                                             uint32_t *__restrict__ bad) {
+    const uint64_t k = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (k >= nt)
+        return;
+    const uint32_t i = t[k];
+    if (i < n)
+        flags[i] = 1u;
+    else
+        atomicOr(bad, 1u);
+}
+
+dzs_status dzs_mark_targets(dzs_ctx *ctx, const uint32_t *targets, uint64_t n_targets,
+                            uint64_t n, uint8_t *flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n,
+                       flags, (uint8_t)0);
+    DZS_TRY(dzs_check_launch(ctx, "fill_u8"));
+    if (n_targets == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_mark_targets, dim3(blocks_for(n_targets, PT_THREADS)), dim3(PT_THREADS),
+                       0, s, n_targets, targets, n, flags, ctx->bstate + DZS_BS_BADINPUT);
+    return dzs_check_launch(ctx, "mark_targets");
+}
+
+__global__ __launch_bounds__(PT_THREADS) void k_hier_active(uint64_t n,
+                                                            const uint8_t *__restrict__ bins,
+                                                            uint32_t jn, uint32_t B,
+                                                            uint8_t *__restrict__ active) {
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i < n)
+        active[i] = (jn & ((1u << (B - bins[i])) - 1u)) == 0u ? 1u : 0u;
+}
+
+dzs_status dzs_launch_hier_active(dzs_ctx *ctx, uint64_t n, const uint8_t *bins, uint32_t jn,
+                                  uint32_t B, uint8_t *active, hipStream_t s) {
+    if (n == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_hier_active, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n,
+                       bins, jn, B, active);
+    return dzs_check_launch(ctx, "hier_active");
 }

@@ -1003,14 +1003,12 @@ dzs_status dzs_pm_batch_prepare(dzs_ctx *ctx, uint32_t nb, dzs_bbox *hb, hipStre
                 members.push_back(b);
     }
     ctx->batch_cls_first.push_back((uint32_t)members.size());
-    if (tab.size() > ctx->batch_tab_cap) {
-        if (ctx->batch_tab)
-            DZS_HIP(ctx, hipFree(ctx->batch_tab));
-        ctx->batch_tab = nullptr;
-        ctx->batch_tab_cap = 0;
-        DZS_HIP(ctx, hipMalloc(&ctx->batch_tab, sizeof(double) * tab.size()));
-        ctx->batch_tab_cap = tab.size();
-    }
+    // per box 2 ng and per distinct side 2 ng doubles: within the 4 max_boxes max_mesh_side
+    // the context holds
+    if (tab.size() > ctx->batch_tab_cap)
+        return dzs_fail(ctx, DZS_ECAPACITY, "batch: tables of %llu doubles exceed the context's "
+                        "%llu", (unsigned long long)tab.size(),
+                        (unsigned long long)ctx->batch_tab_cap);
     DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_tab, tab.data(), sizeof(double) * tab.size(),
                                 hipMemcpyHostToDevice, s));
     DZS_HIP(ctx, hipMemcpyAsync(ctx->batch_members, members.data(),

@@ -34,22 +34,25 @@ static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n
 #define BS_NF 0         // frontier nodes at the current level
 #define BS_NODES 1      // nodes so far
 #define BS_GROUPS 2     // target groups
-#define BS_OVERFLOW 3   // sticky: the tree needed more than the node capacity
+#define BS_OVERFLOW DZS_BS_OVERFLOW  // sticky: the tree needed more than the node capacity
 #define BS_CHILDREN 4   // scan totals of the current level
 #define BS_INTERNAL 5
 #define BS_LEVEL 8      // [BS_LEVEL + k]: first node of level k (k <= DZS_KEY_BITS + 1)
 
+// An input flagged out of order (DZS_BS_BADINPUT) builds an empty root and nothing below it.
 __global__ void k_tree_root(uint32_t n, uint32_t *nd_first, uint32_t *nd_count,
                             uint32_t *nd_child, uint8_t *nd_nchild, uint8_t *nd_level,
                             uint32_t *frontier,
                             uint32_t *bs, uint32_t leaf, int KB) {
+    if (bs[DZS_BS_BADINPUT])
+        n = 0;
     nd_first[0] = 0;
     nd_count[0] = n;
     nd_child[0] = 0;
     nd_nchild[0] = 0;
     nd_level[0] = 0;
     frontier[0] = 0;
-    bs[BS_NF] = (n > leaf || KB > 0) ? 1u : 0u;
+    bs[BS_NF] = (n > leaf || (KB > 0 && n > 0)) ? 1u : 0u;
     bs[BS_NODES] = 1;
     bs[BS_GROUPS] = 0;
     bs[BS_LEVEL + 0] = 0;
@@ -259,11 +262,11 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
     const uint8_t *__restrict__ nd_nchild, double *nd_mass, double *nd_com, double *nd_bmin,
     double *nd_bmax, double *nd_hmax, const uint64_t *__restrict__ key,
     const dzs_bbox *__restrict__ boxes) {
-    const uint32_t v = bs[BS_LEVEL + k] + blockIdx.x * TB_THREADS + threadIdx.x;
-    if (v >= bs[BS_LEVEL + k + 1])
-        return;
-    node_moments(v, cap, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild, nd_mass,
-                 nd_com, nd_bmin, nd_bmax, nd_hmax, key, boxes);
+    const uint32_t end = bs[BS_LEVEL + k + 1];
+    for (uint32_t v = bs[BS_LEVEL + k] + blockIdx.x * TB_THREADS + threadIdx.x; v < end;
+         v += gridDim.x * TB_THREADS)
+        node_moments(v, cap, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild,
+                     nd_mass, nd_com, nd_bmin, nd_bmax, nd_hmax, key, boxes);
 }
 
 // Target groups: each node with more than G particles packs its consecutive children that
@@ -361,9 +364,6 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
     const uint32_t leaf = (uint32_t)leaf_size;
     const uint64_t cap = ctx->cap_nodes;
     uint32_t *bs = ctx->bstate;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    DZS_HIP(ctx, hipStreamIsCapturing(s, &cs));
-    const bool may_sync = !ctx->defer_checks && cs == hipStreamCaptureStatusNone;
     int deepest = 0;  // the deepest level the build may have created
     {
         dzs_timed t(ctx, KC_TREE_BUILD, s);
@@ -399,16 +399,6 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
             uint32_t *tmp = fr;
             fr = fr_next;
             fr_next = tmp;
-            // Outside a captured or deferred-check call, stop once the frontier is empty: a
-            // read-back at a few depths costs less than the empty levels' launches.  The
-            // tree is the same either way.
-            if (may_sync && (k == 9 || k == 12 || k == 15)) {
-                DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 10, bs + BS_NF, sizeof(uint32_t),
-                                            hipMemcpyDeviceToHost, s));
-                DZS_HIP(ctx, hipStreamSynchronize(s));
-                if (ctx->h_small[10] == 0)
-                    break;
-            }
         }
     }
     {
@@ -418,7 +408,9 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
             uint64_t ub = n;
             if (k < 8 && (1ull << (3 * k)) < ub)
                 ub = 1ull << (3 * k);
-            hipLaunchKernelGGL(k_tree_moments, dim3(blocks_for(ub, TB_THREADS)), dim3(TB_THREADS),
+            uint32_t nbk = blocks_for(ub, TB_THREADS);
+            nbk = nbk < 8192u ? nbk : 8192u;   // grid-stride beyond
+            hipLaunchKernelGGL(k_tree_moments, dim3(nbk), dim3(TB_THREADS),
                                0, s, (const uint32_t *)bs, k, cap, x, y, z, mult, box->m0,
                                2.8 * box->eps0, ctx->nd_first, ctx->nd_count, ctx->nd_child,
                                ctx->nd_nchild, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
@@ -453,15 +445,23 @@ dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s) {
                                 hipMemcpyDeviceToHost, s));
     DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 9, ctx->walk_counter + 2, sizeof(uint32_t),
                                 hipMemcpyDeviceToHost, s));
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + 11, ctx->bstate + DZS_BS_BADREPORT,
+                                sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     DZS_HIP(ctx, hipStreamSynchronize(s));
     const uint32_t tree_over = ctx->h_small[8], walk_over = ctx->h_small[9];
-    if (tree_over || walk_over) {
+    const uint32_t bad = ctx->h_small[11];
+    if (tree_over || walk_over || bad) {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, (uint64_t)1,
                            ctx->bstate + BS_OVERFLOW, 0u);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, (uint64_t)1,
                            ctx->walk_counter + 2, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, (uint64_t)1,
+                           ctx->bstate + DZS_BS_BADREPORT, 0u);
         DZS_HIP(ctx, hipStreamSynchronize(s));
     }
+    if (bad)
+        return dzs_fail(ctx, DZS_EINVAL, "tree_force: particles out of key order under "
+                        "presorted, or a target index out of range (nothing was computed)");
     if (tree_over)
         return dzs_fail(ctx, DZS_ECAPACITY, "tree needs more than %llu nodes",
                         (unsigned long long)ctx->cap_nodes);
@@ -469,6 +469,37 @@ dzs_status dzs_tree_check(dzs_ctx *ctx, hipStream_t s) {
         return dzs_fail(ctx, DZS_ECAPACITY, "tree walk stack overflow (depth %llu)",
                         (unsigned long long)ctx->walk_stack_depth);
     return DZS_OK;
+}
+
+// presorted input: keys (ctx->key) must ascend to the tree's depth; a descent flags the input
+__global__ __launch_bounds__(TB_THREADS) void k_check_order(uint64_t n,
+                                                            const uint64_t *__restrict__ key,
+                                                            uint32_t *__restrict__ bad) {
+    const int shift = 3 * (DZS_KEY_BITS - DZS_TREE_LEVELS);
+    for (uint64_t i = (uint64_t)blockIdx.x * TB_THREADS + threadIdx.x; i + 1 < n;
+         i += (uint64_t)gridDim.x * TB_THREADS)
+        if ((key[i] >> shift) > (key[i + 1] >> shift))
+            atomicOr(bad, 1u);
+}
+
+__global__ void k_latch_bad(uint32_t *bs) {
+    bs[DZS_BS_BADREPORT] |= bs[DZS_BS_BADINPUT];
+    bs[DZS_BS_BADINPUT] = 0u;
+}
+
+dzs_status dzs_latch_bad_input(dzs_ctx *ctx, hipStream_t s) {
+    hipLaunchKernelGGL(k_latch_bad, dim3(1), dim3(1), 0, s, ctx->bstate);
+    return dzs_check_launch(ctx, "latch_bad");
+}
+
+dzs_status dzs_check_order(dzs_ctx *ctx, uint64_t n, hipStream_t s) {
+    if (n < 2)
+        return DZS_OK;
+    uint64_t nb = (n + TB_THREADS - 1) / TB_THREADS;
+    nb = nb < 8192 ? nb : 8192;
+    hipLaunchKernelGGL(k_check_order, dim3((uint32_t)nb), dim3(TB_THREADS), 0, s, n,
+                       (const uint64_t *)ctx->key, ctx->bstate + DZS_BS_BADINPUT);
+    return dzs_check_launch(ctx, "check_order");
 }
 
 // ---------------------------------------------------------------------------------------
@@ -531,10 +562,11 @@ struct walk_args {
     // alpha_open / G (the walk's masses and distances carry no G)
     const float *aold;
     double alpha_g;
-    // individual time steps: only targets with (hier_jn mod 2^(hier_B - bin)) == 0 get a
-    // force (bins == nullptr: every target)
-    const uint8_t *bins;
-    uint32_t hier_jn, hier_B;
+    // only flagged targets get a force (nullptr: every target); the force of tree slot i
+    // goes to entry out_perm[i] (nullptr: i)
+    const uint8_t *active;
+    const uint32_t *out_perm;
+    const uint32_t *bad;  // tree_force input rejected on the device: the walk does nothing
 };
 
 // Geometry and constants of the box a group lives in.
@@ -786,6 +818,8 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     const uint32_t tl = lane % G, ph = lane / G;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t *stk = A.stack + (uint64_t)blockIdx.x * A.depth;
+    if (A.bad && *A.bad)
+        return;
 
     for (;;) {
         if (lane == 0)
@@ -811,10 +845,9 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         }
         const bool valid = tl < cnt;
         const uint32_t i = valid ? first + tl : first;
-        const bool active =
-            valid && (!A.bins || (A.hier_jn & ((1u << (A.hier_B - A.bins[i])) - 1u)) == 0u);
-        if (A.bins && __ballot(active) == 0ull)
-            continue;  // no target of this group ends a step at this boundary
+        const bool active = valid && (!A.active || A.active[i] != 0);
+        if (A.active && __ballot(active) == 0ull)
+            continue;  // no target in this group
         const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
         const double hi = W.h0 * mult_cbrt(A.mult[i]);
         // group bounding box
@@ -1121,14 +1154,15 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         }
         if (active && ph == 0) {
             const double gxv = W.Gc * (double)ax, gyv = W.Gc * (double)ay, gzv = W.Gc * (double)az;
+            const uint32_t o = A.out_perm ? A.out_perm[i] : i;
             if (A.accumulate) {
-                A.gx[i] += gxv;
-                A.gy[i] += gyv;
-                A.gz[i] += gzv;
+                A.gx[o] += gxv;
+                A.gy[o] += gyv;
+                A.gz[o] += gzv;
             } else {
-                A.gx[i] = gxv;
-                A.gy[i] = gyv;
-                A.gz[i] = gzv;
+                A.gx[o] = gxv;
+                A.gy[o] = gyv;
+                A.gz[o] = gzv;
             }
         }
     }
@@ -1240,8 +1274,8 @@ static double split_poly_f32(double wmax, float *qf) {
 dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                          const double *y, const double *z, const uint32_t *mult, double *gx,
                          double *gy, double *gz, const dzs_tree_params *prm, hipStream_t s,
-                         const float *aold) {
-    return dzs_tree_walk_ex(ctx, box, n, x, y, z, mult, gx, gy, gz, prm, nullptr, s, aold);
+                         const dzs_walk_io &io) {
+    return dzs_tree_walk_ex(ctx, box, n, x, y, z, mult, gx, gy, gz, prm, nullptr, s, io);
 }
 
 // boxes != nullptr: a batch (device table of the boxes; the keys in ctx->key carry the box);
@@ -1249,9 +1283,10 @@ dzs_status dzs_tree_walk(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const dou
 dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                             const double *y, const double *z, const uint32_t *mult, double *gx,
                             double *gy, double *gz, const dzs_tree_params *prm,
-                            const dzs_bbox *boxes, hipStream_t s, const float *aold) {
+                            const dzs_bbox *boxes, hipStream_t s, const dzs_walk_io &io) {
     if (n == 0 || !ctx->tree_built)
         return DZS_OK;
+    const float *aold = io.aold;
     const bool relative = prm->opening == DZS_OPEN_RELATIVE && aold && !boxes;
     walk_args A;
     memset(&A, 0, sizeof(A));
@@ -1277,9 +1312,9 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.accumulate = prm->accumulate;
     A.G_lanes = prm->group_size;
     A.aold = relative ? aold : nullptr;
-    A.bins = boxes ? nullptr : ctx->walk_bins;
-    A.hier_jn = ctx->walk_jn;
-    A.hier_B = ctx->walk_B;
+    A.active = boxes ? nullptr : io.active;
+    A.out_perm = boxes ? nullptr : io.out_perm;
+    A.bad = ctx->bstate + DZS_BS_BADINPUT;
     A.alpha_g = relative ? prm->alpha_open / box->G : 0.0;
     const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
     if (ctx->q_wmax != wmax) {
@@ -1349,5 +1384,5 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
             hipLaunchKernelGGL((k_tree_walk<double, false, false>), dim3(slots), dim3(64), 0, s, A);
         DZS_TRY(dzs_check_launch(ctx, "tree_walk"));
     }
-    return ctx->defer_checks ? DZS_OK : dzs_tree_check(ctx, s);
+    return DZS_OK;  // overflows stay on the device until dzs_check
 }

@@ -43,6 +43,8 @@ def test_record_and_struct_layout():
     assert C.sizeof(_abi.Box) == 32
     assert C.sizeof(_abi.Particles) == 12 * 8 + 16
     assert C.sizeof(_abi.LCParams) == 3 * 8 + 5 * 8 + 8 + 2 * 24 * 8
+    assert C.sizeof(_abi.Capacity) == 8 + 4 * 4
+    assert C.sizeof(_abi.TreeParams) == 3 * 8 + 6 * 4 + 8
 
 
 @pytest.mark.parametrize("a0,a1", [(0.02, 0.02 * math.exp(0.07824)), (0.5, 0.55),
@@ -85,7 +87,7 @@ def test_null_context_is_an_error_not_a_crash():
     from paper_2005_05328_amd import _abi
     p = _abi.Particles()
     assert L.pm_force(None, C.byref(box), C.byref(p), None, None) == _abi.DZS_EINVAL
-    assert L.tree_force(None, C.byref(box), C.byref(p), None, None) == _abi.DZS_EINVAL
+    assert L.tree_force(None, C.byref(box), C.byref(p), None, None, 0, None) == _abi.DZS_EINVAL
     assert L.dzs_ctx_destroy(None) == _abi.DZS_EINVAL
     h = C.c_void_p()
     assert L.dzs_ctx_create(C.byref(h), 0, None) == _abi.DZS_EINVAL
