@@ -217,6 +217,8 @@ class Context:
         particle when None).  Capacity and order errors surface at the next check()."""
         v = st.view()
         nt = 0 if targets is None else int(targets.numel())
+        if targets is not None and nt == 0:
+            return   # an empty subset (a null pointer would mean every particle)
         self._check("tree_force", _lib.tree_force(self._h, C.byref(box), C.byref(v), C.byref(prm),
                                                   _ptr(targets), nt, _stream_handle(stream)))
 

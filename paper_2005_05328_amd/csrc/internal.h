@@ -131,7 +131,7 @@ struct dzs_ctx {
     double q_coef[32] = {0};           // split-factor polynomial (see tree.hip)
     double q_wmax = -1.0;
     double q_err = 1.0;
-    float qf_coef[16] = {0};           // its FP32 fit (precision form)
+    float4 stab[65];                   // the precision form's table of S(u) (tree.hip)
     dzs_bbox *batch_box = nullptr;     // batched step: per-box table [DZS_BATCH_MAX]
     dzs_bbox *batch_box_h = nullptr;   // pinned host staging of the same
     double *batch_tab = nullptr;       // Green's function tables of every box

@@ -519,7 +519,12 @@ dzs_status dzs_check_order(dzs_ctx *ctx, uint64_t n, hipStream_t s) {
 // ---------------------------------------------------------------------------------------
 #define WALK_QN 18  // split-factor polynomial coefficients (Horner, fully unrolled): worst
                     // relative error in S 1.3e-13 at r_cut = 4.5 r_s, 7e-12 at 5 r_s
-#define WALK_QF 12  // the same for FP32 evaluation
+// FP32: S(u) from a table of cubics, one per interval of u = r / r_s on [0, r_cut / r_s]:
+// Hermite interpolation of S and dS/du at both ends of each interval (worst absolute error
+// in S below 1e-7 at 64 intervals, FP32 coefficients included; checked on the host), plus
+// an entry past the cutoff that extends the last one linearly (a pair within rounding of
+// r_cut).  The table rides in the kernel arguments and each workgroup stages it in LDS.
+#define WALK_TAB_N 64
 // list region / cutoff sphere below which a group evaluates densely: in FP32 the one-pass loop
 // wins even for wide groups (512^3 walk: 300 ms masked, 285 ms at 2.5, 282 ms at 3-4, 281 ms
 // dense everywhere), in FP64 the masked loop wins everywhere (128^3 walk: 2.38 ms masked,
@@ -549,7 +554,8 @@ struct walk_args {
     uint32_t *counter;  // [0] next group, [1] overflow flag
     unsigned long long *pair_count;
     double q[WALK_QN];
-    float qf[WALK_QF];  // the same split factor fitted for FP32 evaluation
+    float4 stab[WALK_TAB_N + 1];  // FP32 form: the cubics of S(u), coefficients of f^0..f^3
+    double stab_scale;            // intervals per unit of u (WALK_TAB_N r_s / r_cut)
     // start cells: the walk of a group begins at the level-K nodes (and shallower leaves) of
     // the cells that meet its bounding box grown by r_cut, instead of at the root
     const uint32_t *cell_node;  // [8^K] node covering each level-K cell (Morton order)
@@ -667,10 +673,6 @@ template <> struct split_coef<double> {
     static constexpr int N = WALK_QN;
     static __device__ __forceinline__ double at(const walk_args &A, int k) { return A.q[k]; }
 };
-template <> struct split_coef<float> {
-    static constexpr int N = WALK_QF;
-    static __device__ __forceinline__ float at(const walk_args &A, int k) { return A.qf[k]; }
-};
 
 // 1/sqrt: the FP32 form takes the hardware approximation (about 1 ulp; its inputs are far
 // from the denormal range).  The plain form refines the hardware FP64 estimate y by one
@@ -706,7 +708,7 @@ __device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T
 
 // Pair force factor g (the force on the target is m r_ij g): g_soft(r) S(r/r_s) with
 // S = 1 - u^3 q(u^2), u = r/r_s; outside the spline support g_soft = r^-3 and the product is
-// r^-3 - r_s^-3 q, one fused operation.
+// r^-3 - r_s^-3 q, one fused operation.  (FP64; the FP32 form is pair_factor_tab.)
 template <typename T>
 __device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T eh2, T hi, T hi2,
                                          T rs_inv2, T rs_inv3, T t_scale) {
@@ -730,6 +732,43 @@ __device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T eh2, 
     return g;
 }
 
+// FP32 pair force factor g_soft(r) S(r/r_s) with S from the LDS table: x = u WALK_TAB_N /
+// u_cut = r tscale, interval k = floor(x) (at most WALK_TAB_N, the entry past the cutoff), the
+// cubic at f = x - k.  r2 = 0 (the target itself) gives a finite g: its separation is zero.
+__device__ __forceinline__ float pair_factor_tab(const float4 *__restrict__ tab, float r2,
+                                                float eh, float eh2, float hi, float hi2,
+                                                float tscale) {
+    const float rinv = pair_rsqrt(fmaxf(r2, 1e-30f));
+    const float r = r2 * rinv;
+    const float x = r * tscale;
+    uint32_t k = (uint32_t)x;
+    k = k < (uint32_t)WALK_TAB_N ? k : (uint32_t)WALK_TAB_N;
+    const float f = x - (float)k;
+    const float4 c = tab[k];
+    const float S = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(c.w, f, c.z), f, c.y), f, c.x);
+    if (r2 < pair_hmax(eh2, hi2))
+        return gsoft_inner(r, fmaxf(eh, hi)) * S;
+    return (rinv * rinv) * (rinv * S);
+}
+
+template <typename T> struct pair_eval;
+template <> struct pair_eval<double> {
+    const walk_args *A;
+    double rs_inv2, rs_inv3, t_scale;
+    __device__ __forceinline__ double operator()(double r2, double eh, double eh2, double hi,
+                                                 double hi2) const {
+        return pair_factor<double>(*A, r2, eh, eh2, hi, hi2, rs_inv2, rs_inv3, t_scale);
+    }
+};
+template <> struct pair_eval<float> {
+    const float4 *tab;
+    float tscale;
+    __device__ __forceinline__ float operator()(float r2, float eh, float eh2, float hi,
+                                                float hi2) const {
+        return pair_factor_tab(tab, r2, eh, eh2, hi, hi2, tscale);
+    }
+};
+
 // The lane's share of the list (entries s, s + P, s + 2P, ...) in two passes per block of 32
 // of its entries: a cheap pass shifts one acceptance bit per entry (inside r_cut, not the
 // target itself) into a 32-bit mask, first entry highest, then the lane evaluates only the
@@ -738,13 +777,11 @@ __device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T eh2, 
 // would step through the force arithmetic for every entry some lane accepts.  The caller
 // fills the P entries past the list with far-away sentinels, so the block bound is uniform.
 template <typename T, bool MINIMG>
-__device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W,
+__device__ __forceinline__ void pair_loop(const pair_eval<T> &ev, const walk_geom &W,
                                           const src_entry<T> *src, uint32_t nlist, uint32_t s,
                                           uint32_t P, T xi, T yi, T zi, T hi, T hi2, T &ax,
                                           T &ay, T &az, uint32_t &n_pairs) {
-    const T rcut2 = T(W.rcut2), rs_inv2 = T(W.rs_inv2);
-    const T rs_inv3 = T(W.rs_inv * W.rs_inv2);
-    const T t_scale = T(A.t_scale), L = T(W.L);
+    const T rcut2 = T(W.rcut2), L = T(W.L);
     // entries per lane: uniform, so the block loops run on the scalar unit
     const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
     for (uint32_t kb = 0; kb < n_max; kb += 32u) {
@@ -765,7 +802,7 @@ __device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W
             const src_entry<T> &e = blk[k * P];
             T dx, dy, dz;
             const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
-            const T f = e.m * pair_factor<T>(A, r2, e.h, e.h2, hi, hi2, rs_inv2, rs_inv3, t_scale);
+            const T f = e.m * ev(r2, e.h, e.h2, hi, hi2);
             ax = wfma(f, dx, ax);
             ay = wfma(f, dy, ay);
             az = wfma(f, dz, az);
@@ -778,20 +815,18 @@ __device__ __forceinline__ void pair_loop(const walk_args &A, const walk_geom &W
 // entry and every lane works on every iteration, so when most of the list lies inside most
 // targets' cutoff spheres (a compact group) this costs less than the masked two-pass loop.
 template <typename T, bool MINIMG>
-__device__ __forceinline__ void pair_dense(const walk_args &A, const walk_geom &W,
+__device__ __forceinline__ void pair_dense(const pair_eval<T> &ev, const walk_geom &W,
                                            const src_entry<T> *src, uint32_t nlist, uint32_t s,
                                            uint32_t P, T xi, T yi, T zi, T hi, T hi2, T &ax,
                                            T &ay, T &az, uint32_t &n_pairs) {
-    const T rcut2 = T(W.rcut2), rs_inv2 = T(W.rs_inv2);
-    const T rs_inv3 = T(W.rs_inv * W.rs_inv2);
-    const T t_scale = T(A.t_scale), L = T(W.L);
+    const T rcut2 = T(W.rcut2), L = T(W.L);
     const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
     for (uint32_t k = 0; k < n_max; ++k) {
         const src_entry<T> &e = src[s + k * P];
         T dx, dy, dz;
         const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
         const bool in = r2 < rcut2 && r2 > T(0.0);
-        const T g = pair_factor<T>(A, r2, e.h, e.h2, hi, hi2, rs_inv2, rs_inv3, t_scale);
+        const T g = ev(r2, e.h, e.h2, hi, hi2);
         // the factor of a pair outside (or of the target itself: r = 0) is not used
         const T f = in ? e.m * g : T(0.0);
         ax = wfma(f, dx, ax);
@@ -811,6 +846,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     __shared__ double q_shift[3][64];
     __shared__ uint32_t q_wide[64];
     __shared__ uint32_t s_g;
+    __shared__ float4 s_tab[sizeof(T) == 4 ? WALK_TAB_N + 1 : 1];
 
     const uint32_t lane = threadIdx.x;
     const uint32_t G = (uint32_t)A.G_lanes;
@@ -820,6 +856,11 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
     uint32_t *stk = A.stack + (uint64_t)blockIdx.x * A.depth;
     if (A.bad && *A.bad)
         return;
+    if (sizeof(T) == 4) {
+        for (uint32_t k = lane; k <= WALK_TAB_N; k += 64)
+            s_tab[k] = A.stab[k];
+        __syncthreads();
+    }
 
     for (;;) {
         if (lane == 0)
@@ -886,6 +927,16 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         const T txi = T(xi - ox), tyi = T(yi - oy), tzi = T(zi - oz), thi = T(hi);
         const T thi2 = thi * thi;
 
+        pair_eval<T> ev;
+        if constexpr (sizeof(T) == 4) {
+            ev.tab = s_tab;
+            ev.tscale = float(A.stab_scale * W.rs_inv);
+        } else {
+            ev.A = &A;
+            ev.rs_inv2 = W.rs_inv2;
+            ev.rs_inv3 = W.rs_inv * W.rs_inv2;
+            ev.t_scale = A.t_scale;
+        }
         T ax = T(0.0), ay = T(0.0), az = T(0.0);
         uint32_t nlist = 0;
         uint32_t n_pairs = 0;
@@ -900,16 +951,16 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             __syncthreads();
             if (dense) {
                 if (wide)
-                    pair_dense<T, true>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
+                    pair_dense<T, true>(ev, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
                                         ay, az, n_pairs);
                 else
-                    pair_dense<T, false>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
+                    pair_dense<T, false>(ev, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
                                          ay, az, n_pairs);
             } else if (wide) {
-                pair_loop<T, true>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
+                pair_loop<T, true>(ev, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
                                    az, n_pairs);
             } else {
-                pair_loop<T, false>(A, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
+                pair_loop<T, false>(ev, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
                                     az, n_pairs);
             }
             nlist = 0;
@@ -1250,24 +1301,38 @@ static double split_poly(double wmax, double *q) {
     return (double)worst;
 }
 
-// The WALK_QF-coefficient fit for FP32 evaluation, its coefficients rounded to FP32, and its
-// worst absolute error in S on [0, wmax] (S is 1 at contact: FP32 resolves ~1e-7 of it).
-static double split_poly_f32(double wmax, float *qf) {
-    long double mono[WALK_QF];
-    fit_q(wmax, WALK_QF, mono);
-    for (int i = 0; i < WALK_QF; ++i)
-        qf[i] = (float)mono[i];
-    long double worst = 0.0L;
-    for (int k = 0; k <= 800; ++k) {
-        long double w = wmax * k / 800.0L;
-        long double t = 2.0L * w / wmax - 1.0L;
-        long double qa = 0.0L;
-        for (int i = WALK_QF - 1; i >= 0; --i)
-            qa = qa * t + (long double)qf[i];
-        long double u = sqrtl(w);
-        long double err = fabsl(u * w * (qa - q_taylor(w)));
-        worst = err > worst ? err : worst;
+// The FP32 table of S(u) on [0, ucut] (WALK_TAB_N intervals): on interval j, with
+// h = ucut / WALK_TAB_N and f in [0, 1], the cubic Hermite interpolant of S and h dS/du at
+// both ends, in powers of f; entry WALK_TAB_N continues the last interval's end linearly.
+// Returns the worst absolute error in S (FP32 coefficients, exact long double evaluation).
+static double split_table_f32(double ucut, float4 *tab) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    auto S = [&](long double u) {
+        return erfcl(0.5L * u) + u / sqrtl(pi) * expl(-0.25L * u * u);
+    };
+    auto dS = [&](long double u) { return -u * u / (2.0L * sqrtl(pi)) * expl(-0.25L * u * u); };
+    const long double h = (long double)ucut / WALK_TAB_N;
+    for (int j = 0; j <= WALK_TAB_N; ++j) {
+        const long double u0 = h * j, u1 = h * (j + 1);
+        const long double s0 = S(u0), d0 = h * dS(u0);
+        if (j == WALK_TAB_N) {
+            tab[j] = make_float4((float)s0, (float)d0, 0.0f, 0.0f);
+            break;
+        }
+        const long double s1 = S(u1), d1 = h * dS(u1);
+        tab[j] = make_float4((float)s0, (float)d0, (float)(3.0L * (s1 - s0) - 2.0L * d0 - d1),
+                             (float)(2.0L * (s0 - s1) + d0 + d1));
     }
+    long double worst = 0.0L;
+    for (int j = 0; j < WALK_TAB_N; ++j)
+        for (int k = 0; k <= 16; ++k) {
+            const long double f = k / 16.0L;
+            const float4 c = tab[j];
+            const long double v = (long double)c.x +
+                                  f * ((long double)c.y + f * ((long double)c.z + f * c.w));
+            const long double e = fabsl(v - S(h * (j + f)));
+            worst = e > worst ? e : worst;
+        }
     return (double)worst;
 }
 
@@ -1319,17 +1384,18 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
     if (ctx->q_wmax != wmax) {
         ctx->q_err = split_poly(wmax, ctx->q_coef);
-        ctx->qf_err = split_poly_f32(wmax, ctx->qf_coef);
+        ctx->qf_err = split_table_f32(sqrt(wmax), ctx->stab);
         ctx->q_wmax = wmax;
     }
     const bool fp32 = prm->precision == DZS_FP32;
-    if (!(ctx->q_err < 1e-10) || (fp32 && !(ctx->qf_err < 1e-6)))
+    if (!(ctx->q_err < 1e-10) || (fp32 && !(ctx->qf_err < 2e-7)))
         return dzs_fail(ctx, DZS_EINVAL, "tree: split-factor fit error %.2e / %.2e (FP32) for "
                         "r_cut/r_s = %.3f", ctx->q_err, ctx->qf_err, sqrt(wmax));
     for (int k = 0; k < WALK_QN; ++k)
         A.q[k] = ctx->q_coef[k];
-    for (int k = 0; k < WALK_QF; ++k)
-        A.qf[k] = ctx->qf_coef[k];
+    for (int k = 0; k <= WALK_TAB_N; ++k)
+        A.stab[k] = ctx->stab[k];
+    A.stab_scale = WALK_TAB_N * prm->r_s / prm->r_cut;
     A.t_scale = 2.0 / wmax;
     A.stack = ctx->walk_stack;
     A.depth = (uint32_t)ctx->walk_stack_depth;
@@ -1386,3 +1452,6 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     }
     return DZS_OK;  // overflows stay on the device until dzs_check
 }
+
+static_assert(sizeof(((dzs_ctx *)nullptr)->stab) == sizeof(float4) * (WALK_TAB_N + 1),
+              "the context's table of S(u) holds WALK_TAB_N + 1 cubics");

@@ -241,7 +241,10 @@ def test_captured_kdk_step_replays_match_eager_steps(dz, fp32):
     with torch.cuda.graph(graph, stream=stream):
         ctx_g.kdk_step(box, st_g, sp, ring_g)
     torch.cuda.synchronize()
+    seen = 0
     for r in range(4):
+        ring_e.reset()
+        ring_g.reset()
         graph.replay()
         torch.cuda.synchronize()
         ctx_e.kdk_step(box, st_e, sp, ring_e)
@@ -255,7 +258,9 @@ def test_captured_kdk_step_replays_match_eager_steps(dz, fp32):
         oe, og = np.argsort(re_["id"]), np.argsort(rg["id"])
         assert np.array_equal(re_["id"][oe], rg["id"][og])
         assert np.array_equal(re_["a_cross"][oe], rg["a_cross"][og])
-    assert ring_g.records()["count"] > 0
+        assert np.array_equal(re_["d"][oe], rg["d"][og])
+        seen += rg["count"]
+    assert seen > 0
     ctx_e.check()
     ctx_g.check()
     ctx_e.close()
