@@ -209,9 +209,7 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     };
     const uint64_t o_first = carve(off_t, 4 * nn), o_count = carve(off_t, 4 * nn),
                    o_child = carve(off_t, 4 * nn), o_nchild = carve(off_t, nn),
-                   o_level = carve(off_t, nn), o_mass = carve(off_t, 8 * nn),
-                   o_com = carve(off_t, 24 * nn), o_bmin = carve(off_t, 24 * nn),
-                   o_bmax = carve(off_t, 24 * nn), o_hmax = carve(off_t, 8 * nn),
+                   o_level = carve(off_t, nn), o_rec = carve(off_t, sizeof(dzs_node_rec) * nn),
                    o_fr = carve(off_t, 4 * nn), o_frn = carve(off_t, 4 * nn),
                    o_nc = carve(off_t, 4 * nn), o_ni = carve(off_t, 4 * nn),
                    o_co = carve(off_t, 4 * nn), o_io = carve(off_t, 4 * nn),
@@ -229,11 +227,7 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     c->nd_child = (uint32_t *)(A + o_child);
     c->nd_nchild = (uint8_t *)(A + o_nchild);
     c->nd_level = (uint8_t *)(A + o_level);
-    c->nd_mass = (double *)(A + o_mass);
-    c->nd_com = (double *)(A + o_com);
-    c->nd_bmin = (double *)(A + o_bmin);
-    c->nd_bmax = (double *)(A + o_bmax);
-    c->nd_hmax = (double *)(A + o_hmax);
+    c->nd_rec = (dzs_node_rec *)(A + o_rec);
     c->frontier = (uint32_t *)(A + o_fr);
     c->frontier_next = (uint32_t *)(A + o_frn);
     c->fr_nchild = (uint32_t *)(A + o_nc);

@@ -90,6 +90,21 @@ struct dzs_bbox {
     uint32_t root;                    // tree node of the box (its key prefix)
 };
 
+// One tree node as the walk reads it, 96 bytes (six 16-byte loads, one cache line for most
+// nodes): the particles' bounding box as a centre (FP64) and half extents (FP32 rounded up,
+// so the box still holds every particle), the centre of mass, mass and largest softening
+// support (FP64), and the topology (first particle, count, first child, children and level).
+struct alignas(16) dzs_node_rec {
+    double cx, cy, cz;
+    double comx, comy, comz;
+    double mass, hmax;
+    float hx, hy, hz;
+    uint32_t first;
+    uint32_t count, child, nl;  // nl = nchild | level << 8
+    uint32_t pad;
+};
+static_assert(sizeof(dzs_node_rec) == 96, "node record layout");
+
 struct dzs_ctx {
     int device = 0;
     uint64_t cap_n = 0;
@@ -118,8 +133,7 @@ struct dzs_ctx {
     uint64_t cap_nodes = 0;
     uint32_t *nd_first = nullptr, *nd_count = nullptr, *nd_child = nullptr;
     uint8_t *nd_nchild = nullptr, *nd_level = nullptr;
-    double *nd_mass = nullptr, *nd_com = nullptr /*3*cap*/, *nd_bmin = nullptr /*3*cap*/,
-           *nd_bmax = nullptr /*3*cap*/, *nd_hmax = nullptr;
+    struct dzs_node_rec *nd_rec = nullptr;  // moments and topology as the walk reads them
     uint32_t *frontier = nullptr, *frontier_next = nullptr;
     uint32_t *fr_nchild = nullptr, *fr_ninternal = nullptr, *fr_child_off = nullptr,
              *fr_int_off = nullptr;

@@ -194,14 +194,20 @@ __device__ __forceinline__ double mult_cbrt(uint32_t mult) {
     return mult == 1u ? 1.0 : cbrt((double)mult);
 }
 
+// Half extent of [mn, mx] about c, as an FP32 value rounded up: the box c +- h holds both ends.
+__device__ __forceinline__ float half_up(double mn, double mx, double c) {
+    return __double2float_ru(fmax(mx - c, c - mn));
+}
+
 // Moments of node v (mass, centre of mass, particle bounding box, largest softening): of its
-// particles for a leaf, of its children (already complete) otherwise.
+// particles for a leaf, of its children (already complete) otherwise; written with the
+// node's topology into its walk record.
 __device__ __forceinline__ void node_moments(
-    uint32_t v, uint64_t cap, const double *__restrict__ x, const double *__restrict__ y,
+    uint32_t v, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const uint32_t *__restrict__ mult, double m0, double h0,
     const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild,
-    double *nd_mass, double *nd_com, double *nd_bmin, double *nd_bmax, double *nd_hmax,
+    const uint8_t *__restrict__ nd_level, dzs_node_rec *__restrict__ rec,
     const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes) {
     if (boxes && nd_nchild[v] == 0) {
         // a batch: the leaf's box (its key prefix) sets the mass unit and the softening
@@ -231,42 +237,53 @@ __device__ __forceinline__ void node_moments(
     } else {
         const uint32_t c0 = nd_child[v];
         for (uint32_t c = c0; c < c0 + nc; ++c) {
-            const double mc = nd_mass[c];
+            const dzs_node_rec &r = rec[c];
+            const double mc = r.mass;
             m += mc;
-            sx += mc * nd_com[c];
-            sy += mc * nd_com[cap + c];
-            sz += mc * nd_com[2 * cap + c];
-            mnx = fmin(mnx, nd_bmin[c]); mny = fmin(mny, nd_bmin[cap + c]);
-            mnz = fmin(mnz, nd_bmin[2 * cap + c]);
-            mxx = fmax(mxx, nd_bmax[c]); mxy = fmax(mxy, nd_bmax[cap + c]);
-            mxz = fmax(mxz, nd_bmax[2 * cap + c]);
-            hmax = fmax(hmax, nd_hmax[c]);
+            sx += mc * r.comx;
+            sy += mc * r.comy;
+            sz += mc * r.comz;
+            mnx = fmin(mnx, r.cx - (double)r.hx); mny = fmin(mny, r.cy - (double)r.hy);
+            mnz = fmin(mnz, r.cz - (double)r.hz);
+            mxx = fmax(mxx, r.cx + (double)r.hx); mxy = fmax(mxy, r.cy + (double)r.hy);
+            mxz = fmax(mxz, r.cz + (double)r.hz);
+            hmax = fmax(hmax, r.hmax);
         }
     }
-    nd_mass[v] = m;
-    nd_com[v] = sx / m;
-    nd_com[cap + v] = sy / m;
-    nd_com[2 * cap + v] = sz / m;
-    nd_bmin[v] = mnx; nd_bmin[cap + v] = mny; nd_bmin[2 * cap + v] = mnz;
-    nd_bmax[v] = mxx; nd_bmax[cap + v] = mxy; nd_bmax[2 * cap + v] = mxz;
-    nd_hmax[v] = hmax;
+    dzs_node_rec out;
+    out.cx = 0.5 * (mnx + mxx);
+    out.cy = 0.5 * (mny + mxy);
+    out.cz = 0.5 * (mnz + mxz);
+    out.comx = sx / m;
+    out.comy = sy / m;
+    out.comz = sz / m;
+    out.mass = m;
+    out.hmax = hmax;
+    out.hx = half_up(mnx, mxx, out.cx);
+    out.hy = half_up(mny, mxy, out.cy);
+    out.hz = half_up(mnz, mxz, out.cz);
+    out.first = nd_first[v];
+    out.count = nd_count[v];
+    out.child = nd_child[v];
+    out.nl = nc | ((uint32_t)nd_level[v] << 8);
+    out.pad = 0u;
+    rec[v] = out;
 }
 
 // Moments of the nodes of level k, [level_start[k], level_start[k+1]) read on the device;
 // levels run bottom-up, so the children of every node are complete before it.
 __global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
-    const uint32_t *__restrict__ bs, int k, uint64_t cap, const double *__restrict__ x,
+    const uint32_t *__restrict__ bs, int k, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const uint32_t *__restrict__ mult,
     double m0, double h0, const uint32_t *__restrict__ nd_first,
     const uint32_t *__restrict__ nd_count, const uint32_t *__restrict__ nd_child,
-    const uint8_t *__restrict__ nd_nchild, double *nd_mass, double *nd_com, double *nd_bmin,
-    double *nd_bmax, double *nd_hmax, const uint64_t *__restrict__ key,
-    const dzs_bbox *__restrict__ boxes) {
+    const uint8_t *__restrict__ nd_nchild, const uint8_t *__restrict__ nd_level,
+    dzs_node_rec *rec, const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes) {
     const uint32_t end = bs[BS_LEVEL + k + 1];
     for (uint32_t v = bs[BS_LEVEL + k] + blockIdx.x * TB_THREADS + threadIdx.x; v < end;
          v += gridDim.x * TB_THREADS)
-        node_moments(v, cap, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild,
-                     nd_mass, nd_com, nd_bmin, nd_bmax, nd_hmax, key, boxes);
+        node_moments(v, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild, nd_level,
+                     rec, key, boxes);
 }
 
 // Target groups: each node with more than G particles packs its consecutive children that
@@ -410,11 +427,10 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
                 ub = 1ull << (3 * k);
             uint32_t nbk = blocks_for(ub, TB_THREADS);
             nbk = nbk < 8192u ? nbk : 8192u;   // grid-stride beyond
-            hipLaunchKernelGGL(k_tree_moments, dim3(nbk), dim3(TB_THREADS),
-                               0, s, (const uint32_t *)bs, k, cap, x, y, z, mult, box->m0,
-                               2.8 * box->eps0, ctx->nd_first, ctx->nd_count, ctx->nd_child,
-                               ctx->nd_nchild, ctx->nd_mass, ctx->nd_com, ctx->nd_bmin,
-                               ctx->nd_bmax, ctx->nd_hmax, (const uint64_t *)ctx->key, boxes);
+            hipLaunchKernelGGL(k_tree_moments, dim3(nbk), dim3(TB_THREADS), 0, s,
+                               (const uint32_t *)bs, k, x, y, z, mult, box->m0, 2.8 * box->eps0,
+                               ctx->nd_first, ctx->nd_count, ctx->nd_child, ctx->nd_nchild,
+                               ctx->nd_level, ctx->nd_rec, (const uint64_t *)ctx->key, boxes);
             DZS_TRY(dzs_check_launch(ctx, "tree_moments"));
         }
     }
@@ -541,10 +557,7 @@ struct walk_args {
     const uint32_t *n_groups;   // device: the build's group count
     const double *x, *y, *z;
     const uint32_t *mult;
-    const uint32_t *nd_first, *nd_count, *nd_child;
-    const uint8_t *nd_nchild, *nd_level;
-    const double *nd_mass, *nd_com, *nd_bmin, *nd_bmax, *nd_hmax;
-    uint64_t cap;
+    const dzs_node_rec *rec;  // the nodes as the walk reads them
     double L, halfL, rcut2, rcut, theta2, rs_inv, rs_inv2, G, m0, h0, t_scale;
     double *gx, *gy, *gz;
     int accumulate;
@@ -661,11 +674,22 @@ template <typename T> __device__ __forceinline__ T gsoft_inner(T r, T h) {
                  T(1.0) / (T(15.0) * u * u * u));
 }
 
-// One interaction-list entry in LDS: position (shifted to the image nearest the group; in
-// FP32 relative to the group centre), mass, spline support and its square.
+// One interaction-list entry in LDS: pm = position (shifted to the image nearest the group;
+// in FP32 relative to the group centre) and mass; hh = (hm2, h): the entry's spline support h
+// and hm2 = max(h^2, the largest h_i^2 of the group's targets), an upper bound of the pair's
+// squared support that decides, with one comparison, whether the exact spline test is
+// needed.  FP32: 32 bytes, one 16-byte read for pm and one 4-byte read for hm2.
+template <typename T> struct vec4_of;
+template <> struct vec4_of<float> { typedef float4 type; typedef float2 half; };
+struct dvec4 { double x, y, z, w; };   // 8-byte aligned: a 48-byte FP64 entry
+struct dvec2 { double x, y; };
+template <> struct vec4_of<double> { typedef dvec4 type; typedef dvec2 half; };
 template <typename T> struct src_entry {
-    T x, y, z, m;
-    T h, h2;
+    typename vec4_of<T>::type pm;
+    typename vec4_of<T>::half hh;
+};
+template <typename T> struct src_list {
+    src_entry<T> *e;
 };
 
 template <typename T> struct split_coef;
@@ -692,9 +716,9 @@ __device__ __forceinline__ float pair_hmax(float a, float b) {
 }
 
 // Separation of a list entry from the target (minimum image for wide groups).
-template <typename T, bool MINIMG>
-__device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T L, T &dx,
-                                      T &dy, T &dz) {
+template <typename T, bool MINIMG, typename E>
+__device__ __forceinline__ T pair_sep(const E &e, T xi, T yi, T zi, T L, T &dx, T &dy,
+                                      T &dz) {
     dx = e.x - xi;
     dy = e.y - yi;
     dz = e.z - zi;
@@ -710,7 +734,7 @@ __device__ __forceinline__ T pair_sep(const src_entry<T> &e, T xi, T yi, T zi, T
 // S = 1 - u^3 q(u^2), u = r/r_s; outside the spline support g_soft = r^-3 and the product is
 // r^-3 - r_s^-3 q, one fused operation.  (FP64; the FP32 form is pair_factor_tab.)
 template <typename T>
-__device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T eh2, T hi, T hi2,
+__device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T hm2, T hi, T hi2,
                                          T rs_inv2, T rs_inv3, T t_scale) {
     constexpr int QN = split_coef<T>::N;
     const T rinv = pair_rsqrt(r2);
@@ -721,13 +745,11 @@ __device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T eh2, 
     for (int c = QN - 2; c >= 0; --c)
         q = wfma(q, t, split_coef<T>::at(A, c));
     const T rq = rs_inv3 * q;
-    T g;
-    if (r2 < pair_hmax(eh2, hi2)) {
+    T g = wfma(rinv * rinv, rinv, -rq);
+    if (r2 < hm2 && r2 < pair_hmax(eh * eh, hi2)) {
         const T r = r2 * rinv;
         const T ks = gsoft_inner(r, wmax(eh, hi));
         g = ks - ks * (r2 * r) * rq;
-    } else {
-        g = wfma(rinv * rinv, rinv, -rq);
     }
     return g;
 }
@@ -735,37 +757,47 @@ __device__ __forceinline__ T pair_factor(const walk_args &A, T r2, T eh, T eh2, 
 // FP32 pair force factor g_soft(r) S(r/r_s) with S from the LDS table: x = u WALK_TAB_N /
 // u_cut = r tscale, interval k = floor(x) (at most WALK_TAB_N, the entry past the cutoff), the
 // cubic at f = x - k.  r2 = 0 (the target itself) gives a finite g: its separation is zero.
+//
+// x in [WALK_TAB_N, ...) (r at or past r_cut: only a pair within rounding of the cutoff is
+// kept) takes the last entry at the fraction of x, a linear continuation from S(r_cut).
+// r2 = 0 (the target itself) makes g NaN: the caller masks the pair out by r2 > 0.
 __device__ __forceinline__ float pair_factor_tab(const float4 *__restrict__ tab, float r2,
-                                                float eh, float eh2, float hi, float hi2,
-                                                float tscale) {
-    const float rinv = pair_rsqrt(fmaxf(r2, 1e-30f));
+                                                float hm2, const float *eh_ptr, float hi,
+                                                float hi2, float tscale) {
+    const float rinv = pair_rsqrt(r2);
     const float r = r2 * rinv;
     const float x = r * tscale;
     uint32_t k = (uint32_t)x;
     k = k < (uint32_t)WALK_TAB_N ? k : (uint32_t)WALK_TAB_N;
-    const float f = x - (float)k;
+    const float f = __builtin_amdgcn_fractf(x);
     const float4 c = tab[k];
     const float S = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(c.w, f, c.z), f, c.y), f, c.x);
-    if (r2 < pair_hmax(eh2, hi2))
-        return gsoft_inner(r, fmaxf(eh, hi)) * S;
-    return (rinv * rinv) * (rinv * S);
+    float g = (rinv * rinv) * (rinv * S);
+    if (r2 < hm2) {  // rare: the exact spline test
+        const float eh = *eh_ptr;
+        if (r2 < pair_hmax(eh * eh, hi2))
+            g = gsoft_inner(r, fmaxf(eh, hi)) * S;
+    }
+    return g;
 }
 
 template <typename T> struct pair_eval;
 template <> struct pair_eval<double> {
     const walk_args *A;
     double rs_inv2, rs_inv3, t_scale;
-    __device__ __forceinline__ double operator()(double r2, double eh, double eh2, double hi,
+    // hh: the entry's (hm2, h)
+    __device__ __forceinline__ double operator()(double r2, const dvec2 *hh, double hi,
                                                  double hi2) const {
-        return pair_factor<double>(*A, r2, eh, eh2, hi, hi2, rs_inv2, rs_inv3, t_scale);
+        const dvec2 v = *hh;
+        return pair_factor<double>(*A, r2, v.y, v.x, hi, hi2, rs_inv2, rs_inv3, t_scale);
     }
 };
 template <> struct pair_eval<float> {
     const float4 *tab;
     float tscale;
-    __device__ __forceinline__ float operator()(float r2, float eh, float eh2, float hi,
+    __device__ __forceinline__ float operator()(float r2, const float2 *hh, float hi,
                                                 float hi2) const {
-        return pair_factor_tab(tab, r2, eh, eh2, hi, hi2, tscale);
+        return pair_factor_tab(tab, r2, hh->x, &hh->y, hi, hi2, tscale);
     }
 };
 
@@ -778,20 +810,20 @@ template <> struct pair_eval<float> {
 // fills the P entries past the list with far-away sentinels, so the block bound is uniform.
 template <typename T, bool MINIMG>
 __device__ __forceinline__ void pair_loop(const pair_eval<T> &ev, const walk_geom &W,
-                                          const src_entry<T> *src, uint32_t nlist, uint32_t s,
+                                          const src_list<T> src, uint32_t nlist, uint32_t s,
                                           uint32_t P, T xi, T yi, T zi, T hi, T hi2, T &ax,
                                           T &ay, T &az, uint32_t &n_pairs) {
     const T rcut2 = T(W.rcut2), L = T(W.L);
     // entries per lane: uniform, so the block loops run on the scalar unit
     const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
     for (uint32_t kb = 0; kb < n_max; kb += 32u) {
-        const src_entry<T> *blk = src + s + kb * P;
+        const uint32_t blk = s + kb * P;
         const uint32_t kmax =
             (uint32_t)__builtin_amdgcn_readfirstlane((int)(n_max - kb < 32u ? n_max - kb : 32u));
         uint32_t mask = 0;
         for (uint32_t k = 0; k < kmax; ++k) {
             T dx, dy, dz;
-            const T r2 = pair_sep<T, MINIMG>(blk[k * P], xi, yi, zi, L, dx, dy, dz);
+            const T r2 = pair_sep<T, MINIMG>(src.e[blk + k * P].pm, xi, yi, zi, L, dx, dy, dz);
             mask = mask + mask + ((r2 < rcut2 && r2 > T(0.0)) ? 1u : 0u);
         }
         mask <<= 32u - kmax;
@@ -799,10 +831,10 @@ __device__ __forceinline__ void pair_loop(const pair_eval<T> &ev, const walk_geo
         while (mask) {
             const uint32_t k = (uint32_t)__builtin_clz(mask);
             mask ^= 0x80000000u >> k;
-            const src_entry<T> &e = blk[k * P];
+            const auto e = src.e[blk + k * P].pm;
             T dx, dy, dz;
             const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
-            const T f = e.m * ev(r2, e.h, e.h2, hi, hi2);
+            const T f = e.w * ev(r2, &src.e[blk + k * P].hh, hi, hi2);
             ax = wfma(f, dx, ax);
             ay = wfma(f, dy, ay);
             az = wfma(f, dz, az);
@@ -814,37 +846,51 @@ __device__ __forceinline__ void pair_loop(const pair_eval<T> &ev, const walk_geo
 // r_cut (and the target itself) are multiplied by zero.  All lanes of a phase read the same
 // entry and every lane works on every iteration, so when most of the list lies inside most
 // targets' cutoff spheres (a compact group) this costs less than the masked two-pass loop.
+// 0 < r2 < rcut2: in FP32 one unsigned comparison of the bit patterns (r2 is a sum of
+// squares: +0, positive, or +inf for the far sentinels), so the result is a single mask
+__device__ __forceinline__ bool pair_inside(float r2, float rcut2) {
+    return __float_as_uint(r2) - 1u < __float_as_uint(rcut2) - 1u;
+}
+__device__ __forceinline__ bool pair_inside(double r2, double rcut2) {
+    return r2 < rcut2 && r2 > 0.0;
+}
+
 template <typename T, bool MINIMG>
 __device__ __forceinline__ void pair_dense(const pair_eval<T> &ev, const walk_geom &W,
-                                           const src_entry<T> *src, uint32_t nlist, uint32_t s,
+                                           const src_list<T> src, uint32_t nlist, uint32_t s,
                                            uint32_t P, T xi, T yi, T zi, T hi, T hi2, T &ax,
-                                           T &ay, T &az, uint32_t &n_pairs) {
+                                           T &ay, T &az, uint64_t act_mask, uint32_t &np_wave) {
     const T rcut2 = T(W.rcut2), L = T(W.L);
     const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
     for (uint32_t k = 0; k < n_max; ++k) {
-        const src_entry<T> &e = src[s + k * P];
+        const src_entry<T> *q = src.e + s + k * P;
+        const auto e = q->pm;
         T dx, dy, dz;
         const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
-        const bool in = r2 < rcut2 && r2 > T(0.0);
-        const T g = ev(r2, e.h, e.h2, hi, hi2);
+        const bool in = pair_inside(r2, rcut2);
+        // pairs of the flagged targets, counted on the scalar unit
+        np_wave += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & act_mask);
+        const T g = ev(r2, &q->hh, hi, hi2);
         // the factor of a pair outside (or of the target itself: r = 0) is not used
-        const T f = in ? e.m * g : T(0.0);
+        const T f = in ? e.w * g : T(0.0);
         ax = wfma(f, dx, ax);
         ay = wfma(f, dy, ay);
         az = wfma(f, dz, az);
-        n_pairs += in ? 1u : 0u;
     }
 }
 
+// one wave per workgroup; the FP32 walk fits 4 waves per SIMD (128 VGPRs), the FP64 one 3
 template <typename T, bool CELLS, bool BATCH>
-__global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_args A) {
     static_assert(!(CELLS && BATCH), "a batch walk starts at the box nodes");
     constexpr int KBL = BATCH ? DZS_BATCH_LEVELS : 0;  // tree levels above a box
-    __shared__ src_entry<T> src[WALK_LIST + 64];
+    __shared__ src_entry<T> s_list[WALK_LIST + 64];
+    const src_list<T> src{s_list};
     __shared__ uint32_t q_first[64];
     __shared__ uint32_t q_pref[65];
     __shared__ double q_shift[3][64];
     __shared__ uint32_t q_wide[64];
+    __shared__ uint32_t q_mark[64];
     __shared__ uint32_t s_g;
     __shared__ float4 s_tab[sizeof(T) == 4 ? WALK_TAB_N + 1 : 1];
 
@@ -926,6 +972,11 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         const double ox = rel ? gcx : 0.0, oy = rel ? gcy : 0.0, oz = rel ? gcz : 0.0;
         const T txi = T(xi - ox), tyi = T(yi - oy), tzi = T(zi - oz), thi = T(hi);
         const T thi2 = thi * thi;
+        // the largest squared support among the group's targets (the bound stored as hm2)
+        T hg2 = valid ? thi2 : T(0.0);
+        for (int o = 32; o >= 1; o >>= 1)
+            hg2 = wmax(hg2, (T)__shfl_xor(hg2, o, 64));
+        const uint64_t act_mask = __ballot(active);
 
         pair_eval<T> ev;
         if constexpr (sizeof(T) == 4) {
@@ -939,23 +990,23 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
         }
         T ax = T(0.0), ay = T(0.0), az = T(0.0);
         uint32_t nlist = 0;
-        uint32_t n_pairs = 0;
+        uint32_t n_pairs = 0;   // per lane (the masked loop)
+        uint32_t np_wave = 0;   // the wave's (the dense loop)
         bool wide = false;
 
         auto flush = [&]() {
             if (lane < P) {  // sentinels: far outside every cutoff, in any image
-                src_entry<T> &e = src[nlist + lane];
-                e.x = e.y = e.z = T(1e30);
-                e.m = e.h = e.h2 = T(0.0);
+                src.e[nlist + lane].pm = {T(1e30), T(1e30), T(1e30), T(0.0)};
+                src.e[nlist + lane].hh = {T(0.0), T(0.0)};
             }
             __syncthreads();
             if (dense) {
                 if (wide)
                     pair_dense<T, true>(ev, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
-                                        ay, az, n_pairs);
+                                        ay, az, act_mask, np_wave);
                 else
                     pair_dense<T, false>(ev, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax,
-                                         ay, az, n_pairs);
+                                         ay, az, act_mask, np_wave);
             } else if (wide) {
                 pair_loop<T, true>(ev, W, src, nlist, ph, P, txi, tyi, tzi, thi, thi2, ax, ay,
                                    az, n_pairs);
@@ -1034,28 +1085,26 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             int act = 0;
             double shx = 0.0, shy = 0.0, shz = 0.0;
             uint32_t ncount = 0, nchild = 0, child = 0, nfirst = 0;
-            double comx = 0.0, comy = 0.0, comz = 0.0;
+            double comx = 0.0, comy = 0.0, comz = 0.0, nmass = 0.0, nhmax = 0.0;
             bool node_wide = false;
             if (has) {
-                const uint64_t c = A.cap;
-                // every field the classification may need, in one round of loads
-                const double bnx = A.nd_bmin[node], bny = A.nd_bmin[c + node], bnz = A.nd_bmin[2 * c + node];
-                const double bxx = A.nd_bmax[node], bxy = A.nd_bmax[c + node], bxz = A.nd_bmax[2 * c + node];
-                comx = A.nd_com[node];
-                comy = A.nd_com[c + node];
-                comz = A.nd_com[2 * c + node];
-                const int nlev = A.nd_level[node];
-                nchild = A.nd_nchild[node];
-                ncount = A.nd_count[node];
-                nfirst = A.nd_first[node];
-                child = A.nd_child[node];
-                double dcx = 0.5 * (bnx + bxx) - gcx, dcy = 0.5 * (bny + bxy) - gcy,
-                       dcz = 0.5 * (bnz + bxz) - gcz;
+                // the node's record: one address, the fields read where they are needed
+                const dzs_node_rec &nd = A.rec[node];
+                comx = nd.comx;
+                comy = nd.comy;
+                comz = nd.comz;
+                const uint32_t nl = nd.nl;
+                const int nlev = (int)(nl >> 8);
+                nchild = nl & 0xffu;
+                ncount = nd.count;
+                nfirst = nd.first;
+                child = nd.child;
+                double dcx = nd.cx - gcx, dcy = nd.cy - gcy, dcz = nd.cz - gcz;
                 shx = dcx > W.halfL ? -W.L : (dcx < -W.halfL ? W.L : 0.0);
                 shy = dcy > W.halfL ? -W.L : (dcy < -W.halfL ? W.L : 0.0);
                 shz = dcz > W.halfL ? -W.L : (dcz < -W.halfL ? W.L : 0.0);
                 dcx += shx; dcy += shy; dcz += shz;
-                const double nhx = 0.5 * (bxx - bnx), nhy = 0.5 * (bxy - bny), nhz = 0.5 * (bxz - bnz);
+                const double nhx = nd.hx, nhy = nd.hy, nhz = nd.hz;
                 const double gx_ = fmax(0.0, fabs(dcx) - nhx - ghx);
                 const double gy_ = fmax(0.0, fabs(dcy) - nhy - ghy);
                 const double gz_ = fmax(0.0, fabs(dcz) - nhz - ghz);
@@ -1078,10 +1127,14 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                         const double side = ldexp(W.L, -(nlev - KBL));
                         if (A.aold) {
                             // G M l^2 < alpha a_min d^4
-                            if (A.nd_mass[node] * (side * side) < alpha_a * (d2 * d2))
+                            if (nd.mass * (side * side) < alpha_a * (d2 * d2))
                                 act = 2;
                         } else if (side * side < A.theta2 * d2) {
                             act = 2;
+                        }
+                        if (act == 2) {
+                            nmass = nd.mass;
+                            nhmax = nd.hmax;
                         }
                     }
                 }
@@ -1108,13 +1161,10 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                     flush();
                 if (act == 2) {
                     const uint32_t slot = nlist + (uint32_t)__popcll(mono & lt_mask);
-                    src[slot].x = T(comx + shx - ox);
-                    src[slot].y = T(comy + shy - oy);
-                    src[slot].z = T(comz + shz - oz);
-                    src[slot].m = T(A.nd_mass[node]);
-                    const T hn = T(A.nd_hmax[node]);
-                    src[slot].h = hn;
-                    src[slot].h2 = hn * hn;
+                    src.e[slot].pm = {T(comx + shx - ox), T(comy + shy - oy),
+                                      T(comz + shz - oz), T(nmass)};
+                    const T hn = T(nhmax);
+                    src.e[slot].hh = {wmax(hn * hn, hg2), hn};
                 }
                 nlist += nmono;
             }
@@ -1139,20 +1189,34 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                 if (lane == 0)
                     q_pref[nq] = Ptot;
                 __syncthreads();
+                // candidate f of a pass belongs to the last leaf starting at or before it: each
+                // leaf marks its start in the pass's window, a wave max-scan spreads the marks
+                // (the leaf of the window's first slot carries over from the pass before)
+                const uint32_t lstart = lincl - lc;
+                const uint32_t lq = (uint32_t)__popcll(lmask & lt_mask);
+                uint32_t carry = 0;
                 for (uint32_t done = 0; done < Ptot; done += 64) {
                     const uint32_t f = done + lane;
+                    q_mark[lane] = 0u;
+                    __syncthreads();
+                    if (act == 1 && lstart >= done && lstart - done < 64u)
+                        q_mark[lstart - done] = lq + 1u;
+                    __syncthreads();
+                    uint32_t v = q_mark[lane];
+                    if (lane == 0)
+                        v = v > carry + 1u ? v : carry + 1u;
+#pragma unroll
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const uint32_t t = __shfl_up(v, d, 64);
+                        if (lane >= (uint32_t)d)
+                            v = v > t ? v : t;
+                    }
+                    const uint32_t lo = v - 1u;
+                    carry = __shfl(lo, 63, 64);
                     bool keep = false;
                     double ex_ = 0.0, ey_ = 0.0, ez_ = 0.0;
                     uint32_t mj = 0;
                     if (f < Ptot) {
-                        uint32_t lo = 0, hi2 = nq - 1;
-                        while (lo < hi2) {
-                            uint32_t mid = (lo + hi2 + 1) >> 1;
-                            if (q_pref[mid] <= f)
-                                lo = mid;
-                            else
-                                hi2 = mid - 1;
-                        }
                         const uint32_t j = q_first[lo] + (f - q_pref[lo]);
                         ex_ = A.x[j] + q_shift[0][lo];
                         ey_ = A.y[j] + q_shift[1][lo];
@@ -1169,15 +1233,12 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
                         if (nlist + nk > WALK_LIST)
                             flush();
                         if (keep) {
-                            src_entry<T> &e = src[nlist + (uint32_t)__popcll(kmask & lt_mask)];
+                            const uint32_t slot = nlist + (uint32_t)__popcll(kmask & lt_mask);
                             const double md = (double)mj;
-                            e.x = T(ex_ - ox);
-                            e.y = T(ey_ - oy);
-                            e.z = T(ez_ - oz);
-                            e.m = T(W.m0 * md);
+                            src.e[slot].pm = {T(ex_ - ox), T(ey_ - oy), T(ez_ - oz),
+                                              T(W.m0 * md)};
                             const T hj = T(W.h0 * mult_cbrt(mj));
-                            e.h = hj;
-                            e.h2 = hj * hj;
+                            src.e[slot].hh = {wmax(hj * hj, hg2), hj};
                         }
                         nlist += nk;
                     }
@@ -1201,7 +1262,7 @@ __global__ __launch_bounds__(64) void k_tree_walk(walk_args A) {
             for (int o = 32; o >= 1; o >>= 1)
                 cnt_pairs += __shfl_xor(cnt_pairs, o, 64);
             if (lane == 0)
-                atomicAdd(A.pair_count, (unsigned long long)cnt_pairs);
+                atomicAdd(A.pair_count, (unsigned long long)(cnt_pairs + np_wave));
         }
         if (active && ph == 0) {
             const double gxv = W.Gc * (double)ax, gyv = W.Gc * (double)ay, gzv = W.Gc * (double)az;
@@ -1358,11 +1419,7 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.grp_first = ctx->grp_first;
     A.n_groups = ctx->bstate + BS_GROUPS;
     A.x = x; A.y = y; A.z = z; A.mult = mult;
-    A.nd_first = ctx->nd_first; A.nd_count = ctx->nd_count; A.nd_child = ctx->nd_child;
-    A.nd_nchild = ctx->nd_nchild; A.nd_level = ctx->nd_level;
-    A.nd_mass = ctx->nd_mass; A.nd_com = ctx->nd_com; A.nd_bmin = ctx->nd_bmin;
-    A.nd_bmax = ctx->nd_bmax; A.nd_hmax = ctx->nd_hmax;
-    A.cap = ctx->cap_nodes;
+    A.rec = ctx->nd_rec;
     A.L = box->L;
     A.halfL = 0.5 * box->L;
     A.rcut = prm->r_cut;
