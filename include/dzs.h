@@ -356,6 +356,21 @@ dzs_status dzs_coarsen(dzs_ctx *ctx, const dzs_box *box, dzs_particles *inout,
 dzs_status pm_force(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                     const dzs_pm_params *prm, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pm_force with its meshes in a static
+ * device array of the library instead of a context, so no call allocates anything.  The
+ * array holds meshes of up to DZS_PM_NOALLOC_MAX_SIDE points per side (32 bytes per cell plus
+ * the per-axis tables: 8 MiB + 2 KiB), one copy per GPU the library runs on, held until the
+ * process ends; a larger mesh side fails with DZS_ECAPACITY.  Arguments, results (the same
+ * bits as pm_force) and the other errors are those of pm_force; no context means no error
+ * text.  The first call on a device looks up that device's copy; a call with new mesh
+ * parameters uploads the mesh tables and synchronises the stream, as pm_force does.  Every
+ * call on a GPU shares that GPU's array (the density is cleared by each call), so calls that
+ * overlap on one GPU (two streams, two host threads) race. */
+#define DZS_PM_NOALLOC_MAX_SIDE 64
+dzs_status pm_force_noalloc(const dzs_box *box, const dzs_particles *p,
+                            const dzs_pm_params *prm, void *stream);
+
 /* Tree short-range acceleration into g (or added to g) of the targets: targets (device,
  * n_targets indices into the particle arrays, each below n and listed once) or every particle
  * when targets is NULL; the other entries of g are not touched.  Every particle is a source.

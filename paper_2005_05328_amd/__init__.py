@@ -27,7 +27,7 @@ __all__ = ["Context", "State", "Box", "CoarsenParams", "PMParams", "TreeParams",
            "DZS_CRIT_GEOMETRIC", "DZS_CRIT_DYNAMICAL", "DZS_OPEN_GEOMETRIC",
            "DZS_OPEN_RELATIVE", "DZS_PM_CHUNK_MIN", "DZS_PM_CHUNK_MAX",
            "DZS_PM_CHUNK_DEFAULT", "halt_check", "forecast_speedup",
-           "lib"]
+           "pm_force_noalloc", "lib"]
 
 
 def lib():
@@ -157,6 +157,15 @@ def forecast_speedup(L: float, n_part: float, omega_m: float = 0.3) -> _abi.Fore
     if rc != 0:
         raise DZSError("dzs_forecast_speedup", rc, "no a_DZS in [1e-4, 1] or bad argument")
     return out
+
+
+def pm_force_noalloc(box: Box, st: "State", prm: PMParams, stream=None):
+    """pm_force without a context or any device allocation: the meshes live in the library's
+    static per-device array (mesh sides up to DZS_PM_NOALLOC_MAX_SIDE)."""
+    v = st.view()
+    rc = _lib.pm_force_noalloc(C.byref(box), C.byref(v), C.byref(prm), _stream_handle(stream))
+    if rc != 0:
+        raise DZSError("pm_force_noalloc", rc, "see include/dzs.h (no context, no error text)")
 
 
 def step_factors(a0: float, a1: float, omega_m: float = 0.3) -> StepParams:

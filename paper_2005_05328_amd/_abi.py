@@ -23,11 +23,12 @@ EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_fact
            "dzs_coarsen", "pm_force", "tree_force", "lightcone_emit", "kdk_step",
            "kdk_step_batch", "kdk_step_batch_stage", "dzs_check", "dzs_morton_keys",
            "dzs_sort_state", "dzs_counters", "dzs_timing", "dzs_halt_check",
-           "dzs_forecast_speedup", "kdk_step_hier", "dzs_source_hash")
+           "dzs_forecast_speedup", "kdk_step_hier", "dzs_source_hash", "pm_force_noalloc")
 DZS_HIER_MAX_BIN = 6
 DZS_HALT_BALANCE, DZS_HALT_RATIO, DZS_HALT_PREDICTED = 1, 2, 4
 DZS_BATCH_MAX = 512
 DZS_PM_CHUNK_MIN, DZS_PM_CHUNK_MAX, DZS_PM_CHUNK_DEFAULT = 256, 16384, 256
+DZS_PM_NOALLOC_MAX_SIDE = 64
 
 
 class HierParams(C.Structure):
@@ -163,6 +164,8 @@ def load():
     L.dzs_coarsen.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(CoarsenParams),
                               P, C.POINTER(CoarsenReport), P]
     L.pm_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(PMParams), P]
+    L.pm_force_noalloc.argtypes = [C.POINTER(Box), C.POINTER(Particles), C.POINTER(PMParams), P]
+    L.pm_force_noalloc.restype = st
     L.tree_force.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(TreeParams), P,
                              C.c_uint64, P]
     L.lightcone_emit.argtypes = [P, C.POINTER(Box), C.POINTER(Particles), C.POINTER(LCParams),

@@ -596,6 +596,63 @@ extern "C" dzs_status tree_force(dzs_ctx *ctx, const dzs_box *box, const dzs_par
     return dzs_latch_bad_input(ctx, s);
 }
 
+// ---------------------------------------------------------------------------------------
+// PM force without any allocation: the meshes in a static device array of the library
+// ---------------------------------------------------------------------------------------
+#define NOALLOC_CELLS ((uint64_t)DZS_PM_NOALLOC_MAX_SIDE * DZS_PM_NOALLOC_MAX_SIDE * \
+                       DZS_PM_NOALLOC_MAX_SIDE)
+#define NOALLOC_DEVICES 64
+// fixed-point density (8 B/cell), complex work mesh (16), potential (8), per-axis tables
+static __device__ __align__(256) unsigned char
+    scratch[32 * NOALLOC_CELLS + 4 * sizeof(double) * DZS_PM_NOALLOC_MAX_SIDE];
+
+// Per device: a context shell whose meshes point into that device's copy of scratch.
+struct noalloc_pm {
+    bool ready = false;
+    dzs_ctx shell;
+    double host_tab[4 * DZS_PM_NOALLOC_MAX_SIDE];
+};
+static noalloc_pm g_noalloc[NOALLOC_DEVICES];
+
+extern "C" dzs_status pm_force_noalloc(const dzs_box *box, const dzs_particles *p,
+                                       const dzs_pm_params *prm, void *stream) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return DZS_EHIP;
+    }
+    if (dev < 0 || dev >= NOALLOC_DEVICES)
+        return DZS_EINVAL;
+    noalloc_pm &S = g_noalloc[dev];
+    if (!S.ready) {
+        // the device's own copy of the array: its address, looked up once with that device
+        // current (the array's name is a host-side stand-in, not a device address)
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return DZS_EHIP;
+        }
+        char *base = (char *)ptr;
+        dzs_ctx &c = S.shell;
+        c.device = dev;
+        c.cap_n = ~0ull >> 1;  // the PM keeps no per-particle scratch
+        c.cap_ng = DZS_PM_NOALLOC_MAX_SIDE;
+        c.mesh_q = (long long *)base;
+        c.mesh_c = (double2 *)(base + 8 * NOALLOC_CELLS);
+        c.mesh_phi = (double *)(base + 24 * NOALLOC_CELLS);
+        c.pm_tables = (double *)(base + 32 * NOALLOC_CELLS);
+        c.pm_host_tab = S.host_tab;
+        S.ready = true;
+    }
+    dzs_ctx *ctx = &S.shell;
+    DZS_TRY(check_common(ctx, box, p));
+    DZS_TRY(check_pm(ctx, prm));
+    if (p->n > 0 && (!p->gx || !p->gy || !p->gz))
+        return dzs_fail(ctx, DZS_EINVAL, "null acceleration array");
+    return dzs_pm_run(ctx, box, p, prm, (hipStream_t)stream);
+}
+
 extern "C" dzs_status lightcone_emit(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,
                                      const dzs_lc_params *prm, dzs_lc_ring *ring, void *stream) {
     DZS_TRY(check_common(ctx, box, p));

@@ -176,6 +176,7 @@ struct dzs_ctx {
     double2 *mesh_c = nullptr;    // complex work mesh, ng^3
     double *mesh_phi = nullptr;   // real potential, ng^3
     double *pm_tables = nullptr;  // per-axis tables (twiddles, Green factors)
+    double *pm_host_tab = nullptr;  // host staging of those tables (null: a temporary)
     int pm_tab_ng = 0;
     double pm_tab_L = 0.0, pm_tab_rs = 0.0;
 

@@ -758,7 +758,10 @@ bool dzs_pm_mesh_ok(int ng) {
 
 // tables at ctx->pm_tables: [0, 2n) twiddles (double2), [2n, 3n) gt, [3n, 4n) k^2
 static dzs_status upload_tables(dzs_ctx *ctx, int ng, double L, double r_s, hipStream_t s) {
-    std::vector<double> h(4 * (size_t)ng);
+    // staged in the context's host table when it has one (the allocation-free entry point),
+    // else in a temporary
+    std::vector<double> tmp(ctx->pm_host_tab ? 0 : 4 * (size_t)ng);
+    double *h = ctx->pm_host_tab ? ctx->pm_host_tab : tmp.data();
     const long double pi = 3.14159265358979323846264338327950288L;
     for (int m = 0; m < ng; ++m) {
         long double ang = -2.0L * pi * m / ng;
@@ -775,7 +778,7 @@ static dzs_status upload_tables(dzs_ctx *ctx, int ng, double L, double r_s, hipS
         h[2 * ng + m] = (double)(expl(-k * k * (long double)r_s * r_s) / w2);
         h[3 * ng + m] = (double)(k * k);
     }
-    DZS_HIP(ctx, hipMemcpyAsync(ctx->pm_tables, h.data(), sizeof(double) * h.size(),
+    DZS_HIP(ctx, hipMemcpyAsync(ctx->pm_tables, h, sizeof(double) * 4 * (size_t)ng,
                                 hipMemcpyHostToDevice, s));
     DZS_HIP(ctx, hipStreamSynchronize(s));
     return DZS_OK;
