@@ -522,13 +522,20 @@ def run_headline(args, dz, torch, dzs_ics):
     free, total = torch.cuda.mem_get_info()
     log(f"resident: {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f}")
 
-    def step(params, s_, acc_):
+    metrics = open(args.metrics, "w") if args.metrics else None
+
+    def step(params, s_, acc_, run="shared"):
         t1 = time.perf_counter()
         rep = ctx.kdk_step(box, st, params[s_], ring)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         nrec = acc_.drain(ring)
         torch.cuda.synchronize()
+        if metrics:
+            metrics.write(json.dumps({"run": run, "step": s_ + 1, "a0": params[s_].lc.a0,
+                                      "a1": params[s_].lc.a1, "wall_s": dt, "particles": st.n,
+                                      "merged_nodes": int(rep.n_groups), "records": nrec}) + "\n")
+            metrics.flush()
         return dt, int(rep.n_groups), nrec
 
     per_step = []          # shared prefix
@@ -578,7 +585,7 @@ def run_headline(args, dz, torch, dzs_ics):
     def tail(params, acc_, name):
         times, counts, merged = [], [], 0
         for s_ in range(prefix, n_steps):
-            dt, m, nrec = step(params, s_, acc_)
+            dt, m, nrec = step(params, s_, acc_, name)
             times.append(dt)
             counts.append(st.n)
             merged += m
@@ -623,6 +630,8 @@ def run_headline(args, dz, torch, dzs_ics):
                      "time (the PM overlaps them on a second stream)")}
     free, total = torch.cuda.mem_get_info()
     ctx.close()
+    if metrics:
+        metrics.close()
     t_dzs = t_prefix + sum(t_dzs_tail)
     t_std = t_prefix + sum(t_std_tail)
     fp32 = True
@@ -1086,6 +1095,9 @@ def main():
                     help="individual power-of-two time steps: 2^B sub-steps per global step")
     ap.add_argument("--eta", type=float, default=0.025,
                     help="accuracy parameter of the individual time-step bins")
+    ap.add_argument("--metrics", default=None, metavar="JSONL",
+                    help="c5: one JSON line per step (run, step, a0, a1, wall_s, particles, "
+                         "merged_nodes, records) written to this file as the run goes")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default=None,
                     help="fp64: plain form; fp32: FP32 pair, mesh and FFT arithmetic "
                          "(default: the workload's)")
