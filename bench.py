@@ -202,36 +202,24 @@ def run_ensemble(args, dz, torch, dzs_ics):
     # fallen below 90%, the batch is packed again (new offsets, tables and context) and the
     # same steps are timed on the smaller batch.
     log("run control: second coarsening and re-packing")
-    h_all = st.to_host()
+    from paper_2005_05328_amd import ensemble
     rctx = dz.Context(max(first[b + 1] - first[b] for b in range(64)) + 64, max(ngs))
-    parts2, first2 = [], [0]
+    cps = []
     for b in range(64):
-        lo, hi = first[b], first[b + 1]
-        sub = _P()
-        for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
-            setattr(sub, k, h_all[k][lo:hi])
-        sst = dz.State.from_host(sub)
         cp = dz.CoarsenParams()
         cp.R_lc, cp.b, cp.theta = 0.125 * specs[b]["L"], 0.0, 1.0
         cp.k_min = k_min_for(specs[b]["n_side"], 2 ** specs[b]["level"])
-        rctx.dzs_coarsen(boxes[b], sst, cp)
-        torch.cuda.synchronize()
-        hb = sst.to_host()
-        parts2.append(hb)
-        first2.append(first2[-1] + hb["x"].shape[0])
+        cps.append(cp)
+    counts, _ = ensemble.coarsen_boxes(rctx, boxes, st, first, cps)
+    torch.cuda.synchronize()
     rctx.close()
-    N2 = first2[-1]
-    ratio = N2 / N
-    reasons = dz.halt_check(balance=1.0, ratio=ratio, ratio_prev=1.0, t=1.0, t_prev=0.0,
-                            min_ratio=0.9)
+    N2 = sum(counts)
+    ratio, reasons = ensemble.control(counts, N, min_ratio=0.9)
     repack = {"particles_before": N, "particles_after": N2, "ratio": ratio,
               "halt_reasons": reasons, "repacked": False}
     if reasons & dz._abi.DZS_HALT_RATIO:
-        allp2 = _P()
-        for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
-            setattr(allp2, k, np.concatenate([hb[k] for hb in parts2]))
+        pst, first2 = ensemble.repack(st, first, counts, capacity=N2 + 64)
         pctx = dz.Context(N2 + 64, side)
-        pst = dz.State.from_host(allp2, capacity=N2 + 64)
         pst0 = dz.State(N2 + 64)
         copy_state(pst0, pst)
         for s_ in range(args.warmup):

@@ -1458,8 +1458,10 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.depth = (uint32_t)ctx->walk_stack_depth;
     A.counter = ctx->walk_counter;
     A.pair_count = (unsigned long long *)(ctx->walk_counter + 8);
-    // start level K: the deepest level whose cells are at least r_cut wide (so no node above
-    // it can be a monopole while theta <= 1), at most DZS_CELL_K_MAX
+    // start level K: the deepest level whose cells are at least r_cut wide, at most
+    // DZS_CELL_K_MAX.  Every node above level K is opened: eq. 1 could accept some of them
+    // (a group's box can lie up to r_cut + sqrt(3) l from the centre of mass of a node of
+    // side l, farther than l / theta), so the walk is at least as accurate as eq. 1 alone
     A.key = (const uint64_t *)ctx->key;
     A.boxes = boxes;
     int K = 0;

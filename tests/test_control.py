@@ -64,3 +64,27 @@ def test_halt_conditions():
     # several reasons at once
     both = dz.halt_check(1.5, 0.2, 0.25, 4000.0, 3000.0, **base)
     assert both == (H._abi.DZS_HALT_BALANCE | H._abi.DZS_HALT_RATIO | H._abi.DZS_HALT_PREDICTED)
+
+
+def test_ensemble_repack_and_control_on_host_tensors():
+    """The re-pack keeps each box's survivors, in order, in consecutive ranges of a state
+    fitted to their total; the control reports the ratio to the last packing and asks for a
+    re-pack once it falls under the threshold (CPU tensors: the re-pack is plain copies)."""
+    import torch
+    from paper_2005_05328_amd import ensemble
+    first, counts = [0, 5, 5, 12], [3, 0, 4]
+    st = dz.State(12, device="cpu")
+    for k in ensemble._ARR:
+        t = getattr(st, k)
+        t.copy_(torch.arange(12).to(t.dtype) + (100 if k == "id" else 0))
+    st.n = 12
+    out, nf = ensemble.repack(st, first, counts, device="cpu")
+    assert nf == [0, 3, 3, 7] and out.n == out.capacity == 7
+    assert out.id.tolist() == [100, 101, 102, 105, 106, 107, 108]
+    assert out.x.tolist() == [0.0, 1.0, 2.0, 5.0, 6.0, 7.0, 8.0]
+    out2, _ = ensemble.repack(st, first, counts, capacity=20, device="cpu")
+    assert out2.capacity == 20 and out2.n == 7
+    r, why = ensemble.control(counts, 12, min_ratio=0.9)
+    assert r == pytest.approx(7 / 12) and why == dz._abi.DZS_HALT_RATIO
+    r, why = ensemble.control([5, 0, 6], 12, min_ratio=0.9)
+    assert why == 0
