@@ -16,6 +16,10 @@ What each part follows:
                                        shell output), in its zero-width every-step limit
   * kick-drift-kick, cosmology ....... not specified by the paper (readings listed in the
                                        design notes): flat LCDM, p = a^2 dx/dt, KDK in a.
+  * individual time steps ............ Sec. 2.1 (power-of-two steps), Sec. 2.2 (DZS at
+                                       global steps, the out-of-lightcone limiter); the
+                                       long-range force on the global step only (the TreePM
+                                       split carried into time)
 
 Parity status: every function here is pinned by the ``-m "not gpu"`` tests against closed
 forms, invariants or brute force, except the tree-walk force at a non-zero opening angle
@@ -558,6 +562,96 @@ def kdk_step_hier(ps, g, box: Box, a0, a1, max_bin, eta, ng, r_s, r_cut, x_obs, 
                     s.px[sel] = kick(s.px[sel], g[0, sel], K)
                     s.py[sel] = kick(s.py[sel], g[1, sel], K)
                     s.pz[sel] = kick(s.pz[sel], g[2, sel], K)
+    if coarsen_params is not None:
+        extra = {}
+        if coarsen_params.get("alpha_dyn") is not None:
+            extra = {"g": g, "Gm0": box.G * box.m0}
+        out, group_of, nm = coarsen(s, x_obs, **coarsen_params, **extra)
+        cres = (out, group_of, nm)
+        for k in ("x", "y", "z", "px", "py", "pz", "mult", "id", "type"):
+            setattr(s, k, out[k])
+        if nm > 0:
+            g = total_force(s.x, s.y, s.z, s.mult, box, ng, r_s, r_cut)
+        else:
+            g2 = np.empty_like(g)
+            g2[:, group_of] = g
+            g = g2
+    return s, g, records, cres, bins
+
+
+# ======================================================================================
+# Individual time steps with the long-range force on the global step only (Sec. 2.1: the
+# TreePM split carried into time, as the paper's code integrates its PM force with the
+# largest step and the tree force with the individual ones).
+#
+# Reading: the state's g on entry is the total force at a0 (PM + short range, as every step
+# leaves it).  The PM force is computed at a0, and the short-range part of the entry force
+# is g - g_PM(a0).  The global step opens with a long-range half-kick g_PM(a0) K(a0, a_h)
+# for every particle (a_h = sqrt(a0 a1), the step's midpoint in ln a), then runs the
+# sub-step schedule of kdk_step_hier with the short-range force alone (kicks, drifts,
+# lightcone tests and the short-range force of the particles that end a step at a sub-step
+# boundary, computed on every particle's current position), and closes with the PM force at
+# a1 and the half-kick g_PM(a1) K(a_h, a1) after the last short-range kicks.  The force left
+# in the state is g_PM(a1) + g_SR(a1) (every particle ends a step at a1).  DZS at a1 as in
+# kdk_step_hier, then a new total force if anything merged.  The bins come from |g| at a0.
+# ======================================================================================
+
+def kdk_step_hier_split(ps, g, box: Box, a0, a1, max_bin, eta, ng, r_s, r_cut, x_obs,
+                        R_lim=None, coarsen_params=None, solve=False, bins=None):
+    """One global step a0 -> a1: long-range kicks on the global step, short-range kicks on
+    individual power-of-two steps.  Returns (new state, g (3, n) at a1, lightcone records of
+    every sub-drift, coarsening result or None, bins)."""
+    s = ps.copy()
+    g = np.array(g, np.float64, copy=True)
+    if bins is None:
+        bins = hier_bins(s, g, box, a0, a1, max_bin, eta, x_obs, R_lim)
+    S = 1 << max_bin
+    u = hier_grid(a0, a1, max_bin)
+    chi2 = [0.0 if uk >= 1.0 else chi(uk) ** 2 for uk in u]
+    g_pm = pm_force(s.x, s.y, s.z, s.mult, box, ng, r_s)
+    g_sr = g - g_pm
+    K = kick_factor(a0, u[S])
+    s.px = kick(s.px, g_pm[0], K)
+    s.py = kick(s.py, g_pm[1], K)
+    s.pz = kick(s.pz, g_pm[2], K)
+    records, cres = [], None
+    for j in range(S):
+        for b in range(max_bin + 1):
+            Lb = 1 << (max_bin - b)
+            if j % Lb == 0:
+                sel = bins == b
+                if sel.any():
+                    K = kick_factor(u[2 * j], u[2 * j + Lb])
+                    s.px[sel] = kick(s.px[sel], g_sr[0, sel], K)
+                    s.py[sel] = kick(s.py[sel], g_sr[1, sel], K)
+                    s.pz[sel] = kick(s.pz[sel], g_sr[2, sel], K)
+        D = drift_factor(u[2 * j], u[2 * j + 2])
+        records.append(lightcone_records(s, x_obs, u[2 * j], u[2 * j + 2], D, chi2[2 * j],
+                                         chi2[2 * j + 2], solve=solve))
+        s.x = drift(s.x, s.px, D, s.L)
+        s.y = drift(s.y, s.py, D, s.L)
+        s.z = drift(s.z, s.pz, D, s.L)
+        jn = j + 1
+        active = np.array([(jn % (1 << (max_bin - int(b)))) == 0 for b in bins], bool)
+        if not active.any():
+            continue
+        idx = np.nonzero(active)[0]
+        g_sr[:, idx] = short_range(s.x, s.y, s.z, s.mult, box, r_s, r_cut, targets=idx)
+        for b in range(max_bin + 1):
+            Lb = 1 << (max_bin - b)
+            if jn % Lb == 0:
+                sel = (bins == b) & active
+                if sel.any():
+                    K = kick_factor(u[2 * jn - Lb], u[2 * jn])
+                    s.px[sel] = kick(s.px[sel], g_sr[0, sel], K)
+                    s.py[sel] = kick(s.py[sel], g_sr[1, sel], K)
+                    s.pz[sel] = kick(s.pz[sel], g_sr[2, sel], K)
+    g_pm = pm_force(s.x, s.y, s.z, s.mult, box, ng, r_s)
+    K = kick_factor(u[S], a1)
+    s.px = kick(s.px, g_pm[0], K)
+    s.py = kick(s.py, g_pm[1], K)
+    s.pz = kick(s.pz, g_pm[2], K)
+    g = g_pm + g_sr
     if coarsen_params is not None:
         extra = {}
         if coarsen_params.get("alpha_dyn") is not None:

@@ -141,3 +141,85 @@ def test_bin_rule_and_limiter():
     # nobody inside: no limit
     assert np.array_equal(oracle.hier_bins(ps, g, box, a0, a1, B, eta, x_obs=xo, R_lim=0.0),
                           bins)
+
+
+# ---- the long-range force on the global step only (kdk_step_hier_split) -----------------
+
+def test_split_step_with_one_bin_is_the_plain_step():
+    """B = 0: the long-range half-kicks and the short-range kicks of the one sub-step make up
+    the plain step's kicks (the PM force at a0 and a1, the short range at a0 and a1)."""
+    ps, box = _box(12, 50.0)
+    ng, r_s = 24, 1.25 * 50.0 / 24
+    g = oracle.total_force(ps.x, ps.y, ps.z, ps.mult, box, ng, r_s, 4.5 * r_s)
+    a0, a1 = 0.05, 0.06
+    sh, gh, _, _, bins = oracle.kdk_step_hier_split(ps, g, box, a0, a1, 0, 0.025, ng, r_s,
+                                                    4.5 * r_s, [0.0, 0.0, 0.0])
+    assert np.all(bins == 0)
+    sp, gp = _plain_steps(ps, g, box, oracle.hier_grid(a0, a1, 0), ng, r_s, 4.5 * r_s, 2)
+    for k in ("x", "y", "z", "px", "py", "pz"):
+        assert _close(getattr(sh, k), getattr(sp, k), 1e-13), k
+    assert _close(gh, gp, 1e-12)
+
+
+def test_split_step_without_short_range_pairs_ignores_the_bins():
+    """With no pair inside r_cut the force is the PM force alone, which the split step
+    applies on the global step only: any spread of bins gives the plain step (the sub-drifts
+    add up to the step's drift)."""
+    ps, box = _box(12, 50.0)
+    ng, r_s = 24, 1.25 * 50.0 / 24
+    r_cut = 1e-4 * 50.0 / 12
+    g = oracle.total_force(ps.x, ps.y, ps.z, ps.mult, box, ng, r_s, r_cut)
+    a0, a1, B = 0.05, 0.07, 2
+    bins = np.arange(ps.n) % (B + 1)
+    sh, gh, _, _, _ = oracle.kdk_step_hier_split(ps, g, box, a0, a1, B, 0.025, ng, r_s, r_cut,
+                                                 [0.0, 0.0, 0.0], bins=bins)
+    sp, gp = _plain_steps(ps, g, box, oracle.hier_grid(a0, a1, 0), ng, r_s, r_cut, 2)
+    for k in ("x", "y", "z", "px", "py", "pz"):
+        assert _close(getattr(sh, k), getattr(sp, k), 1e-12), k
+    assert _close(gh, gp, 1e-12)
+    # the same bins in the step that recomputes the whole force at every sub-step differ
+    so, _, _, _, _ = oracle.kdk_step_hier(ps, g, box, a0, a1, B, 0.025, ng, r_s, r_cut,
+                                          [0.0, 0.0, 0.0], bins=bins)
+    assert not _close(so.px, sp.px, 1e-9)
+
+
+def test_split_step_grows_a_plane_wave_at_the_linear_rate():
+    """Mixed bins with the long-range force on the global step follow the linear growth of a
+    Zel'dovich plane wave (an independent ODE) and stay with the run that puts every particle
+    in the finest bin."""
+    n_side, L = 16, 64.0
+    lam = L / n_side
+    ng = 2 * n_side
+    r_s = 1.25 * L / ng
+    k = 2 * math.pi / L
+    A0 = 0.05 * lam
+    a_i, a_f, n_steps = 0.02, 0.2, 12
+    sol = _linear_growth([a_f])
+    D_i, dD_i = sol.sol(a_i)
+    a_grid = np.exp(np.linspace(math.log(a_i), math.log(a_f), n_steps + 1))
+
+    def run(fixed_bin):
+        ps = dzs_ics.lattice(n_side, L)
+        box = oracle.Box(L=L, m0=dzs_ics.particle_mass(L, ps.n), eps0=lam / 40)
+        q = ps.x.copy()
+        psi = A0 * np.sin(k * q)
+        ps.x = oracle.wrap(q + psi, L)
+        H_i = oracle.H0 * math.sqrt(OM / a_i ** 3 + 1 - OM)
+        ps.px = a_i ** 2 * H_i * (a_i * dD_i / D_i) * psi
+        g = oracle.total_force(ps.x, ps.y, ps.z, ps.mult, box, ng, r_s, 4.5 * r_s)
+        seen = set()
+        for n in range(n_steps):
+            bins = None if fixed_bin is None else np.full(ps.n, fixed_bin)
+            ps, g, _, _, b = oracle.kdk_step_hier_split(ps, g, box, a_grid[n], a_grid[n + 1],
+                                                        2, 0.01, ng, r_s, 4.5 * r_s,
+                                                        [0.0, 0.0, 0.0], bins=bins)
+            seen |= set(np.unique(b).tolist())
+        disp = oracle.min_image(ps.x - q, L)
+        return 2 * np.mean(disp * np.sin(k * q)) / (A0 * sol.sol(a_f)[0] / D_i), seen
+
+    fine, _ = run(2)
+    mixed, seen = run(None)
+    assert len(seen) >= 2
+    assert abs(mixed - fine) <= 2e-3
+    for v in (fine, mixed):
+        assert abs(v - 1) < 1e-2
