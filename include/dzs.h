@@ -71,6 +71,9 @@ typedef struct {
  * also hold the fixed-point deposit, 4-byte potential: 12 instead of 32 bytes per cell);
  * plain-form PM calls on such a context fail with DZS_EINVAL. */
 #define DZS_CAP_FP32_MESHES 1u
+/* Capacity flag: room for the PM force of kdk_step_hier's long-range-on-the-global-step
+ * form (dzs_hier_params.pm_global): 24 bytes per particle more. */
+#define DZS_CAP_HIER_SPLIT 4u
 /* Capacity flag: no sorted copies for tree_force (28 bytes per particle fewer); tree_force on
  * such a context needs particles already in key order (dzs_tree_params.presorted = 1). */
 #define DZS_CAP_NO_COPIES 2u
@@ -255,7 +258,19 @@ typedef struct {
  * inside).  Every particle ending a step at a sub-step boundary gets its new force there
  * (PM + tree; the walk serves only those targets).  DZS runs once all particles are
  * synchronised at a1 (after the closing kicks), and a coarsening that merged particles is
- * followed by a new force for the whole state. */
+ * followed by a new force for the whole state.
+ *
+ * pm_global = 1 (the TreePM split carried into time, Sec. 2.1; needs a context created with
+ * DZS_CAP_HIER_SPLIT): the long-range force acts on the global step only.  The entry g is
+ * taken as the total force at a0; the PM force at a0 is computed and g - g_PM is the
+ * short-range part.  The step opens with the half-kick g_PM(a0) K(a0, a_h) of every particle
+ * (a_h = sqrt(a0 a1)), runs the sub-steps above with the short-range force alone, and closes
+ * with the half-kick g_PM(a1) K(a_h, a1) after the last short-range kicks; the state keeps
+ * g_PM(a1) + g_SR(a1).  The particles are sorted and the tree built once, at a0; at every
+ * sub-step boundary the nodes' moments and bounding boxes are recomputed from the drifted
+ * positions (the topology kept, members that crossed a face of the periodic box unwrapped)
+ * and the walk, started at the root, serves the targets that end a step there.  The state
+ * is left in the key order of a0 unless DZS ran. */
 #define DZS_HIER_MAX_BIN 6
 typedef struct {
     int32_t max_bin;   /* 0..DZS_HIER_MAX_BIN (0: the plain step) */
@@ -264,6 +279,8 @@ typedef struct {
     double R_lim;      /* limiter radius (the lightcone radius at a0 plus the buffer) */
     double a0, a1;     /* the global step */
     double omega_m;    /* flat LCDM */
+    int32_t pm_global; /* 1: the long-range force on the global step only (see above) */
+    int32_t reserved;  /* 0 */
 } dzs_hier_params;
 
 /* ---- context ------------------------------------------------------------------------ */
@@ -272,8 +289,9 @@ typedef struct {
  * 123 bytes per particle (keys and sort indices 24; one arena of 89 shared by the tree, with
  * node capacity max_particles/2 + 4096, and the DZS coarsening buffers; group starts 4; the
  * relative criterion's |g| 4; time-step bins and the walk's target flags 2), plus 28 bytes per
- * particle of sorted copies for tree_force unless DZS_CAP_NO_COPIES, plus the meshes (32 bytes
- * per cell, 12 with DZS_CAP_FP32_MESHES).  No call allocates device memory afterwards.
+ * particle of sorted copies for tree_force unless DZS_CAP_NO_COPIES, plus 24 bytes per
+ * particle with DZS_CAP_HIER_SPLIT, plus the meshes (32 bytes per cell, 12 with
+ * DZS_CAP_FP32_MESHES).  No call allocates device memory afterwards.
  * Returns DZS_ENOMEM if the device memory does not suffice. */
 dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap);
 dzs_status dzs_ctx_destroy(dzs_ctx *ctx);

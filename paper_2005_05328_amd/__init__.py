@@ -181,9 +181,11 @@ class Context:
     mesh on one device."""
 
     def __init__(self, max_particles: int, max_mesh_side: int, device: int = 0,
-                 fp32_meshes: bool = False, no_copies: bool = False, max_boxes: int = 0):
+                 fp32_meshes: bool = False, no_copies: bool = False, max_boxes: int = 0,
+                 hier_split: bool = False):
         flags = (_abi.DZS_CAP_FP32_MESHES if fp32_meshes else 0) | \
-            (_abi.DZS_CAP_NO_COPIES if no_copies else 0)
+            (_abi.DZS_CAP_NO_COPIES if no_copies else 0) | \
+            (_abi.DZS_CAP_HIER_SPLIT if hier_split else 0)
         cap = _abi.Capacity(int(max_particles), int(max_mesh_side), flags, int(max_boxes), 0)
         h = C.c_void_p()
         rc = _lib.dzs_ctx_create(C.byref(h), int(device), C.byref(cap))
@@ -251,13 +253,14 @@ class Context:
     def kdk_step_hier(self, box: Box, st: State, prm: StepParams, max_bin: int, eta: float,
                       a0: float, a1: float, omega_m: float = 0.3, limiter: bool = False,
                       R_lim: float = 0.0, ring: LCRing | None = None, bins_out=None,
-                      stream=None):
+                      pm_global: bool = False, stream=None):
         """One global step a0 -> a1 with individual power-of-two time steps (bins 0..max_bin);
-        bins_out (optional uint8 tensor) receives the bins in the entry order."""
+        bins_out (optional uint8 tensor) receives the bins in the entry order.  pm_global: the
+        long-range force on the global step only (a context made with hier_split=True)."""
         v = st.view()
         rep = CoarsenReport()
         hp = _abi.HierParams(int(max_bin), int(bool(limiter)), float(eta), float(R_lim),
-                             float(a0), float(a1), float(omega_m))
+                             float(a0), float(a1), float(omega_m), int(bool(pm_global)), 0)
         rv = C.byref(ring.view()) if ring is not None else None
         self._check("kdk_step_hier", _lib.kdk_step_hier(self._h, C.byref(box), C.byref(v),
                                                         C.byref(prm), C.byref(hp), rv,

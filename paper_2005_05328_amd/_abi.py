@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libdzs.so")
 DZS_OK, DZS_EINVAL, DZS_ENOMEM, DZS_ECAPACITY, DZS_EHIP = 0, -1, -2, -3, -4
 DZS_CHEB_MAX = 24
 DZS_FP64, DZS_FP32 = 0, 1
-DZS_CAP_FP32_MESHES, DZS_CAP_NO_COPIES = 1, 2
+DZS_CAP_FP32_MESHES, DZS_CAP_NO_COPIES, DZS_CAP_HIER_SPLIT = 1, 2, 4
 DZS_CRIT_GEOMETRIC, DZS_CRIT_DYNAMICAL = 0, 1
 DZS_OPEN_GEOMETRIC, DZS_OPEN_RELATIVE = 0, 1
 
@@ -34,7 +34,7 @@ DZS_PM_NOALLOC_MAX_SIDE = 64
 class HierParams(C.Structure):
     _fields_ = [("max_bin", C.c_int32), ("limiter", C.c_int32), ("eta", C.c_double),
                 ("R_lim", C.c_double), ("a0", C.c_double), ("a1", C.c_double),
-                ("omega_m", C.c_double)]
+                ("omega_m", C.c_double), ("pm_global", C.c_int32), ("reserved", C.c_int32)]
 
 
 class HaltParams(C.Structure):

@@ -145,7 +145,7 @@ static dzs_status alloc(dzs_ctx *ctx, T **p, uint64_t count) {
 static void release(dzs_ctx *ctx) {
     void *ptrs[] = {ctx->key, ctx->key_alt, ctx->idx, ctx->idx_alt, ctx->hist, ctx->hist_scan,
                     ctx->scan_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult, ctx->aold,
-                    ctx->hbins, ctx->active, ctx->arena, ctx->bstate, ctx->grp_first,
+                    ctx->hbins, ctx->active, ctx->gpm, ctx->arena, ctx->bstate, ctx->grp_first,
                     ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl,
                     ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members,
                     ctx->step_dev, ctx->fp32_meshes ? nullptr : (void *)ctx->mesh_q, ctx->mesh_c,
@@ -257,6 +257,8 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->aold, n));
     DZS_TRY(alloc(c, &c->hbins, n));
     DZS_TRY(alloc(c, &c->active, n));
+    if (cap->flags & DZS_CAP_HIER_SPLIT)
+        DZS_TRY(alloc(c, &c->gpm, 3 * n));
     if (!(cap->flags & DZS_CAP_NO_COPIES)) {
         // tree_force's sorted copies of an input in any order
         DZS_TRY(alloc(c, &c->sx, n));
@@ -315,7 +317,7 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
 extern "C" dzs_status dzs_ctx_create(dzs_ctx **out, int32_t device, const dzs_capacity *cap) {
     if (!out || !cap || cap->max_particles == 0 || cap->max_particles > 0xfffff000ull ||
         cap->max_boxes > DZS_BATCH_MAX || cap->reserved != 0 ||
-        (cap->flags & ~(DZS_CAP_FP32_MESHES | DZS_CAP_NO_COPIES)) != 0)
+        (cap->flags & ~(DZS_CAP_FP32_MESHES | DZS_CAP_NO_COPIES | DZS_CAP_HIER_SPLIT)) != 0)
         return DZS_EINVAL;
     if (cap->max_mesh_side != 0 && (cap->max_mesh_side < 8 || cap->max_mesh_side > 1024))
         return DZS_EINVAL;
@@ -805,6 +807,13 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
         return dzs_fail(ctx, DZS_EINVAL, "hier: null lightcone ring");
     if (prm->do_coarsen)
         DZS_TRY(check_coarsen(ctx, &prm->coarsen));
+    if (hp->pm_global != 0 && hp->pm_global != 1)
+        return dzs_fail(ctx, DZS_EINVAL, "hier: pm_global must be 0 or 1");
+    if (hp->reserved != 0)
+        return dzs_fail(ctx, DZS_EINVAL, "hier: reserved must be 0");
+    if (hp->pm_global && !ctx->gpm)
+        return dzs_fail(ctx, DZS_EINVAL, "hier: pm_global needs a context created with "
+                        "DZS_CAP_HIER_SPLIT");
     const int B = hp->max_bin;
     if (B < 0 || B > DZS_HIER_MAX_BIN || !(hp->eta > 0.0) || !(hp->a0 > 0.0) ||
         !(hp->a1 > hp->a0) || !(hp->a1 <= 1.0) || !(hp->omega_m > 0.0) ||
@@ -831,6 +840,28 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
         if (bins_out)
             DZS_HIP(ctx, hipMemcpyAsync(bins_out, ctx->hbins, st->n, hipMemcpyDeviceToDevice, s));
     }
+    // the long-range force on the global step: state in key order and tree once, at a0; the
+    // PM force at a0 (into gpm) opens the step with its half-kick and leaves g the short-range
+    // part of the entry force
+    const bool split = hp->pm_global != 0 && st->n > 0;
+    dzs_particles pmv = *st;   // the state with gpm as its force
+    if (split) {
+        pmv.gx = ctx->gpm;
+        pmv.gy = ctx->gpm + ctx->cap_n;
+        pmv.gz = ctx->gpm + 2 * ctx->cap_n;
+        DZS_TRY(sort_state(ctx, box, st, 0, 1, s, true));   // the entry force moves along
+        DZS_TRY(dzs_permute_u8(ctx, ctx->hbins, ctx->idx, st->n, s));
+        pmv.n = st->n;
+        dzs_pm_params pm = prm->pm;
+        pm.accumulate = 0;
+        DZS_TRY(dzs_pm_solve(ctx, box, &pmv, &pm, s));
+        DZS_TRY(dzs_pm_apply(ctx, box, &pmv, &pm, s));
+        DZS_TRY(dzs_launch_add3(ctx, st->n, st->gx, st->gy, st->gz, pmv.gx, pmv.gy, pmv.gz, -1.0,
+                                s));
+        DZS_TRY(dzs_launch_kick(ctx, &pmv, dzs_kick_factor(a0, u[S], om), s));
+        DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
+                               t.group_size, s));
+    }
     for (int j = 0; j < S && st->n > 0; ++j) {
         double K[DZS_HIER_MAX_BIN + 1] = {0.0};
         for (int b = 0; b <= B; ++b) {
@@ -843,13 +874,37 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
         DZS_TRY(dzs_step_factors(u[2 * j], u[2 * j + 2], om, &sub));
         DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &sub.lc, ring, prm->do_lightcone, 1, s));
         const int jn = j + 1;
-        DZS_TRY(hier_force(ctx, box, st, prm, t, ctx->hbins, (uint32_t)jn, (uint32_t)B, false,
-                           s));
+        if (split) {
+            // the short-range force of the targets that end a step here, on the kept tree
+            DZS_TRY(dzs_tree_refresh(ctx, box, st->n, st->x, st->y, st->z, st->mult, s));
+            DZS_TRY(dzs_launch_hier_active(ctx, st->n, ctx->hbins, (uint32_t)jn, (uint32_t)B,
+                                           ctx->active, s));
+            dzs_tree_params ts = t;
+            ts.accumulate = 0;
+            dzs_walk_io io;
+            io.active = ctx->active;
+            io.kept_tree = true;
+            DZS_TRY(dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx,
+                                  st->gy, st->gz, &ts, s, io));
+        } else {
+            DZS_TRY(hier_force(ctx, box, st, prm, t, ctx->hbins, (uint32_t)jn, (uint32_t)B,
+                               false, s));
+        }
         for (int b = 0; b <= B; ++b) {
             const int L = 1 << (B - b);
             K[b] = jn % L == 0 ? dzs_kick_factor(u[2 * jn - L], u[2 * jn], om) : 0.0;
         }
         DZS_TRY(dzs_launch_kick_bins(ctx, st, ctx->hbins, K, s));
+    }
+    if (split) {
+        // the PM force at a1 closes the step; the state keeps g_PM + g_SR
+        dzs_pm_params pm = prm->pm;
+        pm.accumulate = 0;
+        DZS_TRY(dzs_pm_solve(ctx, box, &pmv, &pm, s));
+        DZS_TRY(dzs_pm_apply(ctx, box, &pmv, &pm, s));
+        DZS_TRY(dzs_launch_kick(ctx, &pmv, dzs_kick_factor(u[S], a1, om), s));
+        DZS_TRY(dzs_launch_add3(ctx, st->n, st->gx, st->gy, st->gz, pmv.gx, pmv.gy, pmv.gz, 1.0,
+                                s));
     }
     // every particle is synchronised at a1: DZS, then a new force if anything merged
     const bool can_merge = prm->do_coarsen &&

@@ -134,6 +134,8 @@ struct dzs_ctx {
     uint32_t *nd_first = nullptr, *nd_count = nullptr, *nd_child = nullptr;
     uint8_t *nd_nchild = nullptr, *nd_level = nullptr;
     struct dzs_node_rec *nd_rec = nullptr;  // moments and topology as the walk reads them
+    int tree_deepest = 0;                    // deepest level the last build may have made
+    double *gpm = nullptr;  // [3 cap] the PM force of the split individual step (capacity flag)
     uint32_t *frontier = nullptr, *frontier_next = nullptr;
     uint32_t *fr_nchild = nullptr, *fr_ninternal = nullptr, *fr_child_off = nullptr,
              *fr_int_off = nullptr;
@@ -388,7 +390,20 @@ struct dzs_walk_io {
     const float *aold = nullptr;
     const uint8_t *active = nullptr;
     const uint32_t *out_perm = nullptr;
+    // a tree kept from an earlier build and refreshed (dzs_tree_refresh): the walk starts at
+    // the root and unwraps targets and leaf members that crossed a face of the box
+    bool kept_tree = false;
 };
+// Recompute the moments and bounding boxes of the last built tree from positions that moved
+// since (same particles in the same slots), bottom-up, unwrapping members that crossed a
+// face of the periodic box; a leaf with such a member is flagged in its record (pad bit 0).
+dzs_status dzs_tree_refresh(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                            const double *y, const double *z, const uint32_t *mult,
+                            hipStream_t s);
+// a[i] += s b[i] for the three components (exact for s = +-1)
+dzs_status dzs_launch_add3(dzs_ctx *ctx, uint64_t n, double *ax, double *ay, double *az,
+                           const double *bx, const double *by, const double *bz, double s,
+                           hipStream_t st);
 dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
                           const double *y, const double *z, const uint32_t *mult,
                           int leaf_size, int group_size, hipStream_t s);

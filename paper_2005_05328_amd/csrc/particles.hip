@@ -38,6 +38,30 @@ dzs_status dzs_launch_kick(dzs_ctx *ctx, const dzs_particles *p, double K, hipSt
     return dzs_check_launch(ctx, "kick");
 }
 
+__global__ __launch_bounds__(PT_THREADS) void k_add3(uint64_t n, double *__restrict__ ax,
+                                                     double *__restrict__ ay,
+                                                     double *__restrict__ az,
+                                                     const double *__restrict__ bx,
+                                                     const double *__restrict__ by,
+                                                     const double *__restrict__ bz, double s) {
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i >= n)
+        return;
+    ax[i] = ax[i] + s * bx[i];
+    ay[i] = ay[i] + s * by[i];
+    az[i] = az[i] + s * bz[i];
+}
+
+dzs_status dzs_launch_add3(dzs_ctx *ctx, uint64_t n, double *ax, double *ay, double *az,
+                           const double *bx, const double *by, const double *bz, double s,
+                           hipStream_t st) {
+    if (n == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_add3, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, st, n, ax,
+                       ay, az, bx, by, bz, s);
+    return dzs_check_launch(ctx, "add3");
+}
+
 // box of particle i in a batch: the last b with first[b] <= i (first[] ascending, nb entries)
 __device__ __forceinline__ uint32_t batch_box_of(const uint64_t *first, uint32_t nb, uint64_t i) {
     uint32_t lo = 0, hi = nb - 1;
@@ -124,24 +148,36 @@ __global__ __launch_bounds__(PT_THREADS) void k_drift_lc(
         const double ey = dzs_min_image(ny - A.xo[1], L);
         const double ez = dzs_min_image(nz - A.xo[2], L);
         const double f1 = (ex * ex + ey * ey + ez * ez) - A.chi2_1;
-        if (f0 < 0.0 && f1 >= 0.0) {
-            double cx, cy, cz;
-            double t = lc_solve(A, dx, dy, dz, pxi, pyi, pzi, &cx, &cy, &cz);
-            unsigned long long slot = atomicAdd(rec_count, 1ull);
-            if (slot < rec_cap) {
-                dzs_lc_record r;
-                r.id = id[i];
-                r.mult = mult[i];
-                r.a_cross = A.a0 + 0.5 * (t + 1.0) * (A.a1 - A.a0);
-                r.d[0] = cx;
-                r.d[1] = cy;
-                r.d[2] = cz;
-                r.p[0] = pxi;
-                r.p[1] = pyi;
-                r.p[2] = pzi;
-                rec[slot] = r;
-            } else {
-                *overflow = 1u;
+        // one atomic per wave: the wave's emitters take consecutive slots
+        const bool emit = f0 < 0.0 && f1 >= 0.0;
+        const uint64_t m = __ballot(emit);
+        if (m != 0ull) {
+            const uint32_t lane = threadIdx.x & 63u;
+            const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
+            unsigned long long base = 0ull;
+            if (lane == leader)
+                base = atomicAdd(rec_count, (unsigned long long)__popcll(m));
+            base = __shfl(base, (int)leader, 64);
+            if (emit) {
+                double cx, cy, cz;
+                const double t = lc_solve(A, dx, dy, dz, pxi, pyi, pzi, &cx, &cy, &cz);
+                const unsigned long long slot =
+                    base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+                if (slot < rec_cap) {
+                    dzs_lc_record r;
+                    r.id = id[i];
+                    r.mult = mult[i];
+                    r.a_cross = A.a0 + 0.5 * (t + 1.0) * (A.a1 - A.a0);
+                    r.d[0] = cx;
+                    r.d[1] = cy;
+                    r.d[2] = cz;
+                    r.p[0] = pxi;
+                    r.p[1] = pyi;
+                    r.p[2] = pzi;
+                    rec[slot] = r;
+                } else {
+                    *overflow = 1u;
+                }
             }
         }
     }

@@ -208,7 +208,7 @@ __device__ __forceinline__ void node_moments(
     const uint32_t *__restrict__ nd_first, const uint32_t *__restrict__ nd_count,
     const uint32_t *__restrict__ nd_child, const uint8_t *__restrict__ nd_nchild,
     const uint8_t *__restrict__ nd_level, dzs_node_rec *__restrict__ rec,
-    const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes) {
+    const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes, double L, int unwrap) {
     if (boxes && nd_nchild[v] == 0) {
         // a batch: the leaf's box (its key prefix) sets the mass unit and the softening
         const uint64_t b = key[nd_first[v]] >> DZS_BATCH_SHIFT;
@@ -218,13 +218,28 @@ __device__ __forceinline__ void node_moments(
     double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, hmax = 0.0;
     double mnx = 1e300, mny = 1e300, mnz = 1e300, mxx = -1e300, mxy = -1e300, mxz = -1e300;
     const uint32_t nc = nd_nchild[v];
+    // kept tree: a member (child) more than half a box from the first one crossed a face of
+    // the periodic box since the build; it is taken at the image next to the first one
+    const double halfL = 0.5 * L;
+    auto near = [&](double a, double a0) -> double {
+        return a - a0 > halfL ? a - L : (a - a0 < -halfL ? a + L : a);
+    };
+    uint32_t crossed = 0u;
     if (nc == 0) {
         const uint32_t s = nd_first[v], e = s + nd_count[v];
+        const double x0 = x[s], y0 = y[s], z0 = z[s];
         uint32_t mmax = 0;
         for (uint32_t j = s; j < e; ++j) {
             const uint32_t mu = mult[j];
             const double mj = m0 * (double)mu;
-            const double xj = x[j], yj = y[j], zj = z[j];
+            double xj = x[j], yj = y[j], zj = z[j];
+            if (unwrap) {
+                const double ux = near(xj, x0), uy = near(yj, y0), uz = near(zj, z0);
+                crossed |= (ux != xj || uy != yj || uz != zj) ? 1u : 0u;
+                xj = ux;
+                yj = uy;
+                zj = uz;
+            }
             m += mj;
             sx += mj * xj;
             sy += mj * yj;
@@ -236,17 +251,27 @@ __device__ __forceinline__ void node_moments(
         hmax = h0 * mult_cbrt(mmax);  // the softening grows with the multiplicity
     } else {
         const uint32_t c0 = nd_child[v];
+        const double x0 = rec[c0].cx, y0 = rec[c0].cy, z0 = rec[c0].cz;
         for (uint32_t c = c0; c < c0 + nc; ++c) {
             const dzs_node_rec &r = rec[c];
             const double mc = r.mass;
+            double rcx = r.cx, rcy = r.cy, rcz = r.cz;
+            double rmx = r.comx, rmy = r.comy, rmz = r.comz;
+            if (unwrap) {
+                // the child's box and centre of mass move together, by the box's shift
+                const double dx = near(rcx, x0) - rcx, dy = near(rcy, y0) - rcy,
+                             dz = near(rcz, z0) - rcz;
+                rcx += dx; rcy += dy; rcz += dz;
+                rmx += dx; rmy += dy; rmz += dz;
+            }
             m += mc;
-            sx += mc * r.comx;
-            sy += mc * r.comy;
-            sz += mc * r.comz;
-            mnx = fmin(mnx, r.cx - (double)r.hx); mny = fmin(mny, r.cy - (double)r.hy);
-            mnz = fmin(mnz, r.cz - (double)r.hz);
-            mxx = fmax(mxx, r.cx + (double)r.hx); mxy = fmax(mxy, r.cy + (double)r.hy);
-            mxz = fmax(mxz, r.cz + (double)r.hz);
+            sx += mc * rmx;
+            sy += mc * rmy;
+            sz += mc * rmz;
+            mnx = fmin(mnx, rcx - (double)r.hx); mny = fmin(mny, rcy - (double)r.hy);
+            mnz = fmin(mnz, rcz - (double)r.hz);
+            mxx = fmax(mxx, rcx + (double)r.hx); mxy = fmax(mxy, rcy + (double)r.hy);
+            mxz = fmax(mxz, rcz + (double)r.hz);
             hmax = fmax(hmax, r.hmax);
         }
     }
@@ -266,7 +291,7 @@ __device__ __forceinline__ void node_moments(
     out.count = nd_count[v];
     out.child = nd_child[v];
     out.nl = nc | ((uint32_t)nd_level[v] << 8);
-    out.pad = 0u;
+    out.pad = crossed;
     rec[v] = out;
 }
 
@@ -278,12 +303,13 @@ __global__ __launch_bounds__(TB_THREADS) void k_tree_moments(
     double m0, double h0, const uint32_t *__restrict__ nd_first,
     const uint32_t *__restrict__ nd_count, const uint32_t *__restrict__ nd_child,
     const uint8_t *__restrict__ nd_nchild, const uint8_t *__restrict__ nd_level,
-    dzs_node_rec *rec, const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes) {
+    dzs_node_rec *rec, const uint64_t *__restrict__ key, const dzs_bbox *__restrict__ boxes,
+    double L, int unwrap) {
     const uint32_t end = bs[BS_LEVEL + k + 1];
     for (uint32_t v = bs[BS_LEVEL + k] + blockIdx.x * TB_THREADS + threadIdx.x; v < end;
          v += gridDim.x * TB_THREADS)
         node_moments(v, x, y, z, mult, m0, h0, nd_first, nd_count, nd_child, nd_nchild, nd_level,
-                     rec, key, boxes);
+                     rec, key, boxes, L, unwrap);
 }
 
 // Target groups: each node with more than G particles packs its consecutive children that
@@ -370,6 +396,37 @@ __global__ __launch_bounds__(TB_THREADS) void k_fill_u32(uint64_t n, uint32_t *a
 // return at once): the counts stay on the device and nothing here waits for the host.  The
 // launches of level k are sized for the largest frontier it can have: 8^k nodes, and below
 // the forced levels the internal nodes of more than `leaf` particles, at most n / (leaf + 1).
+// Moments of every level of the last built tree, bottom-up (levels 0 .. ctx->tree_deepest).
+static dzs_status tree_moments(dzs_ctx *ctx, const dzs_box *box, uint32_t n, const double *x,
+                               const double *y, const double *z, const uint32_t *mult,
+                               const dzs_bbox *boxes, int unwrap, hipStream_t s) {
+    dzs_timed t(ctx, KC_TREE_MOMENTS, s);
+    for (int k = ctx->tree_deepest; k >= 0; --k) {
+        // at most 8^k nodes on level k, and never more than the particles
+        uint64_t ub = n;
+        if (k < 8 && (1ull << (3 * k)) < ub)
+            ub = 1ull << (3 * k);
+        uint32_t nbk = blocks_for(ub, TB_THREADS);
+        nbk = nbk < 8192u ? nbk : 8192u;   // grid-stride beyond
+        hipLaunchKernelGGL(k_tree_moments, dim3(nbk), dim3(TB_THREADS), 0, s,
+                           (const uint32_t *)ctx->bstate, k, x, y, z, mult, box->m0,
+                           2.8 * box->eps0, ctx->nd_first, ctx->nd_count, ctx->nd_child,
+                           ctx->nd_nchild, ctx->nd_level, ctx->nd_rec,
+                           (const uint64_t *)ctx->key, boxes, box->L, unwrap);
+        DZS_TRY(dzs_check_launch(ctx, "tree_moments"));
+    }
+    return DZS_OK;
+}
+
+dzs_status dzs_tree_refresh(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const double *x,
+                            const double *y, const double *z, const uint32_t *mult,
+                            hipStream_t s) {
+    if (!ctx->tree_built || n != ctx->tree_n)
+        return dzs_fail(ctx, DZS_EINVAL, "tree refresh: no tree of %llu particles",
+                        (unsigned long long)n);
+    return tree_moments(ctx, box, (uint32_t)n, x, y, z, mult, nullptr, 1, s);
+}
+
 dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const double *x,
                              const double *y, const double *z, const uint32_t *mult,
                              int leaf_size, int group_size, int KB, const dzs_bbox *boxes,
@@ -418,22 +475,8 @@ dzs_status dzs_tree_build_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, con
             fr_next = tmp;
         }
     }
-    {
-        dzs_timed t(ctx, KC_TREE_MOMENTS, s);
-        for (int k = deepest; k >= 0; --k) {
-            // at most 8^k nodes on level k, and never more than the particles
-            uint64_t ub = n;
-            if (k < 8 && (1ull << (3 * k)) < ub)
-                ub = 1ull << (3 * k);
-            uint32_t nbk = blocks_for(ub, TB_THREADS);
-            nbk = nbk < 8192u ? nbk : 8192u;   // grid-stride beyond
-            hipLaunchKernelGGL(k_tree_moments, dim3(nbk), dim3(TB_THREADS), 0, s,
-                               (const uint32_t *)bs, k, x, y, z, mult, box->m0, 2.8 * box->eps0,
-                               ctx->nd_first, ctx->nd_count, ctx->nd_child, ctx->nd_nchild,
-                               ctx->nd_level, ctx->nd_rec, (const uint64_t *)ctx->key, boxes);
-            DZS_TRY(dzs_check_launch(ctx, "tree_moments"));
-        }
-    }
+    ctx->tree_deepest = deepest;
+    DZS_TRY(tree_moments(ctx, box, n, x, y, z, mult, boxes, 0, s));
     {
         dzs_timed t(ctx, KC_TREE_GROUPS, s);
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s,
@@ -586,6 +629,9 @@ struct walk_args {
     const uint8_t *active;
     const uint32_t *out_perm;
     const uint32_t *bad;  // tree_force input rejected on the device: the walk does nothing
+    // a kept, refreshed tree: targets are taken at the image next to the group's first one,
+    // and a leaf flagged for members across a face keeps them all with minimum-image pairs
+    int kept;
 };
 
 // Geometry and constants of the box a group lives in.
@@ -935,7 +981,13 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
         const bool active = valid && (!A.active || A.active[i] != 0);
         if (A.active && __ballot(active) == 0ull)
             continue;  // no target in this group
-        const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+        double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+        if (A.kept) {
+            const double x0 = __shfl(xi, 0, 64), y0 = __shfl(yi, 0, 64), z0 = __shfl(zi, 0, 64);
+            xi = xi - x0 > W.halfL ? xi - W.L : (xi - x0 < -W.halfL ? xi + W.L : xi);
+            yi = yi - y0 > W.halfL ? yi - W.L : (yi - y0 < -W.halfL ? yi + W.L : yi);
+            zi = zi - z0 > W.halfL ? zi - W.L : (zi - z0 < -W.halfL ? zi + W.L : zi);
+        }
         const double hi = W.h0 * mult_cbrt(A.mult[i]);
         // group bounding box
         double mnx = xi, mny = yi, mnz = zi, mxx = xi, mxy = yi, mxz = zi;
@@ -1109,7 +1161,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                 const double gy_ = fmax(0.0, fabs(dcy) - nhy - ghy);
                 const double gz_ = fmax(0.0, fabs(dcz) - nhz - ghz);
                 const double dist2 = gx_ * gx_ + gy_ * gy_ + gz_ * gz_;
-                node_wide = fmax(nhx, fmax(nhy, nhz)) + ghmax > W.wide;
+                node_wide = fmax(nhx, fmax(nhy, nhz)) + ghmax > W.wide || nd.pad != 0u;
                 if (dist2 >= W.rcut2) {
                     act = 0;
                 } else if (nchild == 0) {
@@ -1437,6 +1489,7 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.active = boxes ? nullptr : io.active;
     A.out_perm = boxes ? nullptr : io.out_perm;
     A.bad = ctx->bstate + DZS_BS_BADINPUT;
+    A.kept = (io.kept_tree && !boxes) ? 1 : 0;
     A.alpha_g = relative ? prm->alpha_open / box->G : 0.0;
     const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
     if (ctx->q_wmax != wmax) {
@@ -1465,7 +1518,7 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.key = (const uint64_t *)ctx->key;
     A.boxes = boxes;
     int K = 0;
-    if ((prm->theta <= 1.0 || relative) && !boxes)
+    if ((prm->theta <= 1.0 || relative) && !boxes && !A.kept)
         while (K < DZS_CELL_K_MAX && ldexp(box->L, -(K + 1)) >= prm->r_cut)
             ++K;
     A.cell_K = K;

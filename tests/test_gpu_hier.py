@@ -131,6 +131,107 @@ def test_hier_step_with_dzs_at_the_end(dz):
     ctx.close()
 
 
+def _split_case(kind):
+    if kind == "crossing":
+        # fast particles: a fifth of them cross a face of the box during the global step, so
+        # the kept tree's leaves and target groups straddle faces
+        ps = dzs_ics.clustered_random(4000, L, seed=93, r_clump=L / 25, vel=600.0)
+        ps.x = oracle.wrap(ps.x + 0.5 * L, L)   # clumps across the faces
+        m0 = dzs_ics.particle_mass(L, 16 ** 3)
+        obox = oracle.Box(L=L, m0=m0, eps0=L / 16 / 40)
+        g0 = oracle.total_force(ps.x, ps.y, ps.z, ps.mult, obox, NG, R_S, R_CUT)
+        return ps, obox, g0
+    return _case()
+
+
+@pytest.mark.parametrize("kind,limiter", [("clustered", False), ("clustered", True),
+                                          ("crossing", False)])
+def test_split_hier_step_matches_oracle(dz, kind, limiter):
+    """The long-range force on the global step only (pm_global): the tree is built once at a0
+    and refreshed at every sub-step boundary; against the oracle's split step at opening
+    angle 0 (the exact short-range sum): equal bins, positions and momenta to 1e-9, force
+    1e-9."""
+    import torch
+    ps, obox, g0 = _split_case(kind)
+    xo = [float(ps.x[427]), float(ps.y[427]), float(ps.z[427])] if limiter else [0.0, 0.0, 0.0]
+    R_lim = 2.0 if limiter else None
+    _log(f"hier split kind={kind} limiter={limiter}")
+    ref, ref_g, _, _, ref_bins = oracle.kdk_step_hier_split(ps, g0, obox, A0, A1, B, ETA, NG,
+                                                            R_S, R_CUT, xo, R_lim=R_lim)
+    if kind == "crossing":
+        moved = oracle.min_image(ref.x - ps.x, L)
+        crossed = np.abs(ps.x + moved - ref.x) > 0.5 * L
+        _log(f"  {int(crossed.sum())} particles crossed an x face")
+        assert crossed.sum() > 100
+    box = dz.make_box(L, obox.m0, obox.eps0)
+    ctx = dz.Context(ps.n, NG, hier_split=True)
+    st = dz.State.from_host(ps, g=g0)
+    sp = _params(dz)
+    for d in range(3):
+        sp.coarsen.x_obs[d] = xo[d]
+    ring = dz.LCRing(4096)
+    ring.reset()
+    bins = torch.zeros(ps.n, dtype=torch.uint8, device="cuda")
+    ctx.kdk_step_hier(box, st, sp, B, ETA, A0, A1, limiter=limiter, R_lim=R_lim or 0.0,
+                      ring=ring, bins_out=bins, pm_global=True)
+    torch.cuda.synchronize()
+    ctx.check()
+    got_bins = bins.cpu().numpy().astype(np.int64)
+    _log(f"  bins {np.bincount(got_bins, minlength=B + 1)}")
+    assert np.array_equal(got_bins, ref_bins)
+    assert len(np.unique(got_bins)) >= 2
+    out = st.to_host()
+    o, r = np.argsort(out["id"]), np.argsort(ref.id)
+    for k in ("x", "y", "z"):
+        d = oracle.min_image(out[k][o] - getattr(ref, k)[r], L)
+        assert np.abs(d).max() <= 1e-9 * L, k
+    for k in ("px", "py", "pz"):
+        scale = np.abs(getattr(ref, k)).max()
+        assert np.abs(out[k][o] - getattr(ref, k)[r]).max() <= 1e-9 * scale, k
+    gg = np.stack([out["gx"][o], out["gy"][o], out["gz"][o]])
+    err = math.sqrt(np.mean(np.sum((gg - ref_g[:, r]) ** 2, 0)) / np.mean(np.sum(ref_g ** 2, 0)))
+    _log(f"  g rms rel err {err:.3e}")
+    assert err <= 1e-9
+    ctx.close()
+
+
+def test_split_hier_step_with_dzs_and_its_capacity(dz):
+    import torch
+    ps, obox, g0 = _case()
+    cpar = dict(x_obs=[0.0, 0.0, 0.0], R_lc=10.0, b=1.0, theta=1.0, k_min=3)
+    ocp = {k: v for k, v in cpar.items() if k != "x_obs"}
+    ref, ref_g, _, cres, _ = oracle.kdk_step_hier_split(ps, g0, obox, A0, A1, B, ETA, NG, R_S,
+                                                        R_CUT, cpar["x_obs"], coarsen_params=ocp)
+    assert cres[2] > 0
+    box = dz.make_box(L, obox.m0, obox.eps0)
+    # without the capacity flag the form is refused
+    ctx0 = dz.Context(ps.n, NG)
+    st = dz.State.from_host(ps, g=g0)
+    with pytest.raises(dz.DZSError):
+        ctx0.kdk_step_hier(box, st, _params(dz, cpar), B, ETA, A0, A1, pm_global=True)
+    ctx0.close()
+    ctx = dz.Context(ps.n, NG, hier_split=True)
+    st = dz.State.from_host(ps, g=g0)
+    ring = dz.LCRing(4096)
+    ring.reset()
+    rep = ctx.kdk_step_hier(box, st, _params(dz, cpar), B, ETA, A0, A1, ring=ring,
+                            pm_global=True)
+    torch.cuda.synchronize()
+    assert rep.n_groups == cres[2] and st.n == ref.n
+    out = st.to_host()
+    o, r = np.argsort(out["id"]), np.argsort(ref.id)
+    for k in ("mult", "id", "type"):
+        assert np.array_equal(out[k][o], getattr(ref, k)[r]), k
+    for k in ("x", "y", "z"):
+        d = oracle.min_image(out[k][o] - getattr(ref, k)[r], L)
+        assert np.abs(d).max() <= 1e-9 * L, k
+    gg = np.stack([out["gx"][o], out["gy"][o], out["gz"][o]])
+    err = math.sqrt(np.mean(np.sum((gg - ref_g[:, r]) ** 2, 0)) / np.mean(np.sum(ref_g ** 2, 0)))
+    _log(f"  split + DZS: {cres[2]} merged nodes, g rms rel err {err:.3e}")
+    assert err <= 1e-9
+    ctx.close()
+
+
 def test_hier_rejects(dz):
     ps, obox, g0 = _case()
     box = dz.make_box(L, obox.m0, obox.eps0)

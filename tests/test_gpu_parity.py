@@ -265,6 +265,53 @@ def test_tree_force_matches_direct_sum(dz, ctx, kind, n, theta, tol, gsize):
     assert np.array_equal(st.gx[: ps.n].cpu().numpy(), g[0])
 
 
+@pytest.mark.parametrize("kind,n,gsize", [("clustered", 20000, 16), ("merged", 30001, 64)])
+def test_cell_start_walk_is_no_less_accurate_than_the_root_start(dz, ctx, kind, n, gsize):
+    """The single-box walk starts at the level-K cells at least r_cut wide and always opens
+    the nodes above them, some of which eq. 1 alone would accept as monopoles (a group box
+    can sit up to r_cut + sqrt(3) l from a node's centre of mass).  The batched step walks
+    from each box's root with eq. 1 at every level: at opening angle 0.5 both stay within the
+    bar of the direct sum, and the cell start is the more accurate of the two."""
+    import torch
+    L, ng = 100.0, 64
+    r_s = 1.25 * L / ng
+    r_cut = 4.5 * r_s
+    ps = _force_case(kind, n, L, 27)
+    _log(f"walk start kind={kind} n={ps.n} group={gsize}")
+    box, obox = _box(dz, L, ps.n, 32)
+    ref = oracle.total_force(ps.x, ps.y, ps.z, ps.mult, obox, ng, r_s, r_cut)
+    # cells: PM then the short range accumulated onto it
+    st = dz.State.from_host(ps)
+    ctx.pm_force(box, st, dz.PMParams(ng, dz.DZS_FP64, r_s, 0, 0))
+    tp = dz.TreeParams(r_s, r_cut, 0.5, 8, gsize, dz.DZS_FP64, 0)
+    tp.accumulate = 1
+    ctx.tree_force(box, st, tp)
+    torch.cuda.synchronize()
+    g_cells = np.stack([st.gx[: ps.n].cpu().numpy(), st.gy[: ps.n].cpu().numpy(),
+                        st.gz[: ps.n].cpu().numpy()])
+    # root: a batch of this one box, with zero kick and drift factors
+    st2 = dz.State.from_host(ps)
+    sp = dz.step_factors(0.5, 0.51, 0.3)
+    sp.K1 = sp.K2 = 0.0
+    sp.lc.D = 0.0
+    sp.do_lightcone, sp.do_coarsen = 0, 0
+    sp.pm = dz.PMParams(0, dz.DZS_FP64, 0.0, 0, 0)
+    sp.tree = dz.TreeParams(0.0, 0.0, 0.5, 8, gsize, dz.DZS_FP64, 0)
+    ctx.kdk_step_batch([box], [0, ps.n], [ng], [r_s], [r_cut], st2, sp)
+    torch.cuda.synchronize()
+    ctx.check()
+    h = st2.to_host()
+    o = np.argsort(h["id"])
+    assert np.array_equal(h["id"][o], np.sort(ps.id))
+    r = np.argsort(ps.id)
+    g_root = np.stack([h["gx"][o], h["gy"][o], h["gz"][o]])
+    err_cells = _rms_rel(g_cells[:, r], ref[:, r])
+    err_root = _rms_rel(g_root, ref[:, r])
+    _log(f"  total force rms rel: cells {err_cells:.3e}, root {err_root:.3e}")
+    # equal up to rounding when eq. 1 accepts no node above level K (the usual case)
+    assert err_root <= 5e-3 and err_cells <= err_root * (1.0 + 1e-9)
+
+
 @pytest.mark.parametrize("kind,n,gsize", [("clustered", 20000, 32), ("merged", 30001, 16)])
 def test_tree_force_relative_opening(dz, ctx, kind, n, gsize):
     """Relative opening criterion (G M l^2 < alpha a_min d^4, a_min from the accelerations
