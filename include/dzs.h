@@ -147,20 +147,21 @@ typedef struct {
                             interpolation: a power of two in [DZS_PM_CHUNK_MIN,
                             DZS_PM_CHUNK_MAX]; 0 = the library's default
                             (DZS_PM_CHUNK_DEFAULT); -1 = no tiles.  A workgroup takes a chunk of
-                            consecutive particles (compact in key order).  Deposit: it sums
-                            their cloud-in-cell contributions into an LDS tile spanning their
-                            points, up to 4096 of them, and adds each non-zero point to the mesh
-                            once.  Interpolation (only when the particles are at least half as
-                            many as the mesh points): it loads the potential their 4-point
-                            stencils read, up to 4096 values, into LDS once.  A chunk whose points do
-                            not fit (or, in a batch, that spans two boxes) reads and adds
+                            consecutive particles (compact in key order), in pieces.  Deposit:
+                            a piece sums its cloud-in-cell contributions into an LDS tile
+                            spanning its points, up to 4096 of them, and adds each non-zero
+                            point to the mesh once.  Interpolation (only when the particles are
+                            at least half as many as the mesh points): a piece loads the
+                            potential its 4-point stencils read, up to 32 KB of values, into LDS
+                            once.  A piece whose points do not fit (or, in a batch, that spans
+                            two boxes) is halved, down to 128 particles, which read and add
                             directly.  Mesh and forces are the same bits for every value: the
                             choice changes speed only. */
 } dzs_pm_params;
 
 #define DZS_PM_CHUNK_MIN 256
 #define DZS_PM_CHUNK_MAX 16384
-#define DZS_PM_CHUNK_DEFAULT 256
+#define DZS_PM_CHUNK_DEFAULT 2048
 
 /* Tree (short-range) parameters: g_i = -G sum m_j r_ij g_soft(r_ij, h_ij) S(r_ij/r_s) over
  * sources closer than r_cut, S(u) = erfc(u/2) + u/sqrt(pi) exp(-u^2/4).  Opening criteria

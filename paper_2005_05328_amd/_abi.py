@@ -27,7 +27,7 @@ EXPORTS = ("dzs_ctx_create", "dzs_ctx_destroy", "dzs_last_error", "dzs_step_fact
 DZS_HIER_MAX_BIN = 6
 DZS_HALT_BALANCE, DZS_HALT_RATIO, DZS_HALT_PREDICTED = 1, 2, 4
 DZS_BATCH_MAX = 512
-DZS_PM_CHUNK_MIN, DZS_PM_CHUNK_MAX, DZS_PM_CHUNK_DEFAULT = 256, 16384, 256
+DZS_PM_CHUNK_MIN, DZS_PM_CHUNK_MAX, DZS_PM_CHUNK_DEFAULT = 256, 16384, 2048
 DZS_PM_NOALLOC_MAX_SIDE = 64
 
 

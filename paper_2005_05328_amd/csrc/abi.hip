@@ -145,7 +145,8 @@ static dzs_status alloc(dzs_ctx *ctx, T **p, uint64_t count) {
 static void release(dzs_ctx *ctx) {
     void *ptrs[] = {ctx->key, ctx->key_alt, ctx->idx, ctx->idx_alt, ctx->hist, ctx->hist_scan,
                     ctx->scan_tmp, ctx->sx, ctx->sy, ctx->sz, ctx->smult, ctx->aold,
-                    ctx->hbins, ctx->active, ctx->gpm, ctx->arena, ctx->bstate, ctx->grp_first,
+                    ctx->hbins, ctx->active, ctx->gpm, ctx->grp_list, ctx->tg_flag,
+                    ctx->tg_tscan, ctx->tg_gscan, ctx->tg_pos, ctx->arena, ctx->bstate, ctx->grp_first,
                     ctx->walk_stack, ctx->walk_counter, ctx->cell_node, ctx->cell_dl,
                     ctx->batch_box, ctx->batch_tab, ctx->batch_first, ctx->batch_members,
                     ctx->step_dev, ctx->fp32_meshes ? nullptr : (void *)ctx->mesh_q, ctx->mesh_c,
@@ -257,8 +258,14 @@ static dzs_status create(dzs_ctx *c, const dzs_capacity *cap) {
     DZS_TRY(alloc(c, &c->aold, n));
     DZS_TRY(alloc(c, &c->hbins, n));
     DZS_TRY(alloc(c, &c->active, n));
-    if (cap->flags & DZS_CAP_HIER_SPLIT)
+    if (cap->flags & DZS_CAP_HIER_SPLIT) {
         DZS_TRY(alloc(c, &c->gpm, 3 * n));
+        DZS_TRY(alloc(c, &c->grp_list, n));
+        DZS_TRY(alloc(c, &c->tg_flag, n));
+        DZS_TRY(alloc(c, &c->tg_tscan, n));
+        DZS_TRY(alloc(c, &c->tg_gscan, n));
+        DZS_TRY(alloc(c, &c->tg_pos, n + 1));
+    }
     if (!(cap->flags & DZS_CAP_NO_COPIES)) {
         // tree_force's sorted copies of an input in any order
         DZS_TRY(alloc(c, &c->sx, n));
@@ -783,6 +790,11 @@ static dzs_status hier_force(dzs_ctx *ctx, const dzs_box *box, dzs_particles *st
     if (bins) {
         DZS_TRY(dzs_launch_hier_active(ctx, st->n, bins, jn, B, ctx->active, s));
         io.active = ctx->active;
+        if (ctx->grp_list && jn < (1u << B)) {
+            // a part of the targets: walked in groups of consecutive active targets
+            DZS_TRY(dzs_tree_active_targets(ctx, st->n, ctx->active, s));
+            io.target_list = true;
+        }
     }
     return dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx, st->gy, st->gz,
                          &t, s, io);
@@ -840,6 +852,24 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
         if (bins_out)
             DZS_HIP(ctx, hipMemcpyAsync(bins_out, ctx->hbins, st->n, hipMemcpyDeviceToDevice, s));
     }
+    // which bins hold particles: a sub-step boundary where none of them ends a step has no
+    // target and is skipped
+    bool populated[8] = {false};
+    if (st->n > 0) {
+        DZS_TRY(dzs_launch_bin_hist(ctx, st->n, ctx->hbins, s));
+        DZS_HIP(ctx, hipMemcpyAsync(ctx->h_small + DZS_SMALL_BIN_COUNT,
+                                    ctx->d_small + DZS_SMALL_BIN_COUNT, 8 * sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, s));
+        DZS_HIP(ctx, hipStreamSynchronize(s));
+        for (int b = 0; b <= B; ++b)
+            populated[b] = ctx->h_small[DZS_SMALL_BIN_COUNT + b] != 0u;
+    }
+    auto ends_here = [&](int jn) {
+        for (int b = 0; b <= B; ++b)
+            if (populated[b] && jn % (1 << (B - b)) == 0)
+                return true;
+        return false;
+    };
     // the long-range force on the global step: state in key order and tree once, at a0; the
     // PM force at a0 (into gpm) opens the step with its half-kick and leaves g the short-range
     // part of the entry force
@@ -861,6 +891,7 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
         DZS_TRY(dzs_launch_kick(ctx, &pmv, dzs_kick_factor(a0, u[S], om), s));
         DZS_TRY(dzs_tree_build(ctx, box, st->n, st->x, st->y, st->z, st->mult, t.leaf_size,
                                t.group_size, s));
+        DZS_TRY(dzs_drift_bound_reset(ctx, s));
     }
     for (int j = 0; j < S && st->n > 0; ++j) {
         double K[DZS_HIER_MAX_BIN + 1] = {0.0};
@@ -872,9 +903,13 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
         DZS_TRY(dzs_launch_kick_bins(ctx, st, ctx->hbins, K, s));
         dzs_step_params sub = *prm;
         DZS_TRY(dzs_step_factors(u[2 * j], u[2 * j + 2], om, &sub));
+        if (split)   // the kept tree's walk widens its start cells by the displacement bound
+            DZS_TRY(dzs_drift_bound_add(ctx, st, sub.lc.D, s));
         DZS_TRY(dzs_launch_drift_lc(ctx, box, st, &sub.lc, ring, prm->do_lightcone, 1, s));
         const int jn = j + 1;
-        if (split) {
+        if (!ends_here(jn)) {
+            // no particle ends a step here: no force, no kick
+        } else if (split) {
             // the short-range force of the targets that end a step here, on the kept tree
             DZS_TRY(dzs_tree_refresh(ctx, box, st->n, st->x, st->y, st->z, st->mult, s));
             DZS_TRY(dzs_launch_hier_active(ctx, st->n, ctx->hbins, (uint32_t)jn, (uint32_t)B,
@@ -884,6 +919,11 @@ extern "C" dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_partic
             dzs_walk_io io;
             io.active = ctx->active;
             io.kept_tree = true;
+            if (jn < S) {
+                // a part of the targets: walked in groups of consecutive active targets
+                DZS_TRY(dzs_tree_active_targets(ctx, st->n, ctx->active, s));
+                io.target_list = true;
+            }
             DZS_TRY(dzs_tree_walk(ctx, box, st->n, st->x, st->y, st->z, st->mult, st->gx,
                                   st->gy, st->gz, &ts, s, io));
         } else {
@@ -995,7 +1035,7 @@ extern "C" dzs_status kdk_step_batch(dzs_ctx *ctx, const dzs_batch *batch, dzs_p
         h.rcut2 = rc * rc;
         h.rs_inv = 1.0 / rs;
         h.rs_inv2 = h.rs_inv * h.rs_inv;
-        h.wide_limit = h.halfL - rc;
+        h.wide_limit = 0.5 * (h.halfL - rc);   // see the walk's minimum-image rule
         h.first = batch->first[b];
         h.count = batch->first[b + 1] - batch->first[b];
         h.ng = batch->ng[b];

@@ -136,6 +136,8 @@ struct dzs_ctx {
     struct dzs_node_rec *nd_rec = nullptr;  // moments and topology as the walk reads them
     int tree_deepest = 0;                    // deepest level the last build may have made
     double *gpm = nullptr;  // [3 cap] the PM force of the split individual step (capacity flag)
+    uint32_t *grp_list = nullptr;  // [cap] slots of the active targets (same capacity flag)
+    uint32_t *tg_flag = nullptr, *tg_tscan = nullptr, *tg_gscan = nullptr, *tg_pos = nullptr;
     uint32_t *frontier = nullptr, *frontier_next = nullptr;
     uint32_t *fr_nchild = nullptr, *fr_ninternal = nullptr, *fr_child_off = nullptr,
              *fr_int_off = nullptr;
@@ -393,6 +395,8 @@ struct dzs_walk_io {
     // a tree kept from an earlier build and refreshed (dzs_tree_refresh): the walk starts at
     // the root and unwraps targets and leaf members that crossed a face of the box
     bool kept_tree = false;
+    // walk only the targets listed by dzs_tree_active_targets, in its groups
+    bool target_list = false;
 };
 // Recompute the moments and bounding boxes of the last built tree from positions that moved
 // since (same particles in the same slots), bottom-up, unwrapping members that crossed a
@@ -448,6 +452,26 @@ dzs_status dzs_pm_run_batch(dzs_ctx *ctx, const dzs_particles *p, int precision,
 #define DZS_SMALL_UNSORTED 20
 // d_small word 24: largest bin + 1 inside the limiter sphere (0: nobody inside)
 #define DZS_SMALL_HIER_CAP 24
+// d_small words 26..27: the bits of the current sub-step's largest drift bound; 28..29: the
+// bound on any particle's displacement since the kept tree was built (a double)
+#define DZS_SMALL_DRIFT_STEP 26
+#define DZS_SMALL_DRIFT_TOTAL 28
+// d_small word 30: the number of targets in ctx->grp_list, 31: the number of their groups;
+// 32..39: particles per time-step bin
+#define DZS_SMALL_GROUP_LIST 30
+#define DZS_SMALL_BIN_COUNT 32
+// Particles per bin (bins 0..7) into d_small[DZS_SMALL_BIN_COUNT ..].
+dzs_status dzs_launch_bin_hist(dzs_ctx *ctx, uint64_t n, const uint8_t *bins, hipStream_t s);
+// The slots of the targets flagged in `active`, ascending, in ctx->grp_list (their number in
+// d_small[DZS_SMALL_GROUP_LIST]), grouped as the last built tree groups them, groups without
+// a flagged target left out (start positions in ctx->tg_pos, their number in the next word),
+// for the walk to take instead of every tree group.
+dzs_status dzs_tree_active_targets(dzs_ctx *ctx, uint64_t n, const uint8_t *active,
+                                   hipStream_t s);
+// The kept tree's displacement bound: reset (at the build), add a drift's
+// max_i (|px| + |py| + |pz|) |D| (before it), both on the device.
+dzs_status dzs_drift_bound_reset(dzs_ctx *ctx, hipStream_t s);
+dzs_status dzs_drift_bound_add(dzs_ctx *ctx, const dzs_particles *p, double D, hipStream_t s);
 // Reduce the dynamical criterion's a_min^2 over the state (before any reordering that leaves
 // g behind) into d_small[DZS_SMALL_AMIN].
 dzs_status dzs_coarsen_amin(dzs_ctx *ctx, const dzs_box *box, const dzs_particles *p,

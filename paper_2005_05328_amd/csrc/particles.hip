@@ -62,6 +62,63 @@ dzs_status dzs_launch_add3(dzs_ctx *ctx, uint64_t n, double *ax, double *ay, dou
     return dzs_check_launch(ctx, "add3");
 }
 
+// Largest |px| + |py| + |pz| times |D| (a bound on the drift's displacement) over the state:
+// a block maximum, one atomic per block on the bits of the non-negative double.
+__global__ __launch_bounds__(PT_THREADS) void k_drift_bound(uint64_t n,
+                                                            const double *__restrict__ px,
+                                                            const double *__restrict__ py,
+                                                            const double *__restrict__ pz,
+                                                            double D,
+                                                            unsigned long long *step_max) {
+    __shared__ double s_m[PT_THREADS / 64];
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    double v = 0.0;
+    if (i < n)
+        v = (fabs(px[i]) + fabs(py[i]) + fabs(pz[i])) * fabs(D);
+    for (int o = 32; o >= 1; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63u) == 0u)
+        s_m[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = s_m[0];
+        for (int w = 1; w < PT_THREADS / 64; ++w)
+            m = fmax(m, s_m[w]);
+        atomicMax(step_max, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// total += the step's bound; the step's slot back to zero
+__global__ void k_drift_bound_acc(unsigned long long *step_max, double *total) {
+    *total = *total + __longlong_as_double((long long)*step_max);
+    *step_max = 0ull;
+}
+
+__global__ void k_drift_bound_reset(unsigned long long *step_max, double *total) {
+    *step_max = 0ull;
+    *total = 0.0;
+}
+
+dzs_status dzs_drift_bound_reset(dzs_ctx *ctx, hipStream_t s) {
+    hipLaunchKernelGGL(k_drift_bound_reset, dim3(1), dim3(1), 0, s,
+                       (unsigned long long *)(ctx->d_small + DZS_SMALL_DRIFT_STEP),
+                       (double *)(ctx->d_small + DZS_SMALL_DRIFT_TOTAL));
+    return dzs_check_launch(ctx, "drift_bound_reset");
+}
+
+dzs_status dzs_drift_bound_add(dzs_ctx *ctx, const dzs_particles *p, double D, hipStream_t s) {
+    if (p->n == 0)
+        return DZS_OK;
+    unsigned long long *step = (unsigned long long *)(ctx->d_small + DZS_SMALL_DRIFT_STEP);
+    hipLaunchKernelGGL(k_drift_bound, dim3(blocks_for(p->n, PT_THREADS)), dim3(PT_THREADS), 0, s,
+                       p->n, (const double *)p->px, (const double *)p->py,
+                       (const double *)p->pz, D, step);
+    DZS_TRY(dzs_check_launch(ctx, "drift_bound"));
+    hipLaunchKernelGGL(k_drift_bound_acc, dim3(1), dim3(1), 0, s, step,
+                       (double *)(ctx->d_small + DZS_SMALL_DRIFT_TOTAL));
+    return dzs_check_launch(ctx, "drift_bound_acc");
+}
+
 // box of particle i in a batch: the last b with first[b] <= i (first[] ascending, nb entries)
 __device__ __forceinline__ uint32_t batch_box_of(const uint64_t *first, uint32_t nb, uint64_t i) {
     uint32_t lo = 0, hi = nb - 1;
@@ -560,6 +617,37 @@ __global__ __launch_bounds__(PT_THREADS) void k_hier_active(uint64_t n,
     const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
     if (i < n)
         active[i] = (jn & ((1u << (B - bins[i])) - 1u)) == 0u ? 1u : 0u;
+}
+
+__global__ void k_bin_hist_clear(uint32_t *counts) {
+    for (int b = 0; b < 8; ++b)
+        counts[b] = 0u;
+}
+
+__global__ __launch_bounds__(PT_THREADS) void k_bin_hist(uint64_t n,
+                                                         const uint8_t *__restrict__ bins,
+                                                         uint32_t *counts) {
+    __shared__ uint32_t s_c[8];
+    if (threadIdx.x < 8)
+        s_c[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * PT_THREADS + threadIdx.x;
+    if (i < n)
+        atomicAdd(&s_c[bins[i] & 7u], 1u);
+    __syncthreads();
+    if (threadIdx.x < 8 && s_c[threadIdx.x])
+        atomicAdd(&counts[threadIdx.x], s_c[threadIdx.x]);
+}
+
+dzs_status dzs_launch_bin_hist(dzs_ctx *ctx, uint64_t n, const uint8_t *bins, hipStream_t s) {
+    uint32_t *counts = ctx->d_small + DZS_SMALL_BIN_COUNT;
+    hipLaunchKernelGGL(k_bin_hist_clear, dim3(1), dim3(1), 0, s, counts);
+    DZS_TRY(dzs_check_launch(ctx, "bin_hist_clear"));
+    if (n == 0)
+        return DZS_OK;
+    hipLaunchKernelGGL(k_bin_hist, dim3(blocks_for(n, PT_THREADS)), dim3(PT_THREADS), 0, s, n,
+                       bins, counts);
+    return dzs_check_launch(ctx, "bin_hist");
 }
 
 dzs_status dzs_launch_hier_active(dzs_ctx *ctx, uint64_t n, const uint8_t *bins, uint32_t jn,

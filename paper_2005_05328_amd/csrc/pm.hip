@@ -27,7 +27,8 @@
 #define FFT_MAX_SLOTS 4
 #define DEP_FRAC 4294967296.0  // 2^32: fixed-point scale of the deposit
 #define DEP_TILE 4096          // mesh points of the LDS deposit tile (32 KB of 64-bit sums)
-#define INTERP_TILE 4096       // potential values of the LDS interpolation tile
+#define INTERP_TILE_BYTES 32768  // LDS interpolation tile (8192 FP32 / 4096 FP64 values)
+#define PM_PIECE_MIN 128       // smallest piece of a chunk that still tries an LDS tile
 
 static inline uint32_t blocks_for(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
 
@@ -286,84 +287,100 @@ __device__ __forceinline__ void chunk_bounds(uint64_t p0, uint64_t p1, const dou
 }
 
 // LDS-binned deposit.  A workgroup takes `chunk` consecutive particles (in key order they
-// fill a compact region), finds the box of mesh points their clouds touch (unwrapped
-// indices, so a region across the periodic boundary stays compact) and, when it holds at most
-// DEP_TILE points and the particles share one box of a batch, sums their contributions into
-// an LDS tile with 64-bit LDS atomics and then adds each non-zero tile point to the mesh
-// (wrapped) with one global atomic.  Otherwise the chunk adds directly.  The mesh is the same
-// integer sum either way.
+// fill a compact region) in pieces: a piece finds the box of mesh points its clouds touch
+// (unwrapped indices, so a region across the periodic boundary stays compact) and, when it
+// holds at most DEP_TILE points and the particles share one box of a batch, sums their
+// contributions into an LDS tile with 64-bit LDS atomics, then adds each non-zero tile point
+// to the mesh (wrapped) with one global atomic.  A piece whose box is too large is halved (a
+// sparse region) down to PM_PIECE_MIN particles, below which it adds directly.  The mesh is
+// the same integer sum either way.
 __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
     uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const uint32_t *__restrict__ mult, double delta, int ng,
     unsigned long long *__restrict__ q, pm_batch B, uint32_t chunk) {
     __shared__ unsigned long long s_tile[DEP_TILE];
     __shared__ int s_red[PM_THREADS / 64][8];
-    const uint64_t p0 = (uint64_t)blockIdx.x * chunk;
-    const uint64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
     const uint32_t tid = threadIdx.x;
-    int lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi;
-    chunk_bounds(p0, p1, x, y, z, delta, B, s_red, lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi);
-    // points spanned per axis (base .. base + 1); every thread holds the same values, so the
-    // choice below is uniform over the workgroup
-    const int64_t ex = (int64_t)hi0 - lo0 + 2, ey = (int64_t)hi1 - lo1 + 2,
-                  ez = (int64_t)hi2 - lo2 + 2;
-    const bool fits = (!B.boxes || blo == bhi) && ex <= DEP_TILE && ey <= DEP_TILE &&
-                      ez <= DEP_TILE && ex * ey * ez <= DEP_TILE;
-    unsigned long long *qb = q;
-    if (B.boxes && blo == bhi) {
-        const dzs_bbox &bx = B.boxes[blo];
-        delta = bx.delta;
-        ng = bx.ng;
-        qb = q + bx.mesh_off;
-    }
-    if (!fits) {
-        for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
-            double d = delta;
-            int g = ng;
-            unsigned long long *qq = q;
-            if (B.boxes) {
-                const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
-                d = bx.delta;
-                g = bx.ng;
-                qq = q + bx.mesh_off;
-            }
-            dep_direct(x, y, z, mult, p, d, g, qq);
-        }
-        return;
-    }
-    const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez;
-    const uint32_t cells = (uint32_t)(ex * ey * ez);
-    for (uint32_t c = tid; c < cells; c += PM_THREADS)
-        s_tile[c] = 0ull;
-    __syncthreads();
-    for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
-        double wx[2], wy[2], wz[2];
-        const uint32_t i = (uint32_t)(cic_base(x[p], delta, wx[0], wx[1]) - lo0);
-        const uint32_t j = (uint32_t)(cic_base(y[p], delta, wy[0], wy[1]) - lo1);
-        const uint32_t k = (uint32_t)(cic_base(z[p], delta, wz[0], wz[1]) - lo2);
-        const double m = (double)mult[p] * DEP_FRAC;
-#pragma unroll
-        for (uint32_t a = 0; a < 2; ++a)
-#pragma unroll
-            for (uint32_t b = 0; b < 2; ++b)
-#pragma unroll
-                for (uint32_t c = 0; c < 2; ++c) {
-                    const unsigned long long iv = dep_fixed(m, wx[a], wy[b], wz[c]);
-                    if (iv)
-                        atomicAdd(&s_tile[((i + a) * tey + (j + b)) * tez + (k + c)], iv);
-                }
-    }
-    __syncthreads();
-    const uint32_t pyz = tey * tez;
-    for (uint32_t c = tid; c < cells; c += PM_THREADS) {
-        const unsigned long long v = s_tile[c];
-        if (!v)
+    uint64_t p0 = c0;
+    uint32_t piece = chunk;
+    while (p0 < c1) {
+        const uint64_t p1 = p0 + piece < c1 ? p0 + piece : c1;
+        int lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi;
+        chunk_bounds(p0, p1, x, y, z, delta, B, s_red, lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi);
+        // points spanned per axis (base .. base + 1); every thread holds the same values, so
+        // the choices below are uniform over the workgroup
+        const int64_t ex = (int64_t)hi0 - lo0 + 2, ey = (int64_t)hi1 - lo1 + 2,
+                      ez = (int64_t)hi2 - lo2 + 2;
+        const bool fits = (!B.boxes || blo == bhi) && ex <= DEP_TILE && ey <= DEP_TILE &&
+                          ez <= DEP_TILE && ex * ey * ez <= DEP_TILE;
+        __syncthreads();   // s_red is read by every thread before the next piece writes it
+        if (!fits && piece > PM_PIECE_MIN) {
+            piece >>= 1;
             continue;
-        const uint32_t a = c / pyz, r = c - a * pyz;
-        const uint32_t b = r / tez, e = r - b * tez;
-        const int ix = wrap_index(lo0 + (int)a, ng), iy = wrap_index(lo1 + (int)b, ng),
-                  iz = wrap_index(lo2 + (int)e, ng);
-        atomicAdd(&qb[((uint64_t)ix * ng + iy) * ng + iz], v);
+        }
+        if (!fits) {
+            for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+                double d = delta;
+                int g = ng;
+                unsigned long long *qq = q;
+                if (B.boxes) {
+                    const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
+                    d = bx.delta;
+                    g = bx.ng;
+                    qq = q + bx.mesh_off;
+                }
+                dep_direct(x, y, z, mult, p, d, g, qq);
+            }
+            p0 = p1;
+            continue;
+        }
+        double dl = delta;
+        int gn = ng;
+        unsigned long long *qb = q;
+        if (B.boxes) {
+            const dzs_bbox &bx = B.boxes[blo];
+            dl = bx.delta;
+            gn = bx.ng;
+            qb = q + bx.mesh_off;
+        }
+        const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez;
+        const uint32_t cells = (uint32_t)(ex * ey * ez);
+        for (uint32_t c = tid; c < cells; c += PM_THREADS)
+            s_tile[c] = 0ull;
+        __syncthreads();
+        for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+            double wx[2], wy[2], wz[2];
+            const uint32_t i = (uint32_t)(cic_base(x[p], dl, wx[0], wx[1]) - lo0);
+            const uint32_t j = (uint32_t)(cic_base(y[p], dl, wy[0], wy[1]) - lo1);
+            const uint32_t k = (uint32_t)(cic_base(z[p], dl, wz[0], wz[1]) - lo2);
+            const double m = (double)mult[p] * DEP_FRAC;
+#pragma unroll
+            for (uint32_t a = 0; a < 2; ++a)
+#pragma unroll
+                for (uint32_t b = 0; b < 2; ++b)
+#pragma unroll
+                    for (uint32_t c = 0; c < 2; ++c) {
+                        const unsigned long long iv = dep_fixed(m, wx[a], wy[b], wz[c]);
+                        if (iv)
+                            atomicAdd(&s_tile[((i + a) * tey + (j + b)) * tez + (k + c)], iv);
+                    }
+        }
+        __syncthreads();
+        const uint32_t pyz = tey * tez;
+        for (uint32_t c = tid; c < cells; c += PM_THREADS) {
+            const unsigned long long v = s_tile[c];
+            if (!v)
+                continue;
+            const uint32_t a = c / pyz, r = c - a * pyz;
+            const uint32_t b = r / tez, e = r - b * tez;
+            const int ix = wrap_index(lo0 + (int)a, gn), iy = wrap_index(lo1 + (int)b, gn),
+                      iz = wrap_index(lo2 + (int)e, gn);
+            atomicAdd(&qb[((uint64_t)ix * gn + iy) * gn + iz], v);
+        }
+        __syncthreads();   // the tile is read before the next piece clears it
+        p0 = p1;
     }
 }
 
@@ -644,71 +661,92 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_interp(
     interp_direct<Rt>(x, y, z, phi, p, delta, ng, gx, gy, gz, accumulate);
 }
 
-// LDS-staged: a workgroup takes `chunk` consecutive particles, loads once the block of
-// potential values their stencils read (base - 2 .. base + 3 on each axis, wrapped) into LDS
-// when it holds at most INTERP_TILE values and the chunk lies in one box of a batch, and
-// evaluates every particle from LDS; otherwise each particle reads the mesh directly.
+// LDS-staged: a workgroup takes `chunk` consecutive particles in pieces; a piece loads once
+// the block of potential values its stencils read (base - 2 .. base + 3 on each axis,
+// wrapped) into a 32 KB LDS tile when they fit and the piece lies in one box of a batch, and
+// evaluates every particle from LDS.  A piece whose block is too large is halved down to
+// PM_PIECE_MIN particles, below which each particle reads the mesh directly (the same values
+// and arithmetic: the result does not depend on the path).
 template <typename Rt>
 __global__ __launch_bounds__(PM_THREADS) void k_pm_interp_tiled(
     uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const Rt *__restrict__ phi, double delta, int ng,
     double *__restrict__ gx, double *__restrict__ gy, double *__restrict__ gz, int accumulate,
     pm_batch B, uint32_t chunk) {
-    __shared__ Rt s_phi[INTERP_TILE];
+    constexpr uint32_t TILE = INTERP_TILE_BYTES / sizeof(Rt);
+    __shared__ Rt s_phi[TILE];
     __shared__ int s_red[PM_THREADS / 64][8];
-    const uint64_t p0 = (uint64_t)blockIdx.x * chunk;
-    const uint64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
     const uint32_t tid = threadIdx.x;
-    int lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi;
-    chunk_bounds(p0, p1, x, y, z, delta, B, s_red, lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi);
-    const int64_t ex = (int64_t)hi0 - lo0 + 6, ey = (int64_t)hi1 - lo1 + 6,
-                  ez = (int64_t)hi2 - lo2 + 6;
-    const bool fits = (!B.boxes || blo == bhi) && ex <= INTERP_TILE && ey <= INTERP_TILE &&
-                      ez <= INTERP_TILE && ex * ey * ez <= INTERP_TILE;
-    if (!fits) {
-        for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
-            double d = delta;
-            int g = ng;
-            const Rt *ph = phi;
-            if (B.boxes) {
-                const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
-                d = bx.delta;
-                g = bx.ng;
-                ph = phi + bx.mesh_off;
-            }
-            interp_direct<Rt>(x, y, z, ph, p, d, g, gx, gy, gz, accumulate);
+    uint64_t p0 = c0;
+    uint32_t piece = chunk;
+    while (p0 < c1) {
+        const uint64_t p1 = p0 + piece < c1 ? p0 + piece : c1;
+        int lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi;
+        chunk_bounds(p0, p1, x, y, z, delta, B, s_red, lo0, lo1, lo2, hi0, hi1, hi2, blo, bhi);
+        const int64_t ex = (int64_t)hi0 - lo0 + 6, ey = (int64_t)hi1 - lo1 + 6,
+                      ez = (int64_t)hi2 - lo2 + 6;
+        const bool fits = (!B.boxes || blo == bhi) && ex <= TILE && ey <= TILE && ez <= TILE &&
+                          ex * ey * ez <= TILE;
+        __syncthreads();   // s_red is read by every thread before the next piece writes it
+        if (!fits && piece > PM_PIECE_MIN) {
+            piece >>= 1;
+            continue;
         }
-        return;
-    }
-    if (B.boxes) {
-        const dzs_bbox &bx = B.boxes[blo];
-        delta = bx.delta;
-        ng = bx.ng;
-        phi += bx.mesh_off;
-    }
-    const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez, pyz = tey * tez;
-    const uint32_t cells = (uint32_t)(ex * ey * ez);
-    const uint64_t N = (uint64_t)ng;
-    for (uint32_t c = tid; c < cells; c += PM_THREADS) {
-        const uint32_t a = c / pyz, r = c - a * pyz;
-        const uint32_t b = r / tez, e = r - b * tez;
-        const int ix = wrap_index(lo0 - 2 + (int)a, ng), iy = wrap_index(lo1 - 2 + (int)b, ng),
-                  iz = wrap_index(lo2 - 2 + (int)e, ng);
-        s_phi[c] = phi[((uint64_t)ix * N + iy) * N + iz];
-    }
-    __syncthreads();
-    for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
-        double wx[2], wy[2], wz[2];
-        // tile coordinates of the base point (the tile starts at lo - 2)
-        const int i = cic_base(x[p], delta, wx[0], wx[1]) - lo0 + 2;
-        const int j = cic_base(y[p], delta, wy[0], wy[1]) - lo1 + 2;
-        const int k = cic_base(z[p], delta, wz[0], wz[1]) - lo2 + 2;
-        auto at = [&](int a, int b, int c) -> Rt {
-            return s_phi[((uint32_t)(i + a) * tey + (uint32_t)(j + b)) * tez + (uint32_t)(k + c)];
-        };
-        Rt sx, sy, sz;
-        cic_gradient<Rt>(at, wx, wy, wz, sx, sy, sz);
-        interp_store<Rt>(p, delta, sx, sy, sz, gx, gy, gz, accumulate);
+        if (!fits) {
+            for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+                double d = delta;
+                int g = ng;
+                const Rt *ph = phi;
+                if (B.boxes) {
+                    const dzs_bbox &bx = B.boxes[B.key[p] >> DZS_BATCH_SHIFT];
+                    d = bx.delta;
+                    g = bx.ng;
+                    ph = phi + bx.mesh_off;
+                }
+                interp_direct<Rt>(x, y, z, ph, p, d, g, gx, gy, gz, accumulate);
+            }
+            p0 = p1;
+            continue;
+        }
+        double dl = delta;
+        int gn = ng;
+        const Rt *pb = phi;
+        if (B.boxes) {
+            const dzs_bbox &bx = B.boxes[blo];
+            dl = bx.delta;
+            gn = bx.ng;
+            pb = phi + bx.mesh_off;
+        }
+        const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez, pyz = tey * tez;
+        const uint32_t cells = (uint32_t)(ex * ey * ez);
+        const uint64_t N = (uint64_t)gn;
+        for (uint32_t c = tid; c < cells; c += PM_THREADS) {
+            const uint32_t a = c / pyz, r = c - a * pyz;
+            const uint32_t b = r / tez, e = r - b * tez;
+            const int ix = wrap_index(lo0 - 2 + (int)a, gn),
+                      iy = wrap_index(lo1 - 2 + (int)b, gn),
+                      iz = wrap_index(lo2 - 2 + (int)e, gn);
+            s_phi[c] = pb[((uint64_t)ix * N + iy) * N + iz];
+        }
+        __syncthreads();
+        for (uint64_t p = p0 + tid; p < p1; p += PM_THREADS) {
+            double wx[2], wy[2], wz[2];
+            // tile coordinates of the base point (the tile starts at lo - 2)
+            const int i = cic_base(x[p], dl, wx[0], wx[1]) - lo0 + 2;
+            const int j = cic_base(y[p], dl, wy[0], wy[1]) - lo1 + 2;
+            const int k = cic_base(z[p], dl, wz[0], wz[1]) - lo2 + 2;
+            auto at = [&](int a, int b, int c) -> Rt {
+                return s_phi[((uint32_t)(i + a) * tey + (uint32_t)(j + b)) * tez +
+                             (uint32_t)(k + c)];
+            };
+            Rt sx, sy, sz;
+            cic_gradient<Rt>(at, wx, wy, wz, sx, sy, sz);
+            interp_store<Rt>(p, dl, sx, sy, sz, gx, gy, gz, accumulate);
+        }
+        __syncthreads();   // the tile is read before the next piece loads it
+        p0 = p1;
     }
 }
 

@@ -377,6 +377,86 @@ __global__ __launch_bounds__(TB_THREADS) void k_group_compact(uint32_t n,
         grp_first[scan[n - 1] + flag[n - 1]] = n;
 }
 
+__global__ __launch_bounds__(TB_THREADS) void k_fill_u32(uint64_t n, uint32_t *a, uint32_t v);
+
+// flag[i] = 1 for a flagged target
+__global__ __launch_bounds__(TB_THREADS) void k_target_flag(uint32_t n,
+                                                            const uint8_t *__restrict__ active,
+                                                            uint32_t *__restrict__ flag) {
+    const uint32_t i = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (i < n)
+        flag[i] = active[i] != 0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(TB_THREADS) void k_target_list(uint32_t n,
+                                                            const uint32_t *__restrict__ flag,
+                                                            const uint32_t *__restrict__ scan,
+                                                            uint32_t *__restrict__ list) {
+    const uint32_t i = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (i < n && flag[i])
+        list[scan[i]] = i;
+}
+
+// The tree's groups that hold a flagged target start a group of the target list at their
+// first slot (the group then holds its flagged targets only; a group without one is left out).
+__global__ __launch_bounds__(TB_THREADS) void k_target_groups(
+    uint32_t n, const uint32_t *__restrict__ n_groups, const uint32_t *__restrict__ grp_first,
+    const uint8_t *__restrict__ active, uint32_t *__restrict__ flag) {
+    const uint32_t g = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (g >= n || g >= *n_groups)
+        return;
+    uint32_t any = 0u;
+    for (uint32_t j = grp_first[g]; j < grp_first[g + 1] && !any; ++j)
+        any = active[j] != 0 ? 1u : 0u;
+    if (any)
+        flag[grp_first[g]] = 1u;
+}
+
+// pos[k] = the target-list position where group k starts; pos[count] = the number of targets
+__global__ __launch_bounds__(TB_THREADS) void k_target_group_pos(
+    uint32_t n, const uint32_t *__restrict__ gflag, const uint32_t *__restrict__ gscan,
+    const uint32_t *__restrict__ tscan, const uint32_t *__restrict__ n_tgt,
+    const uint32_t *__restrict__ n_grp, uint32_t *__restrict__ pos) {
+    const uint32_t i = blockIdx.x * TB_THREADS + threadIdx.x;
+    if (i < n && gflag[i])
+        pos[gscan[i]] = tscan[i];
+    if (i == 0)
+        pos[*n_grp] = *n_tgt;
+}
+
+dzs_status dzs_tree_active_targets(dzs_ctx *ctx, uint64_t n64, const uint8_t *active,
+                                   hipStream_t s) {
+    const uint32_t n = (uint32_t)n64;
+    if (!ctx->grp_list || !ctx->tree_built || n != ctx->tree_n)
+        return dzs_fail(ctx, DZS_EINVAL, "active targets: no target list or no tree");
+    uint32_t *n_tgt = ctx->d_small + DZS_SMALL_GROUP_LIST;
+    uint32_t *n_grp = ctx->d_small + DZS_SMALL_GROUP_LIST + 1;
+    // the target list
+    hipLaunchKernelGGL(k_target_flag, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s, n,
+                       active, ctx->tg_flag);
+    DZS_TRY(dzs_check_launch(ctx, "target_flag"));
+    DZS_TRY(dzs_scan_u32(ctx, ctx->tg_flag, ctx->tg_tscan, n, n_tgt, s));
+    hipLaunchKernelGGL(k_target_list, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s, n,
+                       (const uint32_t *)ctx->tg_flag, (const uint32_t *)ctx->tg_tscan,
+                       ctx->grp_list);
+    DZS_TRY(dzs_check_launch(ctx, "target_list"));
+    // their groups (the tree's, less the unflagged targets): flags at group-start slots, then
+    // the list positions where they start
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s,
+                       (uint64_t)n, ctx->tg_flag, 0u);
+    DZS_TRY(dzs_check_launch(ctx, "target_group_clear"));
+    hipLaunchKernelGGL(k_target_groups, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0, s,
+                       n, (const uint32_t *)(ctx->bstate + BS_GROUPS),
+                       (const uint32_t *)ctx->grp_first, active, ctx->tg_flag);
+    DZS_TRY(dzs_check_launch(ctx, "target_groups"));
+    DZS_TRY(dzs_scan_u32(ctx, ctx->tg_flag, ctx->tg_gscan, n, n_grp, s));
+    hipLaunchKernelGGL(k_target_group_pos, dim3(blocks_for(n, TB_THREADS)), dim3(TB_THREADS), 0,
+                       s, n, (const uint32_t *)ctx->tg_flag, (const uint32_t *)ctx->tg_gscan,
+                       (const uint32_t *)ctx->tg_tscan, (const uint32_t *)n_tgt,
+                       (const uint32_t *)n_grp, ctx->tg_pos);
+    return dzs_check_launch(ctx, "target_group_pos");
+}
+
 dzs_status dzs_tree_build(dzs_ctx *ctx, const dzs_box *box, uint64_t n64, const double *x,
                           const double *y, const double *z, const uint32_t *mult, int leaf_size,
                           int group_size, hipStream_t s) {
@@ -630,8 +710,16 @@ struct walk_args {
     const uint32_t *out_perm;
     const uint32_t *bad;  // tree_force input rejected on the device: the walk does nothing
     // a kept, refreshed tree: targets are taken at the image next to the group's first one,
-    // and a leaf flagged for members across a face keeps them all with minimum-image pairs
+    // and a leaf flagged for members across a face keeps them all with minimum-image pairs;
+    // the start cells are widened by the bound on every particle's displacement since the
+    // build (device), since a node's particles may have left its cell
     int kept;
+    const double *cell_extra;
+    // only these targets (nullptr: the tree's groups): tgt[] in slot order, group g holding
+    // tgt[tpos[g] .. tpos[g + 1]), g < *n_tgrp
+    const uint32_t *tgt;
+    const uint32_t *tpos;
+    const uint32_t *n_tgrp;
 };
 
 // Geometry and constants of the box a group lives in.
@@ -960,13 +1048,25 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
         __syncthreads();
         const uint32_t g = s_g;
         __syncthreads();
-        if (g >= *A.n_groups)
-            break;
-        const uint32_t first = A.grp_first[g];
-        const uint32_t cnt = A.grp_first[g + 1] - first;
+        uint32_t first, cnt;
+        if (A.tgt) {
+            if (g >= *A.n_tgrp)
+                break;
+            first = A.tpos[g];
+            cnt = A.tpos[g + 1] - first;
+            if (cnt == 0u)
+                continue;   // a group start with no flagged target before the next one
+        } else {
+            if (g >= *A.n_groups)
+                break;
+            first = A.grp_first[g];
+            cnt = A.grp_first[g + 1] - first;
+        }
         // a source node and the group may be wide enough that the image nearest the group
-        // centre is not every pair's nearest image; above W.wide (half-extent sum) the pair
-        // loop reduces each separation to the minimum image
+        // centre is not every pair's nearest image: an entry kept for the group lies within
+        // 2 (h_node + h_group) + r_cut of any of its targets per axis, which must not exceed
+        // L/2; above W.wide (half-extent sum (L/2 - r_cut) / 2) the pair loop reduces each
+        // separation to the minimum image
         walk_geom W;
         if (BATCH) {
             const dzs_bbox &bx = A.boxes[A.key[first] >> DZS_BATCH_SHIFT];
@@ -974,10 +1074,10 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                           bx.G,      bx.m0,      bx.h0,    bx.wide_limit, bx.root};
         } else {
             W = walk_geom{A.L,  A.halfL, A.rcut, A.rcut2, A.rs_inv, A.rs_inv2,
-                          A.G,  A.m0,    A.h0,   A.halfL - A.rcut, 0u};
+                          A.G,  A.m0,    A.h0,   0.5 * (A.halfL - A.rcut), 0u};
         }
         const bool valid = tl < cnt;
-        const uint32_t i = valid ? first + tl : first;
+        const uint32_t i = A.tgt ? A.tgt[valid ? first + tl : first] : (valid ? first + tl : first);
         const bool active = valid && (!A.active || A.active[i] != 0);
         if (A.active && __ballot(active) == 0ull)
             continue;  // no target in this group
@@ -1081,7 +1181,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
             // rounding, so that every particle in it is found in a listed cell), wrapped
             const int K = A.cell_K;
             const int side = 1 << K, kmask = side - 1;
-            const double inv = (double)side / W.L, margin = 1e-9 * W.L;
+            const double inv = (double)side / W.L,
+                         margin = 1e-9 * W.L + (A.cell_extra ? *A.cell_extra : 0.0);
             const int lox = (int)floor((mnx - W.rcut - margin) * inv);
             const int loy = (int)floor((mny - W.rcut - margin) * inv);
             const int loz = (int)floor((mnz - W.rcut - margin) * inv);
@@ -1490,6 +1591,12 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.out_perm = boxes ? nullptr : io.out_perm;
     A.bad = ctx->bstate + DZS_BS_BADINPUT;
     A.kept = (io.kept_tree && !boxes) ? 1 : 0;
+    A.cell_extra = A.kept ? (const double *)(ctx->d_small + DZS_SMALL_DRIFT_TOTAL) : nullptr;
+    if (io.target_list && !boxes && ctx->grp_list) {
+        A.tgt = ctx->grp_list;
+        A.tpos = ctx->tg_pos;
+        A.n_tgrp = ctx->d_small + DZS_SMALL_GROUP_LIST + 1;
+    }
     A.alpha_g = relative ? prm->alpha_open / box->G : 0.0;
     const double wmax = (prm->r_cut / prm->r_s) * (prm->r_cut / prm->r_s);
     if (ctx->q_wmax != wmax) {
@@ -1518,7 +1625,7 @@ dzs_status dzs_tree_walk_ex(dzs_ctx *ctx, const dzs_box *box, uint64_t n, const 
     A.key = (const uint64_t *)ctx->key;
     A.boxes = boxes;
     int K = 0;
-    if ((prm->theta <= 1.0 || relative) && !boxes && !A.kept)
+    if ((prm->theta <= 1.0 || relative) && !boxes)
         while (K < DZS_CELL_K_MAX && ldexp(box->L, -(K + 1)) >= prm->r_cut)
             ++K;
     A.cell_K = K;
