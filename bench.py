@@ -678,7 +678,8 @@ def run_headline(args, dz, torch, dzs_ics):
                    "preset": "c5", "particles": N, "mesh": W["ng"], "box": L,
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": headline_walk_traffic(), "traffic_unit": "bytes per launch",
                      "kernel": "tree_walk", "avg_ms": walk_ms,
                      "work_per_launch": f"{pairs / walk_calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP",
                      "timed_on": "the walk's own stream, HIP events around each launch in the timed steps"},
@@ -872,6 +873,26 @@ def measured_traffic(prec_name, workload_is_default):
         src = TRAFFIC_SOURCES.get(cls, "pm.hip")
         out[cls] = b if (same(src) and same("internal.h")) else None
     return out
+
+
+def headline_walk_traffic():
+    """The walk's counter-measured HBM bytes per launch at the 1024^3 headline (FETCH_SIZE +
+    WRITE_SIZE over the timed steps' launches, scaled by a plain copy) from the committed
+    rocprofv3 summary; None when it is missing or the walk's sources changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_1024cube_walk.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    doc = json.loads(m.group(1))
+    csrc = os.path.join(ROOT, "paper_2005_05328_amd", "csrc")
+    for f, h in doc["source_sha256_16"].items():
+        if hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16] != h:
+            return None
+    return doc["bytes_per_launch"]
 
 
 def cpu_baseline(W, ics, box_o, n_steps=8):

@@ -72,7 +72,8 @@ typedef struct {
  * plain-form PM calls on such a context fail with DZS_EINVAL. */
 #define DZS_CAP_FP32_MESHES 1u
 /* Capacity flag: room for the PM force of kdk_step_hier's long-range-on-the-global-step
- * form (dzs_hier_params.pm_global): 24 bytes per particle more. */
+ * form (dzs_hier_params.pm_global) and for the lists of the targets that end a step at a
+ * sub-step boundary: 44 bytes per particle more. */
 #define DZS_CAP_HIER_SPLIT 4u
 /* Capacity flag: no sorted copies for tree_force (28 bytes per particle fewer); tree_force on
  * such a context needs particles already in key order (dzs_tree_params.presorted = 1). */
@@ -290,7 +291,7 @@ typedef struct {
  * 123 bytes per particle (keys and sort indices 24; one arena of 89 shared by the tree, with
  * node capacity max_particles/2 + 4096, and the DZS coarsening buffers; group starts 4; the
  * relative criterion's |g| 4; time-step bins and the walk's target flags 2), plus 28 bytes per
- * particle of sorted copies for tree_force unless DZS_CAP_NO_COPIES, plus 24 bytes per
+ * particle of sorted copies for tree_force unless DZS_CAP_NO_COPIES, plus 44 bytes per
  * particle with DZS_CAP_HIER_SPLIT, plus the meshes (32 bytes per cell, 12 with
  * DZS_CAP_FP32_MESHES).  No call allocates device memory afterwards.
  * Returns DZS_ENOMEM if the device memory does not suffice. */
@@ -310,7 +311,10 @@ const char *dzs_source_hash(void);
  * the order of the state on entry.  The state is left in key order (or (key, id) order
  * after a coarsening that merged nothing), synchronised at a1 with g = the force at a1.
  * The relative opening criterion is not supported here (DZS_EINVAL).  Synchronises the
- * stream (the limiter, the capacity checks, the coarsening count). */
+ * stream (the bins' counts, the limiter, the capacity checks, the coarsening count): a
+ * sub-step boundary where no populated bin ends a step is skipped, and with
+ * DZS_CAP_HIER_SPLIT a boundary where some targets end one walks only the tree's groups that
+ * hold them. */
 dzs_status kdk_step_hier(dzs_ctx *ctx, const dzs_box *box, dzs_particles *state,
                          const dzs_step_params *prm, const dzs_hier_params *hp,
                          dzs_lc_ring *ring, dzs_coarsen_report *report, uint8_t *bins_out,
