@@ -45,6 +45,7 @@ def test_record_and_struct_layout():
     assert C.sizeof(_abi.LCParams) == 3 * 8 + 5 * 8 + 8 + 2 * 24 * 8
     assert C.sizeof(_abi.Capacity) == 8 + 4 * 4
     assert C.sizeof(_abi.TreeParams) == 3 * 8 + 6 * 4 + 8
+    assert C.sizeof(_abi.HierParams) == 2 * 4 + 5 * 8 + 2 * 4
 
 
 @pytest.mark.parametrize("a0,a1", [(0.02, 0.02 * math.exp(0.07824)), (0.5, 0.55),
