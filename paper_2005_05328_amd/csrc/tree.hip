@@ -996,6 +996,7 @@ __device__ __forceinline__ void pair_dense(const pair_eval<T> &ev, const walk_ge
                                            T &ay, T &az, uint64_t act_mask, uint32_t &np_wave) {
     const T rcut2 = T(W.rcut2), L = T(W.L);
     const uint32_t n_max = (uint32_t)__builtin_amdgcn_readfirstlane((int)((nlist + P - 1) / P));
+    uint32_t cnt = 0;   // wave-uniform, kept on the scalar unit
     for (uint32_t k = 0; k < n_max; ++k) {
         const src_entry<T> *q = src.e + s + k * P;
         const auto e = q->pm;
@@ -1003,7 +1004,8 @@ __device__ __forceinline__ void pair_dense(const pair_eval<T> &ev, const walk_ge
         const T r2 = pair_sep<T, MINIMG>(e, xi, yi, zi, L, dx, dy, dz);
         const bool in = pair_inside(r2, rcut2);
         // pairs of the flagged targets, counted on the scalar unit
-        np_wave += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & act_mask);
+        cnt = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)(cnt + (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in) & act_mask)));
         const T g = ev(r2, &q->hh, hi, hi2);
         // the factor of a pair outside (or of the target itself: r = 0) is not used
         const T f = in ? e.w * g : T(0.0);
@@ -1011,6 +1013,7 @@ __device__ __forceinline__ void pair_dense(const pair_eval<T> &ev, const walk_ge
         ay = wfma(f, dy, ay);
         az = wfma(f, dz, az);
     }
+    np_wave += cnt;
 }
 
 // one wave per workgroup; the FP32 walk fits 4 waves per SIMD (128 VGPRs), the FP64 one 3
@@ -1110,7 +1113,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
         const double v_list = 8.0 * ghx * ghy * ghz + 8.0 * rc * (ghx * ghy + ghy * ghz + ghz * ghx) +
                               2.0 * pi * rc * rc * (ghx + ghy + ghz) + v_ball;
         const double dense_e = sizeof(T) == 4 ? WALK_DENSE_E_F32 : WALK_DENSE_E_F64;
-        const bool dense = v_list <= dense_e * v_ball;
+        // (every lane holds the same group box: a wave-uniform choice)
+        const bool dense = __builtin_amdgcn_readfirstlane(v_list <= dense_e * v_ball ? 1 : 0) != 0;
         // relative criterion: alpha / G times the smallest previous |g| of the group
         double alpha_a = 0.0;
         if (A.aold) {
