@@ -312,6 +312,38 @@ __device__ __forceinline__ uint32_t dzs_wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Inclusive scans over the 64 lanes by DPP (no LDS round trips): a Hillis-Steele scan inside
+// each row of 16 lanes by row shifts of 1, 2, 4 and 8 (a lane whose source lies before its row
+// takes 0), then the last lane of row 0 broadcast into row 1 and of row 2 into row 3, then the
+// last lane of row 1 into rows 2 and 3.  Every lane of the wave must be active.
+#define DZS_DPP_ROW_SHR(n) (0x110 + (n))
+#define DZS_DPP_ROW_BCAST15 0x142
+#define DZS_DPP_ROW_BCAST31 0x143
+__device__ __forceinline__ uint32_t dzs_wave_scan_add_full(uint32_t v) {
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, DZS_DPP_ROW_SHR(1), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DZS_DPP_ROW_SHR(2), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DZS_DPP_ROW_SHR(4), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DZS_DPP_ROW_SHR(8), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DZS_DPP_ROW_BCAST15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DZS_DPP_ROW_BCAST31, 0xc, 0xf, false);
+    return (uint32_t)x;
+}
+__device__ __forceinline__ uint32_t dzs_wave_scan_max_full(uint32_t v) {
+    uint32_t x = v;
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DZS_DPP_ROW_SHR(1), 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DZS_DPP_ROW_SHR(2), 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DZS_DPP_ROW_SHR(4), 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DZS_DPP_ROW_SHR(8), 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DZS_DPP_ROW_BCAST15, 0xa, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DZS_DPP_ROW_BCAST31, 0xc, 0xf, false));
+    return x;
+}
+// the value of lane 63, uniform over the wave
+__device__ __forceinline__ uint32_t dzs_wave_last(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // ---------------------------------------------------------------------------------------
 // launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------------------

@@ -1133,6 +1133,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
         for (int o = 32; o >= 1; o >>= 1)
             hg2 = wmax(hg2, (T)__shfl_xor(hg2, o, 64));
         const uint64_t act_mask = __ballot(active);
+        const T m_unit = T(W.m0), h_unit = T(W.h0);
+        const typename vec4_of<T>::half hh_unit = {wmax(h_unit * h_unit, hg2), h_unit};
 
         pair_eval<T> ev;
         if constexpr (sizeof(T) == 4) {
@@ -1221,8 +1223,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                     }
                 }
                 const uint32_t put = node != CELL_EMPTY ? 1u : 0u;
-                const uint32_t incl = dzs_wave_incl_scan(put);
-                const uint32_t tot = __shfl(incl, 63, 64);
+                const uint32_t incl = dzs_wave_scan_add_full(put);
+                const uint32_t tot = dzs_wave_last(incl);
                 if (sp + tot > A.depth) {
                     overflow = true;
                     break;
@@ -1300,8 +1302,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                 wide = true;
             // ---- pushes
             const uint32_t npush = act == 3 ? nchild : 0u;
-            const uint32_t pincl = dzs_wave_incl_scan(npush);
-            const uint32_t ptot = __shfl(pincl, 63, 64);
+            const uint32_t pincl = dzs_wave_scan_add_full(npush);
+            const uint32_t ptot = dzs_wave_last(pincl);
             if (sp + ptot > A.depth) {
                 overflow = true;
                 break;
@@ -1331,8 +1333,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
             const uint32_t nq = (uint32_t)__popcll(lmask);
             if (nq > 0) {
                 const uint32_t lc = act == 1 ? ncount : 0u;
-                const uint32_t lincl = dzs_wave_incl_scan(lc);
-                const uint32_t Ptot = __shfl(lincl, 63, 64);
+                const uint32_t lincl = dzs_wave_scan_add_full(lc);
+                const uint32_t Ptot = dzs_wave_last(lincl);
                 __syncthreads();
                 if (act == 1) {
                     const uint32_t q = (uint32_t)__popcll(lmask & lt_mask);
@@ -1362,14 +1364,9 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                     uint32_t v = q_mark[lane];
                     if (lane == 0)
                         v = v > carry + 1u ? v : carry + 1u;
-#pragma unroll
-                    for (int d = 1; d < 64; d <<= 1) {
-                        const uint32_t t = __shfl_up(v, d, 64);
-                        if (lane >= (uint32_t)d)
-                            v = v > t ? v : t;
-                    }
+                    v = dzs_wave_scan_max_full(v);
                     const uint32_t lo = v - 1u;
-                    carry = __shfl(lo, 63, 64);
+                    carry = dzs_wave_last(lo);
                     bool keep = false;
                     double ex_ = 0.0, ey_ = 0.0, ez_ = 0.0;
                     uint32_t mj = 0;
@@ -1391,11 +1388,16 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                             flush();
                         if (keep) {
                             const uint32_t slot = nlist + (uint32_t)__popcll(kmask & lt_mask);
-                            const double md = (double)mj;
-                            src.e[slot].pm = {T(ex_ - ox), T(ey_ - oy), T(ez_ - oz),
-                                              T(W.m0 * md)};
-                            const T hj = T(W.h0 * mult_cbrt(mj));
-                            src.e[slot].hh = {wmax(hj * hj, hg2), hj};
+                            // an original particle (multiplicity 1) takes the group's constants
+                            T mj_mass = m_unit;
+                            typename vec4_of<T>::half mj_hh = hh_unit;
+                            if (mj != 1u) {
+                                mj_mass = T(W.m0 * (double)mj);
+                                const T hj = T(W.h0 * mult_cbrt(mj));
+                                mj_hh = {wmax(hj * hj, hg2), hj};
+                            }
+                            src.e[slot].pm = {T(ex_ - ox), T(ey_ - oy), T(ez_ - oz), mj_mass};
+                            src.e[slot].hh = mj_hh;
                         }
                         nlist += nk;
                     }
