@@ -1029,6 +1029,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
     __shared__ uint32_t q_wide[64];
     __shared__ uint32_t q_mark[64];
     __shared__ uint32_t s_g;
+    __shared__ float s_hbox[12];
     __shared__ float4 s_tab[sizeof(T) == 4 ? WALK_TAB_N + 1 : 1];
 
     const uint32_t lane = threadIdx.x;
@@ -1135,6 +1136,34 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
         const uint64_t act_mask = __ballot(active);
         const T m_unit = T(W.m0), h_unit = T(W.h0);
         const typename vec4_of<T>::half hh_unit = {wmax(h_unit * h_unit, hg2), h_unit};
+        // A dense FP32 group is evaluated as two halves, A (its targets 0 .. G/2-1) and B
+        // (G/2 .. G-1), compact in Morton order, each against the entries near its own box: at
+        // every flush the list is reordered (stably) into the entries near A only, near both and
+        // near B only, so that each half steps through a contiguous part of it with twice the
+        // phases.  Entries farther than r_cut from both boxes are dropped.
+        const uint32_t Gh = G >> 1;
+        const uint32_t Ph = G >= 4u ? 64u / Gh : 1u;
+        const bool halves = sizeof(T) == 4 && dense && G >= 4u;
+        float rc_cls2 = 0.0f;
+        if (sizeof(T) == 4 && halves) {
+            const float inf = __builtin_inff();
+            float b[6] = {valid ? float(txi) : inf, valid ? float(tyi) : inf,
+                          valid ? float(tzi) : inf, valid ? float(txi) : -inf,
+                          valid ? float(tyi) : -inf, valid ? float(tzi) : -inf};
+            for (uint32_t o = 1; o < Gh; o <<= 1)
+                for (int c = 0; c < 6; ++c) {
+                    const float t = __shfl_xor(b[c], (int)o, 64);
+                    b[c] = c < 3 ? fminf(b[c], t) : fmaxf(b[c], t);
+                }
+            // the halves' boxes (lo x, y, z, hi x, y, z in the group-centre frame) to LDS
+            if (lane == 0u || lane == Gh)
+                for (int c = 0; c < 6; ++c)
+                    s_hbox[lane == 0u ? c : 6 + c] = b[c];
+            // a few FP32 ulps of the largest coordinate above r_cut, so that the box test never
+            // drops an entry the pair test would take
+            const double rc_m = W.rcut * (1.0 + 1e-6) + 1e-6 * (W.rcut + 2.0 * ghmax);
+            rc_cls2 = __double2float_ru(rc_m * rc_m);
+        }
 
         pair_eval<T> ev;
         if constexpr (sizeof(T) == 4) {
@@ -1147,12 +1176,112 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
             ev.t_scale = A.t_scale;
         }
         T ax = T(0.0), ay = T(0.0), az = T(0.0);
+        T bx = T(0.0), by = T(0.0), bz = T(0.0);   // half B's (ax, ay, az hold half A's)
         uint32_t nlist = 0;
         uint32_t n_pairs = 0;   // per lane (the masked loop)
         uint32_t np_wave = 0;   // the wave's (the dense loop)
         bool wide = false;
 
         auto flush = [&]() {
+            if constexpr (sizeof(T) == 4) {
+                if (halves) {
+                    uint32_t nA = nlist, bB = 0u, nB = nlist, nt = nlist;
+                    if (!wide) {
+                        // lane l holds entries l and l + 64 (the list holds at most 128)
+                        static_assert(WALK_LIST <= 128, "two list entries per lane");
+                        float hbA[6], hbB[6];
+                        for (int c = 0; c < 6; ++c) {
+                            hbA[c] = s_hbox[c];
+                            hbB[c] = s_hbox[6 + c];
+                        }
+                        float4 p0 = {0.0f, 0.0f, 0.0f, 0.0f}, p1 = p0;
+                        float2 q0 = {0.0f, 0.0f}, q1 = q0;
+                        uint32_t c0 = 0u, c1 = 0u;   // 1 near A only, 2 near both, 3 near B only
+                        auto cls = [&](const float4 &p) -> uint32_t {
+                            auto d2 = [&](const float *bx_) {
+                                const float dx = fmaxf(fmaxf(bx_[0] - p.x, p.x - bx_[3]), 0.0f);
+                                const float dy = fmaxf(fmaxf(bx_[1] - p.y, p.y - bx_[4]), 0.0f);
+                                const float dz = fmaxf(fmaxf(bx_[2] - p.z, p.z - bx_[5]), 0.0f);
+                                return __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                            };
+                            const bool a = d2(hbA) < rc_cls2, b = d2(hbB) < rc_cls2;
+                            return a ? (b ? 2u : 1u) : (b ? 3u : 0u);
+                        };
+                        if (lane < nlist) {
+                            p0 = src.e[lane].pm;
+                            q0 = src.e[lane].hh;
+                            c0 = cls(p0);
+                        }
+                        if (lane + 64u < nlist) {
+                            p1 = src.e[lane + 64u].pm;
+                            q1 = src.e[lane + 64u].hh;
+                            c1 = cls(p1);
+                        }
+                        const uint64_t m01 = __ballot(c0 == 1u), m02 = __ballot(c0 == 2u),
+                                       m03 = __ballot(c0 == 3u), m11 = __ballot(c1 == 1u),
+                                       m12 = __ballot(c1 == 2u), m13 = __ballot(c1 == 3u);
+                        const uint32_t n1 = (uint32_t)(__popcll(m01) + __popcll(m11));
+                        const uint32_t n2 = (uint32_t)(__popcll(m02) + __popcll(m12));
+                        const uint32_t n3 = (uint32_t)(__popcll(m03) + __popcll(m13));
+                        // stable destinations: class base, then the entries of the class before
+                        const uint32_t s0 =
+                            c0 == 1u ? (uint32_t)__popcll(m01 & lt_mask)
+                                     : (c0 == 2u ? n1 + (uint32_t)__popcll(m02 & lt_mask)
+                                                 : n1 + n2 + (uint32_t)__popcll(m03 & lt_mask));
+                        const uint32_t r11 = (uint32_t)(__popcll(m01) + __popcll(m11 & lt_mask));
+                        const uint32_t r12 = (uint32_t)(__popcll(m02) + __popcll(m12 & lt_mask));
+                        const uint32_t r13 = (uint32_t)(__popcll(m03) + __popcll(m13 & lt_mask));
+                        const uint32_t s1 = c1 == 1u ? r11 : (c1 == 2u ? n1 + r12 : n1 + n2 + r13);
+                        __syncthreads();   // every entry read before any is moved
+                        if (c0 != 0u) {
+                            src.e[s0].pm = p0;
+                            src.e[s0].hh = q0;
+                        }
+                        if (c1 != 0u) {
+                            src.e[s1].pm = p1;
+                            src.e[s1].hh = q1;
+                        }
+                        nA = n1 + n2;
+                        bB = n1;
+                        nB = n2 + n3;
+                        nt = n1 + n2 + n3;
+                    }
+                    if (lane < Ph) {  // sentinels: far outside every cutoff, in any image
+                        src.e[nt + lane].pm = {T(1e30), T(1e30), T(1e30), T(0.0)};
+                        src.e[nt + lane].hh = {T(0.0), T(0.0)};
+                    }
+                    __syncthreads();
+                    const uint32_t sph = lane / Gh, t0 = lane % Gh;
+                    {
+                        const uint32_t ts = t0;   // main-layout lane of the target (half A)
+                        const T xs = __shfl(txi, (int)ts, 64), ys = __shfl(tyi, (int)ts, 64),
+                                zs = __shfl(tzi, (int)ts, 64), hs = __shfl(thi, (int)ts, 64);
+                        const uint64_t am = __ballot(__shfl((int)active, (int)ts, 64) != 0);
+                        if (wide)
+                            pair_dense<T, true>(ev, W, src, nA, sph, Ph, xs, ys, zs, hs, hs * hs,
+                                                ax, ay, az, am, np_wave);
+                        else
+                            pair_dense<T, false>(ev, W, src, nA, sph, Ph, xs, ys, zs, hs, hs * hs,
+                                                 ax, ay, az, am, np_wave);
+                    }
+                    {
+                        const uint32_t ts = Gh + t0;   // half B
+                        const T xs = __shfl(txi, (int)ts, 64), ys = __shfl(tyi, (int)ts, 64),
+                                zs = __shfl(tzi, (int)ts, 64), hs = __shfl(thi, (int)ts, 64);
+                        const uint64_t am = __ballot(__shfl((int)active, (int)ts, 64) != 0);
+                        const src_list<T> sB{src.e + bB};
+                        if (wide)
+                            pair_dense<T, true>(ev, W, sB, nB, sph, Ph, xs, ys, zs, hs, hs * hs,
+                                                bx, by, bz, am, np_wave);
+                        else
+                            pair_dense<T, false>(ev, W, sB, nB, sph, Ph, xs, ys, zs, hs, hs * hs,
+                                                 bx, by, bz, am, np_wave);
+                    }
+                    nlist = 0;
+                    __syncthreads();
+                    return;
+                }
+            }
             if (lane < P) {  // sentinels: far outside every cutoff, in any image
                 src.e[nlist + lane].pm = {T(1e30), T(1e30), T(1e30), T(0.0)};
                 src.e[nlist + lane].hh = {T(0.0), T(0.0)};
@@ -1355,6 +1484,9 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                 const uint32_t lq = (uint32_t)__popcll(lmask & lt_mask);
                 uint32_t carry = 0;
                 for (uint32_t done = 0; done < Ptot; done += 64) {
+                    // room for every candidate of the pass: no candidate is held across a flush
+                    if (nlist + min(Ptot - done, 64u) > WALK_LIST)
+                        flush();
                     const uint32_t f = done + lane;
                     q_mark[lane] = 0u;
                     __syncthreads();
@@ -1384,8 +1516,6 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                     const uint64_t kmask = __ballot(keep);
                     const uint32_t nk = (uint32_t)__popcll(kmask);
                     if (nk > 0) {
-                        if (nlist + nk > WALK_LIST)
-                            flush();
                         if (keep) {
                             const uint32_t slot = nlist + (uint32_t)__popcll(kmask & lt_mask);
                             // an original particle (multiplicity 1) takes the group's constants
@@ -1410,11 +1540,31 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                 atomicOr(&A.counter[2], 1u);   // sticky until checked
         }
         flush();
-        // fixed-order sum of the P partial accelerations of each target
-        for (uint32_t o = G; o < 64; o <<= 1) {
-            ax += __shfl_xor(ax, o, 64);
-            ay += __shfl_xor(ay, o, 64);
-            az += __shfl_xor(az, o, 64);
+        if (halves) {
+            // fixed-order sums of the Ph partial accelerations of each half's targets, then each
+            // target's sum moved to its lane (tl) of the group layout
+            for (uint32_t o = Gh; o < 64; o <<= 1) {
+                ax += __shfl_xor(ax, o, 64);
+                ay += __shfl_xor(ay, o, 64);
+                az += __shfl_xor(az, o, 64);
+                bx += __shfl_xor(bx, o, 64);
+                by += __shfl_xor(by, o, 64);
+                bz += __shfl_xor(bz, o, 64);
+            }
+            const int sl = (int)(tl % Gh);
+            const T ax2 = __shfl(ax, sl, 64), ay2 = __shfl(ay, sl, 64), az2 = __shfl(az, sl, 64);
+            const T bx2 = __shfl(bx, sl, 64), by2 = __shfl(by, sl, 64), bz2 = __shfl(bz, sl, 64);
+            const bool inA = tl < Gh;
+            ax = inA ? ax2 : bx2;
+            ay = inA ? ay2 : by2;
+            az = inA ? az2 : bz2;
+        } else {
+            // fixed-order sum of the P partial accelerations of each target
+            for (uint32_t o = G; o < 64; o <<= 1) {
+                ax += __shfl_xor(ax, o, 64);
+                ay += __shfl_xor(ay, o, 64);
+                az += __shfl_xor(az, o, 64);
+            }
         }
         {
             uint64_t cnt_pairs = active ? n_pairs : 0u;
