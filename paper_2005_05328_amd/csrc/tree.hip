@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
     const src_list<T> src{s_list};
     __shared__ uint32_t q_first[64];
     __shared__ uint32_t q_pref[65];
-    __shared__ double q_shift[3][64];
+    __shared__ double q_org[3][64];   // a queued leaf's origin in the list frame (image shift)
     __shared__ uint32_t q_wide[64];
     __shared__ uint32_t q_mark[64];
     __shared__ uint32_t s_g;
@@ -1469,9 +1469,9 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                     const uint32_t q = (uint32_t)__popcll(lmask & lt_mask);
                     q_first[q] = nfirst;
                     q_pref[q] = lincl - lc;
-                    q_shift[0][q] = shx;
-                    q_shift[1][q] = shy;
-                    q_shift[2][q] = shz;
+                    q_org[0][q] = ox - shx;
+                    q_org[1][q] = oy - shy;
+                    q_org[2][q] = oz - shz;
                     q_wide[q] = node_wide ? 1u : 0u;
                 }
                 if (lane == 0)
@@ -1504,13 +1504,15 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                     uint32_t mj = 0;
                     if (f < Ptot) {
                         const uint32_t j = q_first[lo] + (f - q_pref[lo]);
-                        ex_ = A.x[j] + q_shift[0][lo];
-                        ey_ = A.y[j] + q_shift[1][lo];
-                        ez_ = A.z[j] + q_shift[2][lo];
+                        // the particle in the list frame: its nearest image, less the group
+                        // centre in FP32 (then the offset from the centre is the coordinate)
+                        ex_ = A.x[j] - q_org[0][lo];
+                        ey_ = A.y[j] - q_org[1][lo];
+                        ez_ = A.z[j] - q_org[2][lo];
                         mj = A.mult[j];
-                        const double cx = fmax(0.0, fabs(ex_ - gcx) - ghx);
-                        const double cy = fmax(0.0, fabs(ey_ - gcy) - ghy);
-                        const double cz = fmax(0.0, fabs(ez_ - gcz) - ghz);
+                        const double cx = fmax(0.0, fabs(rel ? ex_ : ex_ - gcx) - ghx);
+                        const double cy = fmax(0.0, fabs(rel ? ey_ : ey_ - gcy) - ghy);
+                        const double cz = fmax(0.0, fabs(rel ? ez_ : ez_ - gcz) - ghz);
                         keep = q_wide[lo] != 0u || cx * cx + cy * cy + cz * cz < W.rcut2;
                     }
                     const uint64_t kmask = __ballot(keep);
@@ -1526,7 +1528,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 4 : 3) void k_tree_walk(walk_a
                                 const T hj = T(W.h0 * mult_cbrt(mj));
                                 mj_hh = {wmax(hj * hj, hg2), hj};
                             }
-                            src.e[slot].pm = {T(ex_ - ox), T(ey_ - oy), T(ez_ - oz), mj_mass};
+                            src.e[slot].pm = {T(ex_), T(ey_), T(ez_), mj_mass};
                             src.e[slot].hh = mj_hh;
                         }
                         nlist += nk;

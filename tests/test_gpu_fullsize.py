@@ -182,7 +182,7 @@ def _lattice_sources(n_side, targets, r_cut, lam):
 @pytest.mark.timeout(900)
 def test_full_size_1024cube_on_sampled_targets():
     """The headline configuration: 1024^3 particles, L = 2000, mesh 1024^3, FP32 precision
-    form, opening angle 0.5, groups of 32, leaves of 8, on the z = 49 initial state, in a
+    form, opening angle 0.5, groups of 64, leaves of 8, on the z = 49 initial state, in a
     context of the headline's memory plan but with plain-form-capable meshes.  The state is
     sorted once; the short range of 600 sampled targets (tree_force's target subset on the
     presorted state) against the oracle's direct sum, and the PM against the GPU's FP64 PM."""
@@ -223,13 +223,13 @@ def test_full_size_1024cube_on_sampled_targets():
     g_pm64 = at_targets()
     ctx.pm_force(box, st, dz.PMParams(ng, dz.DZS_FP32, r_s, 0, 0))
     g_pm = at_targets()
-    tp = dz.TreeParams(r_s, r_cut, 0.0, 8, 32, dz.DZS_FP32, 0)
+    tp = dz.TreeParams(r_s, r_cut, 0.0, 8, 64, dz.DZS_FP32, 0)
     tp.presorted = 1
     ctx.tree_force(box, st, tp, targets=slots)
     ctx.check()
     g_sr0 = at_targets()
     ctx.pm_force(box, st, dz.PMParams(ng, dz.DZS_FP32, r_s, 0, 0))
-    tp = dz.TreeParams(r_s, r_cut, 0.5, 8, 32, dz.DZS_FP32, 1)
+    tp = dz.TreeParams(r_s, r_cut, 0.5, 8, 64, dz.DZS_FP32, 1)
     tp.presorted = 1
     ctx.tree_force(box, st, tp, targets=slots)
     ctx.check()

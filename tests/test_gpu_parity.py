@@ -400,7 +400,9 @@ def test_pm_force_fp32_matches_oracle(dz, ctx, kind, n):
 @pytest.mark.parametrize("kind,n,theta,tol,gsize", [("clustered", 20000, 0.0, 1e-5, 64),
                                                     ("merged", 30001, 0.0, 1e-5, 16),
                                                     ("zeldovich", 32768, 0.0, 1e-5, 32),
-                                                    ("clustered", 20000, 0.5, 5e-3, 32)])
+                                                    ("zeldovich", 32768, 0.0, 1e-5, 64),
+                                                    ("clustered", 20000, 0.5, 5e-3, 32),
+                                                    ("clustered", 20000, 0.5, 5e-3, 64)])
 def test_tree_force_fp32_matches_direct_sum(dz, ctx, kind, n, theta, tol, gsize):
     import torch
     L, ng = 100.0, 64
