@@ -682,7 +682,11 @@ def run_headline(args, dz, torch, dzs_ics):
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": headline_walk_traffic(), "traffic_unit": "bytes per launch",
+                     # the committed counters cover this exact run: 1024^3, default group and
+                     # leaf sizes, the launches of steps 6-25
+                     "traffic": (headline_walk_traffic() if not (args.n_side or args.group or
+                                 args.leaf) and (Wu, K) == (5, 20) else None),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "tree_walk", "avg_ms": walk_ms,
                      "work_per_launch": f"{pairs / walk_calls:.4g} interactions x {FLOP_PER_INTERACTION} FLOP",
                      "timed_on": "the walk's own stream, HIP events around each launch in the timed steps"},
