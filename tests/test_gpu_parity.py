@@ -401,6 +401,8 @@ def test_pm_force_fp32_matches_oracle(dz, ctx, kind, n):
                                                     ("merged", 30001, 0.0, 1e-5, 16),
                                                     ("zeldovich", 32768, 0.0, 1e-5, 32),
                                                     ("zeldovich", 32768, 0.0, 1e-5, 64),
+                                                    ("zeldovich", 32768, 0.0, 1e-5, 8),
+                                                    ("clustered", 20000, 0.0, 1e-5, 4),
                                                     ("clustered", 20000, 0.5, 5e-3, 32),
                                                     ("clustered", 20000, 0.5, 5e-3, 64)])
 def test_tree_force_fp32_matches_direct_sum(dz, ctx, kind, n, theta, tol, gsize):
