@@ -294,6 +294,38 @@ __device__ __forceinline__ void chunk_bounds(uint64_t p0, uint64_t p1, const dou
 // to the mesh (wrapped) with one global atomic.  A piece whose box is too large is halved (a
 // sparse region) down to PM_PIECE_MIN particles, below which it adds directly.  The mesh is
 // the same integer sum either way.
+// The coordinates (a, b, e) of tile point c = (a tey + b) tez + e, advanced by a fixed stride
+// with carries instead of two integer divisions per point.
+struct tile_walk {
+    uint32_t a, b, e, da, db, de, tey, tez;
+    __device__ __forceinline__ tile_walk(uint32_t c0, uint32_t stride, uint32_t tey_,
+                                         uint32_t tez_)
+        : tey(tey_), tez(tez_) {
+        const uint32_t pyz = tey * tez;
+        a = c0 / pyz;
+        const uint32_t r = c0 - a * pyz;
+        b = r / tez;
+        e = r - b * tez;
+        da = stride / pyz;
+        const uint32_t q = stride - da * pyz;
+        db = q / tez;
+        de = q - db * tez;
+    }
+    __device__ __forceinline__ void next() {
+        e += de;
+        b += db;
+        a += da;
+        if (e >= tez) {
+            e -= tez;
+            ++b;
+        }
+        if (b >= tey) {
+            b -= tey;
+            ++a;
+        }
+    }
+};
+
 __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
     uint64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const uint32_t *__restrict__ mult, double delta, int ng,
@@ -368,15 +400,13 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
                     }
         }
         __syncthreads();
-        const uint32_t pyz = tey * tez;
-        for (uint32_t c = tid; c < cells; c += PM_THREADS) {
+        tile_walk w(tid, PM_THREADS, tey, tez);
+        for (uint32_t c = tid; c < cells; c += PM_THREADS, w.next()) {
             const unsigned long long v = s_tile[c];
             if (!v)
                 continue;
-            const uint32_t a = c / pyz, r = c - a * pyz;
-            const uint32_t b = r / tez, e = r - b * tez;
-            const int ix = wrap_index(lo0 + (int)a, gn), iy = wrap_index(lo1 + (int)b, gn),
-                      iz = wrap_index(lo2 + (int)e, gn);
+            const int ix = wrap_index(lo0 + (int)w.a, gn), iy = wrap_index(lo1 + (int)w.b, gn),
+                      iz = wrap_index(lo2 + (int)w.e, gn);
             atomicAdd(&qb[((uint64_t)ix * gn + iy) * gn + iz], v);
         }
         __syncthreads();   // the tile is read before the next piece clears it
@@ -719,15 +749,14 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_interp_tiled(
             gn = bx.ng;
             pb = phi + bx.mesh_off;
         }
-        const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez, pyz = tey * tez;
+        const uint32_t tey = (uint32_t)ey, tez = (uint32_t)ez;
         const uint32_t cells = (uint32_t)(ex * ey * ez);
         const uint64_t N = (uint64_t)gn;
-        for (uint32_t c = tid; c < cells; c += PM_THREADS) {
-            const uint32_t a = c / pyz, r = c - a * pyz;
-            const uint32_t b = r / tez, e = r - b * tez;
-            const int ix = wrap_index(lo0 - 2 + (int)a, gn),
-                      iy = wrap_index(lo1 - 2 + (int)b, gn),
-                      iz = wrap_index(lo2 - 2 + (int)e, gn);
+        tile_walk w(tid, PM_THREADS, tey, tez);
+        for (uint32_t c = tid; c < cells; c += PM_THREADS, w.next()) {
+            const int ix = wrap_index(lo0 - 2 + (int)w.a, gn),
+                      iy = wrap_index(lo1 - 2 + (int)w.b, gn),
+                      iz = wrap_index(lo2 - 2 + (int)w.e, gn);
             s_phi[c] = pb[((uint64_t)ix * N + iy) * N + iz];
         }
         __syncthreads();
