@@ -170,9 +170,10 @@ __device__ __forceinline__ void load_twiddles(C *s_tw, const double2 *tw, int n)
 // deposit
 // ---------------------------------------------------------------------------------------
 // Unwrapped cloud-in-cell base index floor(x / Delta) of one axis and the weights of the
-// base point and the next one.
+// base point and the next one (x times the reciprocal of Delta: a loop over particles of one
+// mesh computes the reciprocal once).
 __device__ __forceinline__ int cic_base(double x, double delta, double &w0, double &w1) {
-    const double u = x / delta;
+    const double u = x * (1.0 / delta);
     const double f = floor(u);
     w1 = u - f;
     w0 = 1.0 - w1;
@@ -182,6 +183,14 @@ __device__ __forceinline__ int cic_base(double x, double delta, double &w0, doub
 __device__ __forceinline__ int wrap_index(int i, int ng) {
     i %= ng;
     return i < 0 ? i + ng : i;
+}
+
+// The same for an index within one period of the mesh, -ng <= i < 2 ng, by compares instead
+// of a division: a stencil point i0 + d (|d| <= 3 < ng), or a tile point (the base indices of
+// positions in [0, L) lie in [0, ng], a tile reaches at most ng + 2 points past its lowest and
+// starts at most 2 before it; meshes have at least 8 points per side).
+__device__ __forceinline__ int wrap_near(int i, int ng) {
+    return i < 0 ? i + ng : (i >= ng ? i - ng : i);
 }
 
 __device__ __forceinline__ void cic_axis(double x, double delta, int ng, int &i0, int &i1,
@@ -405,8 +414,8 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_deposit_tiled(
             const unsigned long long v = s_tile[c];
             if (!v)
                 continue;
-            const int ix = wrap_index(lo0 + (int)w.a, gn), iy = wrap_index(lo1 + (int)w.b, gn),
-                      iz = wrap_index(lo2 + (int)w.e, gn);
+            const int ix = wrap_near(lo0 + (int)w.a, gn), iy = wrap_near(lo1 + (int)w.b, gn),
+                      iz = wrap_near(lo2 + (int)w.e, gn);
             atomicAdd(&qb[((uint64_t)ix * gn + iy) * gn + iz], v);
         }
         __syncthreads();   // the tile is read before the next piece clears it
@@ -629,11 +638,6 @@ __device__ __forceinline__ void cic_gradient(const At &at, const double *wx, con
             }
 }
 
-// index i0 + d wrapped to [0, ng) for |d| <= 3 < ng
-__device__ __forceinline__ int wrap_near(int i, int ng) {
-    return i < 0 ? i + ng : (i >= ng ? i - ng : i);
-}
-
 template <typename Rt>
 __device__ __forceinline__ void interp_store(uint64_t p, double delta, Rt sx, Rt sy, Rt sz,
                                              double *__restrict__ gx, double *__restrict__ gy,
@@ -754,9 +758,9 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_interp_tiled(
         const uint64_t N = (uint64_t)gn;
         tile_walk w(tid, PM_THREADS, tey, tez);
         for (uint32_t c = tid; c < cells; c += PM_THREADS, w.next()) {
-            const int ix = wrap_index(lo0 - 2 + (int)w.a, gn),
-                      iy = wrap_index(lo1 - 2 + (int)w.b, gn),
-                      iz = wrap_index(lo2 - 2 + (int)w.e, gn);
+            const int ix = wrap_near(lo0 - 2 + (int)w.a, gn),
+                      iy = wrap_near(lo1 - 2 + (int)w.b, gn),
+                      iz = wrap_near(lo2 - 2 + (int)w.e, gn);
             s_phi[c] = pb[((uint64_t)ix * N + iy) * N + iz];
         }
         __syncthreads();
