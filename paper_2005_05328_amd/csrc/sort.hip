@@ -295,6 +295,25 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__r
     hist[(uint64_t)threadIdx.x * tiles + blockIdx.x] = s_h[threadIdx.x];
 }
 
+// The scanned histogram from digit-major ([256][tiles], the order of the global scan) to
+// tile-major ([tiles][256]), so that a scatter tile reads its 256 start offsets as one
+// contiguous kilobyte: 64 tiles per workgroup through an LDS block (rows padded by one word).
+__global__ __launch_bounds__(SORT_THREADS) void k_hist_tile_major(const uint32_t *__restrict__ in,
+                                                                  uint32_t *__restrict__ out,
+                                                                  uint32_t tiles) {
+    static_assert(SORT_THREADS == 256, "one thread per digit");
+    __shared__ uint32_t s_t[256][65];
+    const uint32_t t0 = blockIdx.x * 64u;
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    for (uint32_t d = w; d < 256u; d += SORT_THREADS / 64) {
+        const uint32_t t = t0 + lane;
+        s_t[d][lane] = t < tiles ? in[(uint64_t)d * tiles + t] : 0u;
+    }
+    __syncthreads();
+    for (uint32_t r = 0; r < 64u && t0 + r < tiles; ++r)
+        out[(uint64_t)(t0 + r) * 256u + threadIdx.x] = s_t[threadIdx.x][r];
+}
+
 // Each wave ranks its own contiguous quarter of the tile (16 rounds of 64 keys, in input
 // order) against running per-wave digit counts in LDS, with no block barrier between rounds:
 // lanes holding the same digit are found with eight ballots, the lowest of them advances the
@@ -304,7 +323,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint64_t *__r
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
     uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out, uint64_t n, int shift,
-    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hist_scan, uint32_t tiles) {
+    const uint32_t *__restrict__ gstart) {
     constexpr int WAVES = SORT_THREADS / 64;
     constexpr int ROUNDS = SORT_ITEMS;  // rounds of 64 keys per wave: 4 waves x 16 x 64 = tile
     __shared__ uint64_t s_key[SORT_TILE];
@@ -318,9 +337,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t cnt = (uint32_t)((n - base) < SORT_TILE ? (n - base) : SORT_TILE);
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
-    const uint32_t c = hist[(uint64_t)tid * tiles + blockIdx.x];
-    s_gstart[tid] = hist_scan[(uint64_t)tid * tiles + blockIdx.x];
-    s_lstart[tid] = block_excl_scan_256(c, s_wave, nullptr);
+    // the tile's global start of each digit (tile-major scanned histogram)
+    s_gstart[tid] = gstart[(uint64_t)blockIdx.x * 256u + tid];
     for (int w = 0; w < WAVES; ++w)
         s_wcnt[w][tid] = 0;
     __syncthreads();
@@ -351,8 +369,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     }
     __syncthreads();
     {
-        // offsets of each wave's run of digit tid inside the tile
-        uint32_t run = s_lstart[tid];
+        // the tile's count of digit tid (the waves' counts), its start inside the tile, and
+        // the offsets of each wave's run of it
+        uint32_t c = 0;
+        for (int w = 0; w < WAVES; ++w)
+            c += s_wcnt[w][tid];
+        const uint32_t ls = block_excl_scan_256(c, s_wave, nullptr);
+        s_lstart[tid] = ls;
+        uint32_t run = ls;
         for (int w = 0; w < WAVES; ++w) {
             const uint32_t t = s_wcnt[w][tid];
             s_wcnt[w][tid] = run;
@@ -400,8 +424,12 @@ dzs_status dzs_radix_sort(dzs_ctx *ctx, uint64_t n, hipStream_t s, int first_pas
                            ctx->hist, tiles);
         DZS_TRY(dzs_check_launch(ctx, "radix_hist"));
         DZS_TRY(dzs_scan_u32(ctx, ctx->hist, ctx->hist_scan, words, nullptr, s));
+        // the counts are no longer needed: their buffer takes the tile-major starts
+        hipLaunchKernelGGL(k_hist_tile_major, dim3((tiles + 63u) / 64u), dim3(SORT_THREADS), 0,
+                           s, (const uint32_t *)ctx->hist_scan, ctx->hist, tiles);
+        DZS_TRY(dzs_check_launch(ctx, "radix_hist_tile_major"));
         hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(SORT_THREADS), 0, s, kin, iin,
-                           kout, iout, n, shift, ctx->hist, ctx->hist_scan, tiles);
+                           kout, iout, n, shift, (const uint32_t *)ctx->hist);
         DZS_TRY(dzs_check_launch(ctx, "radix_scatter"));
         uint64_t *tk = kin; kin = kout; kout = tk;
         uint32_t *ti = iin; iin = iout; iout = ti;
